@@ -1,0 +1,202 @@
+/*
+ * srmra.h -- C ABI of the MI355X (gfx950) EM step for 2-D super-resolution
+ * multi-reference alignment (SR-MRA).
+ *
+ * Method: Shani, Tirer, Giryes, Bendory, "Denoiser-based projections for 2D
+ * super-resolution MRA".  One call performs one *unprojected* EM step from
+ * theta_t = (x, rho1, rho2):
+ *
+ *   model          y_i[n] = x[(n1 K - s1) mod Lh, (n2 K - s2) mod Lh] + eps  (Sec. 1, eq. model_1)
+ *   log-likelihood l(theta_t) = sum_i log sum_s rho[s] exp(-||y_i - P R_s x||^2 / 2 sigma^2)
+ *                                                                (Sec. 2, eq. likelihood_EM)
+ *   posterior      w^{i,s} proportional to rho[s] exp(-||y_i - P R_s x||^2 / 2 sigma^2),
+ *                  sum_s w^{i,s} = 1                              (Sec. 2, eq. weights_EM)
+ *   M-step         A x_new = b                                    (Sec. 2, eq. x_EM)
+ *                  rho_new[s] = sum_i w^{i,s} / sum_i sum_s' w^{i,s'}  (Sec. 2, eq. rho_EM)
+ *
+ * Conventions fixed by this library (the paper leaves them open):
+ *  - shifts are 0-based and taken mod L_high; s1 / rho1 act on axis 0 (rows)
+ *    of the row-major image, s2 / rho2 on axis 1; (R_s x)[m] = x[m - s];
+ *  - P^{-1} in eq. x_EM is P^T, so A is diagonal and x_new = b / A per pixel;
+ *    a pixel with zero posterior mass keeps its input value;
+ *  - rho = rho1 rho2^T; the rho M-step returns the two marginals of the
+ *    numerator of eq. rho_EM over its denominator;
+ *  - loglik is eq. likelihood_EM literally (no Gaussian normalising constant)
+ *    evaluated at the INPUT theta_t;
+ *  - log_rho is used as given (need not be normalised; -inf allowed, but each
+ *    row needs at least one finite entry).
+ *
+ * Memory and execution model:
+ *  - every pointer argument except `probs` / `plan` / `workspace_bytes` of the
+ *    plan calls is a DEVICE pointer; the caller owns every buffer;
+ *  - the library never allocates or frees device memory, never synchronises
+ *    the device and never copies device data to the host;
+ *  - arguments are validated on the host before anything is enqueued; on an
+ *    error return nothing has been enqueued;
+ *  - on success all work is enqueued asynchronously on `stream`; execution
+ *    errors surface through the stream (or as SRMRA_EDEVICE from the launch);
+ *  - the library keeps no global mutable state: concurrent calls on different
+ *    streams with disjoint buffers are safe.
+ *
+ * Layouts (all row-major, contiguous):
+ *  y        float [N][L_low][L_low], 16-byte aligned
+ *  x, x_new float [L_high][L_high],  L_high = K * L_low
+ *  log_rho  float [2][L_high]   row 0 = log rho1 (axis 0), row 1 = log rho2 (axis 1)
+ *  rho_new  float [2][L_high]   probabilities, each row sums to 1
+ *  loglik   double [1]
+ *
+ * Supported shapes: L_low in {8, 12, 16, 24, 32, 48, 64}, K >= 1,
+ * L_high = K * L_low <= 4096, 1 <= N <= 2^31 - 1.  Other L_low return
+ * SRMRA_EUNSUPPORTED.
+ */
+#ifndef SRMRA_H
+#define SRMRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SRMRA_OK = 0,
+    SRMRA_EINVAL = -1,        /* bad argument (null pointer, size, sigma, aliasing) */
+    SRMRA_EUNSUPPORTED = -2,  /* shape or precision not built into this library   */
+    SRMRA_EWORKSPACE = -3,    /* workspace / prepared buffer too small              */
+    SRMRA_EDEVICE = -4        /* a HIP launch reported an error                     */
+} srmra_status;
+
+/* Arithmetic of the two dense contractions (score and back-projection).
+ * Every form accumulates in FP32 and reduces across observations in FP64. */
+typedef enum {
+    SRMRA_FP32_PLAIN = 0,     /* FP32 FMAs on the vector ALUs                       */
+    SRMRA_FP32_MFMA = 1,      /* FP32 matrix cores (v_mfma_f32_32x32x2 / 16x16x4)   */
+    SRMRA_BF16_SPLIT3 = 2     /* BF16 matrix cores, operands split v = hi + lo,
+                                 products hi*hi + hi*lo + lo*hi, FP32 accumulate    */
+} srmra_precision;
+
+/* Human-readable text of a status code (static storage). */
+const char* srmra_status_string(int status);
+
+/* Library version string (static storage). */
+const char* srmra_version(void);
+
+/* Bytes of device workspace srmra_em_step needs for this shape/precision
+ * (0 if the shape is unsupported).  Workspace content need not be initialised
+ * and is not preserved between calls. */
+size_t srmra_em_step_workspace_bytes(int64_t N, int L_low, int K, int precision);
+
+/* One EM step (see top of file).  y, x, log_rho are read; x_new, rho_new,
+ * loglik are written.  x_new must not alias x; outputs must not alias inputs.
+ * sigma > 0 and finite (the known noise standard deviation, Sec. 1).
+ * `workspace` must be 256-byte aligned and hold
+ * srmra_em_step_workspace_bytes(N, L_low, K, precision) bytes.
+ * Returns SRMRA_OK or an error code; see the execution model above. */
+int srmra_em_step(const float* y, int64_t N, int L_low, int K,
+                  const float* x, const float* log_rho, float sigma,
+                  float* x_new, float* rho_new, double* loglik,
+                  int precision, void* workspace, size_t workspace_bytes,
+                  hipStream_t stream);
+
+/* Per-job work that does not depend on theta (per-observation squared norms
+ * ||y_i||^2 in FP64, and for SRMRA_BF16_SPLIT3 the hi/lo BF16 planes of y).
+ * `prep` (256-byte aligned) must hold srmra_prepared_bytes(...) bytes; it is
+ * then passed unchanged to srmra_em_step_prepared for every iteration of the
+ * job.  y must stay alive and unchanged while `prep` is used. */
+size_t srmra_prepared_bytes(int64_t N, int L_low, int K, int precision);
+int srmra_prepare_observations(const float* y, int64_t N, int L_low, int K,
+                               int precision, void* prep, size_t prep_bytes,
+                               hipStream_t stream);
+
+/* Same as srmra_em_step, with the per-job work taken from `prep` (made by
+ * srmra_prepare_observations for the same y, N, L_low, K and precision).
+ * If log_rho_new is not NULL it receives log(rho_new) (float [2][L_high]), the
+ * log-prior input of the next iteration. */
+int srmra_em_step_prepared(const float* y, const void* prep, size_t prep_bytes,
+                           int64_t N, int L_low, int K,
+                           const float* x, const float* log_rho, float sigma,
+                           float* x_new, float* rho_new, float* log_rho_new, double* loglik,
+                           int precision, void* workspace, size_t workspace_bytes,
+                           hipStream_t stream);
+
+/* Diagnostics for parity tests (prep may be NULL): per-observation log-likelihood terms
+ * ll_i = log sum_s rho[s] exp(-||y_i - P R_s x||^2 / 2 sigma^2)  (float [N]),
+ * and the FP64 sufficient statistics of the M-step: b [L_high][L_high] (the
+ * right-hand side of eq. x_EM) and c [L_high][L_high] (c[s1][s2] =
+ * sum_i w^{i,s}).  Any of the three output pointers may be NULL.  Same
+ * argument rules as srmra_em_step_prepared; the step's regular outputs are
+ * also written. */
+int srmra_em_step_debug(const float* y, const void* prep, size_t prep_bytes,
+                        int64_t N, int L_low, int K,
+                        const float* x, const float* log_rho, float sigma,
+                        float* x_new, float* rho_new, float* log_rho_new, double* loglik,
+                        float* ll_obs, double* b_out, double* c_out,
+                        int precision, void* workspace, size_t workspace_bytes,
+                        hipStream_t stream);
+
+/* Same as srmra_em_step_prepared, and records six caller-created HIP events on
+ * `stream` at the phase boundaries of the step: events[0] before the packing
+ * of x, [1] before the score / log-sum-exp pass, [2] after it, [3] before the
+ * posterior / back-projection pass, [4] after it, [5] after the M-step
+ * finalisation.  For measurement (hipEventElapsedTime between them). */
+int srmra_em_step_profiled(const float* y, const void* prep, size_t prep_bytes,
+                           int64_t N, int L_low, int K,
+                           const float* x, const float* log_rho, float sigma,
+                           float* x_new, float* rho_new, float* log_rho_new, double* loglik,
+                           int precision, void* workspace, size_t workspace_bytes,
+                           hipStream_t stream, hipEvent_t* events);
+
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent instances of uneven (L_high, K, N, sigma) in
+ * one persistent launch per pass.  A plan is a host object holding the
+ * instances' shapes, device pointers and a cost-sorted work list; executing it
+ * performs one EM step of every instance.  Per-instance results are bitwise
+ * identical to running that instance alone with the same precision (work
+ * items and reduction order depend only on the instance).
+ */
+typedef struct srmra_problem {
+    const float* y;          /* device [N][L_low][L_low]                     */
+    const void* prep;        /* device, from srmra_prepare_observations      */
+    size_t prep_bytes;
+    int64_t N;
+    int L_low, K;
+    const float* x;          /* device [L_high][L_high] (input)              */
+    const float* log_rho;    /* device [2][L_high]   (input)                 */
+    float sigma;
+    float* x_new;            /* device [L_high][L_high] (output)             */
+    float* rho_new;          /* device [2][L_high]      (output)             */
+    float* log_rho_new;      /* device [2][L_high] (output, may be NULL)     */
+    double* loglik;          /* device [1]              (output)             */
+} srmra_problem;
+
+typedef struct srmra_plan srmra_plan;
+
+/* Build a plan (host only, no device work).  `probs` is copied.  On success
+ * *plan is set and *workspace_bytes receives the device workspace size that
+ * srmra_plan_execute needs.  Returns SRMRA_OK or an error code. */
+int srmra_plan_create(const srmra_problem* probs, int count, int precision,
+                      srmra_plan** plan, size_t* workspace_bytes);
+
+/* Replace the device pointers x, log_rho, x_new, rho_new, log_rho_new of
+ * problem `index` (shape fields are ignored), e.g. to ping-pong iterates. */
+int srmra_plan_set_iterate(srmra_plan* plan, int index, const float* x,
+                           const float* log_rho, float* x_new, float* rho_new,
+                           float* log_rho_new);
+
+/* Enqueue one EM step of every instance on `stream`.  The plan's device-side
+ * descriptors live in `workspace`; the call issues one host-to-device copy of
+ * them (hipMemcpyAsync from pageable memory) unless srmra_plan_upload was
+ * used and the iterates did not change since.  Graph-capturable after
+ * srmra_plan_upload: it then enqueues kernels only. */
+int srmra_plan_upload(srmra_plan* plan, void* workspace, size_t workspace_bytes,
+                      hipStream_t stream);
+int srmra_plan_execute(srmra_plan* plan, void* workspace, size_t workspace_bytes,
+                       hipStream_t stream);
+void srmra_plan_destroy(srmra_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SRMRA_H */

@@ -1,0 +1,89 @@
+"""GPU parity: the HIP EM step (through the C ABI) against the FP64 oracle on
+the same seeded FP32 inputs."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import em_oracle as O  # noqa: E402
+from paper_2204_04754_amd import synth  # noqa: E402
+from tests.gpu_helpers import check_step, gpu_step, rel  # noqa: E402
+
+PRECS = ["fp32_plain", "fp32_mfma"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_small_workload_trajectory(prec):
+    """Lh 16, K 2, N 1000, sigma 0.5: ten EM iterations; at every iteration the
+    oracle starts from the GPU's own FP32 iterate, so each step is compared
+    from identical inputs."""
+    inst = synth.workload("lh16_k2_n1000")
+    x = inst.x0
+    lr = inst.log_rho0
+    for it in range(10):
+        g = gpu_step(inst.y, x, lr, inst.sigma, inst.K, prec)
+        ref = O.em_step(inst.y, x, lr, inst.sigma, inst.K)
+        ex, er = check_step(inst.y, x, lr, inst.sigma, inst.K, g, ref)
+        print(f"it {it} x {ex:.2e} rho {er:.2e} ll {abs(g['loglik']-ref['loglik'])/abs(ref['loglik']):.2e}")
+        x = g["x_new"].astype(np.float32)
+        lr = g["log_rho_new"].astype(np.float32)
+
+
+SHAPES = [  # (Lh, K, N): every supported L_low, ragged N
+    (16, 2, 37), (32, 4, 53), (24, 2, 45), (48, 4, 21), (32, 2, 29), (48, 2, 19),
+    (64, 2, 17), (96, 2, 6), (128, 2, 3), (64, 4, 11), (96, 4, 7), (96, 3, 5), (256, 4, 2),
+]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("Lh,K,N", SHAPES)
+def test_shapes(prec, Lh, K, N):
+    # sigma = 2 keeps the posterior broad enough that every polyphase component
+    # receives posterior mass far above the FP32 underflow threshold even for a
+    # handful of observations (otherwise x' of that component is 0/0 in FP32).
+    inst = synth.make_instance(Lh, K, N, 2.0, config=50, instance=Lh * 10 + K)
+    # a non-uniform prior so that every log-prior term matters
+    rng = np.random.default_rng(Lh + K)
+    lr = np.log(np.stack([rng.dirichlet(np.ones(Lh)), rng.dirichlet(np.ones(Lh))])).astype(np.float32)
+    g = gpu_step(inst.y, inst.x0, lr, inst.sigma, K, prec)
+    ref = O.em_step(inst.y, inst.x0, lr, inst.sigma, K, return_details=True)
+    check_step(inst.y, inst.x0, lr, inst.sigma, K, g, ref)
+    assert rel(g["c"], ref["c"]) < 1e-4
+    assert rel(g["b"], ref["b"]) < 1e-4
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_deterministic(prec):
+    inst = synth.make_instance(64, 2, 3000, 1.0, config=51)
+    a = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 2, prec)
+    b = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 2, prec)
+    for k in ("x_new", "rho_new", "loglik", "ll_obs", "b", "c"):
+        assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_single_observation_and_delta_prior(prec):
+    """N = 1 and a delta prior: all posterior mass on s0, the sampled pixels
+    take the observation's values and every other pixel keeps x."""
+    Lh, K = 32, 2
+    inst = synth.make_instance(Lh, K, 1, 0.5, config=52)
+    lr = np.full((2, Lh), -np.inf, dtype=np.float32)
+    s0 = (5, 9)
+    lr[0, s0[0]] = 0.0
+    lr[1, s0[1]] = 0.0
+    g = gpu_step(inst.y, inst.x0, lr, 0.5, K, prec)
+    ref = O.em_step(inst.y, inst.x0, lr, 0.5, K)
+    rows, cols = O.shift_downsample_indices(Lh, K, *s0)
+    expect = inst.x0.astype(np.float64).copy()
+    expect[np.ix_(rows, cols)] = inst.y[0]
+    np.testing.assert_allclose(g["x_new"], expect, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(g["rho_new"], ref["rho_new"], atol=0)
+    assert abs(g["loglik"] - ref["loglik"]) < 1e-3 * abs(ref["loglik"])
