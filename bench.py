@@ -35,6 +35,7 @@ PEAK = {  # MI355X published dense peaks
     "fp32_mfma": ("mfma", 157.3e12), "fp32_plain": ("alu", 78.6e12),
     "bf16_split3": ("mfma", 2516.6e12),
 }
+KNAME = {"fp32_mfma": "mfma", "fp32_plain": "valu", "bf16_split3": "bf16"}
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE + WRITE_SIZE for the
 # dominant kernel at the default workload (None until counters are taken for
 # the current kernel version).
@@ -53,6 +54,9 @@ def parse():
                     help="observations in the oracle sample (0 = sized for ~15 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="after the timed region, run one device-to-device copy of this many MiB "
+                         "(reference kernel of known traffic for hardware-counter calibration)")
     return ap.parse_args()
 
 
@@ -176,7 +180,7 @@ def main():
     achieved = alg_flop / (k_ms * 1e-3)
     roof = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": TRAFFIC.get((args.workload, args.precision)),
-            "kernel": f"k_backproject_{'mfma' if 'mfma' in args.precision else 'valu'}<{inst.Ll}>",
+            "kernel": f"k_backproject_{KNAME[args.precision]}<{inst.Ll}>",
             "kernel_ms": k_ms, "issued_frac": issued_flop / (k_ms * 1e-3) / peak,
             "score_pass": {"kernel_ms": main_r["phase_ms"][1],
                            "frac": 2.0 * Ll2 * pairs / (main_r["phase_ms"][1] * 1e-3) / peak}}
@@ -184,13 +188,23 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "obs×shift pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": forms[args.precision]["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic",
+           "dtype": {"fp32_mfma": "f32", "fp32_plain": "f32", "bf16_split3": "bf16x3"}[args.precision],
+           "data": "synthetic",
            "config": {"workload": args.workload, "L_high": inst.Lh, "K": inst.K, "L_low": inst.Ll,
                       "N": inst.N, "sigma": inst.sigma, "precision": args.precision,
                       "pairs_per_step": pairs},
            "roofline": roof, "forms": forms}
     if args.baseline_precision in forms and args.baseline_precision != args.precision:
         out["speedup_vs_plain_fp32"] = value / forms[args.baseline_precision]["pairs_per_s"]
+    if args.copy_probe > 0:
+        nb = args.copy_probe << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nb
+        del src, dst
     if not args.no_cpu:
         n = args.cpu_sample or max(64, int(15.0 * 1.0e7 / (inst.Lh * inst.Lh * inst.Ll * inst.Ll / 16)))
         n = min(n, inst.N)

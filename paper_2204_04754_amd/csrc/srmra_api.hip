@@ -26,6 +26,11 @@ bool mfma_geom(int LL, int& cpw, int& nt, size_t& lds1, size_t& lds2, const void
                const void*& f2);
 bool valu_geom(int LL, int KK, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
                const void*& f2);
+bool bf16_geom(int LL, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
+               const void*& f2);
+hipError_t launch_bf16(int LL, int pass, const StepArgs& p, const void* prep_extra, hipStream_t s);
+hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, void* prep_extra, hipStream_t s);
+size_t bf16_prepared_extra(int LL, int64_t N);
 }  // namespace srmra
 
 using namespace srmra;
@@ -69,11 +74,12 @@ int occupancy(const void* f, size_t lds) {
 struct Geom {
     int LL = 0, K = 0, Lh = 0, KK = 0, prec = 0;
     int64_t N = 0;
-    int cpb = 0, n_cg = 0, ntile = 0, n_chunks = 0, n_ll = 0;
+    int cpb = 0, n_cg = 0, n_part = 0, ntile = 0, n_chunks = 0, n_ll = 0;
+    size_t prep_bytes = 0, prep_extra_off = 0;
     int64_t chunk_obs = 0;
     size_t lds1 = 0, lds2 = 0;
     // workspace offsets
-    size_t o_ynorm = 0, o_part = 0, o_lse = 0, o_xt2 = 0, o_beta = 0, o_bpart = 0, o_cpart = 0,
+    size_t o_prep = 0, o_part = 0, o_lse = 0, o_xt2 = 0, o_beta = 0, o_bpart = 0, o_cpart = 0,
            o_llpart = 0, o_bsum = 0, o_csum = 0, total = 0;
 };
 
@@ -81,15 +87,22 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g) {
     if (N < 1 || N > (int64_t)INT32_MAX || K < 1 || LL < 1) return SRMRA_EINVAL;
     if (!supported_ll(LL)) return SRMRA_EUNSUPPORTED;
     if ((int64_t)K * LL > 4096 || K * K > 256) return SRMRA_EUNSUPPORTED;
-    if (prec != SRMRA_FP32_PLAIN && prec != SRMRA_FP32_MFMA) return SRMRA_EUNSUPPORTED;
+    if (prec != SRMRA_FP32_PLAIN && prec != SRMRA_FP32_MFMA && prec != SRMRA_BF16_SPLIT3)
+        return SRMRA_EUNSUPPORTED;
     g.LL = LL; g.K = K; g.Lh = K * LL; g.KK = K * K; g.N = N; g.prec = prec;
     const void* f1 = nullptr;
     const void* f2 = nullptr;
     bool ok;
     if (prec == SRMRA_FP32_MFMA) ok = mfma_geom(LL, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
+    else if (prec == SRMRA_BF16_SPLIT3) ok = bf16_geom(LL, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
     else ok = valu_geom(LL, g.KK, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
     if (!ok) return SRMRA_EUNSUPPORTED;
     g.n_cg = (g.KK + g.cpb - 1) / g.cpb;
+    // pass-1 partials per observation: one per component group, or per component
+    // pair for the BF16 form (two waves of a block hold different pairs)
+    g.n_part = prec == SRMRA_BF16_SPLIT3 ? (g.KK + 1) / 2 : g.n_cg;
+    g.prep_extra_off = align_up(sizeof(double) * (size_t)N);
+    g.prep_bytes = g.prep_extra_off + (prec == SRMRA_BF16_SPLIT3 ? bf16_prepared_extra(LL, N) : 0);
     // one resident wave of blocks over the whole device for the heavier pass
     const int occ = occupancy(f2, g.lds2);
     const int64_t target = (int64_t)device_cus() * occ;
@@ -104,8 +117,8 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g) {
     g.n_ll = (int)((N + 255) / 256);
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
-    g.o_ynorm = with_norms ? take(sizeof(double) * (size_t)N) : 0;
-    g.o_part = take(sizeof(float2) * (size_t)g.n_cg * (size_t)N);
+    g.o_prep = with_norms ? take(g.prep_bytes) : 0;
+    g.o_part = take(sizeof(float2) * (size_t)g.n_part * (size_t)N);
     g.o_lse = take(sizeof(float) * (size_t)N);
     g.o_xt2 = take(sizeof(float) * (size_t)g.KK * LL * 2 * LL);
     g.o_beta = take(sizeof(float) * (size_t)g.KK * LL * LL);
@@ -139,12 +152,14 @@ int check_step_args(const float* y, int64_t N, int L_low, int K, const float* x,
     return SRMRA_OK;
 }
 
-int run_step(const Geom& g, const float* y, const double* ynorm, const float* x,
+int run_step(const Geom& g, const float* y, const char* prep, const float* x,
              const float* log_rho, float sigma, float* x_new, float* rho_new,
              float* log_rho_new, double* loglik, float* ll_obs, double* b_out, double* c_out,
              char* ws, hipStream_t stream, hipEvent_t* ev = nullptr) {
     StepArgs p;
     memset(&p, 0, sizeof(p));
+    const double* ynorm = (const double*)prep;
+    const void* prep_extra = prep + g.prep_extra_off;
     p.y = y;
     p.ynorm = ynorm;
     p.N = g.N;
@@ -172,14 +187,19 @@ int run_step(const Geom& g, const float* y, const double* ynorm, const float* x,
                        (float*)(ws + g.o_xt2), (float*)(ws + g.o_beta));
     if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
     mark(1);
-    hipError_t e = g.prec == SRMRA_FP32_MFMA ? launch_mfma(LL, 1, p, stream) : launch_valu(LL, 1, p, stream);
+    auto pass = [&](int k) -> hipError_t {
+        if (g.prec == SRMRA_FP32_MFMA) return launch_mfma(LL, k, p, stream);
+        if (g.prec == SRMRA_BF16_SPLIT3) return launch_bf16(LL, k, p, prep_extra, stream);
+        return launch_valu(LL, k, p, stream);
+    };
+    hipError_t e = pass(1);
     if (e != hipSuccess) return SRMRA_EDEVICE;
     mark(2);
     hipLaunchKernelGGL(k_lse_combine, dim3(g.n_ll), dim3(256), 0, stream, (const float2*)p.part,
-                       g.n_cg, g.N, ynorm, p.inv_2s2, p.lse, (double*)(ws + g.o_llpart), ll_obs);
+                       g.n_part, g.N, ynorm, p.inv_2s2, p.lse, (double*)(ws + g.o_llpart), ll_obs);
     if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
     mark(3);
-    e = g.prec == SRMRA_FP32_MFMA ? launch_mfma(LL, 2, p, stream) : launch_valu(LL, 2, p, stream);
+    e = pass(2);
     if (e != hipSuccess) return SRMRA_EDEVICE;
     mark(4);
     const int per = g.KK * LL * LL;
@@ -221,20 +241,27 @@ size_t srmra_em_step_workspace_bytes(int64_t N, int L_low, int K, int precision)
 size_t srmra_prepared_bytes(int64_t N, int L_low, int K, int precision) {
     Geom g;
     if (make_geom(N, L_low, K, precision, false, g) != SRMRA_OK) return 0;
-    return align_up(sizeof(double) * (size_t)N);
+    return g.prep_bytes;
+}
+
+static int enqueue_prepare(const Geom& g, const float* y, char* prep, hipStream_t stream) {
+    hipLaunchKernelGGL(k_obs_norms, dim3((unsigned)((g.N + 3) / 4)), dim3(256), 0, stream, y, g.N,
+                       g.LL * g.LL, (double*)prep);
+    if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
+    if (g.prec == SRMRA_BF16_SPLIT3 &&
+        launch_prep_bf16(g.LL, y, g.N, prep + g.prep_extra_off, stream) != hipSuccess)
+        return SRMRA_EDEVICE;
+    return SRMRA_OK;
 }
 
 int srmra_prepare_observations(const float* y, int64_t N, int L_low, int K, int precision,
                                void* prep, size_t prep_bytes, hipStream_t stream) {
-    if (!y || !prep) return SRMRA_EINVAL;
+    if (!y || !prep || (uintptr_t)y % 16 != 0) return SRMRA_EINVAL;
     Geom g;
     const int st = make_geom(N, L_low, K, precision, false, g);
     if (st != SRMRA_OK) return st;
-    if (!aligned(prep) || prep_bytes < srmra_prepared_bytes(N, L_low, K, precision))
-        return SRMRA_EWORKSPACE;
-    hipLaunchKernelGGL(k_obs_norms, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, stream, y, N,
-                       L_low * L_low, (double*)prep);
-    return hipGetLastError() == hipSuccess ? SRMRA_OK : SRMRA_EDEVICE;
+    if (!aligned(prep) || prep_bytes < g.prep_bytes) return SRMRA_EWORKSPACE;
+    return enqueue_prepare(g, y, (char*)prep, stream);
 }
 
 int srmra_em_step_debug(const float* y, const void* prep, size_t prep_bytes, int64_t N, int L_low,
@@ -249,18 +276,16 @@ int srmra_em_step_debug(const float* y, const void* prep, size_t prep_bytes, int
     if (st != SRMRA_OK) return st;
     if (!workspace || !aligned(workspace) || workspace_bytes < g.total) return SRMRA_EWORKSPACE;
     char* ws = (char*)workspace;
-    const double* ynorm;
+    const char* pp;
     if (prep) {
-        if (!aligned(prep) || prep_bytes < srmra_prepared_bytes(N, L_low, K, precision))
-            return SRMRA_EWORKSPACE;
-        ynorm = (const double*)prep;
+        if (!aligned(prep) || prep_bytes < g.prep_bytes) return SRMRA_EWORKSPACE;
+        pp = (const char*)prep;
     } else {
-        hipLaunchKernelGGL(k_obs_norms, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, stream, y, N,
-                           L_low * L_low, (double*)(ws + g.o_ynorm));
-        if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
-        ynorm = (const double*)(ws + g.o_ynorm);
+        st = enqueue_prepare(g, y, ws + g.o_prep, stream);
+        if (st != SRMRA_OK) return st;
+        pp = ws + g.o_prep;
     }
-    return run_step(g, y, ynorm, x, log_rho, sigma, x_new, rho_new, log_rho_new, loglik, ll_obs,
+    return run_step(g, y, pp, x, log_rho, sigma, x_new, rho_new, log_rho_new, loglik, ll_obs,
                     b_out, c_out, ws, stream);
 }
 
@@ -289,9 +314,8 @@ int srmra_em_step_profiled(const float* y, const void* prep, size_t prep_bytes, 
     st = make_geom(N, L_low, K, precision, false, g);
     if (st != SRMRA_OK) return st;
     if (!workspace || !aligned(workspace) || workspace_bytes < g.total) return SRMRA_EWORKSPACE;
-    if (!aligned(prep) || prep_bytes < srmra_prepared_bytes(N, L_low, K, precision))
-        return SRMRA_EWORKSPACE;
-    return run_step(g, y, (const double*)prep, x, log_rho, sigma, x_new, rho_new, log_rho_new,
+    if (!aligned(prep) || prep_bytes < g.prep_bytes) return SRMRA_EWORKSPACE;
+    return run_step(g, y, (const char*)prep, x, log_rho, sigma, x_new, rho_new, log_rho_new,
                     loglik, nullptr, nullptr, nullptr, (char*)workspace, stream, events);
 }
 

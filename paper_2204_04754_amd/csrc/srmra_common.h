@@ -57,7 +57,7 @@ struct StepArgs {
     // pass-2 outputs
     float* bpart;            // [n_chunks][KK][Ll*Ll]   (q1*Ll + q2)
     float* cpart;            // [n_chunks][KK][Ll*Ll]   (t1*Ll + t2)
-    int n_chunks, n_cg;
+    int n_chunks, n_cg;      // grid: observation chunks x component groups
     int cpb;                 // components per block (component group size)
     int ntile;               // observations per block tile
     int64_t chunk_obs;       // observations per chunk (multiple of ntile)

@@ -50,23 +50,38 @@ def score_scale(y, x, sigma, K):
 U32 = 2.0 ** -24
 
 
-def check_step(y, x, log_rho, sigma, K, g, ref, x_tol=1e-4, rho_tol=1e-4, ll_c=16.0):
+# residual of the BF16 hi + lo split: |v - hi - lo| <= 2^-17 |v|, so a split
+# product carries a relative error of about 2^-16
+U_SPLIT = 2.0 ** -16
+
+
+def unit_roundoff(precision):
+    return U_SPLIT if precision == "bf16_split3" else U32
+
+
+def check_step(y, x, log_rho, sigma, K, g, ref, x_tol=1e-4, rho_tol=1e-4, ll_c=16.0, u=None):
     """Compare one GPU step g with the oracle step ref.  Norm-wise relative
     error <= 1e-4 on x and rho (the accuracy target of the build); loglik and
-    the per-observation terms within ll_c * u32 * (magnitude of the rounded
-    terms)."""
+    the per-observation terms within ll_c * u * (magnitude of the rounded
+    terms), u the unit roundoff of the contraction (FP32, or the BF16 split)."""
+    u = U32 if u is None else u
+    xg, xr = g["x_new"], ref["x_new"]
+    assert np.all(np.isfinite(xg))
     if "a" in ref:
-        # the comparison of x' is only meaningful where every component carries
-        # posterior mass well above FP32 underflow (x' = b/A per component)
-        Amin = min(ref["a"][c1::K, c2::K].min() for c1 in range(K) for c2 in range(K))
-        assert Amin > 1e-20 * y.shape[0], f"ill-conditioned test input (min A = {Amin:.2e})"
-    ex = rel(g["x_new"], ref["x_new"])
+        # x' = b / A per component.  A component whose total posterior mass A_c
+        # is below 1e-3 of one observation is decided by a vanishing fraction
+        # of a single observation (and its weights underflow FP32); x' there is
+        # not compared (b and c, the sufficient statistics, still are).
+        keep = ref["a"] >= 1e-3
+        assert keep.mean() >= 0.5, "test input leaves most components without posterior mass"
+        xg, xr = xg[keep], xr[keep]
+    ex = rel(xg, xr)
     er = rel(g["rho_new"], ref["rho_new"])
     assert ex <= x_tol, f"x rel err {ex:.3e}"
     assert er <= rho_tol, f"rho rel err {er:.3e}"
     scale = score_scale(y, x, sigma, K)
     if "ll_obs" in g:
         d = np.abs(g["ll_obs"] - ref["lse"])
-        assert np.all(d <= ll_c * U32 * (1 + scale)), f"ll_obs max err {d.max():.3e}"
-    assert abs(g["loglik"] - ref["loglik"]) <= ll_c * U32 * (1 + scale.sum())
+        assert np.all(d <= ll_c * u * (1 + scale)), f"ll_obs max err {d.max():.3e}"
+    assert abs(g["loglik"] - ref["loglik"]) <= ll_c * u * (1 + scale.sum())
     return ex, er

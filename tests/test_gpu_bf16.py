@@ -1,0 +1,62 @@
+"""GPU parity of the BF16 split-precision form (L_low 24 and 32) against the
+FP64 oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import em_oracle as O  # noqa: E402
+from paper_2204_04754_amd import synth  # noqa: E402
+from tests.gpu_helpers import U_SPLIT, check_step, gpu_step, rel  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("Lh,K,N,sigma", [(48, 2, 41, 2.0), (64, 2, 27, 2.0), (96, 4, 19, 2.0),
+                                          (128, 4, 9, 2.0), (96, 3, 11, 2.0), (64, 2, 600, 0.7)])
+def test_shapes(Lh, K, N, sigma):
+    inst = synth.make_instance(Lh, K, N, sigma, config=60, instance=Lh + K)
+    rng = np.random.default_rng(Lh * K)
+    lr = np.log(np.stack([rng.dirichlet(np.ones(Lh)), rng.dirichlet(np.ones(Lh))])).astype(np.float32)
+    g = gpu_step(inst.y, inst.x0, lr, sigma, K, "bf16_split3")
+    ref = O.em_step(inst.y, inst.x0, lr, sigma, K, return_details=True)
+    ex, er = check_step(inst.y, inst.x0, lr, sigma, K, g, ref, u=U_SPLIT)
+    print(f"Lh {Lh} K {K} N {N}: x {ex:.2e} rho {er:.2e}")
+    assert rel(g["c"], ref["c"]) < 1e-4
+    assert rel(g["b"], ref["b"]) < 1e-4
+
+
+@pytest.mark.parametrize("sigma", [0.5, 2.0])
+def test_precision_workload_subset(sigma):
+    """The precision-study shape (Lh 128, K 4, Ll 32) on a 200-observation
+    prefix, two consecutive steps from the GPU's own iterate."""
+    name = "lh128_k4_n200000_s0.5" if sigma == 0.5 else "lh128_k4_n200000_s2"
+    inst = synth.workload(name, N=200)
+    x, lr = inst.x0, inst.log_rho0
+    for it in range(2):
+        g = gpu_step(inst.y, x, lr, sigma, 4, "bf16_split3")
+        ref = O.em_step(inst.y, x, lr, sigma, 4, return_details=True)
+        ex, er = check_step(inst.y, x, lr, sigma, 4, g, ref, u=U_SPLIT)
+        # b and c are sums of few weights when the posterior is sharp (sigma 0.5),
+        # so they keep more of the split's logit error than the averages x and rho
+        assert rel(g["b"], ref["b"]) < 1e-3 and rel(g["c"], ref["c"]) < 1e-3
+        print(f"sigma {sigma} it {it}: x {ex:.2e} rho {er:.2e} "
+              f"ll {abs(g['loglik'] - ref['loglik']) / abs(ref['loglik']):.2e}")
+        x = g["x_new"].astype(np.float32)
+        lr = g["log_rho_new"].astype(np.float32)
+
+
+def test_deterministic_and_unsupported():
+    inst = synth.make_instance(64, 2, 1000, 1.0, config=61)
+    a = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 2, "bf16_split3")
+    b = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 2, "bf16_split3")
+    for k in ("x_new", "rho_new", "loglik", "ll_obs", "b", "c"):
+        assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+    from paper_2204_04754_amd import binding as B
+    assert B.srmra_em_step_workspace_bytes(100, 16, 2, "bf16_split3") == 0
