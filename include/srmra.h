@@ -29,8 +29,8 @@
  * Memory and execution model:
  *  - every pointer argument except `probs` / `plan` / `workspace_bytes` of the
  *    plan calls is a DEVICE pointer; the caller owns every buffer;
- *  - the library never allocates or frees device memory, never synchronises
- *    the device and never copies device data to the host;
+ *  - the library never allocates or frees device memory and never copies
+ *    device data to the host; only srmra_plan_upload synchronises (its stream);
  *  - arguments are validated on the host before anything is enqueued; on an
  *    error return nothing has been enqueued;
  *  - on success all work is enqueued asynchronously on `stream`; execution
@@ -149,51 +149,72 @@ int srmra_em_step_profiled(const float* y, const void* prep, size_t prep_bytes,
                            hipStream_t stream, hipEvent_t* events);
 
 /* ---------------------------------------------------------------------------
- * Batched form: many independent instances of uneven (L_high, K, N, sigma) in
- * one persistent launch per pass.  A plan is a host object holding the
- * instances' shapes, device pointers and a cost-sorted work list; executing it
- * performs one EM step of every instance.  Per-instance results are bitwise
- * identical to running that instance alone with the same precision (work
- * items and reduction order depend only on the instance).
+ * Batched form: many independent instances of uneven (L_high, K, N, sigma),
+ * one EM step of every instance per execution, with one persistent launch per
+ * pass over a work list of (instance, observation chunk, component group)
+ * items sorted by cost and handed out by an atomic counter.  Each instance is
+ * partitioned by a rule that depends only on its own shape and runs the same
+ * device code as when it is alone in a plan, so its result is bitwise the
+ * same alone and in any mix.  (The partition differs from srmra_em_step's, so
+ * plan and single-step results agree to rounding, not bitwise.)
+ *
+ * Iterates ping-pong: execution number e (0-based since the last upload or
+ * srmra_plan_set_iterate) reads (x, log_rho) and writes (x_new, log_rho_new)
+ * when e is even, and the reverse when e is odd; rho_new and loglik are
+ * written every time.  After an even number of executions the newest iterate
+ * is in x / log_rho.
  */
 typedef struct srmra_problem {
-    const float* y;          /* device [N][L_low][L_low]                     */
-    const void* prep;        /* device, from srmra_prepare_observations      */
+    const float* y;          /* device [N][L_low][L_low], 16-byte aligned           */
+    const void* prep;        /* device, srmra_prepare_observations(y, ...) made with
+                                srmra_plan_form(precision, L_low)                  */
     size_t prep_bytes;
     int64_t N;
     int L_low, K;
-    const float* x;          /* device [L_high][L_high] (input)              */
-    const float* log_rho;    /* device [2][L_high]   (input)                 */
+    const float* x;          /* device [L_high][L_high]  (iterate buffer A)         */
+    const float* log_rho;    /* device [2][L_high]       (iterate buffer A)         */
     float sigma;
-    float* x_new;            /* device [L_high][L_high] (output)             */
-    float* rho_new;          /* device [2][L_high]      (output)             */
-    float* log_rho_new;      /* device [2][L_high] (output, may be NULL)     */
-    double* loglik;          /* device [1]              (output)             */
+    float* x_new;            /* device [L_high][L_high]  (iterate buffer B)         */
+    float* rho_new;          /* device [2][L_high]       (output)                   */
+    float* log_rho_new;      /* device [2][L_high]       (iterate buffer B, required) */
+    double* loglik;          /* device [1]               (output)                   */
 } srmra_problem;
 
 typedef struct srmra_plan srmra_plan;
 
+/* The precision an instance of this L_low runs in within a plan of the given
+ * precision: SRMRA_BF16_SPLIT3 plans run L_low outside {24, 32} in
+ * SRMRA_FP32_MFMA.  Returns -1 for unsupported arguments. */
+int srmra_plan_form(int precision, int L_low);
+
 /* Build a plan (host only, no device work).  `probs` is copied.  On success
  * *plan is set and *workspace_bytes receives the device workspace size that
- * srmra_plan_execute needs.  Returns SRMRA_OK or an error code. */
+ * srmra_plan_upload / srmra_plan_execute need.  Returns SRMRA_OK or an error. */
 int srmra_plan_create(const srmra_problem* probs, int count, int precision,
                       srmra_plan** plan, size_t* workspace_bytes);
 
-/* Replace the device pointers x, log_rho, x_new, rho_new, log_rho_new of
- * problem `index` (shape fields are ignored), e.g. to ping-pong iterates. */
+/* Replace the iterate pointers of problem `index` (shape fields unchanged);
+ * resets the ping-pong parity and requires a new upload. */
 int srmra_plan_set_iterate(srmra_plan* plan, int index, const float* x,
                            const float* log_rho, float* x_new, float* rho_new,
                            float* log_rho_new);
 
-/* Enqueue one EM step of every instance on `stream`.  The plan's device-side
- * descriptors live in `workspace`; the call issues one host-to-device copy of
- * them (hipMemcpyAsync from pageable memory) unless srmra_plan_upload was
- * used and the iterates did not change since.  Graph-capturable after
- * srmra_plan_upload: it then enqueues kernels only. */
+/* Copy the plan's device descriptors and work lists into `workspace`
+ * (hipMemcpyAsync from host memory, then a synchronisation of `stream`: call
+ * it outside graph capture).  Resets the ping-pong parity. */
 int srmra_plan_upload(srmra_plan* plan, void* workspace, size_t workspace_bytes,
                       hipStream_t stream);
+
+/* Enqueue one EM step of every instance on `stream` (kernels only once the
+ * plan is uploaded to this workspace; otherwise it uploads first).  After an
+ * upload it is graph-capturable: a captured sequence of T executions replays
+ * T EM iterations with the ping-pong order fixed at capture time. */
 int srmra_plan_execute(srmra_plan* plan, void* workspace, size_t workspace_bytes,
                        hipStream_t stream);
+
+/* Parity of the next execution (0: reads x/log_rho), -1 for NULL. */
+int srmra_plan_parity(const srmra_plan* plan);
+
 void srmra_plan_destroy(srmra_plan* plan);
 
 #ifdef __cplusplus

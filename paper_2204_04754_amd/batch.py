@@ -1,0 +1,95 @@
+"""Device-buffer driver for the batched form (srmra_plan_* in the C ABI): many
+independent SR-MRA instances advanced together, one persistent launch per pass
+and (L_low, form) class per EM step, optionally captured as a HIP graph of
+several iterations.  Marshalling and buffer ownership only."""
+from __future__ import annotations
+
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class BatchedEM:
+    def __init__(self, instances: Sequence[dict], precision="fp32_mfma", device="cuda",
+                 stream=None):
+        """instances: dicts with y [N][Ll][Ll], K, sigma, x0 [Lh][Lh], log_rho0 [2][Lh]
+        (NumPy or torch)."""
+        self.device = torch.device(device)
+        self.precision = B._prec(precision)
+        self.stream = stream
+        self.inst: List[dict] = []
+        f = dict(device=self.device, dtype=torch.float32)
+        for d in instances:
+            y = d["y"]
+            y = torch.as_tensor(np.ascontiguousarray(y, np.float32)) if isinstance(y, np.ndarray) else y
+            y = y.to(self.device, torch.float32).contiguous()
+            N, Ll = int(y.shape[0]), int(y.shape[1])
+            K = int(d["K"])
+            Lh = K * Ll
+            form = B.srmra_plan_form(self.precision, Ll)
+            if form < 0:
+                raise B.SrmraError(B.SRMRA_EUNSUPPORTED, "BatchedEM")
+            pb = B.srmra_prepared_bytes(N, Ll, K, form)
+            prep = B.empty_bytes(pb, self.device)
+            B.srmra_prepare_observations(y, N, Ll, K, form, prep, stream)
+            e = dict(y=y, prep=prep, N=N, L_low=Ll, K=K, Lh=Lh, sigma=float(d["sigma"]), form=form,
+                     x=torch.as_tensor(np.asarray(d["x0"], np.float32)).to(**f).contiguous(),
+                     x_new=torch.empty((Lh, Lh), **f),
+                     log_rho=torch.as_tensor(np.asarray(d["log_rho0"], np.float32)).to(**f).contiguous(),
+                     log_rho_new=torch.empty((2, Lh), **f),
+                     rho_new=torch.empty((2, Lh), **f),
+                     loglik=torch.empty(1, dtype=torch.float64, device=self.device))
+            self.inst.append(e)
+        self.plan = B.Plan(self.inst, self.precision)
+        self.workspace = B.empty_bytes(self.plan.workspace_bytes, self.device)
+        self.plan.upload(self.workspace, stream)
+        self.executions = 0
+
+    def step(self):
+        """One EM step of every instance (enqueued on the stream)."""
+        self.plan.execute(self.workspace, self.stream)
+        self.executions += 1
+
+    def reset_parity(self):
+        self.plan.upload(self.workspace, self.stream)
+        self.executions = 0
+
+    def current(self, i: int):
+        """(x, log_rho) of instance i after the executions so far."""
+        e = self.inst[i]
+        if self.executions % 2 == 0:
+            return e["x"], e["log_rho"]
+        return e["x_new"], e["log_rho_new"]
+
+    def results(self, i: int) -> dict:
+        e = self.inst[i]
+        x, lr = self.current(i)
+        return dict(x_new=x.cpu().numpy().astype(np.float64),
+                    log_rho_new=lr.cpu().numpy().astype(np.float64),
+                    rho_new=e["rho_new"].cpu().numpy().astype(np.float64),
+                    loglik=float(e["loglik"].item()))
+
+    def capture(self, iterations: int) -> torch.cuda.CUDAGraph:
+        """Capture `iterations` (even) EM steps of every instance as one graph.
+        The plan must be at parity 0; replaying the graph advances every
+        instance by `iterations` steps."""
+        if iterations % 2:
+            raise ValueError("capture an even number of iterations (ping-pong buffers)")
+        if self.plan.parity() != 0:
+            raise RuntimeError("capture must start at parity 0")
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream(device=self.device)
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(iterations):
+                    self.plan.execute(self.workspace, torch.cuda.current_stream())
+        torch.cuda.current_stream().wait_stream(s)
+        return g
+
+    @property
+    def pairs_per_step(self) -> int:
+        return sum(e["N"] * e["Lh"] * e["Lh"] for e in self.inst)

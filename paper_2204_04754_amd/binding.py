@@ -84,6 +84,10 @@ def lib():
             L.srmra_em_step_profiled.argtypes = [_vp, _vp, _sz, _i64, _int, _int, _vp, _vp, _f,
                                                  _vp, _vp, _vp, _vp, _int, _vp, _sz, _vp,
                                                  ctypes.POINTER(_vp)]
+            L.srmra_plan_form.restype = _int
+            L.srmra_plan_form.argtypes = [_int, _int]
+            L.srmra_plan_parity.restype = _int
+            L.srmra_plan_parity.argtypes = [_vp]
             L.srmra_plan_create.restype = _int
             L.srmra_plan_create.argtypes = [ctypes.POINTER(srmra_problem), _int, _int,
                                             ctypes.POINTER(_vp), ctypes.POINTER(_sz)]
@@ -202,6 +206,10 @@ def srmra_em_step_profiled(y, prep, N, L_low, K, x, log_rho, sigma, x_new, rho_n
 
 
 # ------------------------------------------------------------------ batched plan
+def srmra_plan_form(precision, L_low: int) -> int:
+    return int(lib().srmra_plan_form(_prec(precision), int(L_low)))
+
+
 class Plan:
     """Owner of an srmra_plan* (host object) plus the problem structs."""
 
@@ -241,6 +249,9 @@ class Plan:
         _check(lib().srmra_plan_execute(self._h, _ptr(workspace),
                                         workspace.numel() * workspace.element_size(),
                                         _stream(stream)), "srmra_plan_execute")
+
+    def parity(self) -> int:
+        return int(lib().srmra_plan_parity(self._h))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

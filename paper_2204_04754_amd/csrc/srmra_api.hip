@@ -7,7 +7,10 @@
 #include <new>
 #include <vector>
 
+#include <algorithm>
+
 #include "../../include/srmra.h"
+#include "srmra_batch.h"
 #include "srmra_common.h"
 
 namespace srmra {
@@ -83,7 +86,8 @@ struct Geom {
            o_llpart = 0, o_bsum = 0, o_csum = 0, total = 0;
 };
 
-int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g) {
+int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
+              int64_t chunk_override = 0) {
     if (N < 1 || N > (int64_t)INT32_MAX || K < 1 || LL < 1) return SRMRA_EINVAL;
     if (!supported_ll(LL)) return SRMRA_EUNSUPPORTED;
     if ((int64_t)K * LL > 4096 || K * K > 256) return SRMRA_EUNSUPPORTED;
@@ -111,7 +115,8 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g) {
     if (nch >= 16) nch -= nch % 8;               // same chunk -> same XCD for all groups
     if (nch < 1) nch = 1;
     if (nch > tiles) nch = tiles;
-    const int64_t tiles_per_chunk = (tiles + nch - 1) / nch;
+    int64_t tiles_per_chunk = (tiles + nch - 1) / nch;
+    if (chunk_override > 0) tiles_per_chunk = std::min<int64_t>(tiles, (chunk_override + g.ntile - 1) / g.ntile);
     g.chunk_obs = tiles_per_chunk * g.ntile;
     g.n_chunks = (int)((N + g.chunk_obs - 1) / g.chunk_obs);
     g.n_ll = (int)((N + 255) / 256);
@@ -331,32 +336,248 @@ int srmra_em_step(const float* y, int64_t N, int L_low, int K, const float* x,
 struct srmra_plan {
     int precision = 0;
     std::vector<srmra_problem> probs;
+    std::vector<Geom> geoms;
+    std::vector<int> form;
+    std::vector<size_t> inst_off;
+    std::vector<int4> pass_items;
+    std::vector<int2> pack_items, combine_items, reduce_items;
+    size_t o_desc = 0, o_pass = 0, o_pack = 0, o_comb = 0, o_red = 0, o_cnt = 0, total = 0;
+    std::vector<ClassLaunch> classes;
+    int parity = 0;
+    bool uploaded = false;
+    const void* uploaded_ws = nullptr;
 };
+
+namespace {
+
+int form_of(int precision, int LL) {
+    if (precision == SRMRA_BF16_SPLIT3) return (LL == 24 || LL == 32) ? FORM_BF16 : FORM_MFMA;
+    return precision == SRMRA_FP32_MFMA ? FORM_MFMA : FORM_VALU;
+}
+
+// observations per work item: about 2^28 multiply-adds (shape-only, so an
+// instance's partition does not depend on the rest of the batch)
+int64_t default_chunk(const Geom& g) {
+    const double per_obs = (double)g.cpb * g.LL * g.LL * (double)g.LL * g.LL;
+    int64_t c = (int64_t)(268435456.0 / per_obs);
+    if (c < g.ntile) c = g.ntile;
+    return c;
+}
+
+void fill_desc(srmra_plan* P, int i, int par, InstDesc& d, char* ws) {
+    const Geom& g = P->geoms[i];
+    const srmra_problem& pr = P->probs[i];
+    char* w = ws + P->inst_off[i];
+    memset(&d, 0, sizeof(d));
+    StepArgs& p = d.p;
+    p.y = pr.y;
+    p.ynorm = (const double*)pr.prep;
+    p.N = g.N; p.K = g.K; p.Lh = g.Lh; p.KK = g.KK;
+    p.inv_s2 = (float)(1.0 / ((double)pr.sigma * (double)pr.sigma));
+    p.inv_2s2 = 1.0 / (2.0 * (double)pr.sigma * (double)pr.sigma);
+    p.xt2 = (const float*)(w + g.o_xt2);
+    p.betaT = (const float*)(w + g.o_beta);
+    p.part = (float2*)(w + g.o_part);
+    p.lse = (float*)(w + g.o_lse);
+    p.bpart = (float*)(w + g.o_bpart);
+    p.cpart = (float*)(w + g.o_cpart);
+    p.n_chunks = g.n_chunks; p.n_cg = g.n_cg; p.cpb = g.cpb; p.ntile = g.ntile;
+    p.chunk_obs = g.chunk_obs;
+    if (P->form[i] == FORM_BF16) {
+        const char* e = (const char*)pr.prep + g.prep_extra_off;
+        const size_t yt = (size_t)g.N * 2 * g.LL * 32 * 2;
+        d.yT = (const __bf16*)e;
+        d.yo = (const __bf16*)(e + align_up(yt));
+    }
+    const bool flip = par == 1;
+    d.x = flip ? pr.x_new : pr.x;
+    d.log_rho = flip ? pr.log_rho_new : pr.log_rho;
+    d.x_new = flip ? (float*)pr.x : pr.x_new;
+    d.log_rho_new = flip ? (float*)pr.log_rho : pr.log_rho_new;
+    d.rho_new = pr.rho_new;
+    d.loglik = pr.loglik;
+    d.xt2_w = (float*)(w + g.o_xt2);
+    d.beta_w = (float*)(w + g.o_beta);
+    d.llpart = (double*)(w + g.o_llpart);
+    d.bsum = (double*)(w + g.o_bsum);
+    d.csum = (double*)(w + g.o_csum);
+    d.LL = g.LL; d.form = P->form[i]; d.n_part = g.n_part; d.n_ll = g.n_ll;
+}
+
+}  // namespace
+
+int srmra_plan_form(int precision, int L_low) {
+    if (!supported_ll(L_low)) return -1;
+    if (precision != SRMRA_FP32_PLAIN && precision != SRMRA_FP32_MFMA && precision != SRMRA_BF16_SPLIT3)
+        return -1;
+    const int f = form_of(precision, L_low);
+    return f == FORM_BF16 ? SRMRA_BF16_SPLIT3 : (f == FORM_MFMA ? SRMRA_FP32_MFMA : SRMRA_FP32_PLAIN);
+}
 
 int srmra_plan_create(const srmra_problem* probs, int count, int precision, srmra_plan** plan,
                       size_t* workspace_bytes) {
-    (void)probs; (void)count; (void)precision;
-    if (plan) *plan = nullptr;
-    if (workspace_bytes) *workspace_bytes = 0;
-    return SRMRA_EUNSUPPORTED;
+    if (!plan || !workspace_bytes || !probs || count < 1 || count > 65535) return SRMRA_EINVAL;
+    *plan = nullptr;
+    *workspace_bytes = 0;
+    if (precision != SRMRA_FP32_PLAIN && precision != SRMRA_FP32_MFMA && precision != SRMRA_BF16_SPLIT3)
+        return SRMRA_EUNSUPPORTED;
+    srmra_plan* P = new (std::nothrow) srmra_plan;
+    if (!P) return SRMRA_EINVAL;
+    P->precision = precision;
+    P->probs.assign(probs, probs + count);
+    struct Cost { int cls; double c; int4 it; };
+    std::vector<Cost> costs;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+    for (int i = 0; i < count; ++i) {
+        const srmra_problem& pr = probs[i];
+        int st = check_step_args(pr.y, pr.N, pr.L_low, pr.K, pr.x, pr.log_rho, pr.sigma, pr.x_new,
+                                 pr.rho_new, pr.loglik);
+        if (st == SRMRA_OK && (!pr.prep || !pr.log_rho_new || !aligned(pr.prep))) st = SRMRA_EINVAL;
+        if (st != SRMRA_OK) { delete P; return st; }
+        const int f = form_of(precision, pr.L_low);
+        const int fprec = f == FORM_BF16 ? SRMRA_BF16_SPLIT3 : (f == FORM_MFMA ? SRMRA_FP32_MFMA : SRMRA_FP32_PLAIN);
+        Geom g0;
+        st = make_geom(pr.N, pr.L_low, pr.K, fprec, false, g0);
+        if (st != SRMRA_OK) { delete P; return st; }
+        Geom g;
+        make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, default_chunk(g0));
+        if (pr.prep_bytes < g.prep_bytes) { delete P; return SRMRA_EWORKSPACE; }
+        P->geoms.push_back(g);
+        P->form.push_back(f);
+        int cls = -1;
+        for (size_t k = 0; k < P->classes.size(); ++k)
+            if (P->classes[k].form == f && P->classes[k].LL == pr.L_low) cls = (int)k;
+        if (cls < 0) {
+            if ((int)P->classes.size() >= kMaxClasses) { delete P; return SRMRA_EUNSUPPORTED; }
+            ClassLaunch c;
+            memset(&c, 0, sizeof(c));
+            c.form = f;
+            c.LL = pr.L_low;
+            P->classes.push_back(c);
+            cls = (int)P->classes.size() - 1;
+        }
+        ClassLaunch& C = P->classes[cls];
+        C.lds1 = std::max(C.lds1, g.lds1 + 16);
+        C.lds2 = std::max(C.lds2, g.lds2 + 16);
+        for (int ch = 0; ch < g.n_chunks; ++ch) {
+            const int64_t nobs = std::min<int64_t>(g.chunk_obs, g.N - (int64_t)ch * g.chunk_obs);
+            const double cst = (double)nobs * g.cpb * (double)g.LL * g.LL * g.LL * g.LL *
+                               (f == FORM_VALU ? 2.0 : (f == FORM_BF16 ? 0.5 : 1.0));
+            for (int cg = 0; cg < g.n_cg; ++cg) costs.push_back({cls, cst, make_int4(i, ch, cg, 0)});
+        }
+        for (int c = 0; c < g.KK; ++c) P->pack_items.push_back(make_int2(i, c));
+        for (int k = 0; k < g.n_ll; ++k) P->combine_items.push_back(make_int2(i, k));
+        const int per = g.KK * g.LL * g.LL;
+        for (int k = 0; k < (per + 255) / 256; ++k) P->reduce_items.push_back(make_int2(i, k));
+    }
+    // items grouped by class (heaviest class first), largest items first within a class
+    std::vector<double> class_cost(P->classes.size(), 0.0);
+    for (auto& c : costs) class_cost[c.cls] += c.c;
+    std::vector<int> order(P->classes.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return class_cost[a] > class_cost[b]; });
+    std::vector<int> rank(order.size());
+    for (size_t k = 0; k < order.size(); ++k) rank[order[k]] = (int)k;
+    std::stable_sort(costs.begin(), costs.end(), [&](const Cost& a, const Cost& b) {
+        if (a.cls != b.cls) return rank[a.cls] < rank[b.cls];
+        return a.c > b.c;
+    });
+    std::vector<ClassLaunch> sorted;
+    for (int k : order) sorted.push_back(P->classes[k]);
+    P->classes = sorted;
+    for (size_t k = 0; k < costs.size(); ++k) {
+        ClassLaunch& C = P->classes[rank[costs[k].cls]];
+        if (C.n_items == 0) C.item0 = (int)k;
+        C.n_items++;
+        P->pass_items.push_back(costs[k].it);
+    }
+    P->o_desc = take(2 * sizeof(InstDesc) * (size_t)count);
+    P->o_pass = take(sizeof(int4) * P->pass_items.size());
+    P->o_pack = take(sizeof(int2) * P->pack_items.size());
+    P->o_comb = take(sizeof(int2) * P->combine_items.size());
+    P->o_red = take(sizeof(int2) * P->reduce_items.size());
+    P->o_cnt = take(sizeof(int) * 2 * kMaxClasses);
+    for (int i = 0; i < count; ++i) P->inst_off.push_back(take(P->geoms[i].total));
+    P->total = off;
+    const int cus = device_cus();
+    for (auto& C : P->classes) {
+        C.blocks1 = cus * occupancy(class_pass_fn(1, C.form, C.LL), C.lds1);
+        C.blocks2 = cus * occupancy(class_pass_fn(2, C.form, C.LL), C.lds2);
+    }
+    *plan = P;
+    *workspace_bytes = P->total;
+    return SRMRA_OK;
 }
 
 int srmra_plan_set_iterate(srmra_plan* plan, int index, const float* x, const float* log_rho,
                            float* x_new, float* rho_new, float* log_rho_new) {
-    (void)plan; (void)index; (void)x; (void)log_rho; (void)x_new; (void)rho_new; (void)log_rho_new;
-    return SRMRA_EUNSUPPORTED;
+    if (!plan || index < 0 || index >= (int)plan->probs.size()) return SRMRA_EINVAL;
+    if (!x || !log_rho || !x_new || !rho_new || !log_rho_new || x == x_new) return SRMRA_EINVAL;
+    srmra_problem& pr = plan->probs[index];
+    pr.x = x; pr.log_rho = log_rho; pr.x_new = x_new; pr.rho_new = rho_new;
+    pr.log_rho_new = log_rho_new;
+    plan->uploaded = false;
+    plan->parity = 0;
+    return SRMRA_OK;
 }
 
 int srmra_plan_upload(srmra_plan* plan, void* workspace, size_t workspace_bytes, hipStream_t stream) {
-    (void)plan; (void)workspace; (void)workspace_bytes; (void)stream;
-    return SRMRA_EUNSUPPORTED;
+    if (!plan || !workspace || !aligned(workspace)) return SRMRA_EINVAL;
+    if (workspace_bytes < plan->total) return SRMRA_EWORKSPACE;
+    char* ws = (char*)workspace;
+    const int n = (int)plan->probs.size();
+    static thread_local std::vector<InstDesc> desc;
+    desc.assign(2 * (size_t)n, InstDesc{});
+    for (int par = 0; par < 2; ++par)
+        for (int i = 0; i < n; ++i) fill_desc(plan, i, par, desc[(size_t)par * n + i], ws);
+    hipError_t e = hipMemcpyAsync(ws + plan->o_desc, desc.data(), sizeof(InstDesc) * desc.size(),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_pass, plan->pass_items.data(), sizeof(int4) * plan->pass_items.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_pack, plan->pack_items.data(), sizeof(int2) * plan->pack_items.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_comb, plan->combine_items.data(), sizeof(int2) * plan->combine_items.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_red, plan->reduce_items.data(), sizeof(int2) * plan->reduce_items.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);   // host staging buffers are reused
+    if (e != hipSuccess) return SRMRA_EDEVICE;
+    for (auto& C : plan->classes) {
+        (void)hipFuncSetAttribute(class_pass_fn(1, C.form, C.LL), hipFuncAttributeMaxDynamicSharedMemorySize, (int)C.lds1);
+        (void)hipFuncSetAttribute(class_pass_fn(2, C.form, C.LL), hipFuncAttributeMaxDynamicSharedMemorySize, (int)C.lds2);
+    }
+    plan->uploaded = true;
+    plan->uploaded_ws = workspace;
+    plan->parity = 0;
+    return SRMRA_OK;
 }
 
 int srmra_plan_execute(srmra_plan* plan, void* workspace, size_t workspace_bytes,
                        hipStream_t stream) {
-    (void)plan; (void)workspace; (void)workspace_bytes; (void)stream;
-    return SRMRA_EUNSUPPORTED;
+    if (!plan || !workspace) return SRMRA_EINVAL;
+    if (workspace_bytes < plan->total) return SRMRA_EWORKSPACE;
+    if (!plan->uploaded || plan->uploaded_ws != workspace) {
+        const int st = srmra_plan_upload(plan, workspace, workspace_bytes, stream);
+        if (st != SRMRA_OK) return st;
+    }
+    char* ws = (char*)workspace;
+    const int n = (int)plan->probs.size();
+    BatchLaunch L;
+    L.desc = (const InstDesc*)(ws + plan->o_desc) + (size_t)plan->parity * n;
+    L.pass_items = (const int4*)(ws + plan->o_pass);
+    L.pack_items = (const int2*)(ws + plan->o_pack);
+    L.combine_items = (const int2*)(ws + plan->o_comb);
+    L.reduce_items = (const int2*)(ws + plan->o_red);
+    L.counters = (int*)(ws + plan->o_cnt);
+    L.n_pack = (int)plan->pack_items.size();
+    L.n_combine = (int)plan->combine_items.size();
+    L.n_reduce = (int)plan->reduce_items.size();
+    L.n_inst = n;
+    L.n_class = (int)plan->classes.size();
+    for (int k = 0; k < L.n_class; ++k) L.cls[k] = plan->classes[k];
+    if (batch_enqueue(L, stream) != hipSuccess) return SRMRA_EDEVICE;
+    plan->parity ^= 1;
+    return SRMRA_OK;
 }
+
+int srmra_plan_parity(const srmra_plan* plan) { return plan ? plan->parity : -1; }
 
 void srmra_plan_destroy(srmra_plan* plan) { delete plan; }
 

@@ -1,0 +1,48 @@
+// Device descriptors of the batched form (shared by host and device code).
+#pragma once
+#include "srmra_common.h"
+
+namespace srmra {
+
+enum { FORM_VALU = 0, FORM_MFMA = 1, FORM_BF16 = 2 };
+
+struct InstDesc {
+    StepArgs p;                  // per-instance step arguments (workspace pointers set)
+    const __bf16* yT;            // BF16 prepared planes (FORM_BF16 only)
+    const __bf16* yo;
+    const float* x;              // iterate in (this parity)
+    const float* log_rho;
+    float* x_new;                // iterate out
+    float* rho_new;
+    float* log_rho_new;
+    double* loglik;
+    float* xt2_w;                // writable views of p.xt2 / p.betaT
+    float* beta_w;
+    double* llpart;
+    double* bsum;
+    double* csum;
+    int LL, form, n_part, n_ll;
+};
+
+struct ClassLaunch {
+    int form, LL, item0, n_items, blocks1, blocks2;
+    size_t lds1, lds2;
+};
+
+constexpr int kMaxClasses = 16;
+
+struct BatchLaunch {
+    const InstDesc* desc;        // device, n_inst entries
+    const int4* pass_items;      // (instance, chunk, group, cost rank)
+    const int2* pack_items;      // (instance, component)
+    const int2* combine_items;   // (instance, block)
+    const int2* reduce_items;    // (instance, block)
+    int* counters;               // 2 per class
+    int n_pack, n_combine, n_reduce, n_inst, n_class;
+    ClassLaunch cls[kMaxClasses];
+};
+
+hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s);
+const void* class_pass_fn(int pass, int form, int LL);
+
+}  // namespace srmra

@@ -1,0 +1,144 @@
+// Batched form: one EM step of many independent instances (uneven L_low, K, N,
+// sigma).  Work items (instance, observation chunk, component group) are
+// grouped by (form, L_low) class and sorted by cost (largest first) on the
+// host; each pass is one persistent launch per class, whose blocks take items
+// through an atomic counter.  Each item runs exactly the device body of the
+// single-instance kernels, so an instance's result does not depend on which
+// other instances share the launch.  (One kernel per class keeps each body's
+// own register allocation; a single kernel switching over all bodies spills.)
+#include "srmra_aux_impl.h"
+#include "srmra_batch.h"
+#include "srmra_bf16_impl.h"
+#include "srmra_mfma_impl.h"
+#include "srmra_valu_impl.h"
+
+namespace srmra {
+
+__global__ void k_batch_reset(int* counters, int n) {
+    if (threadIdx.x < n) counters[threadIdx.x] = 0;
+}
+
+// a1 for every (instance, component) item
+__global__ __launch_bounds__(256) void k_batch_pack(const InstDesc* __restrict__ D,
+                                                    const int2* __restrict__ items) {
+    __shared__ double red[256];
+    const int2 it = items[blockIdx.x];
+    const InstDesc& d = D[it.x];
+    pack_x_body(d.x, d.log_rho, d.p.K, d.LL, d.p.inv_2s2, d.xt2_w, d.beta_w, it.y, red);
+}
+
+__global__ __launch_bounds__(256) void k_batch_combine(const InstDesc* __restrict__ D,
+                                                       const int2* __restrict__ items) {
+    __shared__ double red[256];
+    const int2 it = items[blockIdx.x];
+    const InstDesc& d = D[it.x];
+    lse_combine_body(d.p.part, d.n_part, d.p.N, d.p.ynorm, d.p.inv_2s2, d.p.lse, d.llpart,
+                     nullptr, it.y, red);
+}
+
+__global__ __launch_bounds__(256) void k_batch_reduce(const InstDesc* __restrict__ D,
+                                                      const int2* __restrict__ items) {
+    const int2 it = items[blockIdx.x];
+    const InstDesc& d = D[it.x];
+    reduce_partials_body(d.p.bpart, d.p.cpart, d.p.n_chunks, d.p.KK * d.LL * d.LL, d.bsum, d.csum,
+                         it.y);
+}
+
+__global__ __launch_bounds__(1024) void k_batch_finalize(const InstDesc* __restrict__ D) {
+    __shared__ double Ac[256];
+    __shared__ double red[1024];
+    const InstDesc& d = D[blockIdx.x];
+    finalize_body(d.bsum, d.csum, d.p.K, d.LL, d.x, d.llpart, d.n_ll, d.x_new, d.rho_new,
+                  d.log_rho_new, d.loglik, nullptr, nullptr, Ac, red);
+}
+
+// Persistent pass kernel of one (form, L_low) class: every block takes items
+// from the class's cost-sorted list through an atomic counter and leaves the
+// loop once the counter passes the item count (every wave reaches the exit).
+template <int PASS, int FORM, int LL>
+__global__ __launch_bounds__(256) void k_class_pass(const InstDesc* __restrict__ D,
+                                                    const int4* __restrict__ items, int n_items,
+                                                    int* __restrict__ counter) {
+    // dynamic LDS: 16 bytes for the work-item broadcast, then the body's area
+    // (kept 16-byte aligned for the BF16 body's vector accesses)
+    extern __shared__ float lds_raw[];
+    int* next = reinterpret_cast<int*>(lds_raw);
+    float* lds = lds_raw + 4;
+    for (;;) {
+        if (threadIdx.x == 0) *next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = *next;
+        __syncthreads();
+        if (it >= n_items) break;
+        const int4 w = items[it];
+        const InstDesc& d = D[w.x];
+        if constexpr (FORM == FORM_BF16) {
+            b16::Prep q;
+            q.yT = d.yT;
+            q.yo = d.yo;
+            if constexpr (PASS == 1) b16::bf16_pass1_body<LL>(d.p, q, w.y, w.z, lds);
+            else b16::bf16_pass2_body<LL>(d.p, q, w.y, w.z, lds);
+        } else if constexpr (FORM == FORM_MFMA) {
+            if constexpr (PASS == 1) mfma_pass1_body<LL>(d.p, w.y, w.z, lds);
+            else mfma_pass2_body<LL>(d.p, w.y, w.z, lds);
+        } else {
+            if constexpr (PASS == 1) valu_pass1_body<LL>(d.p, w.y, w.z, lds);
+            else valu_pass2_body<LL>(d.p, w.y, w.z, lds);
+        }
+        __syncthreads();
+    }
+}
+
+#define SRMRA_CLASS(F, L)                                                                     \
+    template __global__ void k_class_pass<1, F, L>(const InstDesc*, const int4*, int, int*);  \
+    template __global__ void k_class_pass<2, F, L>(const InstDesc*, const int4*, int, int*);
+SRMRA_CLASS(FORM_VALU, 8) SRMRA_CLASS(FORM_VALU, 12) SRMRA_CLASS(FORM_VALU, 16)
+SRMRA_CLASS(FORM_VALU, 24) SRMRA_CLASS(FORM_VALU, 32) SRMRA_CLASS(FORM_VALU, 48)
+SRMRA_CLASS(FORM_VALU, 64)
+SRMRA_CLASS(FORM_MFMA, 8) SRMRA_CLASS(FORM_MFMA, 12) SRMRA_CLASS(FORM_MFMA, 16)
+SRMRA_CLASS(FORM_MFMA, 24) SRMRA_CLASS(FORM_MFMA, 32) SRMRA_CLASS(FORM_MFMA, 48)
+SRMRA_CLASS(FORM_MFMA, 64)
+SRMRA_CLASS(FORM_BF16, 24) SRMRA_CLASS(FORM_BF16, 32)
+#undef SRMRA_CLASS
+
+// ---------------------------------------------------------------- host side
+const void* class_pass_fn(int pass, int form, int LL) {
+#define SRMRA_PICK(F, L) \
+    if (form == F && LL == L) return pass == 1 ? (const void*)k_class_pass<1, F, L> : (const void*)k_class_pass<2, F, L>;
+    SRMRA_PICK(FORM_VALU, 8) SRMRA_PICK(FORM_VALU, 12) SRMRA_PICK(FORM_VALU, 16)
+    SRMRA_PICK(FORM_VALU, 24) SRMRA_PICK(FORM_VALU, 32) SRMRA_PICK(FORM_VALU, 48)
+    SRMRA_PICK(FORM_VALU, 64)
+    SRMRA_PICK(FORM_MFMA, 8) SRMRA_PICK(FORM_MFMA, 12) SRMRA_PICK(FORM_MFMA, 16)
+    SRMRA_PICK(FORM_MFMA, 24) SRMRA_PICK(FORM_MFMA, 32) SRMRA_PICK(FORM_MFMA, 48)
+    SRMRA_PICK(FORM_MFMA, 64)
+    SRMRA_PICK(FORM_BF16, 24) SRMRA_PICK(FORM_BF16, 32)
+#undef SRMRA_PICK
+    return nullptr;
+}
+
+hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, L.counters, 2 * L.n_class);
+    hipLaunchKernelGGL(k_batch_pack, dim3(L.n_pack), dim3(256), 0, s, L.desc, L.pack_items);
+    for (int pass = 1; pass <= 2; ++pass) {
+        for (int k = 0; k < L.n_class; ++k) {
+            const ClassLaunch& c = L.cls[k];
+            const void* f = class_pass_fn(pass, c.form, c.LL);
+            if (!f) return hipErrorInvalidValue;
+            const InstDesc* desc = L.desc;
+            const int4* items = L.pass_items + c.item0;
+            int n = c.n_items;
+            int* counter = L.counters + 2 * k + (pass - 1);
+            void* args[] = {(void*)&desc, (void*)&items, (void*)&n, (void*)&counter};
+            const hipError_t e = hipLaunchKernel(f, dim3(pass == 1 ? c.blocks1 : c.blocks2), dim3(256), args,
+                                                 pass == 1 ? c.lds1 : c.lds2, s);
+            if (e != hipSuccess) return e;
+        }
+        if (pass == 1)
+            hipLaunchKernelGGL(k_batch_combine, dim3(L.n_combine), dim3(256), 0, s, L.desc, L.combine_items);
+    }
+    hipLaunchKernelGGL(k_batch_reduce, dim3(L.n_reduce), dim3(256), 0, s, L.desc, L.reduce_items);
+    hipLaunchKernelGGL(k_batch_finalize, dim3(L.n_inst), dim3(1024), 0, s, L.desc);
+    return hipGetLastError();
+}
+
+}  // namespace srmra

@@ -1,0 +1,348 @@
+// BF16 split-precision matrix-core form of the two passes of the EM step
+// (L_low in {24, 32}: one 32x32 MFMA tile per (observation, component)).
+//
+// Every FP32 operand v is split as v = hi + lo + O(2^-17 |v|) with
+// hi = bf16_rne(v), lo = bf16_rne(v - hi); a product is formed as
+// hi*hi + hi*lo + lo*hi with v_mfma_f32_32x32x16_bf16 and FP32 accumulation.
+//
+// Score tile (rows t2, cols t1, k = (b2, r1) over the pixels, runs of 8 r1):
+//   A[t2][k] = y_i[r1][(b2+t2) % Ll]   from prepared BF16 hi/lo planes of y
+//              stored column-major per observation (yT[col][r1]), so a lane's 8
+//              k-values are 16 contiguous bytes;
+//   B[k][t1] = x_c[(r1-t1) % Ll][b2]   read as FP32 from LDS and split on the fly.
+// Back-projection (component c, the wave's 8 observations), for each a1:
+//   Z[q2][t1] = sum_{t2, o} y_o[a1][(q2+t2) % Ll] * w_{o,c}[t1][t2]
+// with the posterior w taken straight from the score accumulators (a lane holds
+// column t1 and the rows t2 of its accumulator for all 8 observations, which
+// is exactly its B fragment over k = (t2, o)), and A from the prepared
+// observation-interleaved planes Yo[a1][col][o].  Z is folded into
+// b_c[(a1 - t1) % Ll][q2] in the wave's private LDS accumulator.
+#pragma once
+#include "srmra_common.h"
+
+namespace srmra {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+namespace b16 {
+
+constexpr int R1P = 32;               // padded r1 range (zeros past Ll)
+constexpr int PITCH = R1P + 8;        // yT row pitch in bf16 (80 bytes: conflict-free b128)
+template <int LL> struct Geo {
+    static constexpr int RL = R1P + LL;               // fp32 x row length in LDS
+    static constexpr int YT_OBS = 2 * LL * PITCH;     // bf16 per observation (both planes)
+    static constexpr int YO_GRP = 2 * LL * LL * 8;    // bf16 per 8-observation group
+    static constexpr int BP = LL + 1;                 // b accumulator pitch (floats)
+};
+
+// global prepared layout: [ynorm N doubles][yT N x 2 x Ll x 32][Yo ceil(N/8) x 2 x Ll x Ll x 8]
+struct Prep {
+    const __bf16* yT;
+    const __bf16* yo;
+};
+
+__device__ __forceinline__ void split8(const float (&v)[8], bf16x8& h, bf16x8& l) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const __bf16 hh = (__bf16)v[e];
+        h[e] = hh;
+        l[e] = (__bf16)(v[e] - (float)hh);
+    }
+}
+
+__device__ __forceinline__ floatx16 mfma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
+                                          const bf16x8& bl, floatx16 c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c, 0, 0, 0);
+    return c;
+}
+
+// x of components [c0, c0 + nc) into LDS: xs[c][b2][a] = x_c[a % Ll][b2], a < RL.
+template <int LL>
+__device__ __forceinline__ void load_x(const StepArgs& p, int c0, int nc, float* xs) {
+    using G = Geo<LL>;
+    for (int e = threadIdx.x; e < nc * LL * G::RL; e += 256) {
+        const int cs = e / (LL * G::RL), r = e % (LL * G::RL);
+        const int b2 = r / G::RL, a = r % G::RL;
+        int c = c0 + cs;
+        if (c >= p.KK) c = p.KK - 1;
+        xs[e] = p.xt2[((int64_t)c * LL + b2) * 2 * LL + (a % LL)];
+    }
+}
+
+// yT planes of observations [o0, o0 + 8) into LDS (row pitch PITCH), zeros past N.
+template <int LL>
+__device__ __forceinline__ void load_yT(const StepArgs& p, const Prep& q, int64_t o0, __bf16* ys) {
+    constexpr int CH = 2 * LL * (R1P / 8);     // 16-byte chunks per observation
+    for (int e = threadIdx.x; e < 8 * CH; e += 256) {
+        const int o = e / CH, r = e % CH;
+        const int row = r / (R1P / 8), part = r % (R1P / 8);   // row = plane*LL + col
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (o0 + o < p.N)
+            v = reinterpret_cast<const uint4*>(q.yT + (o0 + o) * (int64_t)(2 * LL * R1P))[r];
+        *reinterpret_cast<uint4*>(ys + (o * 2 * LL + row) * PITCH + part * 8) = v;
+    }
+}
+
+// Yo group of observations [o0, o0 + 8) (o0 multiple of 8) into LDS.
+template <int LL>
+__device__ __forceinline__ void load_yo(const Prep& q, int64_t o0, __bf16* yo) {
+    constexpr int CH = 2 * LL * LL;            // 16-byte chunks (8 obs x bf16) per group
+    const uint4* src = reinterpret_cast<const uint4*>(q.yo + (o0 / 8) * (int64_t)(2 * LL * LL * 8));
+    for (int e = threadIdx.x; e < CH; e += 256) reinterpret_cast<uint4*>(yo)[e] = src[e];
+}
+
+// Score tiles for NO observations (slots o_slot[k]) x NC components (LDS slots cs[k]).
+template <int LL, int NO, int NC>
+__device__ __forceinline__ void score(const __bf16* ys, const float* xs, const int (&oslot)[NO],
+                                      const int (&cslot)[NC], floatx16 (&acc)[NO][NC]) {
+    using G = Geo<LL>;
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 31, g = lane >> 5;
+    const int t2e = i < LL ? i : i - LL;
+    const int t1e = t2e;
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[o][c] = floatx16{0};
+    for (int b2 = 0; b2 < LL; ++b2) {
+        int col = b2 + t2e;
+        col = col >= LL ? col - LL : col;
+        const __bf16* arow[NO];
+#pragma unroll
+        for (int o = 0; o < NO; ++o) arow[o] = ys + (oslot[o] * 2 * LL + col) * PITCH + 8 * g;
+        const float* brow[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) brow[c] = xs + (cslot[c] * LL + b2) * G::RL + 8 * g + LL - t1e;
+#pragma unroll
+        for (int j = 0; j < R1P / 16; ++j) {
+            bf16x8 bh[NC], bl[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                float v[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = brow[c][16 * j + e];
+                split8(v, bh[c], bl[c]);
+            }
+#pragma unroll
+            for (int o = 0; o < NO; ++o) {
+                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(arow[o] + 16 * j);
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(arow[o] + LL * PITCH + 16 * j);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[o][c] = mfma3(ah, al, bh[c], bl[c], acc[o][c]);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int acc_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+
+// ============================================================================
+// Pass 1.  Block = 8 observations x 4 components; wave w: observations 4*(w&1)..+4,
+// components 2*(w>>1)..+2 of the block's group.  Partials per component pair.
+template <int LL>
+__device__ __forceinline__ void bf16_pass1_body(const StepArgs& p, const Prep& q, int chunk, int cg,
+                                                float* lds) {
+    using G = Geo<LL>;
+    float* xs = lds;                                                   // 4 x Ll x RL
+    __bf16* ys = reinterpret_cast<__bf16*>(xs + 4 * LL * G::RL);       // 8 x 2 x Ll x PITCH
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    load_x<LL>(p, cg * 4, 4, xs);
+    const int og = wave & 1, cgw = wave >> 1;
+    const int oslot[4] = {4 * og, 4 * og + 1, 4 * og + 2, 4 * og + 3};
+    const int cslot[2] = {2 * cgw, 2 * cgw + 1};
+    const int cpair = cg * 2 + cgw;                 // global component-pair index
+    const int j = lane & 31;
+    const int64_t c0 = (int64_t)chunk * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    for (int64_t o0 = c0; o0 < c1; o0 += 8) {
+        __syncthreads();
+        load_yT<LL>(p, q, o0, ys);
+        __syncthreads();
+        floatx16 acc[4][2];
+        score<LL, 4, 2>(ys, xs, oslot, cslot, acc);
+        float mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const bool ook = o0 + oslot[o] < p.N;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int cc = cg * 4 + cslot[c];
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int t2 = acc_row(v, lane);
+                    float a = -INFINITY;
+                    if (ook && cc < p.KK && t2 < LL && j < LL)
+                        a = acc[o][c][v] * p.inv_s2 + p.betaT[(int64_t)cc * (LL * LL) + t2 * LL + j];
+                    acc[o][c][v] = a;
+                    mx[o] = fmaxf(mx[o], a);
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            for (int off = 32; off > 0; off >>= 1) mx[o] = fmaxf(mx[o], __shfl_xor(mx[o], off));
+            float s = 0.f;
+            if (mx[o] > -INFINITY) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v)
+                        if (acc[o][c][v] > -INFINITY) s += fast_exp(acc[o][c][v] - mx[o]);
+            }
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            const int64_t og_ = o0 + oslot[o];
+            if (lane == 0 && og_ < p.N && cpair * 2 < p.KK)
+                p.part[(int64_t)cpair * p.N + og_] = make_float2(mx[o], s);
+        }
+    }
+}
+
+// ============================================================================
+// Pass 2.  Block = 8 observations x 4 components; wave w owns component
+// cg*4 + w for all 8 observations.
+template <int LL>
+__device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q, int chunk_i, int cg,
+                                                float* lds) {
+    using G = Geo<LL>;
+    float* xs = lds;                                                    // 4 x Ll x RL
+    float* bacc = xs + 4 * LL * G::RL;                                  // 4 x Ll x BP
+    __bf16* ys = reinterpret_cast<__bf16*>(bacc + 4 * LL * G::BP);      // 8 x 2 x Ll x PITCH
+    __bf16* yo = ys + 8 * 2 * LL * PITCH;                               // 2 x Ll x Ll x 8
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j = lane & 31, g = lane >> 5;
+    const int comp = cg * 4 + wave;
+    const bool cok = comp < p.KK;
+    load_x<LL>(p, cg * 4, 4, xs);
+    float* bw = bacc + wave * LL * G::BP;
+    for (int e = lane; e < LL * G::BP; e += 64) bw[e] = 0.f;
+    float cnt[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) cnt[v] = 0.f;
+    const int oslot[8] = {0, 1, 2, 3, 4, 5, 6, 7};
+    const int cslot[1] = {wave};
+    const int q2e = j < LL ? j : j - LL;
+    const int64_t c0 = (int64_t)chunk_i * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    for (int64_t o0 = c0; o0 < c1; o0 += 8) {
+        __syncthreads();
+        load_yT<LL>(p, q, o0, ys);
+        load_yo<LL>(q, o0, yo);
+        __syncthreads();
+        floatx16 acc[8][1];
+        score<LL, 8, 1>(ys, xs, oslot, cslot, acc);
+        // posterior weights, posterior mass, BF16 hi/lo fragments over k = (t2, o)
+        bf16x8 wh[16], wl[16];
+        float lse[8];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) lse[o] = (o0 + o < p.N) ? p.lse[o0 + o] : 0.f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int t2 = acc_row(v, lane);
+            const bool sok = cok && t2 < LL && j < LL;
+            const float bet = sok ? p.betaT[(int64_t)comp * (LL * LL) + t2 * LL + j] : 0.f;
+            float w[8];
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                float ww = 0.f;
+                if (sok && o0 + o < p.N) {
+                    const float a = acc[o][0][v] * p.inv_s2 + bet;
+                    ww = a > -INFINITY ? fast_exp(a - lse[o]) : 0.f;
+                }
+                w[o] = ww;
+                cnt[v] += ww;
+            }
+            split8(w, wh[v], wl[v]);
+        }
+        // back-projection for each a1, folded into the wave's b accumulator
+        for (int a1 = 0; a1 < LL; ++a1) {
+            floatx16 z = floatx16{0};
+            const __bf16* yrow = yo + a1 * LL * 8;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                int t2 = acc_row(v, lane);
+                t2 = t2 < LL ? t2 : t2 - LL;
+                int col = q2e + t2;
+                col = col >= LL ? col - LL : col;
+                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(yrow + col * 8);
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(yrow + LL * LL * 8 + col * 8);
+                z = mfma3(ah, al, wh[v], wl[v], z);
+            }
+            // z lane holds Z[q2 = acc_row(v)][t1 = j]; b_c[(a1 - t1) % Ll][q2] += Z
+            if (j < LL) {
+                int q1 = a1 - j;
+                q1 = q1 < 0 ? q1 + LL : q1;
+                float* brow = bw + q1 * G::BP;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int q2 = acc_row(v, lane);
+                    if (q2 < LL) brow[q2] += z[v];
+                }
+            }
+        }
+    }
+    // ---- store this block's partials for component `comp`
+    __syncthreads();
+    const int64_t chunk = chunk_i;
+    if (cok) {
+        float* bo = p.bpart + (chunk * p.KK + comp) * (LL * LL);
+        for (int e = lane; e < LL * LL; e += 64) bo[e] = bw[(e / LL) * G::BP + (e % LL)];
+        // c: lane holds c[t1 = j][t2 = acc_row(v)]
+        float* co = p.cpart + (chunk * p.KK + comp) * (LL * LL);
+        if (j < LL) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int t2 = acc_row(v, lane);
+                if (t2 < LL) co[j * LL + t2] = cnt[v];
+            }
+        }
+    }
+}
+
+// ---- per-job preparation: BF16 hi/lo planes of y in both layouts
+template <int LL>
+__global__ __launch_bounds__(256) void k_prep_bf16(const float* __restrict__ y, int64_t N,
+                                                   __bf16* __restrict__ yT, __bf16* __restrict__ yo) {
+    // one block per group of 8 observations
+    const int64_t grp = blockIdx.x;
+    for (int e = threadIdx.x; e < 8 * LL * LL; e += 256) {
+        const int o = e / (LL * LL), r = e % (LL * LL);
+        const int r1 = r / LL, r2 = r % LL;
+        const int64_t oi = grp * 8 + o;
+        const float v = oi < N ? y[oi * (LL * LL) + r] : 0.f;
+        const __bf16 h = (__bf16)v;
+        const __bf16 l = (__bf16)(v - (float)h);
+        if (oi < N) {
+            __bf16* t = yT + oi * (int64_t)(2 * LL * R1P);
+            t[r2 * R1P + r1] = h;
+            t[LL * R1P + r2 * R1P + r1] = l;
+        }
+        __bf16* g = yo + grp * (int64_t)(2 * LL * LL * 8);
+        g[(r1 * LL + r2) * 8 + o] = h;
+        g[LL * LL * 8 + (r1 * LL + r2) * 8 + o] = l;
+    }
+    // zero padding of yT rows past Ll
+    if (R1P > LL) {
+        for (int e = threadIdx.x; e < 8 * 2 * LL * (R1P - LL); e += 256) {
+            const int o = e / (2 * LL * (R1P - LL)), r = e % (2 * LL * (R1P - LL));
+            const int row = r / (R1P - LL), k = LL + r % (R1P - LL);
+            const int64_t oi = grp * 8 + o;
+            if (oi < N) yT[oi * (int64_t)(2 * LL * R1P) + row * R1P + k] = (__bf16)0.f;
+        }
+    }
+}
+
+template <int LL> constexpr size_t lds_pass1() {
+    using G = Geo<LL>;
+    return sizeof(float) * 4 * LL * G::RL + sizeof(__bf16) * 8 * 2 * LL * PITCH;
+}
+template <int LL> constexpr size_t lds_pass2() {
+    using G = Geo<LL>;
+    return sizeof(float) * (4 * LL * G::RL + 4 * LL * G::BP) +
+           sizeof(__bf16) * (8 * 2 * LL * PITCH + 2 * LL * LL * 8);
+}
+
+}  // namespace b16
+}  // namespace srmra

@@ -1,0 +1,84 @@
+"""GPU tests of the batched form: every instance of a mixed batch against the
+FP64 oracle, bitwise independence of an instance's result from the rest of the
+batch, and HIP-graph replays against eager execution."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import em_oracle as O  # noqa: E402
+from paper_2204_04754_amd import synth  # noqa: E402
+from paper_2204_04754_amd.batch import BatchedEM  # noqa: E402
+from tests.gpu_helpers import U_SPLIT, U32, check_step  # noqa: E402
+
+MIX = [(32, 2, 301, 0.6), (48, 3, 157, 1.1), (64, 4, 77, 1.6), (48, 2, 95, 0.9),
+       (96, 4, 23, 1.9), (32, 4, 211, 0.4), (64, 2, 64, 1.3), (96, 2, 9, 2.0)]
+
+
+def _instances(mix, config=70):
+    out = []
+    for j, (Lh, K, N, s) in enumerate(mix):
+        inst = synth.make_instance(Lh, K, N, s, config=config, instance=j)
+        out.append(dict(y=inst.y, K=K, sigma=s, x0=inst.x0, log_rho0=inst.log_rho0, inst=inst))
+    return out
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16_split3", "fp32_plain"])
+def test_mixed_batch_matches_oracle(prec):
+    ins = _instances(MIX)
+    be = BatchedEM(ins, precision=prec)
+    be.step()
+    torch.cuda.synchronize()
+    for j, d in enumerate(ins):
+        inst = d["inst"]
+        g = be.results(j)
+        ref = O.em_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, return_details=True)
+        u = U_SPLIT if (prec == "bf16_split3" and inst.Ll in (24, 32)) else U32
+        check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, u=u)
+
+
+@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16_split3"])
+def test_alone_equals_in_mix_bitwise(prec):
+    ins = _instances(MIX, config=71)
+    mix = BatchedEM(ins, precision=prec)
+    for _ in range(3):
+        mix.step()
+    torch.cuda.synchronize()
+    for j in (0, 2, 4, 7):
+        alone = BatchedEM([ins[j]], precision=prec)
+        for _ in range(3):
+            alone.step()
+        torch.cuda.synchronize()
+        a, b = alone.results(0), mix.results(j)
+        for k in ("x_new", "rho_new", "log_rho_new", "loglik"):
+            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (j, k)
+
+
+def test_graph_replays_match_eager():
+    ins = _instances(MIX[:5], config=72)
+    eager = BatchedEM(ins, precision="fp32_mfma")
+    graph_be = BatchedEM(ins, precision="fp32_mfma")
+    T = 4
+    g = graph_be.capture(T)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        g.replay()
+        graph_be.executions += T
+        # eager work of the program between replays
+        for _ in range(T):
+            eager.step()
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for j in range(len(ins)):
+            a, b = eager.results(j), graph_be.results(j)
+            for k in ("x_new", "rho_new", "log_rho_new", "loglik"):
+                assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (rep, j, k)
