@@ -54,6 +54,13 @@ def parse():
                     help="observations in the oracle sample (0 = sized for ~15 s)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "serve"],
+                    help="single: one instance (default); batched: 64-instance mix, 20 iterations "
+                         "captured as a HIP graph; serve: Poisson job arrivals, continuous batching")
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--iterations", type=int, default=20)
+    ap.add_argument("--rates", default="5,50,200")
+    ap.add_argument("--jobs", type=int, default=24)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the timed region, run one device-to-device copy of this many MiB "
                          "(reference kernel of known traffic for hardware-counter calibration)")
@@ -135,12 +142,115 @@ def cpu_baseline(inst, n_sample, precision):
                        f"({dt:.1f} s, FP64 NumPy, BLAS threads={threads or 'default'})"), err
 
 
+def bench_batched(args):
+    """64 instances of the uneven mix (Lh in {32,48,64,96}, K in {2,3,4}, N in
+    [5000, 50000], sigma in [0.3, 2]) advanced together; `iterations` EM steps
+    captured as one HIP graph and replayed."""
+    import torch
+    from paper_2204_04754_amd import synth
+    from paper_2204_04754_amd.batch import BatchedEM
+
+    t = time.perf_counter()
+    mix = synth.mixed_batch(args.instances)
+    ins = []
+    for d in mix:
+        inst = synth.make_instance(**d)
+        ins.append(dict(y=inst.y, K=inst.K, sigma=inst.sigma, x0=inst.x0, log_rho0=inst.log_rho0))
+    print(f"[bench] {len(ins)} instances generated in {time.perf_counter() - t:.1f} s",
+          file=sys.stderr, flush=True)
+    forms = {}
+    for prec, iters in ((args.precision, args.iterations), ("fp32_mfma", args.iterations),
+                        ("fp32_plain", 2)):
+        if prec in forms:
+            continue
+        be = BatchedEM(ins, precision=prec)
+        pairs = be.pairs_per_step
+        g = be.capture(iters)
+        g.replay()                                   # warm-up replay
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / iters
+        forms[prec] = dict(pairs_per_s=pairs / (ms * 1e-3), ms_per_step=ms, iterations_in_graph=iters)
+        print(f"[bench] batched {prec}: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+        del g, be
+        torch.cuda.empty_cache()
+    main_p = args.precision
+    out = {"metric": METRIC, "value": forms[main_p]["pairs_per_s"], "unit": "obs×shift pairs/s",
+           "n_gpus": 1, "steps": args.iterations, "warmup": args.iterations,
+           "ms_per_step": forms[main_p]["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": main_p, "data": "synthetic",
+           "config": {"workload": f"batched_mix_{args.instances}", "instances": args.instances,
+                      "pairs_per_step": sum(d['N'] * d['Lh'] ** 2 for d in mix),
+                      "precision": main_p, "graph_iterations": args.iterations},
+           "forms": forms,
+           "speedup_vs_plain_fp32": forms[main_p]["pairs_per_s"] / forms["fp32_plain"]["pairs_per_s"]}
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Poisson arrivals of 20-iteration jobs (90% drawn from the batched mix,
+    10% Lh 256, K 4, N 20000), swept over arrival rates; solves/s and p50/p99
+    latency (arrival -> completion) per rate and precision."""
+    import torch
+    from paper_2204_04754_amd import synth
+    from paper_2204_04754_amd.serve import GPUExecutor, Job, serve
+
+    pool_shapes = synth.mixed_batch(11, config=4) + [dict(Lh=256, K=4, N=20000, sigma=1.0,
+                                                            config=4, instance=999)]
+    t = time.perf_counter()
+    pool = [synth.make_instance(**d) for d in pool_shapes]
+    print(f"[bench] job pool generated in {time.perf_counter() - t:.1f} s", file=sys.stderr,
+          flush=True)
+    rates = [float(r) for r in args.rates.split(",")]
+    results = {}
+    # one job sequence per rate (same jobs and arrival times for every precision)
+    seqs = {}
+    for rate in rates:
+        r = np.random.default_rng(int(rate * 1000) + 7)
+        arr = np.cumsum(r.exponential(1.0 / rate, size=args.jobs))
+        pick = [11 if r.random() < 0.1 else int(r.integers(0, 11)) for _ in range(args.jobs)]
+        seqs[rate] = (arr, pick)
+    for prec in dict.fromkeys([args.precision, "fp32_mfma", "fp32_plain"]):
+        for rate in rates:
+            arr, pick = seqs[rate]
+            jobs = []
+            for k in range(args.jobs):
+                inst = pool[pick[k]]
+                jobs.append(Job(k, inst.y, inst.K, inst.sigma, inst.x0, inst.log_rho0,
+                                iterations=args.iterations, arrival=float(arr[k])))
+            ex = GPUExecutor(precision=prec)
+            rep = serve(jobs, ex, hbm_budget=200 << 30, max_slots=64)
+            summ = rep.summary()
+            results[f"{prec}@{rate:g}"] = summ
+            print(f"[bench] serve {prec} rate {rate:g}/s: {summ}", file=sys.stderr, flush=True)
+            del ex
+            torch.cuda.empty_cache()
+    main_key = f"{args.precision}@{rates[-1]:g}"
+    out = {"metric": METRIC, "value": results[main_key]["solves_per_s"], "unit": "solves/s",
+           "n_gpus": 1, "steps": args.jobs, "warmup": 0, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": args.precision, "data": "synthetic",
+           "config": {"workload": "serve_poisson_mix", "jobs_per_rate": args.jobs,
+                      "iterations_per_job": args.iterations, "rates": rates},
+           "p50_latency_s": results[main_key]["p50_latency_s"],
+           "p99_latency_s": results[main_key]["p99_latency_s"], "per_rate": results}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.mode == "batched":
+        return bench_batched(args)
+    if args.mode == "serve":
+        return bench_serve(args)
     import torch
     from paper_2204_04754_amd import synth
 

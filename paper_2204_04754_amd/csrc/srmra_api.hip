@@ -458,8 +458,8 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision, srmr
             cls = (int)P->classes.size() - 1;
         }
         ClassLaunch& C = P->classes[cls];
-        C.lds1 = std::max(C.lds1, g.lds1 + 16);
-        C.lds2 = std::max(C.lds2, g.lds2 + 16);
+        C.lds1 = std::max(C.lds1, g.lds1);
+        C.lds2 = std::max(C.lds2, g.lds2);
         for (int ch = 0; ch < g.n_chunks; ++ch) {
             const int64_t nobs = std::min<int64_t>(g.chunk_obs, g.N - (int64_t)ch * g.chunk_obs);
             const double cst = (double)nobs * g.cpb * (double)g.LL * g.LL * g.LL * g.LL *

@@ -59,11 +59,11 @@ template <int PASS, int FORM, int LL>
 __global__ __launch_bounds__(256) void k_class_pass(const InstDesc* __restrict__ D,
                                                     const int4* __restrict__ items, int n_items,
                                                     int* __restrict__ counter) {
-    // dynamic LDS: 16 bytes for the work-item broadcast, then the body's area
-    // (kept 16-byte aligned for the BF16 body's vector accesses)
-    extern __shared__ float lds_raw[];
-    int* next = reinterpret_cast<int*>(lds_raw);
-    float* lds = lds_raw + 4;
+    // The work-item index is broadcast through the first word of the body's LDS
+    // area: between the barrier that ends one item and the barrier after the
+    // read, no body is using it.  (The largest body needs the full 160 KB.)
+    extern __shared__ float lds[];
+    int* next = reinterpret_cast<int*>(lds);
     for (;;) {
         if (threadIdx.x == 0) *next = atomicAdd(counter, 1);
         __syncthreads();

@@ -1,0 +1,271 @@
+"""Serving form: continuous batching of EM reconstruction jobs on one GPU.
+
+A job is an SR-MRA instance (observations, K, sigma, initial x and log rho)
+that needs a fixed number of unprojected EM iterations.  The server keeps every
+admitted job's observation stack, prepared data and iterate resident in HBM
+until it finishes.  Each scheduler tick:
+
+1. moves arrived jobs into the FIFO queue (jobs whose footprint exceeds the
+   whole HBM budget are rejected at once);
+2. admits queued jobs in order while a slot is free and the job's footprint
+   fits in the free budget (uploads y and runs the per-job preparation);
+3. advances every active job by one EM step with one batched execution (the
+   plan is rebuilt only when the active set changed), so jobs that arrived
+   while others were running share the device with them from this tick on;
+4. retires jobs that reached their iteration count (copies x, rho, loglik to
+   the host, frees the buffers) and jobs whose log-likelihood is not finite
+   (marked failed; the others are unaffected).
+
+The admission policy (`Scheduler`) is plain Python and is tested on the CPU
+with a fake clock; `GPUExecutor` does the device work through the C ABI.  An
+instance's result does not depend on which jobs share its ticks (each instance
+runs the same device code with a partition fixed by its own shape).
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Callable, Deque, Dict, List, Optional
+
+import numpy as np
+
+QUEUED, ACTIVE, DONE, FAILED, REJECTED, CANCELLED = (
+    "queued", "active", "done", "failed", "rejected", "cancelled")
+
+
+@dataclass
+class Job:
+    job_id: int
+    y: np.ndarray                 # float32 [N][Ll][Ll]
+    K: int
+    sigma: float
+    x0: np.ndarray                # float32 [Lh][Lh]
+    log_rho0: np.ndarray          # float32 [2][Lh]
+    iterations: int = 20
+    arrival: float = 0.0
+    state: str = QUEUED
+    footprint: int = 0
+    iters_done: int = 0
+    t_admit: Optional[float] = None
+    t_done: Optional[float] = None
+    result: Optional[dict] = None
+    error: Optional[str] = None
+
+    @property
+    def N(self) -> int:
+        return int(self.y.shape[0])
+
+    @property
+    def Ll(self) -> int:
+        return int(self.y.shape[1])
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.t_done is None else self.t_done - self.arrival
+
+
+class Scheduler:
+    """FIFO admission by HBM footprint and free slots (no device work)."""
+
+    def __init__(self, hbm_budget: int, max_slots: int, footprint: Callable[[Job], int]):
+        self.budget = int(hbm_budget)
+        self.max_slots = int(max_slots)
+        self.footprint = footprint
+        self.queue: Deque[Job] = deque()
+        self.active: Dict[int, Job] = {}
+        self.used = 0
+        self.finished: List[Job] = []
+
+    def submit(self, job: Job, now: float) -> None:
+        job.footprint = int(self.footprint(job))
+        if job.footprint > self.budget:
+            job.state = REJECTED
+            job.error = f"footprint {job.footprint} B exceeds the HBM budget {self.budget} B"
+            job.t_done = now
+            self.finished.append(job)
+            return
+        job.state = QUEUED
+        self.queue.append(job)
+
+    def cancel(self, job_id: int, now: float) -> bool:
+        for j in list(self.queue):
+            if j.job_id == job_id:
+                self.queue.remove(j)
+                j.state, j.t_done = CANCELLED, now
+                self.finished.append(j)
+                return True
+        if job_id in self.active:
+            j = self.active.pop(job_id)
+            self.used -= j.footprint
+            j.state, j.t_done = CANCELLED, now
+            self.finished.append(j)
+            return True
+        return False
+
+    def admit(self, now: float) -> List[Job]:
+        """Jobs to start now, in FIFO order (head-of-line: stops at the first
+        job that does not fit)."""
+        out = []
+        while self.queue and len(self.active) < self.max_slots:
+            j = self.queue[0]
+            if self.used + j.footprint > self.budget:
+                break
+            self.queue.popleft()
+            j.state, j.t_admit = ACTIVE, now
+            self.active[j.job_id] = j
+            self.used += j.footprint
+            out.append(j)
+        return out
+
+    def retire(self, job: Job, now: float, failed: bool = False, error: str = "") -> None:
+        self.active.pop(job.job_id, None)
+        self.used -= job.footprint
+        job.state = FAILED if failed else DONE
+        job.error = error or None
+        job.t_done = now
+        self.finished.append(job)
+
+    @property
+    def idle(self) -> bool:
+        return not self.queue and not self.active
+
+
+class GPUExecutor:
+    """Device side of the server: per-job buffers and the batched plan."""
+
+    def __init__(self, precision="fp32_mfma", device="cuda"):
+        import torch
+
+        from . import binding as B
+        self.torch = torch
+        self.B = B
+        self.device = torch.device(device)
+        self.precision = B._prec(precision)
+        self.buf: Dict[int, dict] = {}
+        self.plan = None
+        self.plan_ids: Optional[tuple] = None
+        self.workspace = None
+
+    def footprint(self, job: Job) -> int:
+        B = self.B
+        Ll, K, N = job.Ll, job.K, job.N
+        form = B.srmra_plan_form(self.precision, Ll)
+        if form < 0:
+            return 1 << 62
+        Lh = K * Ll
+        return (4 * N * Ll * Ll + B.srmra_prepared_bytes(N, Ll, K, form)
+                + B.srmra_em_step_workspace_bytes(N, Ll, K, form) + 4 * (2 * Lh * Lh + 6 * Lh) + 4096)
+
+    def admit(self, job: Job) -> None:
+        torch, B = self.torch, self.B
+        f = dict(device=self.device, dtype=torch.float32)
+        y = torch.as_tensor(np.ascontiguousarray(job.y, np.float32)).to(self.device)
+        form = B.srmra_plan_form(self.precision, job.Ll)
+        prep = B.empty_bytes(B.srmra_prepared_bytes(job.N, job.Ll, job.K, form), self.device)
+        B.srmra_prepare_observations(y, job.N, job.Ll, job.K, form, prep)
+        Lh = job.K * job.Ll
+        self.buf[job.job_id] = dict(
+            y=y, prep=prep, N=job.N, L_low=job.Ll, K=job.K, sigma=job.sigma,
+            xa=torch.as_tensor(np.asarray(job.x0, np.float32)).to(**f).contiguous(),
+            xb=torch.empty((Lh, Lh), **f),
+            la=torch.as_tensor(np.asarray(job.log_rho0, np.float32)).to(**f).contiguous(),
+            lb=torch.empty((2, Lh), **f),
+            rho_new=torch.empty((2, Lh), **f),
+            loglik=torch.empty(1, dtype=torch.float64, device=self.device),
+            cur=0)
+
+    def _problem(self, b):
+        cur = b["cur"]
+        return dict(y=b["y"], prep=b["prep"], N=b["N"], L_low=b["L_low"], K=b["K"],
+                    sigma=b["sigma"],
+                    x=b["xa"] if cur == 0 else b["xb"], x_new=b["xb"] if cur == 0 else b["xa"],
+                    log_rho=b["la"] if cur == 0 else b["lb"],
+                    log_rho_new=b["lb"] if cur == 0 else b["la"],
+                    rho_new=b["rho_new"], loglik=b["loglik"])
+
+    def tick(self, ids: List[int]) -> Dict[int, float]:
+        """One EM step of every job in `ids`; returns each job's loglik."""
+        torch, B = self.torch, self.B
+        key = tuple(ids)
+        if key != self.plan_ids or self.plan is None:
+            if self.plan is not None:
+                self.plan.close()
+            self.plan = B.Plan([self._problem(self.buf[i]) for i in ids], self.precision)
+            self.workspace = B.empty_bytes(self.plan.workspace_bytes, self.device)
+            self.plan.upload(self.workspace)
+            self.plan_ids = key
+        self.plan.execute(self.workspace)
+        for i in ids:
+            self.buf[i]["cur"] ^= 1
+        lls = torch.cat([self.buf[i]["loglik"] for i in ids]).cpu().numpy()
+        return {i: float(v) for i, v in zip(ids, lls)}
+
+    def retire(self, job: Job, keep_result: bool = True) -> None:
+        b = self.buf.pop(job.job_id)
+        if keep_result:
+            x = b["xa"] if b["cur"] == 0 else b["xb"]
+            lr = b["la"] if b["cur"] == 0 else b["lb"]
+            job.result = dict(x=x.cpu().numpy(), log_rho=lr.cpu().numpy(),
+                              rho=b["rho_new"].cpu().numpy(), loglik=float(b["loglik"].item()))
+        self.plan_ids = None   # the active set changes
+
+
+@dataclass
+class ServeReport:
+    jobs: List[Job] = field(default_factory=list)
+    wall: float = 0.0
+    ticks: int = 0
+
+    def summary(self) -> dict:
+        done = [j for j in self.jobs if j.state == DONE]
+        lat = np.array([j.latency for j in done]) if done else np.zeros(0)
+        first = min((j.arrival for j in self.jobs), default=0.0)
+        last = max((j.t_done for j in done), default=first)
+        span = max(last - first, 1e-9)
+        return dict(jobs=len(self.jobs), done=len(done),
+                    failed=sum(j.state == FAILED for j in self.jobs),
+                    rejected=sum(j.state == REJECTED for j in self.jobs),
+                    solves_per_s=len(done) / span,
+                    p50_latency_s=float(np.percentile(lat, 50)) if lat.size else None,
+                    p99_latency_s=float(np.percentile(lat, 99)) if lat.size else None,
+                    ticks=self.ticks, wall_s=self.wall)
+
+
+def serve(jobs: List[Job], executor, hbm_budget: int, max_slots: int = 64,
+          clock: Callable[[], float] = time.perf_counter, sleep=time.sleep,
+          on_tick: Optional[Callable[[int, Scheduler], None]] = None) -> ServeReport:
+    """Run the continuous-batching loop until every job is finished.  Job
+    arrival times are relative to the start of the loop."""
+    sched = Scheduler(hbm_budget, max_slots, executor.footprint)
+    pending = sorted(jobs, key=lambda j: j.arrival)
+    t0 = clock()
+    k = 0
+    ticks = 0
+    while k < len(pending) or not sched.idle:
+        now = clock() - t0
+        while k < len(pending) and pending[k].arrival <= now:
+            sched.submit(pending[k], pending[k].arrival)
+            k += 1
+        for j in sched.admit(now):
+            executor.admit(j)
+        if sched.active:
+            ids = sorted(sched.active)
+            lls = executor.tick(ids)
+            ticks += 1
+            now = clock() - t0
+            for i in ids:
+                j = sched.active[i]
+                j.iters_done += 1
+                if not np.isfinite(lls[i]):
+                    executor.retire(j, keep_result=False)
+                    sched.retire(j, now, failed=True, error="non-finite log-likelihood")
+                elif j.iters_done >= j.iterations:
+                    executor.retire(j)
+                    sched.retire(j, now)
+            if on_tick:
+                on_tick(ticks, sched)
+        elif k < len(pending):
+            sleep(max(0.0, min(0.05, pending[k].arrival - (clock() - t0))))
+    rep = ServeReport(jobs=sched.finished, wall=clock() - t0, ticks=ticks)
+    return rep

@@ -14,7 +14,8 @@ from paper_2204_04754_amd.batch import BatchedEM  # noqa: E402
 from tests.gpu_helpers import U_SPLIT, U32, check_step  # noqa: E402
 
 MIX = [(32, 2, 301, 0.6), (48, 3, 157, 1.1), (64, 4, 77, 1.6), (48, 2, 95, 0.9),
-       (96, 4, 23, 1.9), (32, 4, 211, 0.4), (64, 2, 64, 1.3), (96, 2, 9, 2.0)]
+       (96, 4, 23, 1.9), (32, 4, 211, 0.4), (64, 2, 64, 1.3), (96, 2, 9, 2.0),
+       (128, 2, 5, 12.0)]   # L_low 64: the class whose pass-2 body fills the whole LDS
 
 
 def _instances(mix, config=70):
