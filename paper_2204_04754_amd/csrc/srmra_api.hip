@@ -34,6 +34,8 @@ bool bf16_geom(int LL, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void
 hipError_t launch_bf16(int LL, int pass, const StepArgs& p, const void* prep_extra, hipStream_t s);
 hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, void* prep_extra, hipStream_t s);
 size_t bf16_prepared_extra(int LL, int64_t N);
+size_t bf16_xb_bytes(int LL, int KK);
+hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, hipStream_t s);
 }  // namespace srmra
 
 using namespace srmra;
@@ -83,7 +85,7 @@ struct Geom {
     size_t lds1 = 0, lds2 = 0;
     // workspace offsets
     size_t o_prep = 0, o_part = 0, o_lse = 0, o_xt2 = 0, o_beta = 0, o_bpart = 0, o_cpart = 0,
-           o_llpart = 0, o_bsum = 0, o_csum = 0, total = 0;
+           o_llpart = 0, o_bsum = 0, o_csum = 0, o_xb = 0, total = 0;
 };
 
 int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
@@ -132,6 +134,7 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     g.o_llpart = take(sizeof(double) * (size_t)g.n_ll);
     g.o_bsum = take(sizeof(double) * (size_t)g.KK * LL * LL);
     g.o_csum = take(sizeof(double) * (size_t)g.KK * LL * LL);
+    g.o_xb = prec == SRMRA_BF16_SPLIT3 ? take(bf16_xb_bytes(LL, g.KK)) : 0;
     g.total = off;
     return SRMRA_OK;
 }
@@ -175,6 +178,7 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
     p.inv_2s2 = 1.0 / (2.0 * (double)sigma * (double)sigma);
     p.xt2 = (const float*)(ws + g.o_xt2);
     p.betaT = (const float*)(ws + g.o_beta);
+    p.xb = g.prec == SRMRA_BF16_SPLIT3 ? (const uint4*)(ws + g.o_xb) : nullptr;
     p.part = (float2*)(ws + g.o_part);
     p.lse = (float*)(ws + g.o_lse);
     p.bpart = (float*)(ws + g.o_bpart);
@@ -191,6 +195,8 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
     hipLaunchKernelGGL(k_pack_x, dim3(g.KK), dim3(256), 0, stream, x, log_rho, g.K, LL, p.inv_2s2,
                        (float*)(ws + g.o_xt2), (float*)(ws + g.o_beta));
     if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
+    if (g.prec == SRMRA_BF16_SPLIT3 && launch_pack_xb(LL, p, x, ws + g.o_xb, stream) != hipSuccess)
+        return SRMRA_EDEVICE;
     mark(1);
     auto pass = [&](int k) -> hipError_t {
         if (g.prec == SRMRA_FP32_MFMA) return launch_mfma(LL, k, p, stream);
@@ -377,6 +383,7 @@ void fill_desc(srmra_plan* P, int i, int par, InstDesc& d, char* ws) {
     p.inv_2s2 = 1.0 / (2.0 * (double)pr.sigma * (double)pr.sigma);
     p.xt2 = (const float*)(w + g.o_xt2);
     p.betaT = (const float*)(w + g.o_beta);
+    p.xb = P->form[i] == FORM_BF16 ? (const uint4*)(w + g.o_xb) : nullptr;
     p.part = (float2*)(w + g.o_part);
     p.lse = (float*)(w + g.o_lse);
     p.bpart = (float*)(w + g.o_bpart);

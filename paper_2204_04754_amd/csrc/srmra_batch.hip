@@ -27,6 +27,20 @@ __global__ __launch_bounds__(256) void k_batch_pack(const InstDesc* __restrict__
     pack_x_body(d.x, d.log_rho, d.p.K, d.LL, d.p.inv_2s2, d.xt2_w, d.beta_w, it.y, red);
 }
 
+// BF16-form instances: x as MFMA B fragments, every k-step of one component
+__global__ __launch_bounds__(256) void k_batch_pack_xb(const InstDesc* __restrict__ D,
+                                                       const int2* __restrict__ items) {
+    const int2 it = items[blockIdx.x];
+    const InstDesc& d = D[it.x];
+    if (d.form != FORM_BF16) return;
+    uint4* xb = const_cast<uint4*>(d.p.xb);
+    if (d.LL == 24) {
+        for (int ks = threadIdx.x >> 6; ks < b16::nk<24>(); ks += 4) b16::pack_xb_body<24>(d.p, d.x, it.y, ks, xb);
+    } else {
+        for (int ks = threadIdx.x >> 6; ks < b16::nk<32>(); ks += 4) b16::pack_xb_body<32>(d.p, d.x, it.y, ks, xb);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_batch_combine(const InstDesc* __restrict__ D,
                                                        const int2* __restrict__ items) {
     __shared__ double red[256];
@@ -56,7 +70,9 @@ __global__ __launch_bounds__(1024) void k_batch_finalize(const InstDesc* __restr
 // from the class's cost-sorted list through an atomic counter and leaves the
 // loop once the counter passes the item count (every wave reaches the exit).
 template <int PASS, int FORM, int LL>
-__global__ __launch_bounds__(256) void k_class_pass(const InstDesc* __restrict__ D,
+__global__ __launch_bounds__(256, ((PASS == 1 && FORM == FORM_BF16) ||
+                                   (PASS == 2 && FORM == FORM_MFMA && LL >= 16 && LL <= 32)) ? 2 : 1)
+void k_class_pass(const InstDesc* __restrict__ D,
                                                     const int4* __restrict__ items, int n_items,
                                                     int* __restrict__ counter) {
     // The work-item index is broadcast through the first word of the body's LDS
@@ -119,6 +135,7 @@ const void* class_pass_fn(int pass, int form, int LL) {
 hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, L.counters, 2 * L.n_class);
     hipLaunchKernelGGL(k_batch_pack, dim3(L.n_pack), dim3(256), 0, s, L.desc, L.pack_items);
+    hipLaunchKernelGGL(k_batch_pack_xb, dim3(L.n_pack), dim3(256), 0, s, L.desc, L.pack_items);
     for (int pass = 1; pass <= 2; ++pass) {
         for (int k = 0; k < L.n_class; ++k) {
             const ClassLaunch& c = L.cls[k];

@@ -5,7 +5,7 @@ namespace srmra {
 namespace b16 {
 
 template <int LL>
-__global__ __launch_bounds__(256) void k_score_lse_bf16(StepArgs p, Prep q) {
+__global__ __launch_bounds__(256, 2) void k_score_lse_bf16(StepArgs p, Prep q) {
     extern __shared__ float lds[];
     bf16_pass1_body<LL>(p, q, blockIdx.x, blockIdx.y, lds);
 }
@@ -16,10 +16,32 @@ __global__ __launch_bounds__(256) void k_backproject_bf16(StepArgs p, Prep q) {
     bf16_pass2_body<LL>(p, q, blockIdx.x, blockIdx.y, lds);
 }
 
+// x as MFMA B fragments: grid (KK, k-steps / 4), 256 threads (4 k-steps per block)
+template <int LL>
+__global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __restrict__ x,
+                                                 uint4* __restrict__ xb) {
+    const int ks = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (ks < nk<LL>()) pack_xb_body<LL>(p, x, blockIdx.x, ks, xb);
+}
+
 }  // namespace b16
 
 
 // ---------------------------------------------------------------- host side
+size_t bf16_xb_bytes(int LL, int KK) {
+    if (LL != 24 && LL != 32) return 0;
+    return (size_t)KK * LL * (b16::R1P / 16) * 128 * sizeof(uint4);
+}
+
+hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, hipStream_t s) {
+    const int nks = LL * (b16::R1P / 16);
+    const dim3 grid(p.KK, (nks + 3) / 4);
+    if (LL == 24) hipLaunchKernelGGL(b16::k_pack_xb<24>, grid, dim3(256), 0, s, p, x, (uint4*)xb);
+    else if (LL == 32) hipLaunchKernelGGL(b16::k_pack_xb<32>, grid, dim3(256), 0, s, p, x, (uint4*)xb);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 size_t bf16_prepared_extra(int LL, int64_t N) {
     if (LL != 24 && LL != 32) return 0;
     const size_t yt = (size_t)N * 2 * LL * b16::R1P * 2;

@@ -42,12 +42,26 @@ struct Prep {
     const __bf16* yo;
 };
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// v = hi + lo with hi = bf16_rne(v), lo = bf16_rne(v - hi); two values per
+// conversion instruction (v_cvt_pk_bf16_f32), and float(hi) recovered by
+// placing the 16 bits in the upper half of an FP32 word.
 __device__ __forceinline__ void split8(const float (&v)[8], bf16x8& h, bf16x8& l) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const __bf16 hh = (__bf16)v[e];
-        h[e] = hh;
-        l[e] = (__bf16)(v[e] - (float)hh);
+    for (int e = 0; e < 8; e += 2) {
+        const f32x2 a = {v[e], v[e + 1]};
+        const bf16x2 hh = __builtin_convertvector(a, bf16x2);
+        const unsigned bits = __builtin_bit_cast(unsigned, hh);
+        const float h0 = __builtin_bit_cast(float, bits << 16);
+        const float h1 = __builtin_bit_cast(float, bits & 0xffff0000u);
+        const f32x2 r = {v[e] - h0, v[e + 1] - h1};
+        const bf16x2 ll = __builtin_convertvector(r, bf16x2);
+        h[e] = hh[0];
+        h[e + 1] = hh[1];
+        l[e] = ll[0];
+        l[e + 1] = ll[1];
     }
 }
 
@@ -59,17 +73,34 @@ __device__ __forceinline__ floatx16 mfma3(const bf16x8& ah, const bf16x8& al, co
     return c;
 }
 
-// x of components [c0, c0 + nc) into LDS: xs[c][b2][a] = x_c[a % Ll][b2], a < RL.
+// Number of k-steps (b2, 16-row block of r1) of one score tile.
+template <int LL> constexpr int nk() { return LL * (R1P / 16); }
+
+// x of component c as the MFMA B operand of every k-step of the score tile:
+// lane (t1 = lane & 31, g = lane >> 5) of k-step (b2, jb) holds the 8 values
+// x_c[(16 jb + 8 g + e - t1) mod Ll][b2], e = 0..7, split into BF16 hi and lo.
+// Layout [c][k-step][plane][lane] of 16-byte fragments (one 1 KiB coalesced
+// load per wave and plane).  One block of 64 threads per (component, k-step).
 template <int LL>
-__device__ __forceinline__ void load_x(const StepArgs& p, int c0, int nc, float* xs) {
-    using G = Geo<LL>;
-    for (int e = threadIdx.x; e < nc * LL * G::RL; e += 256) {
-        const int cs = e / (LL * G::RL), r = e % (LL * G::RL);
-        const int b2 = r / G::RL, a = r % G::RL;
-        int c = c0 + cs;
-        if (c >= p.KK) c = p.KK - 1;
-        xs[e] = p.xt2[((int64_t)c * LL + b2) * 2 * LL + (a % LL)];
+__device__ __forceinline__ void pack_xb_body(const StepArgs& p, const float* __restrict__ x, int c,
+                                             int ks, uint4* __restrict__ xb) {
+    const int lane = threadIdx.x & 63;
+    const int c1 = c / p.K, c2 = c % p.K;
+    const int b2 = ks / (R1P / 16), jb = ks % (R1P / 16);
+    const int t1 = lane & 31, g = lane >> 5;
+    const int t1e = t1 < LL ? t1 : t1 - LL;
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        int r = 16 * jb + 8 * g + e - t1e;
+        r = ((r % LL) + LL) % LL;
+        v[e] = x[(int64_t)(c1 + r * p.K) * p.Lh + (c2 + b2 * p.K)];
     }
+    bf16x8 h, l;
+    split8(v, h, l);
+    uint4* dst = xb + ((int64_t)(c * nk<LL>() + ks) * 2) * 64;
+    dst[lane] = __builtin_bit_cast(uint4, h);
+    dst[64 + lane] = __builtin_bit_cast(uint4, l);
 }
 
 // yT planes of observations [o0, o0 + 8) into LDS (row pitch PITCH), zeros past N.
@@ -96,43 +127,58 @@ __device__ __forceinline__ void load_yo(const Prep& q, int64_t o0, __bf16* yo) {
 
 // Score tiles for NO observations (slots o_slot[k]) x NC components (LDS slots cs[k]).
 template <int LL, int NO, int NC>
-__device__ __forceinline__ void score(const __bf16* ys, const float* xs, const int (&oslot)[NO],
-                                      const int (&cslot)[NC], floatx16 (&acc)[NO][NC]) {
-    using G = Geo<LL>;
+__device__ __forceinline__ void score(const StepArgs& p, const __bf16* ys, const int (&oslot)[NO],
+                                      const int (&cgl)[NC], floatx16 (&acc)[NO][NC]) {
+    constexpr int JS = R1P / 16;
     const int lane = threadIdx.x & 63;
     const int i = lane & 31, g = lane >> 5;
     const int t2e = i < LL ? i : i - LL;
-    const int t1e = t2e;
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[o][c] = floatx16{0};
+    // B fragments of this lane for every component: xb[c][ks][plane][lane]
+    const uint4* bsrc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) bsrc[c] = p.xb + (int64_t)cgl[c] * nk<LL>() * 128 + lane;
     for (int b2 = 0; b2 < LL; ++b2) {
         int col = b2 + t2e;
         col = col >= LL ? col - LL : col;
         const __bf16* arow[NO];
 #pragma unroll
         for (int o = 0; o < NO; ++o) arow[o] = ys + (oslot[o] * 2 * LL + col) * PITCH + 8 * g;
-        const float* brow[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) brow[c] = xs + (cslot[c] * LL + b2) * G::RL + 8 * g + LL - t1e;
-#pragma unroll
-        for (int j = 0; j < R1P / 16; ++j) {
+        for (int j = 0; j < JS; ++j) {
+            const int ks = b2 * JS + j;
             bf16x8 bh[NC], bl[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                float v[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) v[e] = brow[c][16 * j + e];
-                split8(v, bh[c], bl[c]);
+                bh[c] = __builtin_bit_cast(bf16x8, bsrc[c][ks * 128]);
+                bl[c] = __builtin_bit_cast(bf16x8, bsrc[c][ks * 128 + 64]);
             }
+            bf16x8 ah[NO], al[NO];
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
-                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(arow[o] + 16 * j);
-                const bf16x8 al = *reinterpret_cast<const bf16x8*>(arow[o] + LL * PITCH + 16 * j);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) acc[o][c] = mfma3(ah, al, bh[c], bl[c], acc[o][c]);
+                ah[o] = *reinterpret_cast<const bf16x8*>(arow[o] + 16 * j);
+                al[o] = *reinterpret_cast<const bf16x8*>(arow[o] + LL * PITCH + 16 * j);
             }
+            // the three split products in separate sweeps over the independent
+            // accumulators, so consecutive MFMAs never depend on each other
+#pragma unroll
+            for (int o = 0; o < NO; ++o)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[o][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[o], bh[c], acc[o][c], 0, 0, 0);
+#pragma unroll
+            for (int o = 0; o < NO; ++o)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[o][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[o], bl[c], acc[o][c], 0, 0, 0);
+#pragma unroll
+            for (int o = 0; o < NO; ++o)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    acc[o][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o], bh[c], acc[o][c], 0, 0, 0);
         }
     }
 }
@@ -146,13 +192,13 @@ template <int LL>
 __device__ __forceinline__ void bf16_pass1_body(const StepArgs& p, const Prep& q, int chunk, int cg,
                                                 float* lds) {
     using G = Geo<LL>;
-    float* xs = lds;                                                   // 4 x Ll x RL
-    __bf16* ys = reinterpret_cast<__bf16*>(xs + 4 * LL * G::RL);       // 8 x 2 x Ll x PITCH
+    __bf16* ys = reinterpret_cast<__bf16*>(lds);                       // 8 x 2 x Ll x PITCH
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    load_x<LL>(p, cg * 4, 4, xs);
     const int og = wave & 1, cgw = wave >> 1;
     const int oslot[4] = {4 * og, 4 * og + 1, 4 * og + 2, 4 * og + 3};
     const int cslot[2] = {2 * cgw, 2 * cgw + 1};
+    // global component indices of the wave's two components (clamped; masked later)
+    const int cgl[2] = {min(cg * 4 + cslot[0], p.KK - 1), min(cg * 4 + cslot[1], p.KK - 1)};
     const int cpair = cg * 2 + cgw;                 // global component-pair index
     const int j = lane & 31;
     const int64_t c0 = (int64_t)chunk * p.chunk_obs;
@@ -162,20 +208,29 @@ __device__ __forceinline__ void bf16_pass1_body(const StepArgs& p, const Prep& q
         load_yT<LL>(p, q, o0, ys);
         __syncthreads();
         floatx16 acc[4][2];
-        score<LL, 4, 2>(ys, xs, oslot, cslot, acc);
+        score<LL, 4, 2>(p, ys, oslot, cgl, acc);
         float mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        // the bias of a lane's (component, t1, t2) slots does not depend on the
+        // observation: load it once per tile
+        float bet[2][16];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int cc = cg * 4 + cslot[c];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int t2 = acc_row(v, lane);
+                bet[c][v] = (cc < p.KK && t2 < LL && j < LL)
+                                ? p.betaT[(int64_t)cc * (LL * LL) + t2 * LL + j] : -INFINITY;
+            }
+        }
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
             const bool ook = o0 + oslot[o] < p.N;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                const int cc = cg * 4 + cslot[c];
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
-                    const int t2 = acc_row(v, lane);
-                    float a = -INFINITY;
-                    if (ook && cc < p.KK && t2 < LL && j < LL)
-                        a = acc[o][c][v] * p.inv_s2 + p.betaT[(int64_t)cc * (LL * LL) + t2 * LL + j];
+                    const float a = ook ? acc[o][c][v] * p.inv_s2 + bet[c][v] : -INFINITY;
                     acc[o][c][v] = a;
                     mx[o] = fmaxf(mx[o], a);
                 }
@@ -207,22 +262,20 @@ template <int LL>
 __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q, int chunk_i, int cg,
                                                 float* lds) {
     using G = Geo<LL>;
-    float* xs = lds;                                                    // 4 x Ll x RL
-    float* bacc = xs + 4 * LL * G::RL;                                  // 4 x Ll x BP
+    float* bacc = lds;                                                  // 4 x Ll x BP
     __bf16* ys = reinterpret_cast<__bf16*>(bacc + 4 * LL * G::BP);      // 8 x 2 x Ll x PITCH
     __bf16* yo = ys + 8 * 2 * LL * PITCH;                               // 2 x Ll x Ll x 8
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int j = lane & 31, g = lane >> 5;
     const int comp = cg * 4 + wave;
     const bool cok = comp < p.KK;
-    load_x<LL>(p, cg * 4, 4, xs);
     float* bw = bacc + wave * LL * G::BP;
     for (int e = lane; e < LL * G::BP; e += 64) bw[e] = 0.f;
     float cnt[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v) cnt[v] = 0.f;
     const int oslot[8] = {0, 1, 2, 3, 4, 5, 6, 7};
-    const int cslot[1] = {wave};
+    const int cgl[1] = {cok ? comp : p.KK - 1};
     const int q2e = j < LL ? j : j - LL;
     const int64_t c0 = (int64_t)chunk_i * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
@@ -232,7 +285,7 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
         load_yo<LL>(q, o0, yo);
         __syncthreads();
         floatx16 acc[8][1];
-        score<LL, 8, 1>(ys, xs, oslot, cslot, acc);
+        score<LL, 8, 1>(p, ys, oslot, cgl, acc);
         // posterior weights, posterior mass, BF16 hi/lo fragments over k = (t2, o)
         bf16x8 wh[16], wl[16];
         float lse[8];
@@ -258,7 +311,9 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
         }
         // back-projection for each a1, folded into the wave's b accumulator
         for (int a1 = 0; a1 < LL; ++a1) {
-            floatx16 z = floatx16{0};
+            // four independent partial sums (v mod 4) so that consecutive MFMAs
+            // do not depend on each other
+            floatx16 zp[4] = {floatx16{0}, floatx16{0}, floatx16{0}, floatx16{0}};
             const __bf16* yrow = yo + a1 * LL * 8;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
@@ -268,8 +323,11 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
                 col = col >= LL ? col - LL : col;
                 const bf16x8 ah = *reinterpret_cast<const bf16x8*>(yrow + col * 8);
                 const bf16x8 al = *reinterpret_cast<const bf16x8*>(yrow + LL * LL * 8 + col * 8);
-                z = mfma3(ah, al, wh[v], wl[v], z);
+                zp[v & 3] = mfma3(ah, al, wh[v], wl[v], zp[v & 3]);
             }
+            floatx16 z;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) z[e] = (zp[0][e] + zp[1][e]) + (zp[2][e] + zp[3][e]);
             // z lane holds Z[q2 = acc_row(v)][t1 = j]; b_c[(a1 - t1) % Ll][q2] += Z
             if (j < LL) {
                 int q1 = a1 - j;
@@ -335,12 +393,11 @@ __global__ __launch_bounds__(256) void k_prep_bf16(const float* __restrict__ y, 
 }
 
 template <int LL> constexpr size_t lds_pass1() {
-    using G = Geo<LL>;
-    return sizeof(float) * 4 * LL * G::RL + sizeof(__bf16) * 8 * 2 * LL * PITCH;
+    return sizeof(__bf16) * 8 * 2 * LL * PITCH;
 }
 template <int LL> constexpr size_t lds_pass2() {
     using G = Geo<LL>;
-    return sizeof(float) * (4 * LL * G::RL + 4 * LL * G::BP) +
+    return sizeof(float) * (4 * LL * G::BP) +
            sizeof(__bf16) * (8 * 2 * LL * PITCH + 2 * LL * LL * 8);
 }
 

@@ -51,6 +51,7 @@ struct StepArgs {
     // per-step packed x
     const float* xt2;        // [KK][Ll][2Ll]  xt2[c][b2][a] = x_c[a % Ll][b2]
     const float* betaT;      // [KK][Ll(t2)][Ll(t1)]
+    const uint4* xb;         // BF16 form: x as MFMA B fragments [KK][k-step][plane][lane]
     // pass-1 output / pass-2 input
     float2* part;            // [n_cg][N]  (max, sum) of exp over the group's shifts
     float* lse;              // [N]

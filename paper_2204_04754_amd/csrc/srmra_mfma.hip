@@ -9,8 +9,9 @@ __global__ __launch_bounds__(256) void k_score_lse_mfma(StepArgs p) {
     mfma_pass1_body<LL>(p, blockIdx.x, blockIdx.y, lds);
 }
 
+// two waves per SIMD where the body fits 256 registers without spilling
 template <int LL>
-__global__ __launch_bounds__(256) void k_backproject_mfma(StepArgs p) {
+__global__ __launch_bounds__(256, (LL == 8 || LL == 64) ? 1 : 2) void k_backproject_mfma(StepArgs p) {
     extern __shared__ float lds[];
     mfma_pass2_body<LL>(p, blockIdx.x, blockIdx.y, lds);
 }
