@@ -10,7 +10,8 @@ its per-job preparation already resident in HBM.  The main form is timed and
 the plain FP32 (vector ALU) form is timed beside it on the same inputs.
 
 Prints ONE JSON line.  Also reports:
- * roofline of the dominant kernel (the posterior/back-projection pass), its
+ * roofline of the dominant kernel (the single pass, or for two-pass shapes
+   the posterior/back-projection pass), its
    duration measured with HIP events recorded by the library on the step's
    stream, against the MI355X FP32 matrix peak (157.3 TFLOP/s) or, for the
    vector-ALU form, the non-packed FP32 vector peak (78.6 TFLOP/s);
@@ -36,9 +37,9 @@ PEAK = {  # MI355X published dense peaks
     "bf16_split3": ("mfma", 2516.6e12),
 }
 KNAME = {"fp32_mfma": "mfma", "fp32_plain": "valu", "bf16_split3": "bf16"}
-# HBM bytes per launch measured with rocprofv3 FETCH_SIZE + WRITE_SIZE for the
-# dominant kernel at the default workload (None until counters are taken for
-# the current kernel version).
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, keyed by (workload, precision, kernel); absent (null) until the
+# counters are taken for the current kernel version.
 TRAFFIC = {}
 
 
@@ -51,7 +52,9 @@ def parse():
     ap.add_argument("--precision", default="fp32_mfma")
     ap.add_argument("--baseline-precision", default="fp32_plain")
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="observations in the oracle sample (0 = sized for ~15 s)")
+                    help="observations in the oracle sample (0 = sized for --cpu-seconds)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target oracle time on the host for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--mode", default="single", choices=["single", "batched", "serve"],
@@ -117,6 +120,17 @@ def run_form(inst, precision, steps, warmup):
     phase = acc / n_prof
     ll = float(job.loglik.item())
     return dict(ms_per_step=total_ms / steps, phase_ms=phase.tolist(), loglik=ll, job=job)
+
+
+def oracle_sample_size(inst, seconds):
+    """Observations the oracle gets through in about `seconds` on this host,
+    from an untimed calibration step on the first 64 observations."""
+    from oracle import em_oracle as O
+    n0 = min(64, inst.N)
+    t = time.perf_counter()
+    O.em_step(inst.y[:n0], inst.x0, inst.log_rho0, inst.sigma, inst.K)
+    per_obs = (time.perf_counter() - t) / n0
+    return max(n0, int(seconds / max(per_obs, 1e-9)))
 
 
 def cpu_baseline(inst, n_sample, precision):
@@ -281,19 +295,35 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
-    # roofline of the dominant kernel: posterior + back-projection pass (phase 3)
+    # roofline of the dominant kernel (phase 3): the single pass where the
+    # instance's components fit one workgroup (score + back-projection, each
+    # 2 Ll^2 flop per pair), else the posterior / back-projection pass (2 Ll^2
+    # per pair algorithmic; it also re-issues the score).  BF16 split issues 3
+    # products per multiply-add.
+    from paper_2204_04754_amd import binding as B
     Ll2 = inst.Ll * inst.Ll
     bound, peak = PEAK[args.precision]
+    n_pass = B.srmra_em_step_passes(inst.N, inst.Ll, inst.K, args.precision)
+    prod = 3.0 if args.precision == "bf16_split3" else 1.0
     k_ms = main_r["phase_ms"][3]
-    alg_flop = 2.0 * Ll2 * pairs          # back-projection contraction, 2 Ll^2 per pair
-    issued_flop = 4.0 * Ll2 * pairs       # + the recomputed score contraction
+    if n_pass == 1:
+        kname = f"k_fused_{KNAME[args.precision]}<{inst.Ll}>"
+        alg_flop = 4.0 * Ll2 * pairs
+        issued_flop = alg_flop * prod
+    else:
+        kname = f"k_backproject_{KNAME[args.precision]}<{inst.Ll}>"
+        alg_flop = 2.0 * Ll2 * pairs
+        issued_flop = 4.0 * Ll2 * pairs * prod
     achieved = alg_flop / (k_ms * 1e-3)
     roof = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": TRAFFIC.get((args.workload, args.precision)),
-            "kernel": f"k_backproject_{KNAME[args.precision]}<{inst.Ll}>",
-            "kernel_ms": k_ms, "issued_frac": issued_flop / (k_ms * 1e-3) / peak,
-            "score_pass": {"kernel_ms": main_r["phase_ms"][1],
-                           "frac": 2.0 * Ll2 * pairs / (main_r["phase_ms"][1] * 1e-3) / peak}}
+            "frac": achieved / peak, "traffic": TRAFFIC.get((args.workload, args.precision, kname)),
+            "kernel": kname, "kernel_ms": k_ms, "passes": n_pass,
+            "issued_frac": issued_flop / (k_ms * 1e-3) / peak}
+    if n_pass == 2:
+        s_ms = main_r["phase_ms"][1]
+        roof["score_pass"] = {"kernel_ms": s_ms,
+                              "frac": 2.0 * Ll2 * pairs / (s_ms * 1e-3) / peak,
+                              "issued_frac": 2.0 * Ll2 * pairs * prod / (s_ms * 1e-3) / peak}
 
     out = {"metric": METRIC, "value": value, "unit": "obs×shift pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": forms[args.precision]["ms_per_step"],
@@ -316,7 +346,7 @@ def main():
         out["copy_probe_bytes"] = nb
         del src, dst
     if not args.no_cpu:
-        n = args.cpu_sample or max(64, int(15.0 * 1.0e7 / (inst.Lh * inst.Lh * inst.Ll * inst.Ll / 16)))
+        n = args.cpu_sample or oracle_sample_size(inst, args.cpu_seconds)
         n = min(n, inst.N)
         cb, err = cpu_baseline(inst, n, args.precision)
         out["cpu_baseline"] = cb

@@ -88,6 +88,15 @@ const char* srmra_version(void);
  * and is not preserved between calls. */
 size_t srmra_em_step_workspace_bytes(int64_t N, int L_low, int K, int precision);
 
+/* Passes over the observation stack that one step makes for this shape and
+ * precision: 2 (score / log-sum-exp pass, then the posterior / back-projection
+ * pass that recomputes the scores) or 1 (SRMRA_FP32_MFMA when all K^2
+ * polyphase components of an observation fit in one workgroup: the
+ * log-sum-exp of eq. weights_EM completes inside the workgroup and the scores
+ * are computed once).  Returns a negative srmra_status for an unsupported
+ * shape or precision.  Host-only; enqueues nothing. */
+int srmra_em_step_passes(int64_t N, int L_low, int K, int precision);
+
 /* One EM step (see top of file).  y, x, log_rho are read; x_new, rho_new,
  * loglik are written.  x_new must not alias x; outputs must not alias inputs.
  * sigma > 0 and finite (the known noise standard deviation, Sec. 1).

@@ -67,6 +67,8 @@ def lib():
             L.srmra_version.argtypes = []
             L.srmra_em_step_workspace_bytes.restype = _sz
             L.srmra_em_step_workspace_bytes.argtypes = [_i64, _int, _int, _int]
+            L.srmra_em_step_passes.restype = _int
+            L.srmra_em_step_passes.argtypes = [_i64, _int, _int, _int]
             L.srmra_prepared_bytes.restype = _sz
             L.srmra_prepared_bytes.argtypes = [_i64, _int, _int, _int]
             L.srmra_prepare_observations.restype = _int
@@ -146,6 +148,12 @@ def srmra_version() -> str:
 
 def srmra_em_step_workspace_bytes(N: int, L_low: int, K: int, precision) -> int:
     return int(lib().srmra_em_step_workspace_bytes(N, L_low, K, _prec(precision)))
+
+
+def srmra_em_step_passes(N: int, L_low: int, K: int, precision) -> int:
+    r = int(lib().srmra_em_step_passes(N, L_low, K, _prec(precision)))
+    _check(r if r < 0 else 0, "srmra_em_step_passes")
+    return r
 
 
 def srmra_prepared_bytes(N: int, L_low: int, K: int, precision) -> int:

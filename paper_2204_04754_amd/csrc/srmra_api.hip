@@ -27,6 +27,7 @@ hipError_t launch_mfma(int LL, int pass, const StepArgs& p, hipStream_t s);
 hipError_t launch_valu(int LL, int pass, const StepArgs& p, hipStream_t s);
 bool mfma_geom(int LL, int& cpw, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
                const void*& f2);
+bool mfma_fused_geom(int LL, int KK, int& wc, int& nt, size_t& lds, const void*& f);
 bool valu_geom(int LL, int KK, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
                const void*& f2);
 bool bf16_geom(int LL, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
@@ -80,6 +81,7 @@ struct Geom {
     int LL = 0, K = 0, Lh = 0, KK = 0, prec = 0;
     int64_t N = 0;
     int cpb = 0, n_cg = 0, n_part = 0, ntile = 0, n_chunks = 0, n_ll = 0;
+    int fuse_wc = 0;   // FP32 MFMA single pass: component groups per block (0: two passes)
     size_t prep_bytes = 0, prep_extra_off = 0;
     int64_t chunk_obs = 0;
     size_t lds1 = 0, lds2 = 0;
@@ -99,14 +101,28 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     const void* f1 = nullptr;
     const void* f2 = nullptr;
     bool ok;
-    if (prec == SRMRA_FP32_MFMA) ok = mfma_geom(LL, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
-    else if (prec == SRMRA_BF16_SPLIT3) ok = bf16_geom(LL, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
+    if (prec == SRMRA_FP32_MFMA) {
+        ok = mfma_geom(LL, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
+        // one pass when all components of an observation fit in one block
+        int wc = 0, nt = 0;
+        size_t lds = 0;
+        const void* ff = nullptr;
+        if (ok && mfma_fused_geom(LL, g.KK, wc, nt, lds, ff)) {
+            g.fuse_wc = wc;
+            g.cpb *= wc;
+            g.ntile = nt;
+            g.lds1 = 0;
+            g.lds2 = lds;
+            f1 = nullptr;
+            f2 = ff;
+        }
+    } else if (prec == SRMRA_BF16_SPLIT3) ok = bf16_geom(LL, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
     else ok = valu_geom(LL, g.KK, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
     if (!ok) return SRMRA_EUNSUPPORTED;
     g.n_cg = (g.KK + g.cpb - 1) / g.cpb;
     // pass-1 partials per observation: one per component group, or per component
     // pair for the BF16 form (two waves of a block hold different pairs)
-    g.n_part = prec == SRMRA_BF16_SPLIT3 ? (g.KK + 1) / 2 : g.n_cg;
+    g.n_part = prec == SRMRA_BF16_SPLIT3 ? (g.KK + 1) / 2 : g.n_cg;   // 1 for the single pass
     g.prep_extra_off = align_up(sizeof(double) * (size_t)N);
     g.prep_bytes = g.prep_extra_off + (prec == SRMRA_BF16_SPLIT3 ? bf16_prepared_extra(LL, N) : 0);
     // one resident wave of blocks over the whole device for the heavier pass
@@ -188,6 +204,7 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
     p.cpb = g.cpb;
     p.ntile = g.ntile;
     p.chunk_obs = g.chunk_obs;
+    p.fuse_wc = g.fuse_wc;
     const int LL = g.LL;
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], stream); };
 
@@ -203,16 +220,26 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
         if (g.prec == SRMRA_BF16_SPLIT3) return launch_bf16(LL, k, p, prep_extra, stream);
         return launch_valu(LL, k, p, stream);
     };
-    hipError_t e = pass(1);
-    if (e != hipSuccess) return SRMRA_EDEVICE;
-    mark(2);
-    hipLaunchKernelGGL(k_lse_combine, dim3(g.n_ll), dim3(256), 0, stream, (const float2*)p.part,
-                       g.n_part, g.N, ynorm, p.inv_2s2, p.lse, (double*)(ws + g.o_llpart), ll_obs);
-    if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
-    mark(3);
-    e = pass(2);
-    if (e != hipSuccess) return SRMRA_EDEVICE;
-    mark(4);
+    auto combine = [&]() -> hipError_t {
+        hipLaunchKernelGGL(k_lse_combine, dim3(g.n_ll), dim3(256), 0, stream, (const float2*)p.part,
+                           g.n_part, g.N, ynorm, p.inv_2s2, p.lse, (double*)(ws + g.o_llpart), ll_obs);
+        return hipGetLastError();
+    };
+    if (g.fuse_wc) {
+        // single pass; its (max, sum) per observation feed the log-likelihood after it
+        mark(2);
+        mark(3);
+        if (launch_mfma(LL, 3, p, stream) != hipSuccess) return SRMRA_EDEVICE;
+        mark(4);
+        if (combine() != hipSuccess) return SRMRA_EDEVICE;
+    } else {
+        if (pass(1) != hipSuccess) return SRMRA_EDEVICE;
+        mark(2);
+        if (combine() != hipSuccess) return SRMRA_EDEVICE;
+        mark(3);
+        if (pass(2) != hipSuccess) return SRMRA_EDEVICE;
+        mark(4);
+    }
     const int per = g.KK * LL * LL;
     hipLaunchKernelGGL(k_reduce_partials, dim3((per + 255) / 256), dim3(256), 0, stream,
                        (const float*)p.bpart, (const float*)p.cpart, g.n_chunks, per,
@@ -247,6 +274,13 @@ size_t srmra_em_step_workspace_bytes(int64_t N, int L_low, int K, int precision)
     Geom g;
     if (make_geom(N, L_low, K, precision, true, g) != SRMRA_OK) return 0;
     return g.total;
+}
+
+int srmra_em_step_passes(int64_t N, int L_low, int K, int precision) {
+    Geom g;
+    const int st = make_geom(N, L_low, K, precision, false, g);
+    if (st != SRMRA_OK) return st;
+    return g.fuse_wc ? 1 : 2;
 }
 
 size_t srmra_prepared_bytes(int64_t N, int L_low, int K, int precision) {
@@ -347,6 +381,7 @@ struct srmra_plan {
     std::vector<size_t> inst_off;
     std::vector<int4> pass_items;
     std::vector<int2> pack_items, combine_items, reduce_items;
+    int n_combine_early = 0;   // combine items of two-pass instances (the rest run after pass 2)
     size_t o_desc = 0, o_pass = 0, o_pack = 0, o_comb = 0, o_red = 0, o_cnt = 0, total = 0;
     std::vector<ClassLaunch> classes;
     int parity = 0;
@@ -390,6 +425,7 @@ void fill_desc(srmra_plan* P, int i, int par, InstDesc& d, char* ws) {
     p.cpart = (float*)(w + g.o_cpart);
     p.n_chunks = g.n_chunks; p.n_cg = g.n_cg; p.cpb = g.cpb; p.ntile = g.ntile;
     p.chunk_obs = g.chunk_obs;
+    p.fuse_wc = g.fuse_wc;
     if (P->form[i] == FORM_BF16) {
         const char* e = (const char*)pr.prep + g.prep_extra_off;
         const size_t yt = (size_t)g.N * 2 * g.LL * 32 * 2;
@@ -434,6 +470,7 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision, srmr
     P->probs.assign(probs, probs + count);
     struct Cost { int cls; double c; int4 it; };
     std::vector<Cost> costs;
+    std::vector<int2> combine_late;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     for (int i = 0; i < count; ++i) {
@@ -442,7 +479,7 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision, srmr
                                  pr.rho_new, pr.loglik);
         if (st == SRMRA_OK && (!pr.prep || !pr.log_rho_new || !aligned(pr.prep))) st = SRMRA_EINVAL;
         if (st != SRMRA_OK) { delete P; return st; }
-        const int f = form_of(precision, pr.L_low);
+        int f = form_of(precision, pr.L_low);
         const int fprec = f == FORM_BF16 ? SRMRA_BF16_SPLIT3 : (f == FORM_MFMA ? SRMRA_FP32_MFMA : SRMRA_FP32_PLAIN);
         Geom g0;
         st = make_geom(pr.N, pr.L_low, pr.K, fprec, false, g0);
@@ -450,6 +487,7 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision, srmr
         Geom g;
         make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, default_chunk(g0));
         if (pr.prep_bytes < g.prep_bytes) { delete P; return SRMRA_EWORKSPACE; }
+        if (f == FORM_MFMA && g.fuse_wc) f = FORM_FUSED;
         P->geoms.push_back(g);
         P->form.push_back(f);
         int cls = -1;
@@ -474,10 +512,13 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision, srmr
             for (int cg = 0; cg < g.n_cg; ++cg) costs.push_back({cls, cst, make_int4(i, ch, cg, 0)});
         }
         for (int c = 0; c < g.KK; ++c) P->pack_items.push_back(make_int2(i, c));
-        for (int k = 0; k < g.n_ll; ++k) P->combine_items.push_back(make_int2(i, k));
+        for (int k = 0; k < g.n_ll; ++k)
+            (f == FORM_FUSED ? combine_late : P->combine_items).push_back(make_int2(i, k));
         const int per = g.KK * g.LL * g.LL;
         for (int k = 0; k < (per + 255) / 256; ++k) P->reduce_items.push_back(make_int2(i, k));
     }
+    P->n_combine_early = (int)P->combine_items.size();
+    P->combine_items.insert(P->combine_items.end(), combine_late.begin(), combine_late.end());
     // items grouped by class (heaviest class first), largest items first within a class
     std::vector<double> class_cost(P->classes.size(), 0.0);
     for (auto& c : costs) class_cost[c.cls] += c.c;
@@ -509,7 +550,8 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision, srmr
     P->total = off;
     const int cus = device_cus();
     for (auto& C : P->classes) {
-        C.blocks1 = cus * occupancy(class_pass_fn(1, C.form, C.LL), C.lds1);
+        const void* f1 = class_pass_fn(1, C.form, C.LL);
+        C.blocks1 = f1 ? cus * occupancy(f1, C.lds1) : 0;
         C.blocks2 = cus * occupancy(class_pass_fn(2, C.form, C.LL), C.lds2);
     }
     *plan = P;
@@ -547,8 +589,12 @@ int srmra_plan_upload(srmra_plan* plan, void* workspace, size_t workspace_bytes,
     if (e == hipSuccess) e = hipStreamSynchronize(stream);   // host staging buffers are reused
     if (e != hipSuccess) return SRMRA_EDEVICE;
     for (auto& C : plan->classes) {
-        (void)hipFuncSetAttribute(class_pass_fn(1, C.form, C.LL), hipFuncAttributeMaxDynamicSharedMemorySize, (int)C.lds1);
-        (void)hipFuncSetAttribute(class_pass_fn(2, C.form, C.LL), hipFuncAttributeMaxDynamicSharedMemorySize, (int)C.lds2);
+        for (int pass = 1; pass <= 2; ++pass) {
+            const void* f = class_pass_fn(pass, C.form, C.LL);   // null: single-pass class, pass 1
+            if (f && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)(pass == 1 ? C.lds1 : C.lds2)) != hipSuccess)
+                return SRMRA_EDEVICE;
+        }
     }
     plan->uploaded = true;
     plan->uploaded_ws = workspace;
@@ -574,7 +620,8 @@ int srmra_plan_execute(srmra_plan* plan, void* workspace, size_t workspace_bytes
     L.reduce_items = (const int2*)(ws + plan->o_red);
     L.counters = (int*)(ws + plan->o_cnt);
     L.n_pack = (int)plan->pack_items.size();
-    L.n_combine = (int)plan->combine_items.size();
+    L.n_combine = plan->n_combine_early;
+    L.n_combine_late = (int)plan->combine_items.size() - plan->n_combine_early;
     L.n_reduce = (int)plan->reduce_items.size();
     L.n_inst = n;
     L.n_class = (int)plan->classes.size();

@@ -4,7 +4,9 @@
 
 namespace srmra {
 
-enum { FORM_VALU = 0, FORM_MFMA = 1, FORM_BF16 = 2 };
+// FORM_FUSED: FP32 MFMA single pass (no pass-1 launch; the log-likelihood
+// combine of these instances runs after pass 2)
+enum { FORM_VALU = 0, FORM_MFMA = 1, FORM_BF16 = 2, FORM_FUSED = 3 };
 
 struct InstDesc {
     StepArgs p;                  // per-instance step arguments (workspace pointers set)
@@ -35,10 +37,10 @@ struct BatchLaunch {
     const InstDesc* desc;        // device, n_inst entries
     const int4* pass_items;      // (instance, chunk, group, cost rank)
     const int2* pack_items;      // (instance, component)
-    const int2* combine_items;   // (instance, block)
+    const int2* combine_items;   // (instance, block): two-pass instances, then single-pass ones
     const int2* reduce_items;    // (instance, block)
     int* counters;               // 2 per class
-    int n_pack, n_combine, n_reduce, n_inst, n_class;
+    int n_pack, n_combine, n_combine_late, n_reduce, n_inst, n_class;
     ClassLaunch cls[kMaxClasses];
 };
 

@@ -71,7 +71,8 @@ __global__ __launch_bounds__(1024) void k_batch_finalize(const InstDesc* __restr
 // loop once the counter passes the item count (every wave reaches the exit).
 template <int PASS, int FORM, int LL>
 __global__ __launch_bounds__(256, ((PASS == 1 && FORM == FORM_BF16) ||
-                                   (PASS == 2 && FORM == FORM_MFMA && LL >= 16 && LL <= 32)) ? 2 : 1)
+                                   (PASS == 2 && FORM == FORM_MFMA && LL >= 16 && LL <= 32) ||
+                                   (PASS == 2 && FORM == FORM_FUSED && LL >= 16 && LL <= 24)) ? 2 : 1)
 void k_class_pass(const InstDesc* __restrict__ D,
                                                     const int4* __restrict__ items, int n_items,
                                                     int* __restrict__ counter) {
@@ -94,6 +95,8 @@ void k_class_pass(const InstDesc* __restrict__ D,
             q.yo = d.yo;
             if constexpr (PASS == 1) b16::bf16_pass1_body<LL>(d.p, q, w.y, w.z, lds);
             else b16::bf16_pass2_body<LL>(d.p, q, w.y, w.z, lds);
+        } else if constexpr (FORM == FORM_FUSED) {
+            mfma_fused_body<LL>(d.p, w.y, lds);
         } else if constexpr (FORM == FORM_MFMA) {
             if constexpr (PASS == 1) mfma_pass1_body<LL>(d.p, w.y, w.z, lds);
             else mfma_pass2_body<LL>(d.p, w.y, w.z, lds);
@@ -116,6 +119,10 @@ SRMRA_CLASS(FORM_MFMA, 24) SRMRA_CLASS(FORM_MFMA, 32) SRMRA_CLASS(FORM_MFMA, 48)
 SRMRA_CLASS(FORM_MFMA, 64)
 SRMRA_CLASS(FORM_BF16, 24) SRMRA_CLASS(FORM_BF16, 32)
 #undef SRMRA_CLASS
+#define SRMRA_FUSED(L) template __global__ void k_class_pass<2, FORM_FUSED, L>(const InstDesc*, const int4*, int, int*);
+SRMRA_FUSED(8) SRMRA_FUSED(12) SRMRA_FUSED(16) SRMRA_FUSED(24) SRMRA_FUSED(32) SRMRA_FUSED(48)
+SRMRA_FUSED(64)
+#undef SRMRA_FUSED
 
 // ---------------------------------------------------------------- host side
 const void* class_pass_fn(int pass, int form, int LL) {
@@ -129,6 +136,10 @@ const void* class_pass_fn(int pass, int form, int LL) {
     SRMRA_PICK(FORM_MFMA, 64)
     SRMRA_PICK(FORM_BF16, 24) SRMRA_PICK(FORM_BF16, 32)
 #undef SRMRA_PICK
+    // single pass: no pass-1 kernel
+#define SRMRA_PICK(L) if (form == FORM_FUSED && LL == L) return pass == 2 ? (const void*)k_class_pass<2, FORM_FUSED, L> : nullptr;
+    SRMRA_PICK(8) SRMRA_PICK(12) SRMRA_PICK(16) SRMRA_PICK(24) SRMRA_PICK(32) SRMRA_PICK(48) SRMRA_PICK(64)
+#undef SRMRA_PICK
     return nullptr;
 }
 
@@ -139,6 +150,7 @@ hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
     for (int pass = 1; pass <= 2; ++pass) {
         for (int k = 0; k < L.n_class; ++k) {
             const ClassLaunch& c = L.cls[k];
+            if (pass == 1 && c.form == FORM_FUSED) continue;
             const void* f = class_pass_fn(pass, c.form, c.LL);
             if (!f) return hipErrorInvalidValue;
             const InstDesc* desc = L.desc;
@@ -150,9 +162,12 @@ hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
                                                  pass == 1 ? c.lds1 : c.lds2, s);
             if (e != hipSuccess) return e;
         }
-        if (pass == 1)
+        if (pass == 1 && L.n_combine > 0)
             hipLaunchKernelGGL(k_batch_combine, dim3(L.n_combine), dim3(256), 0, s, L.desc, L.combine_items);
     }
+    if (L.n_combine_late > 0)
+        hipLaunchKernelGGL(k_batch_combine, dim3(L.n_combine_late), dim3(256), 0, s, L.desc,
+                           L.combine_items + L.n_combine);
     hipLaunchKernelGGL(k_batch_reduce, dim3(L.n_reduce), dim3(256), 0, s, L.desc, L.reduce_items);
     hipLaunchKernelGGL(k_batch_finalize, dim3(L.n_inst), dim3(1024), 0, s, L.desc);
     return hipGetLastError();

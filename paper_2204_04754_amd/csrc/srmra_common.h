@@ -62,6 +62,7 @@ struct StepArgs {
     int cpb;                 // components per block (component group size)
     int ntile;               // observations per block tile
     int64_t chunk_obs;       // observations per chunk (multiple of ntile)
+    int fuse_wc;             // FP32 MFMA single pass: component groups per block (0: two passes)
 };
 
 __device__ __forceinline__ float fast_exp(float v) { return __expf(v); }

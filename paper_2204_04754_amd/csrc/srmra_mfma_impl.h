@@ -55,12 +55,13 @@ __device__ __forceinline__ void load_x_group(const StepArgs& p, int cg, float* X
     }
 }
 
-// Load observations [o0, o0 + NT) into LDS rows of stride OS (zeros past N).
+// Load observations [o0, o0 + nt) into LDS rows of stride OS (zeros past N).
 template <int LL>
-__device__ __forceinline__ void load_y_tile(const StepArgs& p, int64_t o0, float* Ys) {
+__device__ __forceinline__ void load_y_tile(const StepArgs& p, int64_t o0, float* Ys,
+                                            int nt = Tile<LL>::NT) {
     using TL = Tile<LL>;
     constexpr int P4 = LL * LL / 4;
-    for (int e = threadIdx.x; e < TL::NT * P4; e += 256) {
+    for (int e = threadIdx.x; e < nt * P4; e += 256) {
         const int o = e / P4, q = e % P4;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (o0 + o < p.N) v = reinterpret_cast<const float4*>(p.y + (o0 + o) * (int64_t)(LL * LL))[q];
@@ -319,97 +320,83 @@ __device__ __forceinline__ void backproject(const float* Ys, const float* Ws, in
     }
 }
 
-template <int LL>
-__device__ __forceinline__ void mfma_pass2_body(const StepArgs& p, int chunk_i, int cg, float* lds) {
+// Back-projection of the wave's posterior tiles (acc holds w for every
+// (observation, component) slot of the wave; padding slots hold 0): w of one
+// component (or component pair for T=8) at a time goes to the wave's LDS tile
+// Ws, then into the running sums bacc[u].
+template <int LL, int NU>
+__device__ __forceinline__ void backproject_tiles(const float* Ys, float* Ws, int wobs,
+                                                  floatx16 (&acc)[2][2],
+                                                  float (&bacc)[NU][BP<LL>::NACC]) {
     using TL = Tile<LL>;
-    using B = BP<LL>;
-    float* Xs = lds;
-    float* Ys = Xs + TL::CPW * TL::XS;
-    float* Wall = Ys + TL::NT * TL::OS;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    float* Ws = Wall + wave * B::WS;
-    load_x_group<LL>(p, cg, Xs);
-    // number of back-projection "units": components (T>=16) or component pairs (T=8)
-    constexpr int NU = TL::T == 8 ? TL::CPW / 2 : TL::CPW;
-    float bacc[NU][B::NACC];
-    float cnt[2][B::NCNT];
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 31;
 #pragma unroll
-    for (int u = 0; u < NU; ++u)
-#pragma unroll
-        for (int k = 0; k < B::NACC; ++k) bacc[u][k] = 0.f;
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int k = 0; k < B::NCNT; ++k) cnt[cb][k] = 0.f;
-
-    const int64_t c0 = (int64_t)chunk_i * p.chunk_obs;
-    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    for (int64_t o0 = c0; o0 < c1; o0 += TL::NT) {
-        __syncthreads();
-        load_y_tile<LL>(p, o0, Ys);
-        __syncthreads();
-        const int wobs = wave * TL::OPW;
-        const int64_t wobs_g = o0 + wobs;
-        floatx16 acc[2][2];
-        score_tiles<LL>(Ys, Xs, wobs, acc);
-        float lse_o[TL::OPW];
-#pragma unroll
-        for (int k = 0; k < TL::OPW; ++k) lse_o[k] = (wobs_g + k < p.N) ? p.lse[wobs_g + k] : 0.f;
-        // w = exp(a - lse) in place; accumulate c
+    for (int u = 0; u < NU; ++u) {
+        // layout of Ws: [o][t2][t1] (T=8: [o][pair][t2][t1])
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
-                    int os;
-                    const float a = tile_logit<LL>(p, cg, wobs_g, rb, cb, v, acc[rb][cb][v], os);
-                    const float w = a > -INFINITY ? fast_exp(a - lse_o[os]) : 0.f;
-                    acc[rb][cb][v] = w;
-                    if constexpr (TL::T == 64) cnt[cb][rb * 16 + v] += w;
-                    else cnt[cb][v % B::NCNT] += w;
-                }
-        // back-projection, one component (or component pair for T=8) at a time
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            // write w of unit u to Ws: layout [o][t2][t1] (T=8: [o][pair][t2][t1])
-            const int j = lane & 31;
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                        int os, t2, cs, t1;
-                        Slots<LL>::row(rb, row, os, t2);
-                        Slots<LL>::col(cb, j, cs, t1);
-                        bool mine;
-                        int dst;
-                        if constexpr (TL::T == 64) {
-                            mine = true;
-                            dst = t2 * LL + t1;
-                        } else if constexpr (TL::T == 8) {
-                            mine = (cs >> 1) == u;
-                            dst = ((os * 2 + (cs & 1)) * LL + t2) * LL + t1;
-                        } else {
-                            mine = cs == u;
-                            dst = (os * LL + t2) * LL + t1;
-                        }
-                        if (mine && t1 < LL && t2 < LL) Ws[dst] = acc[rb][cb][v];
+                    const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    int os, t2, cs, t1;
+                    Slots<LL>::row(rb, row, os, t2);
+                    Slots<LL>::col(cb, j, cs, t1);
+                    bool mine;
+                    int dst;
+                    if constexpr (TL::T == 64) {
+                        mine = true;
+                        dst = t2 * LL + t1;
+                    } else if constexpr (TL::T == 8) {
+                        mine = (cs >> 1) == u;
+                        dst = ((os * 2 + (cs & 1)) * LL + t2) * LL + t1;
+                    } else {
+                        mine = cs == u;
+                        dst = (os * LL + t2) * LL + t1;
                     }
-            __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): W stores visible to the wave
-            __builtin_amdgcn_wave_barrier();
-            backproject<LL>(Ys, Ws, wobs, bacc[u]);
-            __builtin_amdgcn_wave_barrier();
-        }
+                    if (mine && t1 < LL && t2 < LL) Ws[dst] = acc[rb][cb][v];
+                }
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): W stores visible to the wave
+        __builtin_amdgcn_wave_barrier();
+        backproject<LL>(Ys, Ws, wobs, bacc[u]);
+        __builtin_amdgcn_wave_barrier();
     }
-    // ---- block reduction of c and b over the 4 waves, then one store per chunk
-    __syncthreads();
-    float* red = lds;   // reuse: 4 waves x (CPW*Ll*Ll) floats for c, then for b
-    const int64_t chunk = chunk_i;
+}
+
+// Posterior mass c of the wave's w tiles, accumulated per lane.
+template <int LL>
+__device__ __forceinline__ void count_tile(float (&cnt)[2][BP<LL>::NCNT], int rb, int cb, int v,
+                                           float w) {
+    using TL = Tile<LL>;
+    if constexpr (TL::T == 64) cnt[cb][rb * 16 + v] += w;
+    else cnt[cb][v % BP<LL>::NCNT] += w;
+}
+
+// Block reduction of c and b and one store per chunk.  The 4 waves form WO =
+// 4 / WC observation groups x WC component groups (wave = wo * WC + g); group g
+// of the block holds components (cg + g) * CPW + cs.  Sums over the WO waves of
+// a group run in a fixed order (pairwise for WO = 4).
+template <int LL, int NU>
+__device__ __forceinline__ void store_chunk_partials(const StepArgs& p, int64_t chunk, int cg,
+                                                     int WC, float* red,
+                                                     const float (&cnt)[2][BP<LL>::NCNT],
+                                                     const float (&bacc)[NU][BP<LL>::NACC]) {
+    using TL = Tile<LL>;
+    using B = BP<LL>;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     constexpr int PER = TL::CPW * LL * LL;
-    // c: map lane accumulators to (component slot, t1, t2)
+    const int WO = 4 / WC;
+    auto fold = [&](const float* r, int e) -> float {
+        const int g = e / PER, k = e % PER;
+        if (WO == 4)
+            return (r[(0 * WC + g) * PER + k] + r[(1 * WC + g) * PER + k]) +
+                   (r[(2 * WC + g) * PER + k] + r[(3 * WC + g) * PER + k]);
+        if (WO == 2) return r[g * PER + k] + r[(WC + g) * PER + k];
+        return r[g * PER + k];
+    };
+    __syncthreads();
     for (int e = threadIdx.x; e < 4 * PER; e += 256) red[e] = 0.f;
     __syncthreads();
     {
@@ -429,10 +416,9 @@ __device__ __forceinline__ void mfma_pass2_body(const StepArgs& p, int chunk_i, 
             }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < PER; e += 256) {
-        const int cs = e / (LL * LL);
-        const int c = cg * TL::CPW + cs;
-        const float s = (red[e] + red[PER + e]) + (red[2 * PER + e] + red[3 * PER + e]);
+    for (int e = threadIdx.x; e < WC * PER; e += 256) {
+        const int c = (cg + e / PER) * TL::CPW + (e % PER) / (LL * LL);
+        const float s = fold(red, e);
         if (c < p.KK) p.cpart[(chunk * p.KK + c) * (LL * LL) + (e % (LL * LL))] = s;
     }
     __syncthreads();
@@ -477,17 +463,208 @@ __device__ __forceinline__ void mfma_pass2_body(const StepArgs& p, int chunk_i, 
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < PER; e += 256) {
-        const int cs = e / (LL * LL);
-        const int c = cg * TL::CPW + cs;
-        const float s = (red[e] + red[PER + e]) + (red[2 * PER + e] + red[3 * PER + e]);
+    for (int e = threadIdx.x; e < WC * PER; e += 256) {
+        const int c = (cg + e / PER) * TL::CPW + (e % PER) / (LL * LL);
+        const float s = fold(red, e);
         if (c < p.KK) p.bpart[(chunk * p.KK + c) * (LL * LL) + (e % (LL * LL))] = s;
     }
+}
+
+template <int LL>
+__device__ __forceinline__ void mfma_pass2_body(const StepArgs& p, int chunk_i, int cg, float* lds) {
+    using TL = Tile<LL>;
+    using B = BP<LL>;
+    float* Xs = lds;
+    float* Ys = Xs + TL::CPW * TL::XS;
+    float* Wall = Ys + TL::NT * TL::OS;
+    const int wave = threadIdx.x >> 6;
+    float* Ws = Wall + wave * B::WS;
+    load_x_group<LL>(p, cg, Xs);
+    // number of back-projection "units": components (T>=16) or component pairs (T=8)
+    constexpr int NU = TL::T == 8 ? TL::CPW / 2 : TL::CPW;
+    float bacc[NU][B::NACC];
+    float cnt[2][B::NCNT];
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int k = 0; k < B::NACC; ++k) bacc[u][k] = 0.f;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int k = 0; k < B::NCNT; ++k) cnt[cb][k] = 0.f;
+
+    const int64_t c0 = (int64_t)chunk_i * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    for (int64_t o0 = c0; o0 < c1; o0 += TL::NT) {
+        __syncthreads();
+        load_y_tile<LL>(p, o0, Ys);
+        __syncthreads();
+        const int wobs = wave * TL::OPW;
+        const int64_t wobs_g = o0 + wobs;
+        floatx16 acc[2][2];
+        score_tiles<LL>(Ys, Xs, wobs, acc);
+        float lse_o[TL::OPW];
+#pragma unroll
+        for (int k = 0; k < TL::OPW; ++k) lse_o[k] = (wobs_g + k < p.N) ? p.lse[wobs_g + k] : 0.f;
+        // w = exp(a - lse) in place; accumulate c
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    int os;
+                    const float a = tile_logit<LL>(p, cg, wobs_g, rb, cb, v, acc[rb][cb][v], os);
+                    const float w = a > -INFINITY ? fast_exp(a - lse_o[os]) : 0.f;
+                    acc[rb][cb][v] = w;
+                    count_tile<LL>(cnt, rb, cb, v, w);
+                }
+        backproject_tiles<LL, NU>(Ys, Ws, wobs, acc, bacc);
+    }
+    store_chunk_partials<LL, NU>(p, chunk_i, cg, 1, lds, cnt, bacc);
+}
+
+// ============================================================================
+// Single pass (FP32 MFMA) for instances whose K^2 components fit in one block:
+// the 4 waves form WO = 4 / WC observation groups x WC component groups of CPW
+// components.  Every wave scores its observations against its group, reduces
+// (max, sum exp) per observation, and the WC waves of an observation group
+// combine these through LDS in a fixed order into the full log-sum-exp; the
+// posterior w = exp(a - max_wave) * exp(max_wave - lse) then feeds the same
+// back-projection as pass 2.  The score map is computed once per pair.  The
+// combined (max, sum) per observation is stored (n_part = 1) for the
+// log-likelihood reduction that follows.
+// grid = (n_chunks); block = 256.
+template <int LL>
+__device__ __forceinline__ void mfma_fused_body(const StepArgs& p, int chunk_i, float* lds) {
+    using TL = Tile<LL>;
+    using B = BP<LL>;
+    const int WC = p.fuse_wc, WO = 4 / WC;
+    const int ntf = WO * TL::OPW;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wc = wave % WC, wo = wave / WC;
+    float* Xs = lds;
+    float* Ys = Xs + WC * TL::CPW * TL::XS;
+    float* Wall = Ys + ntf * TL::OS;
+    float* Ws = Wall + wave * B::WS;
+    for (int g = 0; g < WC; ++g) load_x_group<LL>(p, g, Xs + g * TL::CPW * TL::XS);
+    const float* Xw = Xs + wc * TL::CPW * TL::XS;
+    const bool active = wc * TL::CPW < p.KK;   // a group past the last component only waits
+    constexpr int NU = TL::T == 8 ? TL::CPW / 2 : TL::CPW;
+    float bacc[NU][B::NACC];
+    float cnt[2][B::NCNT];
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+#pragma unroll
+        for (int k = 0; k < B::NACC; ++k) bacc[u][k] = 0.f;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int k = 0; k < B::NCNT; ++k) cnt[cb][k] = 0.f;
+
+    const int64_t c0 = (int64_t)chunk_i * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    for (int64_t o0 = c0; o0 < c1; o0 += ntf) {
+        __syncthreads();
+        load_y_tile<LL>(p, o0, Ys, ntf);
+        __syncthreads();
+        const int wobs = wo * TL::OPW;
+        const int64_t wobs_g = o0 + wobs;
+        floatx16 acc[2][2];
+        float mx[TL::OPW], sm[TL::OPW];
+#pragma unroll
+        for (int k = 0; k < TL::OPW; ++k) { mx[k] = -INFINITY; sm[k] = 0.f; }
+        if (active) {
+            score_tiles<LL>(Ys, Xw, wobs, acc);
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        int os;
+                        const float a = tile_logit<LL>(p, wc, wobs_g, rb, cb, v, acc[rb][cb][v], os);
+                        acc[rb][cb][v] = a;
+                        mx[os] = fmaxf(mx[os], a);
+                    }
+#pragma unroll
+            for (int k = 0; k < TL::OPW; ++k)
+                for (int off = 32; off > 0; off >>= 1) mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], off));
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        int os, t2;
+                        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                        Slots<LL>::row(rb, row, os, t2);
+                        const float a = acc[rb][cb][v];
+                        const float e = a > -INFINITY ? fast_exp(a - mx[os]) : 0.f;
+                        acc[rb][cb][v] = e;
+                        sm[os] += e;
+                    }
+#pragma unroll
+            for (int k = 0; k < TL::OPW; ++k)
+                for (int off = 32; off > 0; off >>= 1) sm[k] += __shfl_xor(sm[k], off);
+        }
+        // exchange (max, sum) between the component groups through the first
+        // 2*OPW floats of each wave's W tile (free until w is written below)
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < TL::OPW; ++k) { Ws[2 * k] = mx[k]; Ws[2 * k + 1] = sm[k]; }
+        }
+        __syncthreads();
+        float scale[TL::OPW];
+#pragma unroll
+        for (int k = 0; k < TL::OPW; ++k) {
+            float M = -INFINITY;
+            for (int g = 0; g < WC; ++g) M = fmaxf(M, Wall[(wo * WC + g) * B::WS + 2 * k]);
+            float S = 0.f;
+            for (int g = 0; g < WC; ++g) {
+                const float mg = Wall[(wo * WC + g) * B::WS + 2 * k];
+                const float sg = Wall[(wo * WC + g) * B::WS + 2 * k + 1];
+                if (mg > -INFINITY) S += sg * fast_exp(mg - M);
+            }
+            const bool valid = wobs_g + k < p.N && M > -INFINITY;
+            const float lse = M + __logf(S);
+            scale[k] = valid && mx[k] > -INFINITY ? fast_exp(mx[k] - lse) : 0.f;
+            if (valid && wc == 0 && lane == 0) p.part[wobs_g + k] = make_float2(M, S);
+        }
+        __syncthreads();   // every wave has read the exchange before W is overwritten
+        if (active) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        int os, t2;
+                        const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                        Slots<LL>::row(rb, row, os, t2);
+                        const float w = acc[rb][cb][v] * scale[os];
+                        acc[rb][cb][v] = w;
+                        count_tile<LL>(cnt, rb, cb, v, w);
+                    }
+            backproject_tiles<LL, NU>(Ys, Ws, wobs, acc, bacc);
+        }
+    }
+    store_chunk_partials<LL, NU>(p, chunk_i, 0, WC, lds, cnt, bacc);
 }
 
 template <int LL> constexpr size_t lds_score_mfma() {
     using TL = Tile<LL>;
     return sizeof(float) * (size_t)(TL::CPW * TL::XS + TL::NT * TL::OS);
+}
+// LDS of the single pass with WC component groups per block (0 if WC is not
+// 1, 2 or 4)
+template <int LL> constexpr size_t lds_fused_mfma(int WC) {
+    using TL = Tile<LL>;
+    if (WC != 1 && WC != 2 && WC != 4) return 0;
+    size_t a = sizeof(float) * ((size_t)WC * TL::CPW * TL::XS + (size_t)(4 / WC) * TL::OPW * TL::OS +
+                                4 * (size_t)BP<LL>::WS);
+    size_t r = sizeof(float) * (size_t)(4 * TL::CPW * LL * LL);
+    return a > r ? a : r;
 }
 template <int LL> constexpr size_t lds_backproject_mfma() {
     using TL = Tile<LL>;

@@ -40,6 +40,9 @@ def test_small_workload_trajectory(prec):
 SHAPES = [  # (Lh, K, N): every supported L_low, ragged N
     (16, 2, 37), (32, 4, 53), (24, 2, 45), (48, 4, 21), (32, 2, 29), (48, 2, 19),
     (64, 2, 17), (96, 2, 6), (128, 2, 3), (64, 4, 11), (96, 4, 7), (96, 3, 5), (256, 4, 3),
+    # FP32 MFMA single pass with 3 component groups rounded up to 4 (one idle
+    # wave group), and K = 1 (one component, the other slot masked)
+    (36, 3, 23), (48, 3, 13), (32, 1, 7),
 ]
 
 
@@ -61,6 +64,16 @@ def test_shapes(prec, Lh, K, N):
     check_step(inst.y, inst.x0, lr, inst.sigma, K, g, ref)
     assert rel(g["c"], ref["c"]) < 1e-4
     assert rel(g["b"], ref["b"]) < 1e-4
+
+
+def test_single_pass_covers_expected_shapes():
+    """The FP32 MFMA form makes one pass where every component group of an
+    observation fits one workgroup; these shapes exercise 1, 2 and 4 groups
+    per workgroup and the two-pass fallback."""
+    from paper_2204_04754_amd import binding as B
+    passes = {(Lh, K): B.srmra_em_step_passes(N, Lh // K, K, "fp32_mfma") for Lh, K, N in SHAPES}
+    assert passes[(64, 2)] == 1 and passes[(48, 3)] == 1 and passes[(96, 2)] == 1
+    assert passes[(96, 3)] == 2 and passes[(128, 2)] == 2 and passes[(96, 4)] == 2
 
 
 @pytest.mark.parametrize("prec", PRECS)
