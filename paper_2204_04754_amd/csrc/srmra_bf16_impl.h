@@ -137,10 +137,18 @@ __device__ __forceinline__ void score(const StepArgs& p, const __bf16* ys, const
     for (int o = 0; o < NO; ++o)
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[o][c] = floatx16{0};
-    // B fragments of this lane for every component: xb[c][ks][plane][lane]
+    // B fragments of this lane for every component: xb[c][ks][plane][lane].
+    // Double-buffered in registers: the fragments of k-step ks + 1 are requested
+    // before the MFMAs of k-step ks, so their L2 latency overlaps a whole k-step.
     const uint4* bsrc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) bsrc[c] = p.xb + (int64_t)cgl[c] * nk<LL>() * 128 + lane;
+    bf16x8 bh[NC], bl[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        bh[c] = __builtin_bit_cast(bf16x8, bsrc[c][0]);
+        bl[c] = __builtin_bit_cast(bf16x8, bsrc[c][64]);
+    }
     for (int b2 = 0; b2 < LL; ++b2) {
         int col = b2 + t2e;
         col = col >= LL ? col - LL : col;
@@ -150,12 +158,16 @@ __device__ __forceinline__ void score(const StepArgs& p, const __bf16* ys, const
 #pragma unroll
         for (int j = 0; j < JS; ++j) {
             const int ks = b2 * JS + j;
-            bf16x8 bh[NC], bl[NC];
+            const int kn = ks + 1 < nk<LL>() ? ks + 1 : ks;   // the last step re-reads its own
+            bf16x8 nh[NC], nl[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                bh[c] = __builtin_bit_cast(bf16x8, bsrc[c][ks * 128]);
-                bl[c] = __builtin_bit_cast(bf16x8, bsrc[c][ks * 128 + 64]);
+                nh[c] = __builtin_bit_cast(bf16x8, bsrc[c][kn * 128]);
+                nl[c] = __builtin_bit_cast(bf16x8, bsrc[c][kn * 128 + 64]);
             }
+            // compiler-only barrier: keeps the requests here instead of letting the
+            // compiler re-issue them next to their use (no instruction, no wait)
+            asm volatile("" ::: "memory");
             bf16x8 ah[NO], al[NO];
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
@@ -179,6 +191,11 @@ __device__ __forceinline__ void score(const StepArgs& p, const __bf16* ys, const
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
                     acc[o][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o], bh[c], acc[o][c], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                bh[c] = nh[c];
+                bl[c] = nl[c];
+            }
         }
     }
 }
