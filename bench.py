@@ -37,6 +37,7 @@ PEAK = {  # MI355X published dense peaks
     "bf16_split3": ("mfma", 2516.6e12),
 }
 KNAME = {"fp32_mfma": "mfma", "fp32_plain": "valu", "bf16_split3": "bf16"}
+HBM_PEAK = 8.0e12   # B/s
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE, keyed by (workload, precision, kernel); absent (null) until the
 # counters are taken for the current kernel version.
@@ -95,6 +96,19 @@ def run_form(inst, precision, steps, warmup):
                                      job.log_rho[b], job.loglik, job.precision, job.workspace)
         job.cur = b
 
+    # a0: the per-job preparation, re-run on the resident stack (HBM-bound; its
+    # algorithmic bytes are one read of y plus the prepared buffer written)
+    pe = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    prep_ms = []
+    for _ in range(3):
+        pe[0].record()
+        B.srmra_prepare_observations(job.y, job.N, job.Ll, job.K, job.precision, job.prep)
+        pe[1].record()
+        torch.cuda.synchronize()
+        prep_ms.append(pe[0].elapsed_time(pe[1]))
+    prep_bytes = 4.0 * job.N * job.Ll * job.Ll + B.srmra_prepared_bytes(job.N, job.Ll, job.K, job.precision)
+    prep = dict(ms=min(prep_ms), bytes=prep_bytes, gb_per_s=prep_bytes / (min(prep_ms) * 1e-3) / 1e9,
+                hbm_frac=prep_bytes / (min(prep_ms) * 1e-3) / HBM_PEAK)
     for _ in range(warmup):
         one(False)
     torch.cuda.synchronize()
@@ -119,7 +133,7 @@ def run_form(inst, precision, steps, warmup):
         acc += [evs[k].elapsed_time(evs[k + 1]) for k in range(5)]
     phase = acc / n_prof
     ll = float(job.loglik.item())
-    return dict(ms_per_step=total_ms / steps, phase_ms=phase.tolist(), loglik=ll, job=job)
+    return dict(ms_per_step=total_ms / steps, phase_ms=phase.tolist(), loglik=ll, job=job, prep=prep)
 
 
 def oracle_sample_size(inst, seconds):
@@ -282,7 +296,7 @@ def main():
     pairs = inst.pairs_per_step
     value = pairs / (main_r["ms_per_step"] * 1e-3)
     forms = {args.precision: dict(pairs_per_s=value, ms_per_step=main_r["ms_per_step"],
-                                  phase_ms=main_r["phase_ms"])}
+                                  phase_ms=main_r["phase_ms"], obs_prep=main_r["prep"])}
     del main_r["job"]
     if not args.no_plain and args.baseline_precision != args.precision:
         base_steps = max(2, args.steps // 4)
@@ -290,7 +304,7 @@ def main():
         del br["job"]
         forms[args.baseline_precision] = dict(
             pairs_per_s=pairs / (br["ms_per_step"] * 1e-3), ms_per_step=br["ms_per_step"],
-            phase_ms=br["phase_ms"])
+            phase_ms=br["phase_ms"], obs_prep=br["prep"])
         print(f"[bench] {args.baseline_precision}: {br['ms_per_step']:.2f} ms/step",
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()

@@ -33,7 +33,8 @@ bool valu_geom(int LL, int KK, int& cpb, int& nt, size_t& lds1, size_t& lds2, co
 bool bf16_geom(int LL, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
                const void*& f2);
 hipError_t launch_bf16(int LL, int pass, const StepArgs& p, const void* prep_extra, hipStream_t s);
-hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, void* prep_extra, hipStream_t s);
+hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, double* ynorm, void* prep_extra,
+                            hipStream_t s);
 size_t bf16_prepared_extra(int LL, int64_t N);
 size_t bf16_xb_bytes(int LL, int KK);
 hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, hipStream_t s);
@@ -289,14 +290,15 @@ size_t srmra_prepared_bytes(int64_t N, int L_low, int K, int precision) {
     return g.prep_bytes;
 }
 
+// a0: squared norms (and for the BF16 form its operand planes, in the same
+// read of y)
 static int enqueue_prepare(const Geom& g, const float* y, char* prep, hipStream_t stream) {
+    if (g.prec == SRMRA_BF16_SPLIT3)
+        return launch_prep_bf16(g.LL, y, g.N, (double*)prep, prep + g.prep_extra_off, stream) == hipSuccess
+                   ? SRMRA_OK : SRMRA_EDEVICE;
     hipLaunchKernelGGL(k_obs_norms, dim3((unsigned)((g.N + 3) / 4)), dim3(256), 0, stream, y, g.N,
                        g.LL * g.LL, (double*)prep);
-    if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
-    if (g.prec == SRMRA_BF16_SPLIT3 &&
-        launch_prep_bf16(g.LL, y, g.N, prep + g.prep_extra_off, stream) != hipSuccess)
-        return SRMRA_EDEVICE;
-    return SRMRA_OK;
+    return hipGetLastError() == hipSuccess ? SRMRA_OK : SRMRA_EDEVICE;
 }
 
 int srmra_prepare_observations(const float* y, int64_t N, int L_low, int K, int precision,

@@ -11,14 +11,21 @@ namespace srmra {
 // eq. likelihood_EM).
 __device__ __forceinline__ void obs_norms_body(const float* __restrict__ y, int64_t N, int npix,
                                                double* __restrict__ ynorm, int64_t blk) {
+    // one wave per observation; lane l adds pixels 4(l + 64k) .. 4(l + 64k) + 3
+    // in that order, then a fixed butterfly (the BF16 preparation kernel uses
+    // the same order, so every form sees the same norms)
     const int lane = threadIdx.x & 63;
     const int64_t i = blk * 4 + (threadIdx.x >> 6);
     if (i >= N) return;
-    const float* yi = y + i * (int64_t)npix;
+    const float4* yi = reinterpret_cast<const float4*>(y + i * (int64_t)npix);
     double acc = 0.0;
-    for (int p = lane; p < npix; p += 64) {
-        double v = (double)yi[p];
-        acc += v * v;
+#pragma unroll 4
+    for (int p = lane; p < npix / 4; p += 64) {
+        const float4 v = yi[p];
+        acc += (double)v.x * v.x;
+        acc += (double)v.y * v.y;
+        acc += (double)v.z * v.z;
+        acc += (double)v.w * v.w;
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) ynorm[i] = acc;

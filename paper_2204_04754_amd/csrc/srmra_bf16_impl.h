@@ -376,36 +376,73 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
     }
 }
 
-// ---- per-job preparation: BF16 hi/lo planes of y in both layouts
+// ---- per-job preparation: BF16 hi/lo planes of y in both layouts, and the
+// FP64 squared norms.  One block per group of 8 observations: the group is
+// staged in LDS with coalesced 16-byte reads, then every 16-byte output run
+// (8 BF16 values of one plane) is assembled in registers and stored whole.
 template <int LL>
 __global__ __launch_bounds__(256) void k_prep_bf16(const float* __restrict__ y, int64_t N,
-                                                   __bf16* __restrict__ yT, __bf16* __restrict__ yo) {
-    // one block per group of 8 observations
+                                                   __bf16* __restrict__ yT, __bf16* __restrict__ yo,
+                                                   double* __restrict__ ynorm) {
+    constexpr int SP = LL + 1;                     // LDS row pitch (floats)
+    __shared__ float s[8 * LL * SP];               // [o][r1][r2]
     const int64_t grp = blockIdx.x;
-    for (int e = threadIdx.x; e < 8 * LL * LL; e += 256) {
-        const int o = e / (LL * LL), r = e % (LL * LL);
-        const int r1 = r / LL, r2 = r % LL;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int P4 = LL * LL / 4;
+    for (int e = threadIdx.x; e < 8 * P4; e += 256) {
+        const int o = e / P4, q = e % P4;
         const int64_t oi = grp * 8 + o;
-        const float v = oi < N ? y[oi * (LL * LL) + r] : 0.f;
-        const __bf16 h = (__bf16)v;
-        const __bf16 l = (__bf16)(v - (float)h);
-        if (oi < N) {
-            __bf16* t = yT + oi * (int64_t)(2 * LL * R1P);
-            t[r2 * R1P + r1] = h;
-            t[LL * R1P + r2 * R1P + r1] = l;
-        }
-        __bf16* g = yo + grp * (int64_t)(2 * LL * LL * 8);
-        g[(r1 * LL + r2) * 8 + o] = h;
-        g[LL * LL * 8 + (r1 * LL + r2) * 8 + o] = l;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (oi < N) v = reinterpret_cast<const float4*>(y + oi * (int64_t)(LL * LL))[q];
+        const int r1 = (4 * q) / LL, r2 = (4 * q) % LL;
+        float* d = s + (o * LL + r1) * SP + r2;
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
     }
-    // zero padding of yT rows past Ll
-    if (R1P > LL) {
-        for (int e = threadIdx.x; e < 8 * 2 * LL * (R1P - LL); e += 256) {
-            const int o = e / (2 * LL * (R1P - LL)), r = e % (2 * LL * (R1P - LL));
-            const int row = r / (R1P - LL), k = LL + r % (R1P - LL);
-            const int64_t oi = grp * 8 + o;
-            if (oi < N) yT[oi * (int64_t)(2 * LL * R1P) + row * R1P + k] = (__bf16)0.f;
+    __syncthreads();
+    // squared norms, same order as obs_norms_body: wave w handles observations 2w, 2w+1
+    for (int k = 0; k < 2; ++k) {
+        const int o = 2 * wave + k;
+        const int64_t oi = grp * 8 + o;
+        double acc = 0.0;
+        for (int p = lane; p < P4; p += 64) {
+            const int r1 = (4 * p) / LL, r2 = (4 * p) % LL;
+            const float* d = s + (o * LL + r1) * SP + r2;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc += (double)d[e] * d[e];
         }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0 && oi < N) ynorm[oi] = acc;
+    }
+    // yT[o][plane][r2][r1]: runs of 8 consecutive r1 (zeros past Ll)
+    constexpr int JR = R1P / 8;
+    for (int e = threadIdx.x; e < 8 * LL * JR; e += 256) {
+        const int o = e / (LL * JR), r = e % (LL * JR);
+        const int r2 = r / JR, jb = r % JR;
+        const int64_t oi = grp * 8 + o;
+        if (oi >= N) continue;
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int r1 = 8 * jb + k;
+            v[k] = r1 < LL ? s[(o * LL + r1) * SP + r2] : 0.f;
+        }
+        bf16x8 h, l;
+        split8(v, h, l);
+        uint4* t = reinterpret_cast<uint4*>(yT + oi * (int64_t)(2 * LL * R1P));
+        t[r2 * JR + jb] = __builtin_bit_cast(uint4, h);
+        t[LL * JR + r2 * JR + jb] = __builtin_bit_cast(uint4, l);
+    }
+    // Yo[plane][r1][r2][o]: runs of the 8 observations (zeros past N)
+    uint4* g = reinterpret_cast<uint4*>(yo + grp * (int64_t)(2 * LL * LL * 8));
+    for (int e = threadIdx.x; e < LL * LL; e += 256) {
+        const int r1 = e / LL, r2 = e % LL;
+        float v[8];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) v[o] = s[(o * LL + r1) * SP + r2];
+        bf16x8 h, l;
+        split8(v, h, l);
+        g[e] = __builtin_bit_cast(uint4, h);
+        g[LL * LL + e] = __builtin_bit_cast(uint4, l);
     }
 }
 
