@@ -38,10 +38,30 @@ PEAK = {  # MI355X published dense peaks
 }
 KNAME = {"fp32_mfma": "mfma", "fp32_plain": "valu", "bf16_split3": "bf16"}
 HBM_PEAK = 8.0e12   # B/s
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, keyed by (workload, precision, kernel); absent (null) until the
-# counters are taken for the current kernel version.
-TRAFFIC = {}
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x 2.0)
+# and WRITE_SIZE (x 1.0), keyed by (workload, precision, kernel), with a hash of
+# the kernel's sources at the time the counters were taken: a changed kernel
+# reports null until its counters are taken again.
+_MFMA_SRC = ("srmra_common.h", "srmra_mfma_impl.h", "srmra_mfma.hip")
+_BF16_SRC = ("srmra_common.h", "srmra_bf16_impl.h", "srmra_bf16.hip")
+TRAFFIC = {
+    ("lh64_k2_n100000", "fp32_mfma", "k_fused_mfma<32>"):
+        dict(bytes=428045926, src=_MFMA_SRC, sha="49c5338c148a502a"),
+    ("lh128_k4_n200000_s0.5", "bf16_split3", "k_backproject_bf16<32>"):
+        dict(bytes=1666526822, src=_BF16_SRC, sha="ba5560ac91e34097"),
+}
+
+
+def traffic_bytes(key):
+    import hashlib
+    e = TRAFFIC.get(key)
+    if e is None:
+        return None
+    m = hashlib.sha256()
+    for f in e["src"]:
+        with open(os.path.join(ROOT, "paper_2204_04754_amd", "csrc", f), "rb") as fh:
+            m.update(fh.read())
+    return e["bytes"] if m.hexdigest()[:16] == e["sha"] else None
 
 
 def parse():
@@ -330,7 +350,7 @@ def main():
         issued_flop = 4.0 * Ll2 * pairs * prod
     achieved = alg_flop / (k_ms * 1e-3)
     roof = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": TRAFFIC.get((args.workload, args.precision, kname)),
+            "frac": achieved / peak, "traffic": traffic_bytes((args.workload, args.precision, kname)),
             "kernel": kname, "kernel_ms": k_ms, "passes": n_pass,
             "issued_frac": issued_flop / (k_ms * 1e-3) / peak}
     if n_pass == 2:
