@@ -202,6 +202,36 @@ int srmra_plan_form(int precision, int L_low);
 int srmra_plan_create(const srmra_problem* probs, int count, int precision,
                       srmra_plan** plan, size_t* workspace_bytes);
 
+/* One entry of a tuning table for srmra_plan_create_tuned (the project's
+ * autotuner, paper_2204_04754_amd/autotune.py, measures and writes these).
+ * Problems with this (L_low, K) in a plan of precision `precision` run in
+ * precision `form` -- the plan's own precision, or SRMRA_FP32_MFMA in a
+ * SRMRA_BF16_SPLIT3 plan -- with `item_obs` observations per work item
+ * (rounded up to the form's observation tile; 0 keeps the default of about
+ * 2^28 multiply-adds per item).  Entries of another precision are ignored;
+ * the first matching entry wins.  A problem's result depends on its own
+ * entry only (form and partition), never on the rest of the plan. */
+typedef struct srmra_tuning {
+    int precision;
+    int L_low, K;
+    int form;
+    int64_t item_obs;
+} srmra_tuning;
+
+/* srmra_plan_create with a tuning table (`table` may be NULL when n_table is
+ * 0, which is srmra_plan_create).  SRMRA_EINVAL for a negative item_obs or a
+ * form the plan's precision does not allow; SRMRA_EUNSUPPORTED for a BF16
+ * entry at an L_low without a BF16 kernel.  The prepared buffer of every
+ * problem must suit the form it runs in (a SRMRA_BF16_SPLIT3 preparation also
+ * serves SRMRA_FP32_MFMA). */
+int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision,
+                            const srmra_tuning* table, int n_table,
+                            srmra_plan** plan, size_t* workspace_bytes);
+
+/* Default observations per work item of a problem run in `form_precision`
+ * (the base the autotuner scales); negative srmra_status on error. */
+int64_t srmra_plan_default_item_obs(int64_t N, int L_low, int K, int form_precision);
+
 /* Replace the iterate pointers of problem `index` (shape fields unchanged);
  * resets the ping-pong parity and requires a new upload. */
 int srmra_plan_set_iterate(srmra_plan* plan, int index, const float* x,

@@ -1,0 +1,100 @@
+"""Autotuner of the batched form.
+
+For every (L_low, K) class of a batch it times candidate settings of the plan's
+tuning table (srmra_tuning in the C ABI) on the class's own problems and keeps
+the fastest:
+
+* the form: in a BF16 split plan, the BF16 kernels or FP32 MFMA (both meet the
+  accuracy target; which is faster depends on the shape), otherwise the plan's
+  own precision;
+* observations per work item, as multiples of the library's default (about
+  2^28 multiply-adds per item): smaller items balance the persistent launch
+  better, larger ones write fewer per-chunk partials.
+
+Timing runs one EM step of the class alone per candidate, on scratch copies of
+the iterates (the problems' own iterates are left unchanged), with HIP events
+on the stream.  Marshalling and timing only: every step runs the library's
+kernels.
+"""
+from __future__ import annotations
+
+from collections import OrderedDict
+from typing import Dict, List, Sequence, Tuple
+
+import torch
+
+from . import binding as B
+
+SCALES = (0.25, 0.5, 1.0, 2.0, 4.0)
+
+
+def candidate_forms(precision: int, L_low: int) -> List[int]:
+    base = B.srmra_plan_form(precision, L_low)
+    if base < 0:
+        raise B.SrmraError(B.SRMRA_EUNSUPPORTED, "autotune")
+    if base == B.SRMRA_BF16_SPLIT3:
+        return [B.SRMRA_BF16_SPLIT3, B.SRMRA_FP32_MFMA]
+    return [base]
+
+
+def _scratch(pr: dict) -> dict:
+    """The problem with its own observations and preparation but fresh iterate
+    buffers (copies of the current iterate)."""
+    d = dict(pr)
+    d["x"] = pr["x"].clone()
+    d["log_rho"] = pr["log_rho"].clone()
+    d["x_new"] = torch.empty_like(pr["x"])
+    d["log_rho_new"] = torch.empty_like(pr["log_rho"])
+    d["rho_new"] = torch.empty_like(pr["rho_new"])
+    d["loglik"] = torch.empty_like(pr["loglik"])
+    return d
+
+
+def _time_plan(problems, precision, entry, reps, warmup, stream) -> float:
+    plan = B.Plan(problems, precision, tuning=[entry])
+    ws = B.empty_bytes(plan.workspace_bytes, problems[0]["y"].device)
+    plan.upload(ws, stream)
+    for _ in range(warmup):
+        plan.execute(ws, stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    s = stream if stream is not None else torch.cuda.current_stream()
+    ev[0].record(s)
+    for _ in range(reps):
+        plan.execute(ws, stream)
+    ev[1].record(s)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    plan.close()
+    return ms
+
+
+def tune(problems: Sequence[dict], precision, scales=SCALES, reps: int = 3, warmup: int = 1,
+         stream=None) -> Tuple[List[dict], List[dict]]:
+    """problems: the batch (dicts with y, prep, N, L_low, K, sigma, x, log_rho,
+    rho_new, loglik, as for binding.Plan); every prepared buffer must suit each
+    candidate form (a BF16 preparation also serves FP32 MFMA).
+    Returns (table, report): one srmra_tuning entry per class, and every timing."""
+    p = B._prec(precision)
+    groups: Dict[Tuple[int, int], List[int]] = OrderedDict()
+    for i, pr in enumerate(problems):
+        groups.setdefault((int(pr["L_low"]), int(pr["K"])), []).append(i)
+    table, report = [], []
+    for (Ll, K), idx in groups.items():
+        scratch = [_scratch(problems[i]) for i in idx]
+        n_max = max(int(problems[i]["N"]) for i in idx)
+        best = None
+        for form in candidate_forms(p, Ll):
+            base = B.srmra_plan_default_item_obs(n_max, Ll, K, form)
+            seen = set()
+            for sc in scales:
+                item = max(1, int(round(base * sc)))
+                if item in seen:
+                    continue
+                seen.add(item)
+                entry = dict(precision=p, L_low=Ll, K=K, form=form, item_obs=item)
+                ms = _time_plan(scratch, p, entry, reps, warmup, stream)
+                report.append(dict(entry, ms=ms, problems=len(idx)))
+                if best is None or ms < best[0]:
+                    best = (ms, entry)
+        table.append(best[1])
+    return table, report

@@ -14,9 +14,10 @@ from . import binding as B
 
 class BatchedEM:
     def __init__(self, instances: Sequence[dict], precision="fp32_mfma", device="cuda",
-                 stream=None):
+                 stream=None, tuning=None):
         """instances: dicts with y [N][Ll][Ll], K, sigma, x0 [Lh][Lh], log_rho0 [2][Lh]
-        (NumPy or torch)."""
+        (NumPy or torch).  tuning: None (library defaults), a list of
+        srmra_tuning entries, or "auto" (run the autotuner on this batch)."""
         self.device = torch.device(device)
         self.precision = B._prec(precision)
         self.stream = stream
@@ -43,7 +44,17 @@ class BatchedEM:
                      rho_new=torch.empty((2, Lh), **f),
                      loglik=torch.empty(1, dtype=torch.float64, device=self.device))
             self.inst.append(e)
-        self.plan = B.Plan(self.inst, self.precision)
+        self.tuning, self.tune_report, self.tune_seconds = None, [], 0.0
+        if tuning == "auto":
+            import time
+
+            from .autotune import tune
+            t0 = time.perf_counter()
+            self.tuning, self.tune_report = tune(self.inst, self.precision, stream=stream)
+            self.tune_seconds = time.perf_counter() - t0
+        elif tuning:
+            self.tuning = list(tuning)
+        self.plan = B.Plan(self.inst, self.precision, tuning=self.tuning)
         self.workspace = B.empty_bytes(self.plan.workspace_bytes, self.device)
         self.plan.upload(self.workspace, stream)
         self.executions = 0

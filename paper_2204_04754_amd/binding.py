@@ -23,9 +23,9 @@ SRMRA_EUNSUPPORTED = -2
 SRMRA_EWORKSPACE = -3
 SRMRA_EDEVICE = -4
 
-FP32_PLAIN = 0
-FP32_MFMA = 1
-BF16_SPLIT3 = 2
+SRMRA_FP32_PLAIN = FP32_PLAIN = 0
+SRMRA_FP32_MFMA = FP32_MFMA = 1
+SRMRA_BF16_SPLIT3 = BF16_SPLIT3 = 2
 PRECISIONS = {"fp32_plain": FP32_PLAIN, "fp32_mfma": FP32_MFMA, "bf16_split3": BF16_SPLIT3}
 
 _lib = None
@@ -50,6 +50,11 @@ class srmra_problem(ctypes.Structure):
         ("K", _int), ("x", _vp), ("log_rho", _vp), ("sigma", _f), ("x_new", _vp),
         ("rho_new", _vp), ("log_rho_new", _vp), ("loglik", _vp),
     ]
+
+
+class srmra_tuning(ctypes.Structure):
+    _fields_ = [("precision", _int), ("L_low", _int), ("K", _int), ("form", _int),
+                ("item_obs", _i64)]
 
 
 def lib():
@@ -93,6 +98,12 @@ def lib():
             L.srmra_plan_create.restype = _int
             L.srmra_plan_create.argtypes = [ctypes.POINTER(srmra_problem), _int, _int,
                                             ctypes.POINTER(_vp), ctypes.POINTER(_sz)]
+            L.srmra_plan_create_tuned.restype = _int
+            L.srmra_plan_create_tuned.argtypes = [ctypes.POINTER(srmra_problem), _int, _int,
+                                                  ctypes.POINTER(srmra_tuning), _int,
+                                                  ctypes.POINTER(_vp), ctypes.POINTER(_sz)]
+            L.srmra_plan_default_item_obs.restype = _i64
+            L.srmra_plan_default_item_obs.argtypes = [_i64, _int, _int, _int]
             L.srmra_plan_set_iterate.restype = _int
             L.srmra_plan_set_iterate.argtypes = [_vp, _int, _vp, _vp, _vp, _vp, _vp]
             L.srmra_plan_upload.restype = _int
@@ -221,7 +232,8 @@ def srmra_plan_form(precision, L_low: int) -> int:
 class Plan:
     """Owner of an srmra_plan* (host object) plus the problem structs."""
 
-    def __init__(self, problems: Sequence[dict], precision):
+    def __init__(self, problems: Sequence[dict], precision, tuning: Optional[Sequence[dict]] = None):
+        """tuning: entries {precision, L_low, K, form, item_obs} (srmra_tuning)."""
         arr = (srmra_problem * len(problems))()
         for k, pr in enumerate(problems):
             s = arr[k]
@@ -238,8 +250,18 @@ class Plan:
             s.loglik = _ptr(pr["loglik"], torch.float64)
         h = _vp()
         ws = _sz()
-        _check(lib().srmra_plan_create(arr, len(problems), _prec(precision), ctypes.byref(h),
-                                       ctypes.byref(ws)), "srmra_plan_create")
+        if tuning:
+            tab = (srmra_tuning * len(tuning))()
+            for k, t in enumerate(tuning):
+                tab[k].precision = _prec(t["precision"])
+                tab[k].L_low = int(t["L_low"]); tab[k].K = int(t["K"])
+                tab[k].form = _prec(t["form"]); tab[k].item_obs = int(t["item_obs"])
+            _check(lib().srmra_plan_create_tuned(arr, len(problems), _prec(precision), tab,
+                                                 len(tuning), ctypes.byref(h), ctypes.byref(ws)),
+                   "srmra_plan_create_tuned")
+        else:
+            _check(lib().srmra_plan_create(arr, len(problems), _prec(precision), ctypes.byref(h),
+                                           ctypes.byref(ws)), "srmra_plan_create")
         self._h = h
         self.workspace_bytes = int(ws.value)
 
@@ -271,6 +293,12 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def srmra_plan_default_item_obs(N: int, L_low: int, K: int, form_precision) -> int:
+    r = int(lib().srmra_plan_default_item_obs(N, L_low, K, _prec(form_precision)))
+    _check(r if r < 0 else 0, "srmra_plan_default_item_obs")
+    return r
 
 
 def empty_bytes(nbytes: int, device="cuda") -> torch.Tensor:

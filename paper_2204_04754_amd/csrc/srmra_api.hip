@@ -459,13 +459,39 @@ int srmra_plan_form(int precision, int L_low) {
     return f == FORM_BF16 ? SRMRA_BF16_SPLIT3 : (f == FORM_MFMA ? SRMRA_FP32_MFMA : SRMRA_FP32_PLAIN);
 }
 
+int64_t srmra_plan_default_item_obs(int64_t N, int L_low, int K, int form_precision) {
+    Geom g;
+    const int st = make_geom(N, L_low, K, form_precision, false, g);
+    if (st != SRMRA_OK) return st;
+    return default_chunk(g);
+}
+
 int srmra_plan_create(const srmra_problem* probs, int count, int precision, srmra_plan** plan,
                       size_t* workspace_bytes) {
+    return srmra_plan_create_tuned(probs, count, precision, nullptr, 0, plan, workspace_bytes);
+}
+
+int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision,
+                            const srmra_tuning* table, int n_table, srmra_plan** plan,
+                            size_t* workspace_bytes) {
     if (!plan || !workspace_bytes || !probs || count < 1 || count > 65535) return SRMRA_EINVAL;
+    if (n_table < 0 || (n_table > 0 && !table)) return SRMRA_EINVAL;
     *plan = nullptr;
     *workspace_bytes = 0;
     if (precision != SRMRA_FP32_PLAIN && precision != SRMRA_FP32_MFMA && precision != SRMRA_BF16_SPLIT3)
         return SRMRA_EUNSUPPORTED;
+    // a table entry may only keep the plan's precision or, in a BF16 plan, pick
+    // FP32 MFMA (more accurate); the BF16 form needs an L_low it is built for
+    for (int k = 0; k < n_table; ++k) {
+        const srmra_tuning& t = table[k];
+        if (t.item_obs < 0) return SRMRA_EINVAL;
+        if (t.precision != precision) continue;
+        const bool ok = t.form == precision ||
+                        (precision == SRMRA_BF16_SPLIT3 && t.form == SRMRA_FP32_MFMA);
+        if (!ok) return SRMRA_EINVAL;
+        if (t.form == SRMRA_BF16_SPLIT3 && form_of(SRMRA_BF16_SPLIT3, t.L_low) != FORM_BF16)
+            return SRMRA_EUNSUPPORTED;
+    }
     srmra_plan* P = new (std::nothrow) srmra_plan;
     if (!P) return SRMRA_EINVAL;
     P->precision = precision;
@@ -482,12 +508,21 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision, srmr
         if (st == SRMRA_OK && (!pr.prep || !pr.log_rho_new || !aligned(pr.prep))) st = SRMRA_EINVAL;
         if (st != SRMRA_OK) { delete P; return st; }
         int f = form_of(precision, pr.L_low);
+        int64_t item_obs = 0;
+        for (int k = 0; k < n_table; ++k) {   // first matching entry wins
+            const srmra_tuning& t = table[k];
+            if (t.precision == precision && t.L_low == pr.L_low && t.K == pr.K) {
+                f = form_of(t.form, pr.L_low);
+                item_obs = t.item_obs;
+                break;
+            }
+        }
         const int fprec = f == FORM_BF16 ? SRMRA_BF16_SPLIT3 : (f == FORM_MFMA ? SRMRA_FP32_MFMA : SRMRA_FP32_PLAIN);
         Geom g0;
         st = make_geom(pr.N, pr.L_low, pr.K, fprec, false, g0);
         if (st != SRMRA_OK) { delete P; return st; }
         Geom g;
-        make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, default_chunk(g0));
+        make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, item_obs > 0 ? item_obs : default_chunk(g0));
         if (pr.prep_bytes < g.prep_bytes) { delete P; return SRMRA_EWORKSPACE; }
         if (f == FORM_MFMA && g.fuse_wc) f = FORM_FUSED;
         P->geoms.push_back(g);

@@ -32,7 +32,8 @@ def test_header_declares_the_entry_points():
     names = _declared()
     for n in ["srmra_em_step", "srmra_em_step_prepared", "srmra_prepare_observations",
               "srmra_em_step_workspace_bytes", "srmra_prepared_bytes", "srmra_em_step_debug",
-              "srmra_plan_create", "srmra_plan_execute", "srmra_plan_destroy",
+              "srmra_plan_create", "srmra_plan_create_tuned", "srmra_plan_default_item_obs",
+              "srmra_plan_execute", "srmra_plan_destroy", "srmra_em_step_passes",
               "srmra_status_string"]:
         assert n in names
 
@@ -111,3 +112,40 @@ def test_pass_count_query():
     assert B.srmra_em_step_passes(100000, 32, 2, "bf16_split3") == 2
     with pytest.raises(B.SrmraError):
         B.srmra_em_step_passes(1000, 20, 2, "fp32_mfma")
+
+
+def test_tuning_table_validated_on_host(L):
+    """srmra_plan_create_tuned: a table entry may keep the plan's precision or,
+    in a BF16 plan, pick FP32 MFMA; BF16 needs an L_low it is built for; a
+    negative item size is rejected; a valid table builds a plan (host only)."""
+    import ctypes
+    from paper_2204_04754_amd import binding as B
+    prob = (B.srmra_problem * 1)()
+    p = prob[0]
+    p.y, p.prep, p.prep_bytes = 0x1000, 0x100000, 1 << 40
+    p.N, p.L_low, p.K = 1000, 32, 2
+    p.x, p.log_rho, p.sigma = 0x200000, 0x300000, 1.0
+    p.x_new, p.rho_new, p.log_rho_new, p.loglik = 0x400000, 0x500000, 0x600000, 0x700000
+
+    def create(precision, entries):
+        tab = (B.srmra_tuning * len(entries))()
+        for k, (prec, ll, K, form, item) in enumerate(entries):
+            tab[k].precision, tab[k].L_low, tab[k].K, tab[k].form, tab[k].item_obs = prec, ll, K, form, item
+        h, ws = ctypes.c_void_p(), ctypes.c_size_t()
+        st = L.srmra_plan_create_tuned(prob, 1, precision, tab, len(entries), ctypes.byref(h), ctypes.byref(ws))
+        if st == B.SRMRA_OK:
+            assert h.value and ws.value > 0
+            L.srmra_plan_destroy(h)
+        else:
+            assert not h.value
+        return st
+
+    F32, BF, PL = B.SRMRA_FP32_MFMA, B.SRMRA_BF16_SPLIT3, B.SRMRA_FP32_PLAIN
+    assert create(F32, [(F32, 32, 2, BF, 0)]) == B.SRMRA_EINVAL
+    assert create(F32, [(F32, 32, 2, PL, 0)]) == B.SRMRA_EINVAL
+    assert create(BF, [(BF, 16, 2, BF, 0)]) == B.SRMRA_EUNSUPPORTED
+    assert create(BF, [(BF, 32, 2, F32, -1)]) == B.SRMRA_EINVAL
+    assert create(BF, [(BF, 32, 2, F32, 100)]) == B.SRMRA_OK
+    assert create(BF, [(F32, 32, 2, F32, 100)]) == B.SRMRA_OK       # other precision: ignored
+    assert create(F32, [(F32, 32, 2, F32, 37)]) == B.SRMRA_OK
+    assert B.srmra_plan_default_item_obs(1000, 32, 2, "fp32_mfma") > 0

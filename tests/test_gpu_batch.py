@@ -83,3 +83,52 @@ def test_graph_replays_match_eager():
             a, b = eager.results(j), graph_be.results(j)
             for k in ("x_new", "rho_new", "log_rho_new", "loglik"):
                 assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (rep, j, k)
+
+
+def test_autotuned_batch_matches_oracle():
+    """The autotuner picks one entry per (L_low, K) class with a form the BF16
+    plan allows; the tuned batch still matches the oracle to the bound of the
+    form each class runs in."""
+    from paper_2204_04754_amd import binding as B
+    ins = _instances(MIX[:6], config=73)
+    be = BatchedEM(ins, precision="bf16_split3", tuning="auto")
+    classes = {(d["inst"].Ll, d["K"]) for d in ins}
+    assert {(t["L_low"], t["K"]) for t in be.tuning} == classes
+    form = {}
+    for t in be.tuning:
+        assert t["form"] in (B.SRMRA_BF16_SPLIT3, B.SRMRA_FP32_MFMA) and t["item_obs"] > 0
+        if t["form"] == B.SRMRA_BF16_SPLIT3:
+            assert t["L_low"] in (24, 32)
+        form[(t["L_low"], t["K"])] = t["form"]
+    assert len(be.tune_report) >= len(classes)
+    be.step()
+    torch.cuda.synchronize()
+    for j, d in enumerate(ins):
+        inst = d["inst"]
+        g = be.results(j)
+        ref = O.em_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, return_details=True)
+        u = U_SPLIT if form[(inst.Ll, inst.K)] == B.SRMRA_BF16_SPLIT3 else U32
+        check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, u=u)
+
+
+def test_tuning_entry_selects_form_and_partition():
+    """An entry that runs an Ll = 32 problem of a BF16 plan in FP32 MFMA with a
+    given item size gives bitwise the result of an FP32 MFMA plan with the same
+    item size (the entry fully decides the problem's device code)."""
+    from paper_2204_04754_amd import binding as B
+    ins = _instances([(64, 2, 301, 0.8)], config=74)
+    item = 40
+    a = BatchedEM(ins, precision="bf16_split3",
+                  tuning=[dict(precision=B.SRMRA_BF16_SPLIT3, L_low=32, K=2,
+                               form=B.SRMRA_FP32_MFMA, item_obs=item)])
+    b = BatchedEM(ins, precision="fp32_mfma",
+                  tuning=[dict(precision=B.SRMRA_FP32_MFMA, L_low=32, K=2,
+                               form=B.SRMRA_FP32_MFMA, item_obs=item)])
+    c = BatchedEM(ins, precision="fp32_mfma")   # default partition: same math, other rounding order
+    for be in (a, b, c):
+        be.step()
+    torch.cuda.synchronize()
+    ra, rb, rc = a.results(0), b.results(0), c.results(0)
+    for k in ("x_new", "rho_new", "log_rho_new", "loglik"):
+        assert np.array_equal(np.asarray(ra[k]), np.asarray(rb[k])), k
+    assert np.max(np.abs(ra["x_new"] - rc["x_new"])) < 1e-4 * np.max(np.abs(rc["x_new"]))
