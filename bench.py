@@ -127,7 +127,8 @@ def run_form(inst, precision, steps, warmup):
         pe[1].record()
         torch.cuda.synchronize()
         prep_ms.append(pe[0].elapsed_time(pe[1]))
-    prep_bytes = 4.0 * job.N * job.Ll * job.Ll + B.srmra_prepared_bytes(job.N, job.Ll, job.K, job.precision)
+    # two reads of y (the offset mu, then the centred norms / planes) + the buffer written
+    prep_bytes = 8.0 * job.N * job.Ll * job.Ll + B.srmra_prepared_bytes(job.N, job.Ll, job.K, job.precision)
     prep = dict(ms=min(prep_ms), bytes=prep_bytes, gb_per_s=prep_bytes / (min(prep_ms) * 1e-3) / 1e9,
                 hbm_frac=prep_bytes / (min(prep_ms) * 1e-3) / HBM_PEAK)
     for _ in range(warmup):

@@ -101,7 +101,8 @@ int srmra_em_step_passes(int64_t N, int L_low, int K, int precision);
  * loglik are written.  x_new must not alias x; outputs must not alias inputs.
  * sigma > 0 and finite (the known noise standard deviation, Sec. 1).
  * `workspace` must be 256-byte aligned and hold
- * srmra_em_step_workspace_bytes(N, L_low, K, precision) bytes.
+ * srmra_em_step_workspace_bytes(N, L_low, K, precision) bytes.  The per-job
+ * preparation (below, with centring) runs inside the call.
  * Returns SRMRA_OK or an error code; see the execution model above. */
 int srmra_em_step(const float* y, int64_t N, int L_low, int K,
                   const float* x, const float* log_rho, float sigma,
@@ -109,15 +110,27 @@ int srmra_em_step(const float* y, int64_t N, int L_low, int K,
                   int precision, void* workspace, size_t workspace_bytes,
                   hipStream_t stream);
 
-/* Per-job work that does not depend on theta (per-observation squared norms
- * ||y_i||^2 in FP64, and for SRMRA_BF16_SPLIT3 the hi/lo BF16 planes of y).
+/* Per-job work that does not depend on theta: the intensity offset mu (the
+ * mean of all observation pixels, FP64, rounded to FP32), the per-observation
+ * squared norms ||y_i - mu||^2 in FP64, and for SRMRA_BF16_SPLIT3 the hi/lo
+ * BF16 planes of y - mu.  The step then works on (y - mu, x - mu) and adds mu
+ * back to x': the model of eq. model_1 is invariant under a common offset of
+ * y and x (x' shifts by mu; rho', the posterior and the log-likelihood of
+ * eq. likelihood_EM are unchanged), and centring keeps the score magnitudes,
+ * hence the rounding of the contractions, small for data with a large mean
+ * (images in [0, 1]).
  * `prep` (256-byte aligned) must hold srmra_prepared_bytes(...) bytes; it is
  * then passed unchanged to srmra_em_step_prepared for every iteration of the
- * job.  y must stay alive and unchanged while `prep` is used. */
+ * job.  y must stay alive and unchanged while `prep` is used.
+ * srmra_prepare_observations centres; srmra_prepare_observations_ex takes
+ * `centre` = 1 (centre) or 0 (mu = 0: the step works on y and x as given). */
 size_t srmra_prepared_bytes(int64_t N, int L_low, int K, int precision);
 int srmra_prepare_observations(const float* y, int64_t N, int L_low, int K,
                                int precision, void* prep, size_t prep_bytes,
                                hipStream_t stream);
+int srmra_prepare_observations_ex(const float* y, int64_t N, int L_low, int K,
+                                  int precision, int centre, void* prep,
+                                  size_t prep_bytes, hipStream_t stream);
 
 /* Same as srmra_em_step, with the per-job work taken from `prep` (made by
  * srmra_prepare_observations for the same y, N, L_low, K and precision).

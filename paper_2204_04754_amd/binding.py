@@ -76,6 +76,8 @@ def lib():
             L.srmra_em_step_passes.argtypes = [_i64, _int, _int, _int]
             L.srmra_prepared_bytes.restype = _sz
             L.srmra_prepared_bytes.argtypes = [_i64, _int, _int, _int]
+            L.srmra_prepare_observations_ex.restype = _int
+            L.srmra_prepare_observations_ex.argtypes = [_vp, _i64, _int, _int, _int, _int, _vp, _sz, _vp]
             L.srmra_prepare_observations.restype = _int
             L.srmra_prepare_observations.argtypes = [_vp, _i64, _int, _int, _int, _vp, _sz, _vp]
             L.srmra_em_step.restype = _int
@@ -169,6 +171,14 @@ def srmra_em_step_passes(N: int, L_low: int, K: int, precision) -> int:
 
 def srmra_prepared_bytes(N: int, L_low: int, K: int, precision) -> int:
     return int(lib().srmra_prepared_bytes(N, L_low, K, _prec(precision)))
+
+
+def srmra_prepare_observations_ex(y: torch.Tensor, N: int, L_low: int, K: int, precision,
+                                  centre: int, prep: torch.Tensor, stream=None) -> None:
+    _check(lib().srmra_prepare_observations_ex(_ptr(y, torch.float32), N, L_low, K, _prec(precision),
+                                               int(centre), _ptr(prep),
+                                               prep.numel() * prep.element_size(), _stream(stream)),
+           "srmra_prepare_observations_ex")
 
 
 def srmra_prepare_observations(y: torch.Tensor, N: int, L_low: int, K: int, precision,

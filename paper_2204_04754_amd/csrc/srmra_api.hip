@@ -15,13 +15,15 @@
 
 namespace srmra {
 // aux kernels (srmra_aux.hip)
-__global__ void k_obs_norms(const float*, int64_t, int, double*);
-__global__ void k_pack_x(const float*, const float*, int, int, double, float*, float*);
+__global__ void k_obs_sums(const float*, int64_t, int, double*);
+__global__ void k_centre(const double*, int64_t, int, int, double*);
+__global__ void k_obs_norms(const float*, int64_t, int, const double*, double*);
+__global__ void k_pack_x(const float*, const float*, int, int, double, const double*, float*, float*);
 __global__ void k_lse_combine(const float2*, int, int64_t, const double*, double, float*, double*,
                               float*);
 __global__ void k_reduce_partials(const float*, const float*, int, int, double*, double*);
-__global__ void k_finalize(const double*, const double*, int, int, const float*, const double*, int,
-                           float*, float*, float*, double*, double*, double*);
+__global__ void k_finalize(const double*, const double*, int, int, const float*, const double*,
+                           const double*, int, float*, float*, float*, double*, double*, double*);
 // pass launchers (srmra_mfma.hip, srmra_valu.hip, srmra_bf16.hip)
 hipError_t launch_mfma(int LL, int pass, const StepArgs& p, hipStream_t s);
 hipError_t launch_valu(int LL, int pass, const StepArgs& p, hipStream_t s);
@@ -33,8 +35,8 @@ bool valu_geom(int LL, int KK, int& cpb, int& nt, size_t& lds1, size_t& lds2, co
 bool bf16_geom(int LL, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
                const void*& f2);
 hipError_t launch_bf16(int LL, int pass, const StepArgs& p, const void* prep_extra, hipStream_t s);
-hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, double* ynorm, void* prep_extra,
-                            hipStream_t s);
+hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* centre, double* ynorm,
+                            void* prep_extra, hipStream_t s);
 size_t bf16_prepared_extra(int LL, int64_t N);
 size_t bf16_xb_bytes(int LL, int KK);
 hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, hipStream_t s);
@@ -83,7 +85,8 @@ struct Geom {
     int64_t N = 0;
     int cpb = 0, n_cg = 0, n_part = 0, ntile = 0, n_chunks = 0, n_ll = 0;
     int fuse_wc = 0;   // FP32 MFMA single pass: component groups per block (0: two passes)
-    size_t prep_bytes = 0, prep_extra_off = 0;
+    // prepared buffer: [||y_i - mu||^2 N doubles][sum_i N doubles][mu][BF16 planes]
+    size_t prep_bytes = 0, prep_sum_off = 0, prep_mu_off = 0, prep_extra_off = 0;
     int64_t chunk_obs = 0;
     size_t lds1 = 0, lds2 = 0;
     // workspace offsets
@@ -124,7 +127,9 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     // pass-1 partials per observation: one per component group, or per component
     // pair for the BF16 form (two waves of a block hold different pairs)
     g.n_part = prec == SRMRA_BF16_SPLIT3 ? (g.KK + 1) / 2 : g.n_cg;   // 1 for the single pass
-    g.prep_extra_off = align_up(sizeof(double) * (size_t)N);
+    g.prep_sum_off = align_up(sizeof(double) * (size_t)N);
+    g.prep_mu_off = g.prep_sum_off + align_up(sizeof(double) * (size_t)N);
+    g.prep_extra_off = g.prep_mu_off + kAlign;
     g.prep_bytes = g.prep_extra_off + (prec == SRMRA_BF16_SPLIT3 ? bf16_prepared_extra(LL, N) : 0);
     // one resident wave of blocks over the whole device for the heavier pass
     const int occ = occupancy(f2, g.lds2);
@@ -184,9 +189,11 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
     StepArgs p;
     memset(&p, 0, sizeof(p));
     const double* ynorm = (const double*)prep;
+    const double* centre = (const double*)(prep + g.prep_mu_off);
     const void* prep_extra = prep + g.prep_extra_off;
     p.y = y;
     p.ynorm = ynorm;
+    p.centre = centre;
     p.N = g.N;
     p.K = g.K;
     p.Lh = g.Lh;
@@ -210,7 +217,7 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], stream); };
 
     mark(0);
-    hipLaunchKernelGGL(k_pack_x, dim3(g.KK), dim3(256), 0, stream, x, log_rho, g.K, LL, p.inv_2s2,
+    hipLaunchKernelGGL(k_pack_x, dim3(g.KK), dim3(256), 0, stream, x, log_rho, g.K, LL, p.inv_2s2, centre,
                        (float*)(ws + g.o_xt2), (float*)(ws + g.o_beta));
     if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
     if (g.prec == SRMRA_BF16_SPLIT3 && launch_pack_xb(LL, p, x, ws + g.o_xb, stream) != hipSuccess)
@@ -247,8 +254,9 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
                        (double*)(ws + g.o_bsum), (double*)(ws + g.o_csum));
     if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, stream, (const double*)(ws + g.o_bsum),
-                       (const double*)(ws + g.o_csum), g.K, LL, x, (const double*)(ws + g.o_llpart),
-                       g.n_ll, x_new, rho_new, log_rho_new, loglik, b_out, c_out);
+                       (const double*)(ws + g.o_csum), g.K, LL, x, centre,
+                       (const double*)(ws + g.o_llpart), g.n_ll, x_new, rho_new, log_rho_new, loglik,
+                       b_out, c_out);
     if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
     mark(5);
     return SRMRA_OK;
@@ -292,23 +300,38 @@ size_t srmra_prepared_bytes(int64_t N, int L_low, int K, int precision) {
 
 // a0: squared norms (and for the BF16 form its operand planes, in the same
 // read of y)
-static int enqueue_prepare(const Geom& g, const float* y, char* prep, hipStream_t stream) {
+static int enqueue_prepare(const Geom& g, const float* y, char* prep, int centre_on,
+                           hipStream_t stream) {
+    double* ynorm = (double*)prep;
+    double* ysum = (double*)(prep + g.prep_sum_off);
+    double* centre = (double*)(prep + g.prep_mu_off);
+    const unsigned blocks = (unsigned)((g.N + 3) / 4);
+    hipLaunchKernelGGL(k_obs_sums, dim3(blocks), dim3(256), 0, stream, y, g.N, g.LL * g.LL, ysum);
+    hipLaunchKernelGGL(k_centre, dim3(1), dim3(1024), 0, stream, (const double*)ysum, g.N, g.LL * g.LL,
+                       centre_on, centre);
+    if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
     if (g.prec == SRMRA_BF16_SPLIT3)
-        return launch_prep_bf16(g.LL, y, g.N, (double*)prep, prep + g.prep_extra_off, stream) == hipSuccess
+        return launch_prep_bf16(g.LL, y, g.N, centre, ynorm, prep + g.prep_extra_off, stream) == hipSuccess
                    ? SRMRA_OK : SRMRA_EDEVICE;
-    hipLaunchKernelGGL(k_obs_norms, dim3((unsigned)((g.N + 3) / 4)), dim3(256), 0, stream, y, g.N,
-                       g.LL * g.LL, (double*)prep);
+    hipLaunchKernelGGL(k_obs_norms, dim3(blocks), dim3(256), 0, stream, y, g.N, g.LL * g.LL,
+                       (const double*)centre, ynorm);
     return hipGetLastError() == hipSuccess ? SRMRA_OK : SRMRA_EDEVICE;
 }
 
-int srmra_prepare_observations(const float* y, int64_t N, int L_low, int K, int precision,
-                               void* prep, size_t prep_bytes, hipStream_t stream) {
+int srmra_prepare_observations_ex(const float* y, int64_t N, int L_low, int K, int precision,
+                                  int centre, void* prep, size_t prep_bytes, hipStream_t stream) {
     if (!y || !prep || (uintptr_t)y % 16 != 0) return SRMRA_EINVAL;
+    if (centre != 0 && centre != 1) return SRMRA_EINVAL;
     Geom g;
     const int st = make_geom(N, L_low, K, precision, false, g);
     if (st != SRMRA_OK) return st;
     if (!aligned(prep) || prep_bytes < g.prep_bytes) return SRMRA_EWORKSPACE;
-    return enqueue_prepare(g, y, (char*)prep, stream);
+    return enqueue_prepare(g, y, (char*)prep, centre, stream);
+}
+
+int srmra_prepare_observations(const float* y, int64_t N, int L_low, int K, int precision,
+                               void* prep, size_t prep_bytes, hipStream_t stream) {
+    return srmra_prepare_observations_ex(y, N, L_low, K, precision, 1, prep, prep_bytes, stream);
 }
 
 int srmra_em_step_debug(const float* y, const void* prep, size_t prep_bytes, int64_t N, int L_low,
@@ -328,7 +351,7 @@ int srmra_em_step_debug(const float* y, const void* prep, size_t prep_bytes, int
         if (!aligned(prep) || prep_bytes < g.prep_bytes) return SRMRA_EWORKSPACE;
         pp = (const char*)prep;
     } else {
-        st = enqueue_prepare(g, y, ws + g.o_prep, stream);
+        st = enqueue_prepare(g, y, ws + g.o_prep, 1, stream);
         if (st != SRMRA_OK) return st;
         pp = ws + g.o_prep;
     }
@@ -415,6 +438,7 @@ void fill_desc(srmra_plan* P, int i, int par, InstDesc& d, char* ws) {
     StepArgs& p = d.p;
     p.y = pr.y;
     p.ynorm = (const double*)pr.prep;
+    p.centre = (const double*)((const char*)pr.prep + g.prep_mu_off);
     p.N = g.N; p.K = g.K; p.Lh = g.Lh; p.KK = g.KK;
     p.inv_s2 = (float)(1.0 / ((double)pr.sigma * (double)pr.sigma));
     p.inv_2s2 = 1.0 / (2.0 * (double)pr.sigma * (double)pr.sigma);

@@ -9,11 +9,9 @@ namespace srmra {
 // ---------------------------------------------------------------- a0: ||y_i||^2
 // One wave per observation; FP64 accumulation (the term -||y_i||^2/(2 sigma^2) of
 // eq. likelihood_EM).
-__device__ __forceinline__ void obs_norms_body(const float* __restrict__ y, int64_t N, int npix,
-                                               double* __restrict__ ynorm, int64_t blk) {
-    // one wave per observation; lane l adds pixels 4(l + 64k) .. 4(l + 64k) + 3
-    // in that order, then a fixed butterfly (the BF16 preparation kernel uses
-    // the same order, so every form sees the same norms)
+// Per-observation FP64 sums of y (for the offset mu): one wave per observation.
+__device__ __forceinline__ void obs_sums_body(const float* __restrict__ y, int64_t N, int npix,
+                                              double* __restrict__ ysum, int64_t blk) {
     const int lane = threadIdx.x & 63;
     const int64_t i = blk * 4 + (threadIdx.x >> 6);
     if (i >= N) return;
@@ -22,29 +20,76 @@ __device__ __forceinline__ void obs_norms_body(const float* __restrict__ y, int6
 #pragma unroll 4
     for (int p = lane; p < npix / 4; p += 64) {
         const float4 v = yi[p];
-        acc += (double)v.x * v.x;
-        acc += (double)v.y * v.y;
-        acc += (double)v.z * v.z;
-        acc += (double)v.w * v.w;
+        acc += (double)v.x;
+        acc += (double)v.y;
+        acc += (double)v.z;
+        acc += (double)v.w;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) ysum[i] = acc;
+}
+
+// mu = mean of all observation pixels (fixed-order FP64 reduction, one block of
+// 1024 threads), rounded to FP32 (the value the kernels subtract); 0 when
+// centring is off.  The model is invariant under y -> y - mu, x -> x - mu
+// (x' shifts by mu; rho', w and the log-likelihood are unchanged).
+__device__ __forceinline__ void centre_body(const double* __restrict__ ysum, int64_t N, int npix,
+                                            int enable, double* __restrict__ centre, double* red) {
+    double s = 0.0;
+    if (enable)
+        for (int64_t i = threadIdx.x; i < N; i += 1024) s += ysum[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *centre = enable ? (double)(float)(red[0] / ((double)N * npix)) : 0.0;
+}
+
+// ||y_i - mu||^2 in FP64 of the FP32 differences the kernels see: one wave per
+// observation; lane l adds pixels 4(l + 64k) .. 4(l + 64k) + 3 in that order,
+// then a fixed butterfly (the BF16 preparation kernel uses the same order, so
+// every form sees the same norms).
+__device__ __forceinline__ void obs_norms_body(const float* __restrict__ y, int64_t N, int npix,
+                                               const double* __restrict__ centre,
+                                               double* __restrict__ ynorm, int64_t blk) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = blk * 4 + (threadIdx.x >> 6);
+    if (i >= N) return;
+    const float mu = centre_of(centre);
+    const float4* yi = reinterpret_cast<const float4*>(y + i * (int64_t)npix);
+    double acc = 0.0;
+#pragma unroll 4
+    for (int p = lane; p < npix / 4; p += 64) {
+        const float4 v = yi[p];
+        const float d0 = v.x - mu, d1 = v.y - mu, d2 = v.z - mu, d3 = v.w - mu;
+        acc += (double)d0 * d0;
+        acc += (double)d1 * d1;
+        acc += (double)d2 * d2;
+        acc += (double)d3 * d3;
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (lane == 0) ynorm[i] = acc;
 }
 
 // ---------------------------------------------------------------- a1: pack x
-// One block per component c.  xt2[c][b2][a] = x_c[a mod Ll][b2] for a in [0, 2Ll);
-// betaT[c][t2][t1] = log rho1[s1] + log rho2[s2] - ||x_c||^2 / (2 sigma^2),
-// s = (t*K - c) mod Lh (eq. weights_EM with rho[s] = rho1[s1] rho2[s2]).
+// One block per component c (x less the offset mu).  xt2[c][b2][a] =
+// x_c[a mod Ll][b2] for a in [0, 2Ll); betaT[c][t2][t1] = log rho1[s1] +
+// log rho2[s2] - ||x_c||^2 / (2 sigma^2), s = (t*K - c) mod Lh (eq. weights_EM
+// with rho[s] = rho1[s1] rho2[s2]).
 __device__ __forceinline__ void pack_x_body(const float* __restrict__ x,
                                             const float* __restrict__ log_rho, int K, int Ll,
-                                            double inv_2s2, float* __restrict__ xt2,
+                                            double inv_2s2, const double* __restrict__ centre,
+                                            float* __restrict__ xt2,
                                             float* __restrict__ betaT, int c, double* red) {
     const int c1 = c / K, c2 = c % K;
     const int Lh = K * Ll;
+    const float mu = centre_of(centre);
     double acc = 0.0;
     for (int e = threadIdx.x; e < Ll * Ll; e += 256) {
         const int l1 = e / Ll, l2 = e % Ll;
-        const float v = x[(int64_t)(c1 + l1 * K) * Lh + (c2 + l2 * K)];
+        const float v = x[(int64_t)(c1 + l1 * K) * Lh + (c2 + l2 * K)] - mu;
         acc += (double)v * (double)v;
     }
     red[threadIdx.x] = acc;
@@ -58,7 +103,7 @@ __device__ __forceinline__ void pack_x_body(const float* __restrict__ x,
     for (int e = threadIdx.x; e < Ll * 2 * Ll; e += 256) {
         const int b2 = e / (2 * Ll), a = e % (2 * Ll);
         const int l1 = a % Ll;
-        xo[e] = x[(int64_t)(c1 + l1 * K) * Lh + (c2 + b2 * K)];
+        xo[e] = x[(int64_t)(c1 + l1 * K) * Lh + (c2 + b2 * K)] - mu;
     }
     float* bo = betaT + (int64_t)c * Ll * Ll;
     const float* lr1 = log_rho;
@@ -125,13 +170,16 @@ __device__ __forceinline__ void reduce_partials_body(const float* __restrict__ b
     csum[e] = sc;
 }
 
-// Stage 2 (one block): A_c = sum_t c_(c,t); x_new[c1 + q1 K][c2 + q2 K] = b_c[q]/A_c
-// (eq. x_EM with P^{-1} = P^T: A is diagonal and constant on each component);
-// rho marginals (eq. rho_EM, product form); loglik = sum of block partials.
+// Stage 2 (one block): A_c = sum_t c_(c,t); x_new[c1 + q1 K][c2 + q2 K] = b_c[q]/A_c + mu
+// (eq. x_EM with P^{-1} = P^T: A is diagonal and constant on each component; b
+// is the back-projection of y - mu); rho marginals (eq. rho_EM, product form);
+// loglik = sum of block partials.  b_out (optional) is the back-projection of y
+// itself, b + mu A_c.
 // Ac: 256 doubles, red: blockDim doubles (blockDim = 1024)
 __device__ __forceinline__ void finalize_body(const double* __restrict__ bsum,
                                               const double* __restrict__ csum, int K, int Ll,
                                               const float* __restrict__ x,
+                                              const double* __restrict__ centre,
                                               const double* __restrict__ llpart, int n_ll,
                                               float* __restrict__ x_new,
                                               float* __restrict__ rho_new,
@@ -157,6 +205,7 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ bsum,
     }
     double tot = 0.0;
     for (int c = 0; c < KK; ++c) tot += Ac[c];
+    const double mu = (double)centre_of(centre);
     // x_new
     for (int e = tid; e < Lh * Lh; e += 1024) {
         const int m1 = e / Lh, m2 = e % Lh;
@@ -164,8 +213,8 @@ __device__ __forceinline__ void finalize_body(const double* __restrict__ bsum,
         const int c = c1 * K + c2;
         const double b = bsum[(int64_t)c * Ll * Ll + q1 * Ll + q2];
         const double a = Ac[c];
-        x_new[e] = a > 0.0 ? (float)(b / a) : x[e];
-        if (b_out) b_out[e] = b;
+        x_new[e] = a > 0.0 ? (float)(b / a + mu) : x[e];
+        if (b_out) b_out[e] = b + mu * a;
     }
     // rho marginals: c_s with s = (t*K - c) mod Lh
     for (int s1 = tid; s1 < Lh; s1 += 1024) {

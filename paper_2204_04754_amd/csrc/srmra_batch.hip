@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void k_batch_pack(const InstDesc* __restrict__
     __shared__ double red[256];
     const int2 it = items[blockIdx.x];
     const InstDesc& d = D[it.x];
-    pack_x_body(d.x, d.log_rho, d.p.K, d.LL, d.p.inv_2s2, d.xt2_w, d.beta_w, it.y, red);
+    pack_x_body(d.x, d.log_rho, d.p.K, d.LL, d.p.inv_2s2, d.p.centre, d.xt2_w, d.beta_w, it.y, red);
 }
 
 // BF16-form instances: x as MFMA B fragments, every k-step of one component
@@ -62,8 +62,8 @@ __global__ __launch_bounds__(1024) void k_batch_finalize(const InstDesc* __restr
     __shared__ double Ac[256];
     __shared__ double red[1024];
     const InstDesc& d = D[blockIdx.x];
-    finalize_body(d.bsum, d.csum, d.p.K, d.LL, d.x, d.llpart, d.n_ll, d.x_new, d.rho_new,
-                  d.log_rho_new, d.loglik, nullptr, nullptr, Ac, red);
+    finalize_body(d.bsum, d.csum, d.p.K, d.LL, d.x, d.p.centre, d.llpart, d.n_ll, d.x_new,
+                  d.rho_new, d.log_rho_new, d.loglik, nullptr, nullptr, Ac, red);
 }
 
 // Persistent pass kernel of one (form, L_low) class: every block takes items

@@ -58,12 +58,12 @@ static b16::Prep prep_ptrs(const void* prep_extra, int LL, int64_t N) {
     return q;
 }
 
-hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, double* ynorm, void* prep_extra,
-                            hipStream_t s) {
+hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* centre, double* ynorm,
+                            void* prep_extra, hipStream_t s) {
     b16::Prep q = prep_ptrs(prep_extra, LL, N);
     const dim3 grid((unsigned)((N + 7) / 8));
-    if (LL == 24) hipLaunchKernelGGL(b16::k_prep_bf16<24>, grid, dim3(256), 0, s, y, N, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
-    else if (LL == 32) hipLaunchKernelGGL(b16::k_prep_bf16<32>, grid, dim3(256), 0, s, y, N, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
+    if (LL == 24) hipLaunchKernelGGL(b16::k_prep_bf16<24>, grid, dim3(256), 0, s, y, N, centre, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
+    else if (LL == 32) hipLaunchKernelGGL(b16::k_prep_bf16<32>, grid, dim3(256), 0, s, y, N, centre, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

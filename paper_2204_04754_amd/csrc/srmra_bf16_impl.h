@@ -76,7 +76,7 @@ __device__ __forceinline__ floatx16 mfma3(const bf16x8& ah, const bf16x8& al, co
 // Number of k-steps (b2, 16-row block of r1) of one score tile.
 template <int LL> constexpr int nk() { return LL * (R1P / 16); }
 
-// x of component c as the MFMA B operand of every k-step of the score tile:
+// x of component c (less the offset mu) as the MFMA B operand of every k-step of the score tile:
 // lane (t1 = lane & 31, g = lane >> 5) of k-step (b2, jb) holds the 8 values
 // x_c[(16 jb + 8 g + e - t1) mod Ll][b2], e = 0..7, split into BF16 hi and lo.
 // Layout [c][k-step][plane][lane] of 16-byte fragments (one 1 KiB coalesced
@@ -89,12 +89,13 @@ __device__ __forceinline__ void pack_xb_body(const StepArgs& p, const float* __r
     const int b2 = ks / (R1P / 16), jb = ks % (R1P / 16);
     const int t1 = lane & 31, g = lane >> 5;
     const int t1e = t1 < LL ? t1 : t1 - LL;
+    const float mu = centre_of(p.centre);
     float v[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         int r = 16 * jb + 8 * g + e - t1e;
         r = ((r % LL) + LL) % LL;
-        v[e] = x[(int64_t)(c1 + r * p.K) * p.Lh + (c2 + b2 * p.K)];
+        v[e] = x[(int64_t)(c1 + r * p.K) * p.Lh + (c2 + b2 * p.K)] - mu;
     }
     bf16x8 h, l;
     split8(v, h, l);
@@ -376,12 +377,14 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
     }
 }
 
-// ---- per-job preparation: BF16 hi/lo planes of y in both layouts, and the
-// FP64 squared norms.  One block per group of 8 observations: the group is
-// staged in LDS with coalesced 16-byte reads, then every 16-byte output run
-// (8 BF16 values of one plane) is assembled in registers and stored whole.
+// ---- per-job preparation: BF16 hi/lo planes of y - mu in both layouts, and
+// the FP64 squared norms ||y_i - mu||^2.  One block per group of 8
+// observations: the group is staged in LDS with coalesced 16-byte reads, then
+// every 16-byte output run (8 BF16 values of one plane) is assembled in
+// registers and stored whole.
 template <int LL>
 __global__ __launch_bounds__(256) void k_prep_bf16(const float* __restrict__ y, int64_t N,
+                                                   const double* __restrict__ centre,
                                                    __bf16* __restrict__ yT, __bf16* __restrict__ yo,
                                                    double* __restrict__ ynorm) {
     constexpr int SP = LL + 1;                     // LDS row pitch (floats)
@@ -389,11 +392,15 @@ __global__ __launch_bounds__(256) void k_prep_bf16(const float* __restrict__ y, 
     const int64_t grp = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int P4 = LL * LL / 4;
+    const float mu = centre_of(centre);
     for (int e = threadIdx.x; e < 8 * P4; e += 256) {
         const int o = e / P4, q = e % P4;
         const int64_t oi = grp * 8 + o;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (oi < N) v = reinterpret_cast<const float4*>(y + oi * (int64_t)(LL * LL))[q];
+        if (oi < N) {
+            v = reinterpret_cast<const float4*>(y + oi * (int64_t)(LL * LL))[q];
+            v.x -= mu; v.y -= mu; v.z -= mu; v.w -= mu;
+        }
         const int r1 = (4 * q) / LL, r2 = (4 * q) % LL;
         float* d = s + (o * LL + r1) * SP + r2;
         d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;

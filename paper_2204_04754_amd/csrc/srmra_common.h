@@ -43,7 +43,8 @@ template <int LL> struct Valu {
 
 struct StepArgs {
     const float* y;          // [N][Ll][Ll]
-    const double* ynorm;     // [N]  ||y_i||^2
+    const double* ynorm;     // [N]  ||y_i - mu||^2
+    const double* centre;    // device scalar mu: intensity offset taken off y and x (0: none)
     int64_t N;
     int K, Lh, KK;           // K, K*Ll, K*K
     float inv_s2;            // 1 / sigma^2
@@ -66,5 +67,10 @@ struct StepArgs {
 };
 
 __device__ __forceinline__ float fast_exp(float v) { return __expf(v); }
+
+// The offset mu as the FP32 value every kernel subtracts (0 without centring).
+__device__ __forceinline__ float centre_of(const double* centre) {
+    return centre ? (float)*centre : 0.f;
+}
 
 }  // namespace srmra

@@ -55,16 +55,21 @@ __device__ __forceinline__ void load_x_group(const StepArgs& p, int cg, float* X
     }
 }
 
-// Load observations [o0, o0 + nt) into LDS rows of stride OS (zeros past N).
+// Load observations [o0, o0 + nt), less the offset mu, into LDS rows of stride
+// OS (zeros past N).
 template <int LL>
 __device__ __forceinline__ void load_y_tile(const StepArgs& p, int64_t o0, float* Ys,
                                             int nt = Tile<LL>::NT) {
     using TL = Tile<LL>;
     constexpr int P4 = LL * LL / 4;
+    const float mu = centre_of(p.centre);
     for (int e = threadIdx.x; e < nt * P4; e += 256) {
         const int o = e / P4, q = e % P4;
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (o0 + o < p.N) v = reinterpret_cast<const float4*>(p.y + (o0 + o) * (int64_t)(LL * LL))[q];
+        if (o0 + o < p.N) {
+            v = reinterpret_cast<const float4*>(p.y + (o0 + o) * (int64_t)(LL * LL))[q];
+            v.x -= mu; v.y -= mu; v.z -= mu; v.w -= mu;
+        }
         float* d = Ys + o * TL::OS + 4 * q;
         d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
     }

@@ -25,14 +25,16 @@ __device__ __forceinline__ void load_x_group_valu(const StepArgs& p, int cg, flo
     }
 }
 
-// y tile with every row doubled: Ys[o][r1][a] = y_o[r1][a % Ll], a in [0, 2Ll)
+// y tile (less the offset mu) with every row doubled: Ys[o][r1][a] = y_o[r1][a % Ll] - mu,
+// a in [0, 2Ll)
 template <int LL>
 __device__ __forceinline__ void load_y_tile_valu(const StepArgs& p, int64_t o0, int nt, float* Ys) {
     using V = Valu<LL>;
+    const float mu = centre_of(p.centre);
     for (int e = threadIdx.x; e < nt * LL * LL; e += 256) {
         const int o = e / (LL * LL), q = e % (LL * LL);
         const int r1 = q / LL, r2 = q % LL;
-        const float v = (o0 + o < p.N) ? p.y[(o0 + o) * (int64_t)(LL * LL) + q] : 0.f;
+        const float v = (o0 + o < p.N) ? p.y[(o0 + o) * (int64_t)(LL * LL) + q] - mu : 0.f;
         float* d = Ys + o * V::YS + r1 * 2 * LL;
         d[r2] = v;
         d[r2 + LL] = v;

@@ -24,7 +24,7 @@ class EMJob:
     """One SR-MRA job resident on the GPU (observations, iterate, workspace)."""
 
     def __init__(self, y, K: int, sigma: float, x0, log_rho0, precision="fp32_mfma",
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, centre: bool = True):
         y = torch.as_tensor(np.ascontiguousarray(y, dtype=np.float32)) if isinstance(y, np.ndarray) else y
         self.device = torch.device(device)
         self.y = y.to(self.device, dtype=torch.float32).contiguous()
@@ -40,8 +40,9 @@ class EMJob:
             raise B.SrmraError(B.SRMRA_EUNSUPPORTED, "EMJob")
         self.prep = B.empty_bytes(pb, self.device)
         self.workspace = B.empty_bytes(wb, self.device)
-        B.srmra_prepare_observations(self.y, self.N, self.Ll, self.K, self.precision, self.prep,
-                                     stream)
+        self.centre = bool(centre)
+        B.srmra_prepare_observations_ex(self.y, self.N, self.Ll, self.K, self.precision,
+                                        int(self.centre), self.prep, stream)
         f = dict(device=self.device, dtype=torch.float32)
         self.x = [torch.as_tensor(np.asarray(x0, np.float32)).to(**f).contiguous(),
                   torch.empty((self.Lh, self.Lh), **f)]

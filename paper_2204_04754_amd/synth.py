@@ -90,10 +90,17 @@ class Instance:
 
 def make_instance(Lh: int, K: int, N: int, sigma: float, config: int = 0,
                   instance: int = 0, blur: float = 1.5,
-                  chunk: int = 65536) -> Instance:
+                  chunk: int = 65536, value_range: str = "std") -> Instance:
+    """value_range "std": the smooth image at zero mean and unit std;
+    "unit": the same image min-max scaled to [0, 1] (mean near 0.5, like the
+    paper's natural images), with the initial iterate 0.5 + 0.25 N(0, 1)."""
     if Lh % K != 0:
         raise ValueError("Lh must be a multiple of K")
+    if value_range not in ("std", "unit"):
+        raise ValueError("value_range must be 'std' or 'unit'")
     img = smooth_image(_rng(config, instance, ROLE_IMAGE), Lh, blur)
+    if value_range == "unit":
+        img = (img - img.min()) / (img.max() - img.min())
     x_true = img.astype(np.float32)
     r = _rng(config, instance, ROLE_RHO)
     rho1 = r.dirichlet(np.ones(Lh))
@@ -110,7 +117,10 @@ def make_instance(Lh: int, K: int, N: int, sigma: float, config: int = 0,
         clean = observe(xt, s1[a:b], s2[a:b], K)
         y[a:b] = (clean + sigma * rn.standard_normal(clean.shape)).astype(np.float32)
     ri = _rng(config, instance, ROLE_INIT)
-    x0 = ri.standard_normal((Lh, Lh)).astype(np.float32)
+    x0 = ri.standard_normal((Lh, Lh))
+    if value_range == "unit":
+        x0 = 0.5 + 0.25 * x0
+    x0 = x0.astype(np.float32)
     log_rho0 = np.full((2, Lh), -np.log(Lh), dtype=np.float32)
     return Instance(Lh, K, N, float(sigma), x_true, rho1, rho2, s1, s2, y, x0, log_rho0)
 
@@ -124,6 +134,10 @@ WORKLOADS = {
     # precision study: Lh 128, K 4, Ll 32, N 2e5, sigma 0.5 and 2.0
     "lh128_k4_n200000_s0.5": dict(Lh=128, K=4, N=200_000, sigma=0.5, config=2),
     "lh128_k4_n200000_s2": dict(Lh=128, K=4, N=200_000, sigma=2.0, config=2, instance=1),
+    # robustness variant: the precision-study image min-max scaled to [0, 1]
+    # (mean near 0.5), sigma 0.25 (the middle of the paper's noise levels)
+    "lh128_k4_n200000_unit_s0.25": dict(Lh=128, K=4, N=200_000, sigma=0.25, config=2,
+                                        value_range="unit"),
 }
 
 

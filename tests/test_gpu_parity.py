@@ -103,3 +103,23 @@ def test_single_observation_and_delta_prior(prec):
     np.testing.assert_allclose(g["x_new"], expect, rtol=0, atol=1e-6)
     np.testing.assert_allclose(g["rho_new"], ref["rho_new"], atol=0)
     assert abs(g["loglik"] - ref["loglik"]) < 1e-3 * abs(ref["loglik"])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_centring_offset_invariance(prec):
+    """A common offset of y and x (here +5) leaves rho', the posterior mass and
+    the log-likelihood unchanged and shifts x' by the offset (the model depends
+    on y - P R_s x only); with centring the GPU result at the offset matches the
+    oracle at the offset, and centring on / off agree on zero-mean data."""
+    inst = synth.make_instance(64, 2, 300, 1.0, config=53)
+    off = np.float32(5.0)
+    y5, x5 = (inst.y + off).astype(np.float32), (inst.x0 + off).astype(np.float32)
+    g5 = gpu_step(y5, x5, inst.log_rho0, 1.0, 2, prec)
+    ref5 = O.em_step(y5, x5, inst.log_rho0, 1.0, 2, return_details=True)
+    check_step(y5, x5, inst.log_rho0, 1.0, 2, g5, ref5)
+    g0 = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 2, prec)
+    assert rel(g5["x_new"] - off, g0["x_new"]) < 1e-4
+    assert rel(g5["rho_new"], g0["rho_new"]) < 1e-5
+    g_off = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 2, prec, centre=False)
+    assert rel(g_off["x_new"], g0["x_new"]) < 1e-5
+    assert abs(g_off["loglik"] - g0["loglik"]) < 1e-6 * abs(g0["loglik"])
