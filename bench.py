@@ -34,9 +34,11 @@ sys.path.insert(0, ROOT)
 METRIC = "EM obs×shift pairs/s vs plain FP32 at rel err ≤1e-4; p50/p99 solve latency"
 PEAK = {  # MI355X published dense peaks
     "fp32_mfma": ("mfma", 157.3e12), "fp32_plain": ("alu", 78.6e12),
-    "bf16_split3": ("mfma", 2516.6e12),
+    "bf16_split3": ("mfma", 2516.6e12), "bf16_split4": ("mfma", 2516.6e12),
 }
-KNAME = {"fp32_mfma": "mfma", "fp32_plain": "valu", "bf16_split3": "bf16"}
+KNAME = {"fp32_mfma": "mfma", "fp32_plain": "valu", "bf16_split3": "bf16", "bf16_split4": "bf16"}
+PRODUCTS = {"bf16_split3": 3, "bf16_split4": 4}   # BF16 products per multiply-add
+DTYPE = {"fp32_mfma": "f32", "fp32_plain": "f32", "bf16_split3": "bf16x3", "bf16_split4": "bf16x4"}
 HBM_PEAK = 8.0e12   # B/s
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x 2.0)
 # and WRITE_SIZE (x 1.0), keyed by (workload, precision, kernel), with a hash of
@@ -47,7 +49,7 @@ _BF16_SRC = ("srmra_common.h", "srmra_bf16_impl.h", "srmra_bf16.hip")
 TRAFFIC = {
     ("lh64_k2_n100000", "fp32_mfma", "k_fused_mfma<32>"):
         dict(bytes=428045926, src=_MFMA_SRC, sha="49c5338c148a502a"),
-    ("lh128_k4_n200000_s0.5", "bf16_split3", "k_backproject_bf16<32>"):
+    ("lh128_k4_n200000_s0.5", "bf16_split3", "k_backproject_bf16<32, 3>"):
         dict(bytes=1666526822, src=_BF16_SRC, sha="ba5560ac91e34097"),
 }
 
@@ -246,7 +248,7 @@ def bench_batched(args):
     out = {"metric": METRIC, "value": forms[best]["pairs_per_s"], "unit": "obs×shift pairs/s",
            "n_gpus": 1, "steps": args.iterations, "warmup": args.iterations,
            "ms_per_step": forms[best]["ms_per_step"], "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": main_p, "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[main_p], "data": "synthetic",
            "config": {"workload": f"batched_mix_{args.instances}", "instances": args.instances,
                       "pairs_per_step": sum(d['N'] * d['Lh'] ** 2 for d in mix),
                       "precision": main_p, "table": "tuned" if best.endswith("+tuned") else "default",
@@ -298,7 +300,7 @@ def bench_serve(args):
     out = {"metric": METRIC, "value": results[main_key]["solves_per_s"], "unit": "solves/s",
            "n_gpus": 1, "steps": args.jobs, "warmup": 0, "ms_per_step": None,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": args.precision, "data": "synthetic",
+           "dtype": DTYPE[args.precision], "data": "synthetic",
            "config": {"workload": "serve_poisson_mix", "jobs_per_rate": args.jobs,
                       "iterations_per_job": args.iterations, "rates": rates},
            "p50_latency_s": results[main_key]["p50_latency_s"],
@@ -355,14 +357,15 @@ def main():
     Ll2 = inst.Ll * inst.Ll
     bound, peak = PEAK[args.precision]
     n_pass = B.srmra_em_step_passes(inst.N, inst.Ll, inst.K, args.precision)
-    prod = 3.0 if args.precision == "bf16_split3" else 1.0
+    prod = float(PRODUCTS.get(args.precision, 1))
+    targ = f"<{inst.Ll}, {PRODUCTS[args.precision]}>" if args.precision in PRODUCTS else f"<{inst.Ll}>"
     k_ms = main_r["phase_ms"][3]
     if n_pass == 1:
-        kname = f"k_fused_{KNAME[args.precision]}<{inst.Ll}>"
+        kname = f"k_fused_{KNAME[args.precision]}{targ}"
         alg_flop = 4.0 * Ll2 * pairs
         issued_flop = alg_flop * prod
     else:
-        kname = f"k_backproject_{KNAME[args.precision]}<{inst.Ll}>"
+        kname = f"k_backproject_{KNAME[args.precision]}{targ}"
         alg_flop = 2.0 * Ll2 * pairs
         issued_flop = 4.0 * Ll2 * pairs * prod
     achieved = alg_flop / (k_ms * 1e-3)
@@ -379,7 +382,7 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "obs×shift pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": forms[args.precision]["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"fp32_mfma": "f32", "fp32_plain": "f32", "bf16_split3": "bf16x3"}[args.precision],
+           "dtype": DTYPE[args.precision],
            "data": "synthetic",
            "config": {"workload": args.workload, "L_high": inst.Lh, "K": inst.K, "L_low": inst.Ll,
                       "N": inst.N, "sigma": inst.sigma, "precision": args.precision,

@@ -73,8 +73,9 @@ typedef enum {
 typedef enum {
     SRMRA_FP32_PLAIN = 0,     /* FP32 FMAs on the vector ALUs                       */
     SRMRA_FP32_MFMA = 1,      /* FP32 matrix cores (v_mfma_f32_32x32x2 / 16x16x4)   */
-    SRMRA_BF16_SPLIT3 = 2     /* BF16 matrix cores, operands split v = hi + lo,
+    SRMRA_BF16_SPLIT3 = 2,    /* BF16 matrix cores, operands split v = hi + lo,
                                  products hi*hi + hi*lo + lo*hi, FP32 accumulate    */
+    SRMRA_BF16_SPLIT4 = 3     /* as SRMRA_BF16_SPLIT3 plus the lo*lo product        */
 } srmra_precision;
 
 /* Human-readable text of a status code (static storage). */
@@ -112,7 +113,7 @@ int srmra_em_step(const float* y, int64_t N, int L_low, int K,
 
 /* Per-job work that does not depend on theta: the intensity offset mu (the
  * mean of all observation pixels, FP64, rounded to FP32), the per-observation
- * squared norms ||y_i - mu||^2 in FP64, and for SRMRA_BF16_SPLIT3 the hi/lo
+ * squared norms ||y_i - mu||^2 in FP64, and for the BF16 split forms the hi/lo
  * BF16 planes of y - mu.  The step then works on (y - mu, x - mu) and adds mu
  * back to x': the model of eq. model_1 is invariant under a common offset of
  * y and x (x' shifts by mu; rho', the posterior and the log-likelihood of
@@ -205,8 +206,8 @@ typedef struct srmra_problem {
 typedef struct srmra_plan srmra_plan;
 
 /* The precision an instance of this L_low runs in within a plan of the given
- * precision: SRMRA_BF16_SPLIT3 plans run L_low outside {24, 32} in
- * SRMRA_FP32_MFMA.  Returns -1 for unsupported arguments. */
+ * precision: SRMRA_BF16_SPLIT3 / SRMRA_BF16_SPLIT4 plans run L_low outside
+ * {24, 32} in SRMRA_FP32_MFMA.  Returns -1 for unsupported arguments. */
 int srmra_plan_form(int precision, int L_low);
 
 /* Build a plan (host only, no device work).  `probs` is copied.  On success
@@ -219,7 +220,7 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision,
  * autotuner, paper_2204_04754_amd/autotune.py, measures and writes these).
  * Problems with this (L_low, K) in a plan of precision `precision` run in
  * precision `form` -- the plan's own precision, or SRMRA_FP32_MFMA in a
- * SRMRA_BF16_SPLIT3 plan -- with `item_obs` observations per work item
+ * BF16 split plan -- with `item_obs` observations per work item
  * (rounded up to the form's observation tile; 0 keeps the default of about
  * 2^28 multiply-adds per item).  Entries of another precision are ignored;
  * the first matching entry wins.  A problem's result depends on its own
@@ -235,7 +236,7 @@ typedef struct srmra_tuning {
  * 0, which is srmra_plan_create).  SRMRA_EINVAL for a negative item_obs or a
  * form the plan's precision does not allow; SRMRA_EUNSUPPORTED for a BF16
  * entry at an L_low without a BF16 kernel.  The prepared buffer of every
- * problem must suit the form it runs in (a SRMRA_BF16_SPLIT3 preparation also
+ * problem must suit the form it runs in (a BF16 split preparation also
  * serves SRMRA_FP32_MFMA). */
 int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision,
                             const srmra_tuning* table, int n_table,

@@ -32,8 +32,8 @@ def candidate_forms(precision: int, L_low: int) -> List[int]:
     base = B.srmra_plan_form(precision, L_low)
     if base < 0:
         raise B.SrmraError(B.SRMRA_EUNSUPPORTED, "autotune")
-    if base == B.SRMRA_BF16_SPLIT3:
-        return [B.SRMRA_BF16_SPLIT3, B.SRMRA_FP32_MFMA]
+    if base in (B.SRMRA_BF16_SPLIT3, B.SRMRA_BF16_SPLIT4):
+        return [base, B.SRMRA_FP32_MFMA]
     return [base]
 
 

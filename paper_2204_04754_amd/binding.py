@@ -26,7 +26,9 @@ SRMRA_EDEVICE = -4
 SRMRA_FP32_PLAIN = FP32_PLAIN = 0
 SRMRA_FP32_MFMA = FP32_MFMA = 1
 SRMRA_BF16_SPLIT3 = BF16_SPLIT3 = 2
-PRECISIONS = {"fp32_plain": FP32_PLAIN, "fp32_mfma": FP32_MFMA, "bf16_split3": BF16_SPLIT3}
+SRMRA_BF16_SPLIT4 = BF16_SPLIT4 = 3
+PRECISIONS = {"fp32_plain": FP32_PLAIN, "fp32_mfma": FP32_MFMA, "bf16_split3": BF16_SPLIT3,
+              "bf16_split4": BF16_SPLIT4}
 
 _lib = None
 _lock = threading.Lock()

@@ -32,9 +32,10 @@ bool mfma_geom(int LL, int& cpw, int& nt, size_t& lds1, size_t& lds2, const void
 bool mfma_fused_geom(int LL, int KK, int& wc, int& nt, size_t& lds, const void*& f);
 bool valu_geom(int LL, int KK, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
                const void*& f2);
-bool bf16_geom(int LL, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
+bool bf16_geom(int LL, int np, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
                const void*& f2);
-hipError_t launch_bf16(int LL, int pass, const StepArgs& p, const void* prep_extra, hipStream_t s);
+hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
+                       hipStream_t s);
 hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* centre, double* ynorm,
                             void* prep_extra, hipStream_t s);
 size_t bf16_prepared_extra(int LL, int64_t N);
@@ -52,6 +53,13 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 bool supported_ll(int LL) {
     return LL == 8 || LL == 12 || LL == 16 || LL == 24 || LL == 32 || LL == 48 || LL == 64;
 }
+
+bool valid_prec(int p) {
+    return p == SRMRA_FP32_PLAIN || p == SRMRA_FP32_MFMA || p == SRMRA_BF16_SPLIT3 ||
+           p == SRMRA_BF16_SPLIT4;
+}
+bool is_bf16(int p) { return p == SRMRA_BF16_SPLIT3 || p == SRMRA_BF16_SPLIT4; }
+int split_products(int p) { return p == SRMRA_BF16_SPLIT4 ? 4 : 3; }
 
 // Device facts used by the launch geometry, cached per device id.
 struct DeviceInfo {
@@ -99,8 +107,7 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     if (N < 1 || N > (int64_t)INT32_MAX || K < 1 || LL < 1) return SRMRA_EINVAL;
     if (!supported_ll(LL)) return SRMRA_EUNSUPPORTED;
     if ((int64_t)K * LL > 4096 || K * K > 256) return SRMRA_EUNSUPPORTED;
-    if (prec != SRMRA_FP32_PLAIN && prec != SRMRA_FP32_MFMA && prec != SRMRA_BF16_SPLIT3)
-        return SRMRA_EUNSUPPORTED;
+    if (!valid_prec(prec)) return SRMRA_EUNSUPPORTED;
     g.LL = LL; g.K = K; g.Lh = K * LL; g.KK = K * K; g.N = N; g.prec = prec;
     const void* f1 = nullptr;
     const void* f2 = nullptr;
@@ -120,17 +127,19 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
             f1 = nullptr;
             f2 = ff;
         }
-    } else if (prec == SRMRA_BF16_SPLIT3) ok = bf16_geom(LL, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
+    } else if (is_bf16(prec)) {
+        ok = bf16_geom(LL, split_products(prec), g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
+    }
     else ok = valu_geom(LL, g.KK, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
     if (!ok) return SRMRA_EUNSUPPORTED;
     g.n_cg = (g.KK + g.cpb - 1) / g.cpb;
     // pass-1 partials per observation: one per component group, or per component
     // pair for the BF16 form (two waves of a block hold different pairs)
-    g.n_part = prec == SRMRA_BF16_SPLIT3 ? (g.KK + 1) / 2 : g.n_cg;   // 1 for the single pass
+    g.n_part = is_bf16(prec) ? (g.KK + 1) / 2 : g.n_cg;   // 1 for the single pass
     g.prep_sum_off = align_up(sizeof(double) * (size_t)N);
     g.prep_mu_off = g.prep_sum_off + align_up(sizeof(double) * (size_t)N);
     g.prep_extra_off = g.prep_mu_off + kAlign;
-    g.prep_bytes = g.prep_extra_off + (prec == SRMRA_BF16_SPLIT3 ? bf16_prepared_extra(LL, N) : 0);
+    g.prep_bytes = g.prep_extra_off + (is_bf16(prec) ? bf16_prepared_extra(LL, N) : 0);
     // one resident wave of blocks over the whole device for the heavier pass
     const int occ = occupancy(f2, g.lds2);
     const int64_t target = (int64_t)device_cus() * occ;
@@ -156,7 +165,7 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     g.o_llpart = take(sizeof(double) * (size_t)g.n_ll);
     g.o_bsum = take(sizeof(double) * (size_t)g.KK * LL * LL);
     g.o_csum = take(sizeof(double) * (size_t)g.KK * LL * LL);
-    g.o_xb = prec == SRMRA_BF16_SPLIT3 ? take(bf16_xb_bytes(LL, g.KK)) : 0;
+    g.o_xb = is_bf16(prec) ? take(bf16_xb_bytes(LL, g.KK)) : 0;
     g.total = off;
     return SRMRA_OK;
 }
@@ -202,7 +211,7 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
     p.inv_2s2 = 1.0 / (2.0 * (double)sigma * (double)sigma);
     p.xt2 = (const float*)(ws + g.o_xt2);
     p.betaT = (const float*)(ws + g.o_beta);
-    p.xb = g.prec == SRMRA_BF16_SPLIT3 ? (const uint4*)(ws + g.o_xb) : nullptr;
+    p.xb = is_bf16(g.prec) ? (const uint4*)(ws + g.o_xb) : nullptr;
     p.part = (float2*)(ws + g.o_part);
     p.lse = (float*)(ws + g.o_lse);
     p.bpart = (float*)(ws + g.o_bpart);
@@ -220,12 +229,12 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
     hipLaunchKernelGGL(k_pack_x, dim3(g.KK), dim3(256), 0, stream, x, log_rho, g.K, LL, p.inv_2s2, centre,
                        (float*)(ws + g.o_xt2), (float*)(ws + g.o_beta));
     if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
-    if (g.prec == SRMRA_BF16_SPLIT3 && launch_pack_xb(LL, p, x, ws + g.o_xb, stream) != hipSuccess)
+    if (is_bf16(g.prec) && launch_pack_xb(LL, p, x, ws + g.o_xb, stream) != hipSuccess)
         return SRMRA_EDEVICE;
     mark(1);
     auto pass = [&](int k) -> hipError_t {
         if (g.prec == SRMRA_FP32_MFMA) return launch_mfma(LL, k, p, stream);
-        if (g.prec == SRMRA_BF16_SPLIT3) return launch_bf16(LL, k, p, prep_extra, stream);
+        if (is_bf16(g.prec)) return launch_bf16(LL, split_products(g.prec), k, p, prep_extra, stream);
         return launch_valu(LL, k, p, stream);
     };
     auto combine = [&]() -> hipError_t {
@@ -310,7 +319,7 @@ static int enqueue_prepare(const Geom& g, const float* y, char* prep, int centre
     hipLaunchKernelGGL(k_centre, dim3(1), dim3(1024), 0, stream, (const double*)ysum, g.N, g.LL * g.LL,
                        centre_on, centre);
     if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
-    if (g.prec == SRMRA_BF16_SPLIT3)
+    if (is_bf16(g.prec))
         return launch_prep_bf16(g.LL, y, g.N, centre, ynorm, prep + g.prep_extra_off, stream) == hipSuccess
                    ? SRMRA_OK : SRMRA_EDEVICE;
     hipLaunchKernelGGL(k_obs_norms, dim3(blocks), dim3(256), 0, stream, y, g.N, g.LL * g.LL,
@@ -417,9 +426,23 @@ struct srmra_plan {
 namespace {
 
 int form_of(int precision, int LL) {
-    if (precision == SRMRA_BF16_SPLIT3) return (LL == 24 || LL == 32) ? FORM_BF16 : FORM_MFMA;
+    if (is_bf16(precision)) {
+        if (LL != 24 && LL != 32) return FORM_MFMA;
+        return precision == SRMRA_BF16_SPLIT4 ? FORM_BF16X4 : FORM_BF16;
+    }
     return precision == SRMRA_FP32_MFMA ? FORM_MFMA : FORM_VALU;
 }
+
+// the precision a batched form runs in
+int prec_of_form(int f) {
+    switch (f) {
+        case FORM_BF16: return SRMRA_BF16_SPLIT3;
+        case FORM_BF16X4: return SRMRA_BF16_SPLIT4;
+        case FORM_VALU: return SRMRA_FP32_PLAIN;
+    }
+    return SRMRA_FP32_MFMA;
+}
+bool is_bf16_form(int f) { return f == FORM_BF16 || f == FORM_BF16X4; }
 
 // observations per work item: about 2^28 multiply-adds (shape-only, so an
 // instance's partition does not depend on the rest of the batch)
@@ -444,7 +467,7 @@ void fill_desc(srmra_plan* P, int i, int par, InstDesc& d, char* ws) {
     p.inv_2s2 = 1.0 / (2.0 * (double)pr.sigma * (double)pr.sigma);
     p.xt2 = (const float*)(w + g.o_xt2);
     p.betaT = (const float*)(w + g.o_beta);
-    p.xb = P->form[i] == FORM_BF16 ? (const uint4*)(w + g.o_xb) : nullptr;
+    p.xb = is_bf16_form(P->form[i]) ? (const uint4*)(w + g.o_xb) : nullptr;
     p.part = (float2*)(w + g.o_part);
     p.lse = (float*)(w + g.o_lse);
     p.bpart = (float*)(w + g.o_bpart);
@@ -452,7 +475,7 @@ void fill_desc(srmra_plan* P, int i, int par, InstDesc& d, char* ws) {
     p.n_chunks = g.n_chunks; p.n_cg = g.n_cg; p.cpb = g.cpb; p.ntile = g.ntile;
     p.chunk_obs = g.chunk_obs;
     p.fuse_wc = g.fuse_wc;
-    if (P->form[i] == FORM_BF16) {
+    if (is_bf16_form(P->form[i])) {
         const char* e = (const char*)pr.prep + g.prep_extra_off;
         const size_t yt = (size_t)g.N * 2 * g.LL * 32 * 2;
         d.yT = (const __bf16*)e;
@@ -477,10 +500,8 @@ void fill_desc(srmra_plan* P, int i, int par, InstDesc& d, char* ws) {
 
 int srmra_plan_form(int precision, int L_low) {
     if (!supported_ll(L_low)) return -1;
-    if (precision != SRMRA_FP32_PLAIN && precision != SRMRA_FP32_MFMA && precision != SRMRA_BF16_SPLIT3)
-        return -1;
-    const int f = form_of(precision, L_low);
-    return f == FORM_BF16 ? SRMRA_BF16_SPLIT3 : (f == FORM_MFMA ? SRMRA_FP32_MFMA : SRMRA_FP32_PLAIN);
+    if (!valid_prec(precision)) return -1;
+    return prec_of_form(form_of(precision, L_low));
 }
 
 int64_t srmra_plan_default_item_obs(int64_t N, int L_low, int K, int form_precision) {
@@ -502,19 +523,16 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
     if (n_table < 0 || (n_table > 0 && !table)) return SRMRA_EINVAL;
     *plan = nullptr;
     *workspace_bytes = 0;
-    if (precision != SRMRA_FP32_PLAIN && precision != SRMRA_FP32_MFMA && precision != SRMRA_BF16_SPLIT3)
-        return SRMRA_EUNSUPPORTED;
+    if (!valid_prec(precision)) return SRMRA_EUNSUPPORTED;
     // a table entry may only keep the plan's precision or, in a BF16 plan, pick
     // FP32 MFMA (more accurate); the BF16 form needs an L_low it is built for
     for (int k = 0; k < n_table; ++k) {
         const srmra_tuning& t = table[k];
         if (t.item_obs < 0) return SRMRA_EINVAL;
         if (t.precision != precision) continue;
-        const bool ok = t.form == precision ||
-                        (precision == SRMRA_BF16_SPLIT3 && t.form == SRMRA_FP32_MFMA);
+        const bool ok = t.form == precision || (is_bf16(precision) && t.form == SRMRA_FP32_MFMA);
         if (!ok) return SRMRA_EINVAL;
-        if (t.form == SRMRA_BF16_SPLIT3 && form_of(SRMRA_BF16_SPLIT3, t.L_low) != FORM_BF16)
-            return SRMRA_EUNSUPPORTED;
+        if (is_bf16(t.form) && !is_bf16_form(form_of(t.form, t.L_low))) return SRMRA_EUNSUPPORTED;
     }
     srmra_plan* P = new (std::nothrow) srmra_plan;
     if (!P) return SRMRA_EINVAL;
@@ -541,7 +559,7 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
                 break;
             }
         }
-        const int fprec = f == FORM_BF16 ? SRMRA_BF16_SPLIT3 : (f == FORM_MFMA ? SRMRA_FP32_MFMA : SRMRA_FP32_PLAIN);
+        const int fprec = prec_of_form(f);
         Geom g0;
         st = make_geom(pr.N, pr.L_low, pr.K, fprec, false, g0);
         if (st != SRMRA_OK) { delete P; return st; }
@@ -569,7 +587,7 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         for (int ch = 0; ch < g.n_chunks; ++ch) {
             const int64_t nobs = std::min<int64_t>(g.chunk_obs, g.N - (int64_t)ch * g.chunk_obs);
             const double cst = (double)nobs * g.cpb * (double)g.LL * g.LL * g.LL * g.LL *
-                               (f == FORM_VALU ? 2.0 : (f == FORM_BF16 ? 0.5 : 1.0));
+                               (f == FORM_VALU ? 2.0 : (f == FORM_BF16 ? 0.5 : (f == FORM_BF16X4 ? 0.67 : 1.0)));
             for (int cg = 0; cg < g.n_cg; ++cg) costs.push_back({cls, cst, make_int4(i, ch, cg, 0)});
         }
         for (int c = 0; c < g.KK; ++c) P->pack_items.push_back(make_int2(i, c));

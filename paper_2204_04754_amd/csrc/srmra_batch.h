@@ -6,11 +6,11 @@ namespace srmra {
 
 // FORM_FUSED: FP32 MFMA single pass (no pass-1 launch; the log-likelihood
 // combine of these instances runs after pass 2)
-enum { FORM_VALU = 0, FORM_MFMA = 1, FORM_BF16 = 2, FORM_FUSED = 3 };
+enum { FORM_VALU = 0, FORM_MFMA = 1, FORM_BF16 = 2, FORM_FUSED = 3, FORM_BF16X4 = 4 };
 
 struct InstDesc {
     StepArgs p;                  // per-instance step arguments (workspace pointers set)
-    const __bf16* yT;            // BF16 prepared planes (FORM_BF16 only)
+    const __bf16* yT;            // BF16 prepared planes (BF16 forms only)
     const __bf16* yo;
     const float* x;              // iterate in (this parity)
     const float* log_rho;

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_batch_pack_xb(const InstDesc* __restric
                                                        const int2* __restrict__ items) {
     const int2 it = items[blockIdx.x];
     const InstDesc& d = D[it.x];
-    if (d.form != FORM_BF16) return;
+    if (d.form != FORM_BF16 && d.form != FORM_BF16X4) return;
     uint4* xb = const_cast<uint4*>(d.p.xb);
     if (d.LL == 24) {
         for (int ks = threadIdx.x >> 6; ks < b16::nk<24>(); ks += 4) b16::pack_xb_body<24>(d.p, d.x, it.y, ks, xb);
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(1024) void k_batch_finalize(const InstDesc* __restr
 // from the class's cost-sorted list through an atomic counter and leaves the
 // loop once the counter passes the item count (every wave reaches the exit).
 template <int PASS, int FORM, int LL>
-__global__ __launch_bounds__(256, ((PASS == 1 && FORM == FORM_BF16) ||
+__global__ __launch_bounds__(256, ((PASS == 1 && (FORM == FORM_BF16 || FORM == FORM_BF16X4)) ||
                                    (PASS == 2 && FORM == FORM_MFMA && LL >= 16 && LL <= 32) ||
                                    (PASS == 2 && FORM == FORM_FUSED && LL >= 16 && LL <= 24)) ? 2 : 1)
 void k_class_pass(const InstDesc* __restrict__ D,
@@ -89,12 +89,13 @@ void k_class_pass(const InstDesc* __restrict__ D,
         if (it >= n_items) break;
         const int4 w = items[it];
         const InstDesc& d = D[w.x];
-        if constexpr (FORM == FORM_BF16) {
+        if constexpr (FORM == FORM_BF16 || FORM == FORM_BF16X4) {
+            constexpr int NP = FORM == FORM_BF16X4 ? 4 : 3;
             b16::Prep q;
             q.yT = d.yT;
             q.yo = d.yo;
-            if constexpr (PASS == 1) b16::bf16_pass1_body<LL>(d.p, q, w.y, w.z, lds);
-            else b16::bf16_pass2_body<LL>(d.p, q, w.y, w.z, lds);
+            if constexpr (PASS == 1) b16::bf16_pass1_body<LL, NP>(d.p, q, w.y, w.z, lds);
+            else b16::bf16_pass2_body<LL, NP>(d.p, q, w.y, w.z, lds);
         } else if constexpr (FORM == FORM_FUSED) {
             mfma_fused_body<LL>(d.p, w.y, lds);
         } else if constexpr (FORM == FORM_MFMA) {
@@ -118,6 +119,7 @@ SRMRA_CLASS(FORM_MFMA, 8) SRMRA_CLASS(FORM_MFMA, 12) SRMRA_CLASS(FORM_MFMA, 16)
 SRMRA_CLASS(FORM_MFMA, 24) SRMRA_CLASS(FORM_MFMA, 32) SRMRA_CLASS(FORM_MFMA, 48)
 SRMRA_CLASS(FORM_MFMA, 64)
 SRMRA_CLASS(FORM_BF16, 24) SRMRA_CLASS(FORM_BF16, 32)
+SRMRA_CLASS(FORM_BF16X4, 24) SRMRA_CLASS(FORM_BF16X4, 32)
 #undef SRMRA_CLASS
 #define SRMRA_FUSED(L) template __global__ void k_class_pass<2, FORM_FUSED, L>(const InstDesc*, const int4*, int, int*);
 SRMRA_FUSED(8) SRMRA_FUSED(12) SRMRA_FUSED(16) SRMRA_FUSED(24) SRMRA_FUSED(32) SRMRA_FUSED(48)
@@ -135,6 +137,7 @@ const void* class_pass_fn(int pass, int form, int LL) {
     SRMRA_PICK(FORM_MFMA, 24) SRMRA_PICK(FORM_MFMA, 32) SRMRA_PICK(FORM_MFMA, 48)
     SRMRA_PICK(FORM_MFMA, 64)
     SRMRA_PICK(FORM_BF16, 24) SRMRA_PICK(FORM_BF16, 32)
+    SRMRA_PICK(FORM_BF16X4, 24) SRMRA_PICK(FORM_BF16X4, 32)
 #undef SRMRA_PICK
     // single pass: no pass-1 kernel
 #define SRMRA_PICK(L) if (form == FORM_FUSED && LL == L) return pass == 2 ? (const void*)k_class_pass<2, FORM_FUSED, L> : nullptr;

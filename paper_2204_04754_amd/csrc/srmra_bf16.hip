@@ -4,16 +4,17 @@
 namespace srmra {
 namespace b16 {
 
-template <int LL>
+// NP: 3 or 4 BF16 products per multiply-add
+template <int LL, int NP>
 __global__ __launch_bounds__(256, 2) void k_score_lse_bf16(StepArgs p, Prep q) {
     extern __shared__ float lds[];
-    bf16_pass1_body<LL>(p, q, blockIdx.x, blockIdx.y, lds);
+    bf16_pass1_body<LL, NP>(p, q, blockIdx.x, blockIdx.y, lds);
 }
 
-template <int LL>
+template <int LL, int NP>
 __global__ __launch_bounds__(256) void k_backproject_bf16(StepArgs p, Prep q) {
     extern __shared__ float lds[];
-    bf16_pass2_body<LL>(p, q, blockIdx.x, blockIdx.y, lds);
+    bf16_pass2_body<LL, NP>(p, q, blockIdx.x, blockIdx.y, lds);
 }
 
 // x as MFMA B fragments: grid (KK, k-steps / 4), 256 threads (4 k-steps per block)
@@ -68,42 +69,51 @@ hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* cen
     return hipGetLastError();
 }
 
-template <int LL>
+template <int LL, int NP>
 static hipError_t launch_bf16_ll(int pass, const StepArgs& p, const b16::Prep& q, hipStream_t s) {
     const dim3 grid(p.n_chunks, p.n_cg);
     if (pass == 1) {
         const size_t lds = b16::lds_pass1<LL>();
-        (void)hipFuncSetAttribute((const void*)b16::k_score_lse_bf16<LL>,
+        (void)hipFuncSetAttribute((const void*)b16::k_score_lse_bf16<LL, NP>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(b16::k_score_lse_bf16<LL>, grid, dim3(256), lds, s, p, q);
+        hipLaunchKernelGGL((b16::k_score_lse_bf16<LL, NP>), grid, dim3(256), lds, s, p, q);
     } else {
         const size_t lds = b16::lds_pass2<LL>();
-        (void)hipFuncSetAttribute((const void*)b16::k_backproject_bf16<LL>,
+        (void)hipFuncSetAttribute((const void*)b16::k_backproject_bf16<LL, NP>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(b16::k_backproject_bf16<LL>, grid, dim3(256), lds, s, p, q);
+        hipLaunchKernelGGL((b16::k_backproject_bf16<LL, NP>), grid, dim3(256), lds, s, p, q);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_bf16(int LL, int pass, const StepArgs& p, const void* prep_extra, hipStream_t s) {
+hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
+                       hipStream_t s) {
     const b16::Prep q = prep_ptrs(prep_extra, LL, p.N);
-    if (LL == 24) return launch_bf16_ll<24>(pass, p, q, s);
-    if (LL == 32) return launch_bf16_ll<32>(pass, p, q, s);
+    if (LL == 24) return np == 4 ? launch_bf16_ll<24, 4>(pass, p, q, s) : launch_bf16_ll<24, 3>(pass, p, q, s);
+    if (LL == 32) return np == 4 ? launch_bf16_ll<32, 4>(pass, p, q, s) : launch_bf16_ll<32, 3>(pass, p, q, s);
     return hipErrorInvalidValue;
 }
 
-bool bf16_geom(int LL, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
+template <int LL, int NP>
+static void bf16_geom_ll(size_t& lds1, size_t& lds2, const void*& f1, const void*& f2) {
+    lds1 = b16::lds_pass1<LL>();
+    lds2 = b16::lds_pass2<LL>();
+    f1 = (const void*)b16::k_score_lse_bf16<LL, NP>;
+    f2 = (const void*)b16::k_backproject_bf16<LL, NP>;
+}
+
+bool bf16_geom(int LL, int np, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
                const void*& f2) {
     cpb = 4;
     nt = 8;
     if (LL == 24) {
-        lds1 = b16::lds_pass1<24>(); lds2 = b16::lds_pass2<24>();
-        f1 = (const void*)b16::k_score_lse_bf16<24>; f2 = (const void*)b16::k_backproject_bf16<24>;
+        if (np == 4) bf16_geom_ll<24, 4>(lds1, lds2, f1, f2);
+        else bf16_geom_ll<24, 3>(lds1, lds2, f1, f2);
         return true;
     }
     if (LL == 32) {
-        lds1 = b16::lds_pass1<32>(); lds2 = b16::lds_pass2<32>();
-        f1 = (const void*)b16::k_score_lse_bf16<32>; f2 = (const void*)b16::k_backproject_bf16<32>;
+        if (np == 4) bf16_geom_ll<32, 4>(lds1, lds2, f1, f2);
+        else bf16_geom_ll<32, 3>(lds1, lds2, f1, f2);
         return true;
     }
     return false;

@@ -3,7 +3,8 @@
 //
 // Every FP32 operand v is split as v = hi + lo + O(2^-17 |v|) with
 // hi = bf16_rne(v), lo = bf16_rne(v - hi); a product is formed as
-// hi*hi + hi*lo + lo*hi with v_mfma_f32_32x32x16_bf16 and FP32 accumulation.
+// hi*hi + hi*lo + lo*hi (NP = 3) or with lo*lo as well (NP = 4) with
+// v_mfma_f32_32x32x16_bf16 and FP32 accumulation.
 //
 // Score tile (rows t2, cols t1, k = (b2, r1) over the pixels, runs of 8 r1):
 //   A[t2][k] = y_i[r1][(b2+t2) % Ll]   from prepared BF16 hi/lo planes of y
@@ -65,11 +66,13 @@ __device__ __forceinline__ void split8(const float (&v)[8], bf16x8& h, bf16x8& l
     }
 }
 
-__device__ __forceinline__ floatx16 mfma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
-                                          const bf16x8& bl, floatx16 c) {
+template <int NP>
+__device__ __forceinline__ floatx16 mfma_split(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
+                                               const bf16x8& bl, floatx16 c) {
     c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c, 0, 0, 0);
+    if constexpr (NP == 4) c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bl, c, 0, 0, 0);
     return c;
 }
 
@@ -127,7 +130,7 @@ __device__ __forceinline__ void load_yo(const Prep& q, int64_t o0, __bf16* yo) {
 }
 
 // Score tiles for NO observations (slots o_slot[k]) x NC components (LDS slots cs[k]).
-template <int LL, int NO, int NC>
+template <int LL, int NO, int NC, int NP>
 __device__ __forceinline__ void score(const StepArgs& p, const __bf16* ys, const int (&oslot)[NO],
                                       const int (&cgl)[NC], floatx16 (&acc)[NO][NC]) {
     constexpr int JS = R1P / 16;
@@ -192,6 +195,13 @@ __device__ __forceinline__ void score(const StepArgs& p, const __bf16* ys, const
 #pragma unroll
                 for (int c = 0; c < NC; ++c)
                     acc[o][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o], bh[c], acc[o][c], 0, 0, 0);
+            if constexpr (NP == 4) {
+#pragma unroll
+                for (int o = 0; o < NO; ++o)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        acc[o][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o], bl[c], acc[o][c], 0, 0, 0);
+            }
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 bh[c] = nh[c];
@@ -206,7 +216,7 @@ __device__ __forceinline__ int acc_row(int v, int lane) { return 8 * (v >> 2) + 
 // ============================================================================
 // Pass 1.  Block = 8 observations x 4 components; wave w: observations 4*(w&1)..+4,
 // components 2*(w>>1)..+2 of the block's group.  Partials per component pair.
-template <int LL>
+template <int LL, int NP>
 __device__ __forceinline__ void bf16_pass1_body(const StepArgs& p, const Prep& q, int chunk, int cg,
                                                 float* lds) {
     using G = Geo<LL>;
@@ -226,7 +236,7 @@ __device__ __forceinline__ void bf16_pass1_body(const StepArgs& p, const Prep& q
         load_yT<LL>(p, q, o0, ys);
         __syncthreads();
         floatx16 acc[4][2];
-        score<LL, 4, 2>(p, ys, oslot, cgl, acc);
+        score<LL, 4, 2, NP>(p, ys, oslot, cgl, acc);
         float mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
         // the bias of a lane's (component, t1, t2) slots does not depend on the
         // observation: load it once per tile
@@ -276,7 +286,7 @@ __device__ __forceinline__ void bf16_pass1_body(const StepArgs& p, const Prep& q
 // ============================================================================
 // Pass 2.  Block = 8 observations x 4 components; wave w owns component
 // cg*4 + w for all 8 observations.
-template <int LL>
+template <int LL, int NP>
 __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q, int chunk_i, int cg,
                                                 float* lds) {
     using G = Geo<LL>;
@@ -303,7 +313,7 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
         load_yo<LL>(q, o0, yo);
         __syncthreads();
         floatx16 acc[8][1];
-        score<LL, 8, 1>(p, ys, oslot, cgl, acc);
+        score<LL, 8, 1, NP>(p, ys, oslot, cgl, acc);
         // posterior weights, posterior mass, BF16 hi/lo fragments over k = (t2, o)
         bf16x8 wh[16], wl[16];
         float lse[8];
@@ -341,7 +351,7 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
                 col = col >= LL ? col - LL : col;
                 const bf16x8 ah = *reinterpret_cast<const bf16x8*>(yrow + col * 8);
                 const bf16x8 al = *reinterpret_cast<const bf16x8*>(yrow + LL * LL * 8 + col * 8);
-                zp[v & 3] = mfma3(ah, al, wh[v], wl[v], zp[v & 3]);
+                zp[v & 3] = mfma_split<NP>(ah, al, wh[v], wl[v], zp[v & 3]);
             }
             floatx16 z;
 #pragma unroll

@@ -56,7 +56,7 @@ U_SPLIT = 2.0 ** -16
 
 
 def unit_roundoff(precision):
-    return U_SPLIT if precision == "bf16_split3" else U32
+    return U_SPLIT if precision in ("bf16_split3", "bf16_split4") else U32
 
 
 def check_step(y, x, log_rho, sigma, K, g, ref, x_tol=1e-4, rho_tol=1e-4, ll_c=16.0, u=None):

@@ -149,3 +149,18 @@ def test_tuning_table_validated_on_host(L):
     assert create(BF, [(F32, 32, 2, F32, 100)]) == B.SRMRA_OK       # other precision: ignored
     assert create(F32, [(F32, 32, 2, F32, 37)]) == B.SRMRA_OK
     assert B.srmra_plan_default_item_obs(1000, 32, 2, "fp32_mfma") > 0
+
+
+def test_split4_precision_accepted():
+    """SRMRA_BF16_SPLIT4 has the same shapes, preparation and workspace as the
+    3-product form, and the same L_low restriction."""
+    from paper_2204_04754_amd import binding as B
+    for N, ll, K in ((1000, 32, 2), (5000, 24, 4)):
+        assert B.srmra_em_step_workspace_bytes(N, ll, K, "bf16_split4") == \
+            B.srmra_em_step_workspace_bytes(N, ll, K, "bf16_split3") > 0
+        assert B.srmra_prepared_bytes(N, ll, K, "bf16_split4") == \
+            B.srmra_prepared_bytes(N, ll, K, "bf16_split3") > 0
+    assert B.srmra_em_step_workspace_bytes(1000, 16, 2, "bf16_split4") == 0
+    assert B.srmra_plan_form(B.SRMRA_BF16_SPLIT4, 32) == B.SRMRA_BF16_SPLIT4
+    assert B.srmra_plan_form(B.SRMRA_BF16_SPLIT4, 16) == B.SRMRA_FP32_MFMA
+    assert B.srmra_plan_form(4, 32) == -1

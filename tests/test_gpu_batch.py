@@ -32,7 +32,7 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16_split3", "fp32_plain"])
+@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16_split3", "bf16_split4", "fp32_plain"])
 def test_mixed_batch_matches_oracle(prec):
     ins = _instances(MIX)
     be = BatchedEM(ins, precision=prec)
@@ -42,7 +42,7 @@ def test_mixed_batch_matches_oracle(prec):
         inst = d["inst"]
         g = be.results(j)
         ref = O.em_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, return_details=True)
-        u = U_SPLIT if (prec == "bf16_split3" and inst.Ll in (24, 32)) else U32
+        u = U_SPLIT if (prec.startswith("bf16") and inst.Ll in (24, 32)) else U32
         check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, u=u)
 
 

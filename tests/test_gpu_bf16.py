@@ -20,13 +20,14 @@ def _gpu():
 
 # ragged N (no multiple of the 8-observation tile), enough observations that
 # every component carries at least one observation's worth of posterior mass
+@pytest.mark.parametrize("prec", ["bf16_split3", "bf16_split4"])
 @pytest.mark.parametrize("Lh,K,N,sigma", [(48, 2, 41, 2.0), (64, 2, 27, 2.0), (96, 4, 151, 2.0),
                                           (128, 4, 133, 2.0), (96, 3, 77, 2.0), (64, 2, 600, 0.7)])
-def test_shapes(Lh, K, N, sigma):
+def test_shapes(Lh, K, N, sigma, prec):
     inst = synth.make_instance(Lh, K, N, sigma, config=60, instance=Lh + K)
     rng = np.random.default_rng(Lh * K)
     lr = np.log(np.stack([rng.dirichlet(np.ones(Lh)), rng.dirichlet(np.ones(Lh))])).astype(np.float32)
-    g = gpu_step(inst.y, inst.x0, lr, sigma, K, "bf16_split3")
+    g = gpu_step(inst.y, inst.x0, lr, sigma, K, prec)
     ref = O.em_step(inst.y, inst.x0, lr, sigma, K, return_details=True)
     ex, er = check_step(inst.y, inst.x0, lr, sigma, K, g, ref, u=U_SPLIT)
     print(f"Lh {Lh} K {K} N {N}: x {ex:.2e} rho {er:.2e}")
@@ -34,15 +35,16 @@ def test_shapes(Lh, K, N, sigma):
     assert rel(g["b"], ref["b"]) < 1e-4
 
 
+@pytest.mark.parametrize("prec", ["bf16_split3", "bf16_split4"])
 @pytest.mark.parametrize("sigma", [0.5, 2.0])
-def test_precision_workload_subset(sigma):
+def test_precision_workload_subset(sigma, prec):
     """The precision-study shape (Lh 128, K 4, Ll 32) on a 200-observation
     prefix, two consecutive steps from the GPU's own iterate."""
     name = "lh128_k4_n200000_s0.5" if sigma == 0.5 else "lh128_k4_n200000_s2"
     inst = synth.workload(name, N=200)
     x, lr = inst.x0, inst.log_rho0
     for it in range(2):
-        g = gpu_step(inst.y, x, lr, sigma, 4, "bf16_split3")
+        g = gpu_step(inst.y, x, lr, sigma, 4, prec)
         ref = O.em_step(inst.y, x, lr, sigma, 4, return_details=True)
         ex, er = check_step(inst.y, x, lr, sigma, 4, g, ref, u=U_SPLIT)
         # b and c are sums of few weights when the posterior is sharp (sigma 0.5),
