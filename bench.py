@@ -80,10 +80,12 @@ def parse():
                     help="target oracle time on the host for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "serve"],
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "serve", "errors"],
                     help="single: one instance (default); batched: 64-instance mix, 20 iterations "
                          "captured as a HIP graph; serve: Poisson job arrivals, continuous batching")
     ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--error-obs", type=int, default=2000,
+                    help="errors mode: observations in the subset the oracle runs on")
     ap.add_argument("--no-tune", action="store_true", help="batched mode: skip the autotuned runs")
     ap.add_argument("--iterations", type=int, default=20)
     ap.add_argument("--rates", default="5,50,200")
@@ -258,6 +260,52 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_errors(args):
+    """Error table: one EM step of every precision form against the FP64 oracle
+    on the first `error_obs` observations of the precision-study workloads
+    (sigma 0.5 and 2; and the [0, 1]-image variant with and without centring),
+    from the initial iterate and from the true image and prior.  Relative
+    norm-wise errors of x' (all pixels, and components with at least one
+    observation's posterior mass), rho', loglik, and the mean absolute error of
+    the per-observation log-likelihood terms."""
+    from oracle import em_oracle as O
+    from paper_2204_04754_amd import synth
+    from tests.gpu_helpers import gpu_step, rel
+
+    cases = [("lh128_k4_n200000_s0.5", True), ("lh128_k4_n200000_s2", True),
+             ("lh128_k4_n200000_unit_s0.25", True), ("lh128_k4_n200000_unit_s0.25", False)]
+    precs = ["fp32_plain", "fp32_mfma", "bf16_split3", "bf16_split4"]
+    rows = []
+    cores = len(os.sched_getaffinity(0))
+    for name, centre in cases:
+        t = time.perf_counter()
+        inst = synth.workload(name)
+        y = np.ascontiguousarray(inst.y[:args.error_obs])
+        K, sig, Lh = inst.K, inst.sigma, inst.Lh
+        starts = {"init": (inst.x0, inst.log_rho0),
+                  "truth": (inst.x_true, np.log(np.stack([inst.rho1, inst.rho2])).astype(np.float32))}
+        for sname, (x, lr) in starts.items():
+            ref = O.em_step(y, x, lr, sig, K, return_details=True)
+            keep = ref["a"] >= 1.0
+            print(f"[bench] errors {name} centre={centre} start={sname}: oracle done "
+                  f"({time.perf_counter() - t:.0f} s)", file=sys.stderr, flush=True)
+            for prec in precs:
+                g = gpu_step(y, x, lr, sig, K, prec, centre=centre)
+                rows.append(dict(workload=name, centre=centre, start=sname, precision=prec,
+                                 x=rel(g["x_new"], ref["x_new"]),
+                                 x_mass1=rel(g["x_new"][keep], ref["x_new"][keep]),
+                                 mass1_frac=float(keep.mean()),
+                                 rho=rel(g["rho_new"], ref["rho_new"]),
+                                 loglik=abs(g["loglik"] - ref["loglik"]) / abs(ref["loglik"]),
+                                 lse_mean_abs=float(np.mean(np.abs(g["ll_obs"] - ref["lse"])))))
+    out = {"metric": "relative error vs FP64 oracle (one EM step)", "value": None, "unit": "",
+           "n_gpus": 1, "data": "synthetic", "config": {"workload": "precision study subsets",
+                                                        "observations": args.error_obs,
+                                                        "oracle_cores": cores},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def bench_serve(args):
     """Poisson arrivals of 20-iteration jobs (90% drawn from the batched mix,
     10% Lh 256, K 4, N 20000), swept over arrival rates; solves/s and p50/p99
@@ -316,6 +364,8 @@ def main():
         sys.exit(2)
     if args.mode == "batched":
         return bench_batched(args)
+    if args.mode == "errors":
+        return bench_errors(args)
     if args.mode == "serve":
         return bench_serve(args)
     import torch
