@@ -80,10 +80,12 @@ def parse():
                     help="target oracle time on the host for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "serve", "errors"],
+    ap.add_argument("--mode", default="single",
+                    choices=["single", "batched", "serve", "errors", "projected"],
                     help="single: one instance (default); batched: 64-instance mix, 20 iterations "
                          "captured as a HIP graph; serve: Poisson job arrivals, continuous batching")
     ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--outer", type=int, default=4, help="projected mode: outer iterations in the graph")
     ap.add_argument("--error-obs", type=int, default=2000,
                     help="errors mode: observations in the subset the oracle runs on")
     ap.add_argument("--no-tune", action="store_true", help="batched mode: skip the autotuned runs")
@@ -260,6 +262,50 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_projected(args):
+    """Projected EM (Alg. 2): F = 5 EM steps then the Gaussian-smoothing
+    projection and the noise-level decay, `outer` outer iterations captured as
+    one HIP graph; throughput over the EM steps with the projections inside
+    the timed region, and the projection's own time."""
+    import torch
+    from paper_2204_04754_amd import binding as B
+    from paper_2204_04754_amd import synth
+    from paper_2204_04754_amd.projected import ProjectedEM
+
+    inst = synth.workload(args.workload)
+    F, T = 5, args.outer
+    pe = ProjectedEM(inst.y, inst.K, inst.sigma, inst.x0, inst.log_rho0, precision=args.precision, F=F)
+    g = pe.capture(T)
+    g.replay()                                        # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_outer = e0.elapsed_time(e1) / T
+    # the projection alone (50 calls on the current iterate's copy)
+    x = pe.x.clone()
+    st = torch.ones(1, dtype=torch.float32, device="cuda")
+    e0.record()
+    for _ in range(50):
+        B.srmra_project_gaussian(x, x, inst.Lh, st, 1.0, pe.pws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_proj = e0.elapsed_time(e1) / 50
+    ms_step = ms_outer / F
+    out = {"metric": METRIC, "value": inst.pairs_per_step / (ms_step * 1e-3), "unit": "obs×shift pairs/s",
+           "n_gpus": 1, "steps": F * T, "warmup": F * T, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": DTYPE[args.precision], "data": "synthetic",
+           "config": {"workload": args.workload, "algorithm": "projected EM", "F": F,
+                      "outer_iterations_in_graph": T, "projection": "gaussian, s_1 = 1, decay 2^-1/10",
+                      "precision": args.precision},
+           "ms_per_outer_iteration": ms_outer, "projection_ms": ms_proj,
+           "sigma_after": float(pe.sigma_state.item())}
+    print(json.dumps(out), flush=True)
+
+
 def bench_errors(args):
     """Error table: one EM step of every precision form against the FP64 oracle
     on the first `error_obs` observations of the precision-study workloads
@@ -366,6 +412,8 @@ def main():
         return bench_batched(args)
     if args.mode == "errors":
         return bench_errors(args)
+    if args.mode == "projected":
+        return bench_projected(args)
     if args.mode == "serve":
         return bench_serve(args)
     import torch

@@ -265,6 +265,25 @@ int srmra_plan_upload(srmra_plan* plan, void* workspace, size_t workspace_bytes,
 int srmra_plan_execute(srmra_plan* plan, void* workspace, size_t workspace_bytes,
                        hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Projection step of the projected EM (Alg. 2): x_out = D(x_in, s) with s
+ * read from the device scalar *sigma_state, then *sigma_state = s * decay in
+ * FP32 (eq. decaying_function: sigma_1 = 1, decay = 2^(-1/10)).  The
+ * denoiser D (BM3D in the paper) is a circular Gaussian blur of standard
+ * deviation s pixels of the L_high x L_high grid: taps k in [-R, R] with
+ * R = min(floor(4 s + 1/2), L_high), weights exp(-k^2 / 2 s^2) normalised to
+ * sum 1, applied along axis 0 and then axis 1 with circular boundary; s below
+ * 1/8, not positive or not finite gives R = 0 (the identity).
+ * x_in, x_out: device [L_high][L_high] (x_out may equal x_in); sigma_state:
+ * device float, read and updated in stream order; workspace: 256-byte
+ * aligned, srmra_project_workspace_bytes(L_high) bytes, content not
+ * preserved.  L_high in [1, 4096], decay > 0 and finite, else SRMRA_EINVAL.
+ * Three kernel launches, no host synchronisation: graph-capturable. */
+size_t srmra_project_workspace_bytes(int L_high);
+int srmra_project_gaussian(const float* x_in, float* x_out, int L_high,
+                           float* sigma_state, float decay, void* workspace,
+                           size_t workspace_bytes, hipStream_t stream);
+
 /* Parity of the next execution (0: reads x/log_rho), -1 for NULL. */
 int srmra_plan_parity(const srmra_plan* plan);
 

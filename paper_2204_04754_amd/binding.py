@@ -114,6 +114,10 @@ def lib():
             L.srmra_plan_upload.argtypes = [_vp, _vp, _sz, _vp]
             L.srmra_plan_execute.restype = _int
             L.srmra_plan_execute.argtypes = [_vp, _vp, _sz, _vp]
+            L.srmra_project_workspace_bytes.restype = _sz
+            L.srmra_project_workspace_bytes.argtypes = [_int]
+            L.srmra_project_gaussian.restype = _int
+            L.srmra_project_gaussian.argtypes = [_vp, _vp, _int, _vp, _f, _vp, _sz, _vp]
             L.srmra_plan_destroy.restype = None
             L.srmra_plan_destroy.argtypes = [_vp]
             _lib = L
@@ -311,6 +315,19 @@ def srmra_plan_default_item_obs(N: int, L_low: int, K: int, form_precision) -> i
     r = int(lib().srmra_plan_default_item_obs(N, L_low, K, _prec(form_precision)))
     _check(r if r < 0 else 0, "srmra_plan_default_item_obs")
     return r
+
+
+def srmra_project_workspace_bytes(L_high: int) -> int:
+    return int(lib().srmra_project_workspace_bytes(L_high))
+
+
+def srmra_project_gaussian(x_in: torch.Tensor, x_out: torch.Tensor, L_high: int,
+                           sigma_state: torch.Tensor, decay: float, workspace: torch.Tensor,
+                           stream=None) -> None:
+    _check(lib().srmra_project_gaussian(_ptr(x_in, torch.float32), _ptr(x_out, torch.float32), L_high,
+                                        _ptr(sigma_state, torch.float32), float(decay),
+                                        _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                        _stream(stream)), "srmra_project_gaussian")
 
 
 def empty_bytes(nbytes: int, device="cuda") -> torch.Tensor:

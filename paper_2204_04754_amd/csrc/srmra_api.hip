@@ -41,6 +41,10 @@ hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* cen
 size_t bf16_prepared_extra(int LL, int64_t N);
 size_t bf16_xb_bytes(int LL, int KK);
 hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, hipStream_t s);
+// projection of Alg. 2 (srmra_project.hip)
+size_t project_workspace_bytes(int Lh);
+hipError_t launch_project(const float* x_in, float* x_out, int Lh, float* sigma_state, float decay,
+                          void* workspace, hipStream_t s);
 }  // namespace srmra
 
 using namespace srmra;
@@ -713,5 +717,21 @@ int srmra_plan_execute(srmra_plan* plan, void* workspace, size_t workspace_bytes
 int srmra_plan_parity(const srmra_plan* plan) { return plan ? plan->parity : -1; }
 
 void srmra_plan_destroy(srmra_plan* plan) { delete plan; }
+
+size_t srmra_project_workspace_bytes(int L_high) {
+    if (L_high < 1 || L_high > 4096) return 0;
+    return project_workspace_bytes(L_high);
+}
+
+int srmra_project_gaussian(const float* x_in, float* x_out, int L_high, float* sigma_state,
+                           float decay, void* workspace, size_t workspace_bytes,
+                           hipStream_t stream) {
+    if (!x_in || !x_out || !sigma_state || L_high < 1 || L_high > 4096) return SRMRA_EINVAL;
+    if (!(decay > 0.f) || !isfinite(decay)) return SRMRA_EINVAL;
+    if (!workspace || !aligned(workspace) || workspace_bytes < project_workspace_bytes(L_high))
+        return SRMRA_EWORKSPACE;
+    return launch_project(x_in, x_out, L_high, sigma_state, decay, workspace, stream) == hipSuccess
+               ? SRMRA_OK : SRMRA_EDEVICE;
+}
 
 }  // extern "C"

@@ -34,6 +34,7 @@ def test_header_declares_the_entry_points():
               "srmra_em_step_workspace_bytes", "srmra_prepared_bytes", "srmra_em_step_debug",
               "srmra_plan_create", "srmra_plan_create_tuned", "srmra_plan_default_item_obs",
               "srmra_plan_execute", "srmra_plan_destroy", "srmra_em_step_passes",
+              "srmra_project_gaussian", "srmra_project_workspace_bytes", "srmra_prepare_observations_ex",
               "srmra_status_string"]:
         assert n in names
 
@@ -164,3 +165,21 @@ def test_split4_precision_accepted():
     assert B.srmra_plan_form(B.SRMRA_BF16_SPLIT4, 32) == B.SRMRA_BF16_SPLIT4
     assert B.srmra_plan_form(B.SRMRA_BF16_SPLIT4, 16) == B.SRMRA_FP32_MFMA
     assert B.srmra_plan_form(4, 32) == -1
+
+
+def test_projection_host_validation(L):
+    """srmra_project_gaussian rejects bad sizes, pointers, decay and workspace on
+    the host (nothing is enqueued)."""
+    import ctypes
+    from paper_2204_04754_amd import binding as B
+    a, b, s, w = (ctypes.c_void_p(v) for v in (0x1000, 0x2000, 0x3000, 0x10000))
+    nb = B.srmra_project_workspace_bytes(64)
+    assert nb >= 64 * 64 * 4 and B.srmra_project_workspace_bytes(0) == 0
+    assert B.srmra_project_workspace_bytes(5000) == 0
+    assert L.srmra_project_gaussian(None, b, 64, s, 0.9, w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_project_gaussian(a, b, 0, s, 0.9, w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_project_gaussian(a, b, 64, None, 0.9, w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_project_gaussian(a, b, 64, s, 0.0, w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_project_gaussian(a, b, 64, s, float("inf"), w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_project_gaussian(a, b, 64, s, 0.9, w, nb - 1, None) == B.SRMRA_EWORKSPACE
+    assert L.srmra_project_gaussian(a, b, 64, s, 0.9, ctypes.c_void_p(0x10010), nb, None) == B.SRMRA_EWORKSPACE
