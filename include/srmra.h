@@ -284,6 +284,18 @@ int srmra_project_gaussian(const float* x_in, float* x_out, int L_high,
                            float* sigma_state, float decay, void* workspace,
                            size_t workspace_bytes, hipStream_t stream);
 
+/* The paper's reconstruction error (Sec. 5): *err = min over circular 2-D
+ * translations s of ||R_s x_hat - x_ref||_F / ||x_ref||_F, (R_s v)[m] =
+ * v[m - s], every distance summed directly in FP64; best_shift (device int[2],
+ * may be NULL) receives the minimising (s1, s2), the lowest s1 * L_high + s2
+ * on ties.  x_hat, x_ref: device [L_high][L_high]; err: device double;
+ * workspace: srmra_shift_error_workspace_bytes(L_high) bytes, 256-byte
+ * aligned.  L_high in [1, 512] (the work grows as L_high^4). */
+size_t srmra_shift_error_workspace_bytes(int L_high);
+int srmra_shift_error(const float* x_hat, const float* x_ref, int L_high, double* err,
+                      int* best_shift, void* workspace, size_t workspace_bytes,
+                      hipStream_t stream);
+
 /* Parity of the next execution (0: reads x/log_rho), -1 for NULL. */
 int srmra_plan_parity(const srmra_plan* plan);
 

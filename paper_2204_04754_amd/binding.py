@@ -118,6 +118,10 @@ def lib():
             L.srmra_project_workspace_bytes.argtypes = [_int]
             L.srmra_project_gaussian.restype = _int
             L.srmra_project_gaussian.argtypes = [_vp, _vp, _int, _vp, _f, _vp, _sz, _vp]
+            L.srmra_shift_error_workspace_bytes.restype = _sz
+            L.srmra_shift_error_workspace_bytes.argtypes = [_int]
+            L.srmra_shift_error.restype = _int
+            L.srmra_shift_error.argtypes = [_vp, _vp, _int, _vp, _vp, _vp, _sz, _vp]
             L.srmra_plan_destroy.restype = None
             L.srmra_plan_destroy.argtypes = [_vp]
             _lib = L
@@ -328,6 +332,18 @@ def srmra_project_gaussian(x_in: torch.Tensor, x_out: torch.Tensor, L_high: int,
                                         _ptr(sigma_state, torch.float32), float(decay),
                                         _ptr(workspace), workspace.numel() * workspace.element_size(),
                                         _stream(stream)), "srmra_project_gaussian")
+
+
+def srmra_shift_error_workspace_bytes(L_high: int) -> int:
+    return int(lib().srmra_shift_error_workspace_bytes(L_high))
+
+
+def srmra_shift_error(x_hat: torch.Tensor, x_ref: torch.Tensor, L_high: int, err: torch.Tensor,
+                      best_shift: Optional[torch.Tensor], workspace: torch.Tensor, stream=None) -> None:
+    _check(lib().srmra_shift_error(_ptr(x_hat, torch.float32), _ptr(x_ref, torch.float32), L_high,
+                                   _ptr(err, torch.float64), _ptr(best_shift, torch.int32),
+                                   _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                   _stream(stream)), "srmra_shift_error")
 
 
 def empty_bytes(nbytes: int, device="cuda") -> torch.Tensor:

@@ -45,6 +45,10 @@ hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, h
 size_t project_workspace_bytes(int Lh);
 hipError_t launch_project(const float* x_in, float* x_out, int Lh, float* sigma_state, float decay,
                           void* workspace, hipStream_t s);
+// reconstruction error (srmra_quality.hip)
+size_t shift_error_workspace_bytes(int Lh);
+hipError_t launch_shift_error(const float* xh, const float* x, int Lh, double* err, int* best,
+                              void* ws, hipStream_t s);
 }  // namespace srmra
 
 using namespace srmra;
@@ -721,6 +725,20 @@ void srmra_plan_destroy(srmra_plan* plan) { delete plan; }
 size_t srmra_project_workspace_bytes(int L_high) {
     if (L_high < 1 || L_high > 4096) return 0;
     return project_workspace_bytes(L_high);
+}
+
+size_t srmra_shift_error_workspace_bytes(int L_high) {
+    if (L_high < 1 || L_high > 512) return 0;
+    return shift_error_workspace_bytes(L_high);
+}
+
+int srmra_shift_error(const float* x_hat, const float* x_ref, int L_high, double* err,
+                      int* best_shift, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (!x_hat || !x_ref || !err || L_high < 1 || L_high > 512) return SRMRA_EINVAL;
+    if (!workspace || !aligned(workspace) || workspace_bytes < shift_error_workspace_bytes(L_high))
+        return SRMRA_EWORKSPACE;
+    return launch_shift_error(x_hat, x_ref, L_high, err, best_shift, workspace, stream) == hipSuccess
+               ? SRMRA_OK : SRMRA_EDEVICE;
 }
 
 int srmra_project_gaussian(const float* x_in, float* x_out, int L_high, float* sigma_state,

@@ -35,6 +35,7 @@ def test_header_declares_the_entry_points():
               "srmra_plan_create", "srmra_plan_create_tuned", "srmra_plan_default_item_obs",
               "srmra_plan_execute", "srmra_plan_destroy", "srmra_em_step_passes",
               "srmra_project_gaussian", "srmra_project_workspace_bytes", "srmra_prepare_observations_ex",
+              "srmra_shift_error", "srmra_shift_error_workspace_bytes",
               "srmra_status_string"]:
         assert n in names
 
@@ -183,3 +184,15 @@ def test_projection_host_validation(L):
     assert L.srmra_project_gaussian(a, b, 64, s, float("inf"), w, nb, None) == B.SRMRA_EINVAL
     assert L.srmra_project_gaussian(a, b, 64, s, 0.9, w, nb - 1, None) == B.SRMRA_EWORKSPACE
     assert L.srmra_project_gaussian(a, b, 64, s, 0.9, ctypes.c_void_p(0x10010), nb, None) == B.SRMRA_EWORKSPACE
+
+
+def test_shift_error_host_validation(L):
+    import ctypes
+    from paper_2204_04754_amd import binding as B
+    a, b, e, w = (ctypes.c_void_p(v) for v in (0x1000, 0x2000, 0x3000, 0x10000))
+    nb = B.srmra_shift_error_workspace_bytes(64)
+    assert nb == 64 * 64 * 8 and B.srmra_shift_error_workspace_bytes(513) == 0
+    assert L.srmra_shift_error(None, b, 64, e, None, w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_shift_error(a, b, 64, None, None, w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_shift_error(a, b, 600, e, None, w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_shift_error(a, b, 64, e, None, w, nb - 8, None) == B.SRMRA_EWORKSPACE

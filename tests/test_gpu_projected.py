@@ -88,3 +88,24 @@ def test_projected_graph_replays_match_eager():
         assert torch.equal(graphed.sigma_state, eager.sigma_state), rep
         assert torch.equal(graphed.job.loglik, eager.job.loglik), rep
     del junk
+
+
+@pytest.mark.parametrize("Lh", [16, 48, 128])
+def test_shift_error_matches_oracle(Lh):
+    from oracle import quality as Q
+    rng = np.random.default_rng(Lh + 7)
+    x = rng.standard_normal((Lh, Lh)).astype(np.float32)
+    xh = (np.roll(x, (3, Lh - 5), axis=(0, 1)) + 0.3 * rng.standard_normal((Lh, Lh))).astype(np.float32)
+    ws = B.empty_bytes(B.srmra_shift_error_workspace_bytes(Lh))
+    err = torch.empty(1, dtype=torch.float64, device="cuda")
+    best = torch.empty(2, dtype=torch.int32, device="cuda")
+    B.srmra_shift_error(torch.as_tensor(xh).cuda(), torch.as_tensor(x).cuda(), Lh, err, best, ws)
+    torch.cuda.synchronize()
+    ref, s = Q.shift_invariant_error(xh, x)
+    assert abs(err.item() - ref) <= 1e-12 * ref
+    assert tuple(best.cpu().tolist()) == s
+    # exact recovery up to a translation reads exactly 0
+    xr = torch.as_tensor(np.roll(x, (1, 2), axis=(0, 1))).cuda()
+    B.srmra_shift_error(xr, torch.as_tensor(x).cuda(), Lh, err, None, ws)
+    torch.cuda.synchronize()
+    assert err.item() == 0.0
