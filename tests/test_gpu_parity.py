@@ -43,6 +43,8 @@ SHAPES = [  # (Lh, K, N): every supported L_low, ragged N
     # FP32 MFMA single pass with 3 component groups rounded up to 4 (one idle
     # wave group), and K = 1 (one component, the other slot masked)
     (36, 3, 23), (48, 3, 13), (32, 1, 7),
+    # the largest K^2 (256), at L_low 8
+    (128, 16, 5),
 ]
 
 
@@ -123,3 +125,40 @@ def test_centring_offset_invariance(prec):
     g_off = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 2, prec, centre=False)
     assert rel(g_off["x_new"], g0["x_new"]) < 1e-5
     assert abs(g_off["loglik"] - g0["loglik"]) < 1e-6 * abs(g0["loglik"])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_largest_supported_grid(prec):
+    """L_high 1024 (L_low 64, K 16: K^2 = 256 components, the library's
+    limits).  The oracle's explicit loop over 2^20 shifts is too slow here, so
+    properties that hold at any size are checked: every observation's
+    posterior sums to 1, rho rows sum to 1, loglik is the sum of its terms, x'
+    keeps x where a component has no mass and is a posterior average of
+    observed values elsewhere, and the result is deterministic."""
+    N = 5
+    inst = synth.make_instance(1024, 16, N, 30.0, config=54)
+    g = gpu_step(inst.y, inst.x0, inst.log_rho0, 30.0, 16, prec)
+    assert abs(g["c"].sum() - N) <= 1e-5 * N
+    assert np.allclose(g["rho_new"].sum(axis=1), 1.0, atol=1e-6)
+    assert abs(g["loglik"] - g["ll_obs"].sum()) <= 1e-5 * abs(g["loglik"])
+    assert np.all(np.isfinite(g["x_new"]))
+    assert g["x_new"].min() >= min(inst.y.min(), inst.x0.min()) - 1e-3
+    assert g["x_new"].max() <= max(inst.y.max(), inst.x0.max()) + 1e-3
+    h = gpu_step(inst.y, inst.x0, inst.log_rho0, 30.0, 16, prec)
+    assert np.array_equal(g["x_new"], h["x_new"]) and g["loglik"] == h["loglik"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_large_sigma_limit(prec):
+    """A step evaluated with sigma = 1000 on data of noise 1: the posterior is
+    the prior up to O(||y|| ||x|| / sigma^2) = O(1e-5) terms, so rho' is the
+    prior (Dirichlet here) and every component gets mass."""
+    Lh, K = 32, 2
+    inst = synth.make_instance(Lh, K, 50, 1.0, config=55)
+    rng = np.random.default_rng(5)
+    rho = np.stack([rng.dirichlet(np.ones(Lh)), rng.dirichlet(np.ones(Lh))])
+    lr = np.log(rho).astype(np.float32)
+    g = gpu_step(inst.y, inst.x0, lr, 1000.0, K, prec)
+    ref = O.em_step(inst.y, inst.x0, lr, 1000.0, K, return_details=True)
+    check_step(inst.y, inst.x0, lr, 1000.0, K, g, ref)
+    assert rel(g["rho_new"], np.exp(lr.astype(np.float64))) < 1e-4
