@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--mode", default="single",
-                    choices=["single", "batched", "serve", "errors", "projected"],
+                    choices=["single", "batched", "serve", "errors", "projected", "moments"],
                     help="single: one instance (default); batched: 64-instance mix, 20 iterations "
                          "captured as a HIP graph; serve: Poisson job arrivals, continuous batching")
     ap.add_argument("--instances", type=int, default=64)
@@ -321,6 +321,46 @@ def bench_projected(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_moments(args):
+    """Empirical moments M1, M2 of the workload's observation stack (one pass,
+    FP32 matrix cores for the Gram matrix): time per call and the Gram
+    kernel's rate against the FP32 matrix peak (algorithmic flops N P (P + 1)
+    for the symmetric product, P = Ll^2)."""
+    import torch
+    from paper_2204_04754_amd import binding as B
+    from paper_2204_04754_amd import synth
+
+    inst = synth.workload(args.workload)
+    N, Ll = inst.N, inst.Ll
+    P = Ll * Ll
+    y = torch.as_tensor(inst.y).cuda()
+    m1 = torch.empty(P, dtype=torch.float64, device="cuda")
+    m2 = torch.empty((P, P), dtype=torch.float64, device="cuda")
+    ws = B.empty_bytes(B.srmra_moments_workspace_bytes(N, Ll))
+    for _ in range(args.warmup):
+        B.srmra_moments(y, N, Ll, m1, m2, ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        B.srmra_moments(y, N, Ll, m1, m2, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    T = (P + 127) // 128
+    alg = float(N) * P * (P + 1)
+    issued = 2.0 * N * (T * (T + 1) // 2) * 128 * 128
+    out = {"metric": "empirical moments (eq. empiric_MOM) per second", "value": 1e3 / ms, "unit": "calls/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": args.workload, "N": N, "L_low": Ll, "P": P},
+           "roofline": {"bound": "mfma", "achieved": alg / (ms * 1e-3) / 1e12, "peak": 157.3,
+                        "unit": "TFLOP/s", "frac": alg / (ms * 1e-3) / 157.3e12,
+                        "issued_frac": issued / (ms * 1e-3) / 157.3e12, "traffic": None,
+                        "kernel": "whole call (Gram tiles + FP64 reductions)"}}
+    print(json.dumps(out), flush=True)
+
+
 def bench_errors(args):
     """Error table: one EM step of every precision form against the FP64 oracle
     on the first `error_obs` observations of the precision-study workloads
@@ -429,6 +469,8 @@ def main():
         return bench_errors(args)
     if args.mode == "projected":
         return bench_projected(args)
+    if args.mode == "moments":
+        return bench_moments(args)
     if args.mode == "serve":
         return bench_serve(args)
     import torch

@@ -284,6 +284,18 @@ int srmra_project_gaussian(const float* x_in, float* x_out, int L_high,
                            float* sigma_state, float decay, void* workspace,
                            size_t workspace_bytes, hipStream_t stream);
 
+/* Empirical moments of the observations (eq. empiric_MOM, the method of
+ * moments' summary of the data): m1[l] = (1/N) sum_i y_i[l] and
+ * m2[l][l'] = (1/N) sum_i y_i[l] y_i[l'] with l = n1 L_low + n2 (row-major
+ * pixel index), m2 symmetric of size L_low^2 x L_low^2.  One pass over y on
+ * FP32 matrix cores, per-chunk FP32 partials summed in FP64 in a fixed order
+ * (deterministic).  y: device [N][L_low][L_low], 16-byte aligned; m1, m2:
+ * device doubles; workspace: srmra_moments_workspace_bytes(N, L_low) bytes,
+ * 256-byte aligned.  L_low even in [2, 64], N >= 1, else SRMRA_EINVAL. */
+size_t srmra_moments_workspace_bytes(int64_t N, int L_low);
+int srmra_moments(const float* y, int64_t N, int L_low, double* m1, double* m2,
+                  void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* The paper's reconstruction error (Sec. 5): *err = min over circular 2-D
  * translations s of ||R_s x_hat - x_ref||_F / ||x_ref||_F, (R_s v)[m] =
  * v[m - s], every distance summed directly in FP64; best_shift (device int[2],

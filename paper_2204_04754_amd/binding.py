@@ -122,6 +122,10 @@ def lib():
             L.srmra_shift_error_workspace_bytes.argtypes = [_int]
             L.srmra_shift_error.restype = _int
             L.srmra_shift_error.argtypes = [_vp, _vp, _int, _vp, _vp, _vp, _sz, _vp]
+            L.srmra_moments_workspace_bytes.restype = _sz
+            L.srmra_moments_workspace_bytes.argtypes = [_i64, _int]
+            L.srmra_moments.restype = _int
+            L.srmra_moments.argtypes = [_vp, _i64, _int, _vp, _vp, _vp, _sz, _vp]
             L.srmra_plan_destroy.restype = None
             L.srmra_plan_destroy.argtypes = [_vp]
             _lib = L
@@ -332,6 +336,18 @@ def srmra_project_gaussian(x_in: torch.Tensor, x_out: torch.Tensor, L_high: int,
                                         _ptr(sigma_state, torch.float32), float(decay),
                                         _ptr(workspace), workspace.numel() * workspace.element_size(),
                                         _stream(stream)), "srmra_project_gaussian")
+
+
+def srmra_moments_workspace_bytes(N: int, L_low: int) -> int:
+    return int(lib().srmra_moments_workspace_bytes(N, L_low))
+
+
+def srmra_moments(y: torch.Tensor, N: int, L_low: int, m1: torch.Tensor, m2: torch.Tensor,
+                  workspace: torch.Tensor, stream=None) -> None:
+    _check(lib().srmra_moments(_ptr(y, torch.float32), N, L_low, _ptr(m1, torch.float64),
+                               _ptr(m2, torch.float64), _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), _stream(stream)),
+           "srmra_moments")
 
 
 def srmra_shift_error_workspace_bytes(L_high: int) -> int:

@@ -12,6 +12,7 @@
 #include "../../include/srmra.h"
 #include "srmra_batch.h"
 #include "srmra_common.h"
+#include "srmra_moments.h"
 
 namespace srmra {
 // aux kernels (srmra_aux.hip)
@@ -725,6 +726,21 @@ void srmra_plan_destroy(srmra_plan* plan) { delete plan; }
 size_t srmra_project_workspace_bytes(int L_high) {
     if (L_high < 1 || L_high > 4096) return 0;
     return project_workspace_bytes(L_high);
+}
+
+size_t srmra_moments_workspace_bytes(int64_t N, int L_low) {
+    if (N < 1 || L_low < 2 || L_low > 64 || L_low % 2) return 0;
+    return moments_geom(N, L_low, device_cus()).total;
+}
+
+int srmra_moments(const float* y, int64_t N, int L_low, double* m1, double* m2, void* workspace,
+                  size_t workspace_bytes, hipStream_t stream) {
+    if (!y || !m1 || !m2 || (uintptr_t)y % 16 != 0) return SRMRA_EINVAL;
+    if (N < 1 || N > (int64_t)INT32_MAX || L_low < 2 || L_low > 64 || L_low % 2) return SRMRA_EINVAL;
+    const MomentsGeom g = moments_geom(N, L_low, device_cus());
+    if (!workspace || !aligned(workspace) || workspace_bytes < g.total) return SRMRA_EWORKSPACE;
+    return launch_moments(y, N, L_low, m1, m2, workspace, g, stream) == hipSuccess ? SRMRA_OK
+                                                                                  : SRMRA_EDEVICE;
 }
 
 size_t srmra_shift_error_workspace_bytes(int L_high) {

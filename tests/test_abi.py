@@ -36,6 +36,7 @@ def test_header_declares_the_entry_points():
               "srmra_plan_execute", "srmra_plan_destroy", "srmra_em_step_passes",
               "srmra_project_gaussian", "srmra_project_workspace_bytes", "srmra_prepare_observations_ex",
               "srmra_shift_error", "srmra_shift_error_workspace_bytes",
+              "srmra_moments", "srmra_moments_workspace_bytes",
               "srmra_status_string"]:
         assert n in names
 
@@ -196,3 +197,17 @@ def test_shift_error_host_validation(L):
     assert L.srmra_shift_error(a, b, 64, None, None, w, nb, None) == B.SRMRA_EINVAL
     assert L.srmra_shift_error(a, b, 600, e, None, w, nb, None) == B.SRMRA_EINVAL
     assert L.srmra_shift_error(a, b, 64, e, None, w, nb - 8, None) == B.SRMRA_EWORKSPACE
+
+
+def test_moments_host_validation(L):
+    import ctypes
+    from paper_2204_04754_amd import binding as B
+    y, m1, m2, w = (ctypes.c_void_p(v) for v in (0x1000, 0x2000, 0x3000, 0x10000))
+    nb = B.srmra_moments_workspace_bytes(1000, 32)
+    assert nb > 0 and B.srmra_moments_workspace_bytes(1000, 33) == 0
+    assert B.srmra_moments_workspace_bytes(0, 32) == 0 and B.srmra_moments_workspace_bytes(10, 66) == 0
+    assert L.srmra_moments(None, 1000, 32, m1, m2, w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_moments(ctypes.c_void_p(0x1004), 1000, 32, m1, m2, w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_moments(y, 0, 32, m1, m2, w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_moments(y, 1000, 31, m1, m2, w, nb, None) == B.SRMRA_EINVAL
+    assert L.srmra_moments(y, 1000, 32, m1, m2, w, nb - 1, None) == B.SRMRA_EWORKSPACE
