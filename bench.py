@@ -48,9 +48,9 @@ _MFMA_SRC = ("srmra_common.h", "srmra_mfma_impl.h", "srmra_mfma.hip")
 _BF16_SRC = ("srmra_common.h", "srmra_bf16_impl.h", "srmra_bf16.hip")
 TRAFFIC = {
     ("lh64_k2_n100000", "fp32_mfma", "k_fused_mfma<32>"):
-        dict(bytes=428045926, src=_MFMA_SRC, sha="49c5338c148a502a"),
+        dict(bytes=428061491, src=_MFMA_SRC, sha="afe068a4c07ebf90"),
     ("lh128_k4_n200000_s0.5", "bf16_split3", "k_backproject_bf16<32, 3>"):
-        dict(bytes=1666526822, src=_BF16_SRC, sha="ba5560ac91e34097"),
+        dict(bytes=1667245261, src=_BF16_SRC, sha="b388cb12823a5049"),
 }
 
 
