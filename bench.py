@@ -35,10 +35,13 @@ METRIC = "EM obs×shift pairs/s vs plain FP32 at rel err ≤1e-4; p50/p99 solve 
 PEAK = {  # MI355X published dense peaks
     "fp32_mfma": ("mfma", 157.3e12), "fp32_plain": ("alu", 78.6e12),
     "bf16_split3": ("mfma", 2516.6e12), "bf16_split4": ("mfma", 2516.6e12),
+    "fp32_fft": ("alu", 78.6e12),
 }
-KNAME = {"fp32_mfma": "mfma", "fp32_plain": "valu", "bf16_split3": "bf16", "bf16_split4": "bf16"}
+KNAME = {"fp32_mfma": "mfma", "fp32_plain": "valu", "bf16_split3": "bf16", "bf16_split4": "bf16",
+         "fp32_fft": "fft"}
 PRODUCTS = {"bf16_split3": 3, "bf16_split4": 4}   # BF16 products per multiply-add
-DTYPE = {"fp32_mfma": "f32", "fp32_plain": "f32", "bf16_split3": "bf16x3", "bf16_split4": "bf16x4"}
+DTYPE = {"fp32_mfma": "f32", "fp32_plain": "f32", "bf16_split3": "bf16x3", "bf16_split4": "bf16x4",
+         "fp32_fft": "f32"}
 HBM_PEAK = 8.0e12   # B/s
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE (x 2.0)
 # and WRITE_SIZE (x 1.0), keyed by (workload, precision, kernel), with a hash of
@@ -515,7 +518,14 @@ def main():
     prod = float(PRODUCTS.get(args.precision, 1))
     targ = f"<{inst.Ll}, {PRODUCTS[args.precision]}>" if args.precision in PRODUCTS else f"<{inst.Ll}>"
     k_ms = main_r["phase_ms"][3]
-    if n_pass == 1:
+    if args.precision == "fp32_fft":
+        # pass 2: an inverse and a forward complex 2-D FFT of Ll^2 points per
+        # (observation, component) pair, 5 n log2 n flop each
+        import math
+        kname = f"k_fft_pass2<{inst.Ll}>"
+        alg_flop = inst.N * inst.K * inst.K * 2 * 5.0 * Ll2 * math.log2(Ll2)
+        issued_flop = alg_flop
+    elif n_pass == 1:
         kname = f"k_fused_{KNAME[args.precision]}{targ}"
         alg_flop = 4.0 * Ll2 * pairs
         issued_flop = alg_flop * prod
@@ -530,9 +540,15 @@ def main():
             "issued_frac": issued_flop / (k_ms * 1e-3) / peak}
     if n_pass == 2:
         s_ms = main_r["phase_ms"][1]
-        roof["score_pass"] = {"kernel_ms": s_ms,
-                              "frac": 2.0 * Ll2 * pairs / (s_ms * 1e-3) / peak,
-                              "issued_frac": 2.0 * Ll2 * pairs * prod / (s_ms * 1e-3) / peak}
+        if args.precision == "fp32_fft":   # one inverse complex FFT per (observation, component)
+            import math
+            s_flop = inst.N * inst.K * inst.K * 5.0 * Ll2 * math.log2(Ll2)
+            roof["score_pass"] = {"kernel_ms": s_ms, "frac": s_flop / (s_ms * 1e-3) / peak,
+                                  "issued_frac": s_flop / (s_ms * 1e-3) / peak}
+        else:
+            roof["score_pass"] = {"kernel_ms": s_ms,
+                                  "frac": 2.0 * Ll2 * pairs / (s_ms * 1e-3) / peak,
+                                  "issued_frac": 2.0 * Ll2 * pairs * prod / (s_ms * 1e-3) / peak}
 
     out = {"metric": METRIC, "value": value, "unit": "obs×shift pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": forms[args.precision]["ms_per_step"],

@@ -75,7 +75,11 @@ typedef enum {
     SRMRA_FP32_MFMA = 1,      /* FP32 matrix cores (v_mfma_f32_32x32x2 / 16x16x4)   */
     SRMRA_BF16_SPLIT3 = 2,    /* BF16 matrix cores, operands split v = hi + lo,
                                  products hi*hi + hi*lo + lo*hi, FP32 accumulate    */
-    SRMRA_BF16_SPLIT4 = 3     /* as SRMRA_BF16_SPLIT3 plus the lo*lo product        */
+    SRMRA_BF16_SPLIT4 = 3,    /* as SRMRA_BF16_SPLIT3 plus the lo*lo product        */
+    SRMRA_FP32_FFT = 4        /* FFT route: both contractions as products of 2-D
+                                 DFTs of the L_low grid (FP32 transforms, FP64 sums
+                                 and inverse); L_low in {8, 16, 32}; single-problem
+                                 calls only (no plan)                               */
 } srmra_precision;
 
 /* Human-readable text of a status code (static storage). */
@@ -283,6 +287,12 @@ size_t srmra_project_workspace_bytes(int L_high);
 int srmra_project_gaussian(const float* x_in, float* x_out, int L_high,
                            float* sigma_state, float decay, void* workspace,
                            size_t workspace_bytes, hipStream_t stream);
+
+/* Batched forward 2-D DFT of real L x L images (the FFT route's transform):
+ * out[i][k1][k2] = sum_n in[i][n1][n2] exp(-2 pi i (k1 n1 + k2 n2) / L), FP32
+ * complex (interleaved re, im).  in: device [count][L][L] float; out: device
+ * [count][L][L] float2.  L in {8, 16, 32}, count >= 1, else SRMRA_EINVAL. */
+int srmra_dft2(const float* in, int64_t count, int L, void* out, hipStream_t stream);
 
 /* Empirical moments of the observations (eq. empiric_MOM, the method of
  * moments' summary of the data): m1[l] = (1/N) sum_i y_i[l] and

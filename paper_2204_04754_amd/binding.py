@@ -27,8 +27,9 @@ SRMRA_FP32_PLAIN = FP32_PLAIN = 0
 SRMRA_FP32_MFMA = FP32_MFMA = 1
 SRMRA_BF16_SPLIT3 = BF16_SPLIT3 = 2
 SRMRA_BF16_SPLIT4 = BF16_SPLIT4 = 3
+SRMRA_FP32_FFT = FP32_FFT = 4
 PRECISIONS = {"fp32_plain": FP32_PLAIN, "fp32_mfma": FP32_MFMA, "bf16_split3": BF16_SPLIT3,
-              "bf16_split4": BF16_SPLIT4}
+              "bf16_split4": BF16_SPLIT4, "fp32_fft": FP32_FFT}
 
 _lib = None
 _lock = threading.Lock()
@@ -126,6 +127,8 @@ def lib():
             L.srmra_moments_workspace_bytes.argtypes = [_i64, _int]
             L.srmra_moments.restype = _int
             L.srmra_moments.argtypes = [_vp, _i64, _int, _vp, _vp, _vp, _sz, _vp]
+            L.srmra_dft2.restype = _int
+            L.srmra_dft2.argtypes = [_vp, _i64, _int, _vp, _vp]
             L.srmra_plan_destroy.restype = None
             L.srmra_plan_destroy.argtypes = [_vp]
             _lib = L
@@ -336,6 +339,11 @@ def srmra_project_gaussian(x_in: torch.Tensor, x_out: torch.Tensor, L_high: int,
                                         _ptr(sigma_state, torch.float32), float(decay),
                                         _ptr(workspace), workspace.numel() * workspace.element_size(),
                                         _stream(stream)), "srmra_project_gaussian")
+
+
+def srmra_dft2(x: torch.Tensor, count: int, L: int, out: torch.Tensor, stream=None) -> None:
+    _check(lib().srmra_dft2(_ptr(x, torch.float32), count, L, _ptr(out), _stream(stream)),
+           "srmra_dft2")
 
 
 def srmra_moments_workspace_bytes(N: int, L_low: int) -> int:

@@ -46,6 +46,15 @@ hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, h
 size_t project_workspace_bytes(int Lh);
 hipError_t launch_project(const float* x_in, float* x_out, int Lh, float* sigma_state, float decay,
                           void* workspace, hipStream_t s);
+// FFT route (srmra_fft.hip)
+bool fft_supported(int LL);
+int fft_tpc(int LL, int KK);
+size_t fft_lds(int LL);
+const void* fft_pass2_fn(int LL);
+hipError_t launch_fft(int LL, int what, const StepArgs& p, const float* x, const float* y,
+                      void* yhat, void* xhat, void* bpart, void* cpart, void* bh, void* ch,
+                      double* bsum, double* csum, hipStream_t s);
+hipError_t launch_dft2(int L, const float* in, int64_t count, float2* out, hipStream_t s);
 // reconstruction error (srmra_quality.hip)
 size_t shift_error_workspace_bytes(int Lh);
 hipError_t launch_shift_error(const float* xh, const float* x, int Lh, double* err, int* best,
@@ -65,7 +74,7 @@ bool supported_ll(int LL) {
 
 bool valid_prec(int p) {
     return p == SRMRA_FP32_PLAIN || p == SRMRA_FP32_MFMA || p == SRMRA_BF16_SPLIT3 ||
-           p == SRMRA_BF16_SPLIT4;
+           p == SRMRA_BF16_SPLIT4 || p == SRMRA_FP32_FFT;
 }
 bool is_bf16(int p) { return p == SRMRA_BF16_SPLIT3 || p == SRMRA_BF16_SPLIT4; }
 int split_products(int p) { return p == SRMRA_BF16_SPLIT4 ? 4 : 3; }
@@ -108,7 +117,7 @@ struct Geom {
     size_t lds1 = 0, lds2 = 0;
     // workspace offsets
     size_t o_prep = 0, o_part = 0, o_lse = 0, o_xt2 = 0, o_beta = 0, o_bpart = 0, o_cpart = 0,
-           o_llpart = 0, o_bsum = 0, o_csum = 0, o_xb = 0, total = 0;
+           o_llpart = 0, o_bsum = 0, o_csum = 0, o_xb = 0, o_xhat = 0, o_bh = 0, o_ch = 0, total = 0;
 };
 
 int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
@@ -138,17 +147,29 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
         }
     } else if (is_bf16(prec)) {
         ok = bf16_geom(LL, split_products(prec), g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
+    } else if (prec == SRMRA_FP32_FFT) {
+        // pass 1: a team per observation over all components; pass 2: component
+        // groups of CG = teams / tpc components
+        ok = fft_supported(LL);
+        if (ok) {
+            const int teams = 256 / LL;
+            g.cpb = teams / fft_tpc(LL, g.KK);   // components per pass-2 block
+            g.ntile = teams;
+            g.lds1 = g.lds2 = fft_lds(LL);
+            f2 = fft_pass2_fn(LL);
+        }
     }
     else ok = valu_geom(LL, g.KK, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
     if (!ok) return SRMRA_EUNSUPPORTED;
     g.n_cg = (g.KK + g.cpb - 1) / g.cpb;
     // pass-1 partials per observation: one per component group, or per component
     // pair for the BF16 form (two waves of a block hold different pairs)
-    g.n_part = is_bf16(prec) ? (g.KK + 1) / 2 : g.n_cg;   // 1 for the single pass
+    g.n_part = is_bf16(prec) ? (g.KK + 1) / 2 : (prec == SRMRA_FP32_FFT ? 1 : g.n_cg);   // 1 for the single pass
     g.prep_sum_off = align_up(sizeof(double) * (size_t)N);
     g.prep_mu_off = g.prep_sum_off + align_up(sizeof(double) * (size_t)N);
     g.prep_extra_off = g.prep_mu_off + kAlign;
-    g.prep_bytes = g.prep_extra_off + (is_bf16(prec) ? bf16_prepared_extra(LL, N) : 0);
+    g.prep_bytes = g.prep_extra_off + (is_bf16(prec) ? bf16_prepared_extra(LL, N) : 0) +
+                   (prec == SRMRA_FP32_FFT ? sizeof(float2) * (size_t)N * LL * LL : 0);
     // one resident wave of blocks over the whole device for the heavier pass
     const int occ = occupancy(f2, g.lds2);
     const int64_t target = (int64_t)device_cus() * occ;
@@ -169,12 +190,18 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     g.o_lse = take(sizeof(float) * (size_t)N);
     g.o_xt2 = take(sizeof(float) * (size_t)g.KK * LL * 2 * LL);
     g.o_beta = take(sizeof(float) * (size_t)g.KK * LL * LL);
-    g.o_bpart = take(sizeof(float) * (size_t)g.n_chunks * g.KK * LL * LL);
-    g.o_cpart = take(sizeof(float) * (size_t)g.n_chunks * g.KK * LL * LL);
+    const size_t pw = prec == SRMRA_FP32_FFT ? sizeof(float2) : sizeof(float);   // complex partials
+    g.o_bpart = take(pw * (size_t)g.n_chunks * g.KK * LL * LL);
+    g.o_cpart = take(pw * (size_t)g.n_chunks * g.KK * LL * LL);
     g.o_llpart = take(sizeof(double) * (size_t)g.n_ll);
     g.o_bsum = take(sizeof(double) * (size_t)g.KK * LL * LL);
     g.o_csum = take(sizeof(double) * (size_t)g.KK * LL * LL);
     g.o_xb = is_bf16(prec) ? take(bf16_xb_bytes(LL, g.KK)) : 0;
+    if (prec == SRMRA_FP32_FFT) {
+        g.o_xhat = take(sizeof(float2) * (size_t)g.KK * LL * LL);
+        g.o_bh = take(2 * sizeof(double) * (size_t)g.KK * LL * LL);
+        g.o_ch = take(2 * sizeof(double) * (size_t)g.KK * LL * LL);
+    }
     g.total = off;
     return SRMRA_OK;
 }
@@ -241,6 +268,32 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
     if (is_bf16(g.prec) && launch_pack_xb(LL, p, x, ws + g.o_xb, stream) != hipSuccess)
         return SRMRA_EDEVICE;
     mark(1);
+    if (g.prec == SRMRA_FP32_FFT) {
+        void* yhat = (void*)((const char*)prep_extra);
+        auto fft = [&](int what) {
+            return launch_fft(LL, what, p, x, y, yhat, ws + g.o_xhat, ws + g.o_bpart, ws + g.o_cpart,
+                              ws + g.o_bh, ws + g.o_ch, (double*)(ws + g.o_bsum),
+                              (double*)(ws + g.o_csum), stream);
+        };
+        if (fft(1) != hipSuccess) return SRMRA_EDEVICE;
+        mark(1);
+        if (fft(2) != hipSuccess) return SRMRA_EDEVICE;
+        mark(2);
+        hipLaunchKernelGGL(k_lse_combine, dim3(g.n_ll), dim3(256), 0, stream, (const float2*)p.part,
+                           g.n_part, g.N, ynorm, p.inv_2s2, p.lse, (double*)(ws + g.o_llpart), ll_obs);
+        if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
+        mark(3);
+        if (fft(3) != hipSuccess) return SRMRA_EDEVICE;
+        mark(4);
+        if (fft(4) != hipSuccess) return SRMRA_EDEVICE;
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, stream, (const double*)(ws + g.o_bsum),
+                           (const double*)(ws + g.o_csum), g.K, LL, x, centre,
+                           (const double*)(ws + g.o_llpart), g.n_ll, x_new, rho_new, log_rho_new, loglik,
+                           b_out, c_out);
+        if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
+        mark(5);
+        return SRMRA_OK;
+    }
     auto pass = [&](int k) -> hipError_t {
         if (g.prec == SRMRA_FP32_MFMA) return launch_mfma(LL, k, p, stream);
         if (is_bf16(g.prec)) return launch_bf16(LL, split_products(g.prec), k, p, prep_extra, stream);
@@ -307,7 +360,7 @@ int srmra_em_step_passes(int64_t N, int L_low, int K, int precision) {
     Geom g;
     const int st = make_geom(N, L_low, K, precision, false, g);
     if (st != SRMRA_OK) return st;
-    return g.fuse_wc ? 1 : 2;
+    return g.fuse_wc ? 1 : 2;   // the FFT route makes two passes
 }
 
 size_t srmra_prepared_bytes(int64_t N, int L_low, int K, int precision) {
@@ -333,7 +386,17 @@ static int enqueue_prepare(const Geom& g, const float* y, char* prep, int centre
                    ? SRMRA_OK : SRMRA_EDEVICE;
     hipLaunchKernelGGL(k_obs_norms, dim3(blocks), dim3(256), 0, stream, y, g.N, g.LL * g.LL,
                        (const double*)centre, ynorm);
-    return hipGetLastError() == hipSuccess ? SRMRA_OK : SRMRA_EDEVICE;
+    if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
+    if (g.prec == SRMRA_FP32_FFT) {   // the DFT of every centred observation
+        StepArgs p;
+        memset(&p, 0, sizeof(p));
+        p.N = g.N;
+        p.centre = centre;
+        if (launch_fft(g.LL, 0, p, nullptr, y, prep + g.prep_extra_off, nullptr, nullptr, nullptr,
+                       nullptr, nullptr, nullptr, nullptr, stream) != hipSuccess)
+            return SRMRA_EDEVICE;
+    }
+    return SRMRA_OK;
 }
 
 int srmra_prepare_observations_ex(const float* y, int64_t N, int L_low, int K, int precision,
@@ -509,7 +572,7 @@ void fill_desc(srmra_plan* P, int i, int par, InstDesc& d, char* ws) {
 
 int srmra_plan_form(int precision, int L_low) {
     if (!supported_ll(L_low)) return -1;
-    if (!valid_prec(precision)) return -1;
+    if (!valid_prec(precision) || precision == SRMRA_FP32_FFT) return -1;
     return prec_of_form(form_of(precision, L_low));
 }
 
@@ -532,7 +595,7 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
     if (n_table < 0 || (n_table > 0 && !table)) return SRMRA_EINVAL;
     *plan = nullptr;
     *workspace_bytes = 0;
-    if (!valid_prec(precision)) return SRMRA_EUNSUPPORTED;
+    if (!valid_prec(precision) || precision == SRMRA_FP32_FFT) return SRMRA_EUNSUPPORTED;
     // a table entry may only keep the plan's precision or, in a BF16 plan, pick
     // FP32 MFMA (more accurate); the BF16 form needs an L_low it is built for
     for (int k = 0; k < n_table; ++k) {
@@ -726,6 +789,12 @@ void srmra_plan_destroy(srmra_plan* plan) { delete plan; }
 size_t srmra_project_workspace_bytes(int L_high) {
     if (L_high < 1 || L_high > 4096) return 0;
     return project_workspace_bytes(L_high);
+}
+
+int srmra_dft2(const float* in, int64_t count, int L, void* out, hipStream_t stream) {
+    if (!in || !out || count < 1 || count > (int64_t)INT32_MAX * 8LL || !fft_supported(L))
+        return SRMRA_EINVAL;
+    return launch_dft2(L, in, count, (float2*)out, stream) == hipSuccess ? SRMRA_OK : SRMRA_EDEVICE;
 }
 
 size_t srmra_moments_workspace_bytes(int64_t N, int L_low) {

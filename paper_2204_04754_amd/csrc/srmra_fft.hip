@@ -1,0 +1,358 @@
+// FFT route of the EM step (SRMRA_FP32_FFT, L_low in {8, 16, 32}): the same
+// step as the dense forms, with both contractions as products in the 2-D DFT
+// domain of the L_low grid.  With (R_t v)[n] = v[n - t]:
+//   score     S_{i,c}[t] = sum_n y_i[n] x_c[n - t]      = IDFT(Y_i . conj(X_c))[t]
+//   back-proj b_c[q]     = sum_i sum_t w_{i,c}[t] y_i[q + t] = IDFT(sum_i Y_i . conj(W_{i,c}))[q]
+//   mass      c_c[t]     = sum_i w_{i,c}[t]              = IDFT(sum_i W_{i,c})[t]
+// Y_i (DFT of y_i - mu) is prepared once per job; X_c once per step.  Pass 1:
+// team per observation, its (max, sum exp) over all components.  Pass 2: team
+// per component (observations split over TPC teams), w = exp(a - LSE_i), its
+// DFT, and the two frequency-domain sums; per-chunk FP32 partials, summed in
+// FP64 and brought back by a direct FP64 inverse DFT.  One component per
+// transform: packing two real signals into one complex transform would give a
+// component of little posterior mass the rounding error of its heavier
+// partner.  The transforms are the in-register team FFTs of srmra_fft_impl.h
+// (O(L^2 log L) per pair instead of the dense 4 L^4).
+#include "srmra_common.h"
+#include "srmra_fft_impl.h"
+
+namespace srmra {
+namespace fft {
+
+template <int L> struct Geo {
+    static constexpr int TEAMS = 256 / L;
+    static constexpr int BUF = L * (L + 1);   // float2 per team buffer
+};
+
+template <int L> constexpr size_t lds_bytes() {
+    return sizeof(float2) * ((size_t)Geo<L>::TEAMS * Geo<L>::BUF + L / 2);
+}
+
+// ---- per job: Y_i = DFT(y_i - mu), [N][L][L] complex (k1-major)
+template <int L>
+__device__ __forceinline__ void prep_y_body(const float* __restrict__ y, int64_t N,
+                                            const double* __restrict__ centre,
+                                            float2* __restrict__ yhat) {
+    extern __shared__ float2 sh[];
+    float2* tw = sh + Geo<L>::TEAMS * Geo<L>::BUF;
+    make_twiddles<L>(tw);
+    __syncthreads();
+    const int team = threadIdx.x / L, r = threadIdx.x % L;
+    float2* buf = sh + team * Geo<L>::BUF;
+    const float mu = centre_of(centre);
+    const int64_t i = (int64_t)blockIdx.x * Geo<L>::TEAMS + team;
+    if (i >= N) return;   // whole teams leave together (a team lies in one wave)
+    float2 v[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) v[k] = make_float2(y[(i * L + r) * L + k] - mu, 0.f);
+    fft2_rows_then_cols<L, false>(v, buf, r, tw);
+#pragma unroll
+    for (int k = 0; k < L; ++k) yhat[(i * L + k) * L + r] = v[k];
+}
+
+template <int L>
+__global__ __launch_bounds__(256) void k_fft_prep_y(const float* __restrict__ y, int64_t N,
+                                                    const double* __restrict__ centre,
+                                                    float2* __restrict__ yhat) {
+    prep_y_body<L>(y, N, centre, yhat);
+}
+
+// ---- per step: X_c = DFT(x_c - mu), [KK][L][L]; one block (first L threads) per component
+template <int L>
+__global__ __launch_bounds__(256) void k_fft_pack_x(const float* __restrict__ x, int K,
+                                                    const double* __restrict__ centre,
+                                                    float2* __restrict__ xhat) {
+    extern __shared__ float2 sh[];
+    float2* tw = sh + Geo<L>::TEAMS * Geo<L>::BUF;
+    make_twiddles<L>(tw);
+    __syncthreads();
+    if (threadIdx.x >= L) return;
+    const int c = blockIdx.x, c1 = c / K, c2 = c % K, Lh = K * L, r = threadIdx.x;
+    const float mu = centre_of(centre);
+    float2 v[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k)
+        v[k] = make_float2(x[(int64_t)(c1 + r * K) * Lh + (c2 + k * K)] - mu, 0.f);
+    fft2_rows_then_cols<L, false>(v, sh, r, tw);
+#pragma unroll
+    for (int k = 0; k < L; ++k) xhat[((int64_t)c * L + k) * L + r] = v[k];
+}
+
+// score column r of (observation o, component c): s[k] = a at (t1 = k, t2 = r)
+template <int L>
+__device__ __forceinline__ void score_column(const StepArgs& p, const float2* __restrict__ yhat,
+                                             const float2* __restrict__ xhat, int64_t o, int c,
+                                             float2* buf, int r, const float2* tw, float (&s)[L]) {
+    float2 v[L];
+    const float2* yr = yhat + (o * L + r) * L;
+    const float2* xr = xhat + ((int64_t)c * L + r) * L;
+#pragma unroll
+    for (int k = 0; k < L; ++k) v[k] = cmulc(yr[k], xr[k]);
+    fft2_rows_then_cols<L, true>(v, buf, r, tw);
+    const float sc = p.inv_s2 / (float)(L * L);
+    const float* bet = p.betaT + (int64_t)c * (L * L) + r * L;   // betaT[c][t2 = r][t1]
+#pragma unroll
+    for (int k = 0; k < L; ++k) s[k] = v[k].x * sc + bet[k];
+}
+
+__device__ __forceinline__ void lse_merge(float& m, float& s, float m2, float s2) {
+    if (m2 == -INFINITY) return;
+    if (m == -INFINITY) { m = m2; s = s2; return; }
+    const float mn = fmaxf(m, m2);
+    s = s * __expf(m - mn) + s2 * __expf(m2 - mn);
+    m = mn;
+}
+
+// ---- pass 1: (max, sum exp) of every observation over all components
+template <int L>
+__global__ __launch_bounds__(256) void k_fft_pass1(StepArgs p, const float2* __restrict__ yhat,
+                                                   const float2* __restrict__ xhat) {
+    extern __shared__ float2 sh[];
+    float2* tw = sh + Geo<L>::TEAMS * Geo<L>::BUF;
+    make_twiddles<L>(tw);
+    __syncthreads();
+    const int team = threadIdx.x / L, r = threadIdx.x % L;
+    float2* buf = sh + team * Geo<L>::BUF;
+    const int64_t c0 = (int64_t)blockIdx.x * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    for (int64_t o = c0 + team; o < c1; o += Geo<L>::TEAMS) {
+        float m = -INFINITY, sm = 0.f;
+        for (int c = 0; c < p.KK; ++c) {
+            float s[L];
+            score_column<L>(p, yhat, xhat, o, c, buf, r, tw, s);
+            float mc = -INFINITY;
+#pragma unroll
+            for (int k = 0; k < L; ++k) mc = fmaxf(mc, s[k]);
+            float sc = 0.f;
+            if (mc > -INFINITY) {
+#pragma unroll
+                for (int k = 0; k < L; ++k) sc += s[k] > -INFINITY ? __expf(s[k] - mc) : 0.f;
+            }
+            lse_merge(m, sm, mc, sc);
+        }
+        // team reduction (the team is L consecutive lanes of one wave)
+        for (int off = L / 2; off > 0; off >>= 1) {
+            const float m2 = __shfl_xor(m, off), s2 = __shfl_xor(sm, off);
+            lse_merge(m, sm, m2, s2);
+        }
+        if (r == 0) p.part[o] = make_float2(m, sm);
+    }
+}
+
+// ---- pass 2: per component group, the frequency-domain sums over the chunk.
+// Component group g holds CG components, TPC = TEAMS / CG teams each
+// (observations split over them); partials [chunk][c][k1][k2] of
+// sum_i Y_i conj(W_i) (bpart) and sum_i W_i (cpart), as float2.
+template <int L>
+__global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __restrict__ yhat,
+                                                   const float2* __restrict__ xhat, int TPC,
+                                                   float2* __restrict__ bpart,
+                                                   float2* __restrict__ cpart) {
+    extern __shared__ float2 sh[];
+    float2* tw = sh + Geo<L>::TEAMS * Geo<L>::BUF;
+    make_twiddles<L>(tw);
+    __syncthreads();
+    const int team = threadIdx.x / L, r = threadIdx.x % L;
+    float2* buf = sh + team * Geo<L>::BUF;
+    const int CG = Geo<L>::TEAMS / TPC;
+    const int c = blockIdx.y * CG + team / TPC, u = team % TPC;
+    const bool active = c < p.KK;
+    const int64_t chunk = blockIdx.x;
+    const int64_t c0 = chunk * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    float2 ab[L], ac[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) { ab[k] = make_float2(0.f, 0.f); ac[k] = ab[k]; }
+    if (active) {
+        for (int64_t o = c0 + u; o < c1; o += TPC) {
+            float s[L];
+            score_column<L>(p, yhat, xhat, o, c, buf, r, tw, s);
+            const float lse = p.lse[o];
+            float2 v[L];
+#pragma unroll
+            for (int k = 0; k < L; ++k)
+                v[k] = make_float2(s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f, 0.f);   // w[k][r]
+            fft2_cols_then_rows<L, false>(v, buf, r, tw);                              // W[r][k]
+            const float2* yr = yhat + (o * L + r) * L;
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const float2 t = cmulc(yr[k], v[k]);
+                ab[k].x += t.x; ab[k].y += t.y;
+                ac[k].x += v[k].x; ac[k].y += v[k].y;
+            }
+        }
+    }
+    // sum the TPC teams of each component in a fixed order, one plane at a time
+    for (int plane = 0; plane < 2; ++plane) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = plane == 0 ? ab[k] : ac[k];
+        __syncthreads();
+        if (active && u == 0) {
+            float2* dst = (plane == 0 ? bpart : cpart) + ((chunk * p.KK + c) * L + r) * L;
+            for (int k = 0; k < L; ++k) {
+                float2 t = make_float2(0.f, 0.f);
+                for (int j = 0; j < TPC; ++j) {
+                    const float2 e = sh[(team + j) * Geo<L>::BUF + r * (L + 1) + k];
+                    t.x += e.x; t.y += e.y;
+                }
+                dst[k] = t;
+            }
+        }
+    }
+}
+
+// ---- FP64 sums of the partials over chunks: [KK][L][L] complex doubles
+__global__ __launch_bounds__(256) void k_fft_reduce(const float2* __restrict__ bpart,
+                                                    const float2* __restrict__ cpart, int n_chunks,
+                                                    int per, double2* __restrict__ bh,
+                                                    double2* __restrict__ ch) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= per) return;
+    double2 sb = make_double2(0.0, 0.0), sc = sb;
+    for (int k = 0; k < n_chunks; ++k) {
+        const float2 b = bpart[(int64_t)k * per + e], c = cpart[(int64_t)k * per + e];
+        sb.x += b.x; sb.y += b.y;
+        sc.x += c.x; sc.y += c.y;
+    }
+    bh[e] = sb;
+    ch[e] = sc;
+}
+
+// ---- direct FP64 inverse DFT: bsum[c][q1 L + q2], csum[c][t1 L + t2] (the
+// layouts the finalize kernel reads); grid (ceil(L^2 / 256), KK)
+template <int L>
+__global__ __launch_bounds__(256) void k_fft_idft(const double2* __restrict__ bh,
+                                                  const double2* __restrict__ ch,
+                                                  double* __restrict__ bsum,
+                                                  double* __restrict__ csum) {
+    __shared__ double cs[L], sn[L];
+    if (threadIdx.x < L) sincospi(2.0 * (double)threadIdx.x / (double)L, &sn[threadIdx.x], &cs[threadIdx.x]);
+    __syncthreads();
+    const int c = blockIdx.y;
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= L * L) return;
+    const int q1 = q / L, q2 = q % L;
+    const double2* B = bh + (int64_t)c * L * L;
+    const double2* C = ch + (int64_t)c * L * L;
+    double rb = 0.0, rc = 0.0;
+    for (int k1 = 0; k1 < L; ++k1)
+        for (int k2 = 0; k2 < L; ++k2) {
+            const int m = (k1 * q1 + k2 * q2) % L;   // exp(+2 pi i m / L)
+            const double2 b = B[k1 * L + k2], cc = C[k1 * L + k2];
+            rb += b.x * cs[m] - b.y * sn[m];
+            rc += cc.x * cs[m] - cc.y * sn[m];
+        }
+    const double inv = 1.0 / (double)(L * L);
+    bsum[(int64_t)c * L * L + q] = rb * inv;
+    csum[(int64_t)c * L * L + q] = rc * inv;
+}
+
+// ---- batched forward DFT of real images (utility): out[i][k1][k2]
+template <int L>
+__global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int64_t count,
+                                              float2* __restrict__ out) {
+    prep_y_body<L>(in, count, nullptr, out);
+}
+
+}  // namespace fft
+
+// ---------------------------------------------------------------- host side
+bool fft_supported(int LL) { return LL == 8 || LL == 16 || LL == 32; }
+
+// teams per component in pass 2 for KK components (a power of 2 dividing TEAMS)
+int fft_tpc(int LL, int KK) {
+    const int teams = 256 / LL;
+    int tpc = 1;
+    while (tpc * 2 <= teams && KK * tpc * 2 <= teams) tpc *= 2;
+    return tpc;
+}
+
+size_t fft_lds(int LL) {
+    switch (LL) {
+        case 8: return fft::lds_bytes<8>();
+        case 16: return fft::lds_bytes<16>();
+        case 32: return fft::lds_bytes<32>();
+    }
+    return 0;
+}
+
+const void* fft_pass2_fn(int LL) {
+    switch (LL) {
+        case 8: return (const void*)fft::k_fft_pass2<8>;
+        case 16: return (const void*)fft::k_fft_pass2<16>;
+        case 32: return (const void*)fft::k_fft_pass2<32>;
+    }
+    return nullptr;
+}
+
+template <int L>
+static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, const float* y,
+                                void* yhat, void* xhat, void* bpart, void* cpart, void* bh,
+                                void* ch, double* bsum, double* csum, hipStream_t s) {
+    const size_t lds = fft::lds_bytes<L>();
+    const int teams = 256 / L;
+    switch (what) {
+        case 0:   // prepare Y
+            (void)hipFuncSetAttribute((const void*)fft::k_fft_prep_y<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(fft::k_fft_prep_y<L>, dim3((unsigned)((p.N + teams - 1) / teams)), dim3(256), lds, s,
+                               y, p.N, p.centre, (float2*)yhat);
+            break;
+        case 1:   // X
+            (void)hipFuncSetAttribute((const void*)fft::k_fft_pack_x<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(fft::k_fft_pack_x<L>, dim3(p.KK), dim3(256), lds, s, x, p.K, p.centre,
+                               (float2*)xhat);
+            break;
+        case 2:
+            (void)hipFuncSetAttribute((const void*)fft::k_fft_pass1<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(fft::k_fft_pass1<L>, dim3(p.n_chunks), dim3(256), lds, s, p,
+                               (const float2*)yhat, (const float2*)xhat);
+            break;
+        case 3: {
+            const int tpc = fft_tpc(L, p.KK);
+            (void)hipFuncSetAttribute((const void*)fft::k_fft_pass2<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(fft::k_fft_pass2<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lds, s, p,
+                               (const float2*)yhat, (const float2*)xhat, tpc, (float2*)bpart, (float2*)cpart);
+            break;
+        }
+        case 4: {
+            const int per = p.KK * L * L;
+            hipLaunchKernelGGL(fft::k_fft_reduce, dim3((per + 255) / 256), dim3(256), 0, s, (const float2*)bpart,
+                               (const float2*)cpart, p.n_chunks, per, (double2*)bh, (double2*)ch);
+            hipLaunchKernelGGL(fft::k_fft_idft<L>, dim3((L * L + 255) / 256, p.KK), dim3(256), 0, s,
+                               (const double2*)bh, (const double2*)ch, bsum, csum);
+            break;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fft(int LL, int what, const StepArgs& p, const float* x, const float* y,
+                      void* yhat, void* xhat, void* bpart, void* cpart, void* bh, void* ch,
+                      double* bsum, double* csum, hipStream_t s) {
+    switch (LL) {
+        case 8: return fft_launch_ll<8>(what, p, x, y, yhat, xhat, bpart, cpart, bh, ch, bsum, csum, s);
+        case 16: return fft_launch_ll<16>(what, p, x, y, yhat, xhat, bpart, cpart, bh, ch, bsum, csum, s);
+        case 32: return fft_launch_ll<32>(what, p, x, y, yhat, xhat, bpart, cpart, bh, ch, bsum, csum, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_dft2(int L, const float* in, int64_t count, float2* out, hipStream_t s) {
+    const int teams = 256 / L;
+    const dim3 grid((unsigned)((count + teams - 1) / teams));
+    size_t lds;
+    switch (L) {
+        case 8: lds = fft::lds_bytes<8>(); hipLaunchKernelGGL(fft::k_dft2<8>, grid, dim3(256), lds, s, in, count, out); break;
+        case 16: lds = fft::lds_bytes<16>(); hipLaunchKernelGGL(fft::k_dft2<16>, grid, dim3(256), lds, s, in, count, out); break;
+        case 32:
+            lds = fft::lds_bytes<32>();
+            (void)hipFuncSetAttribute((const void*)fft::k_dft2<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(fft::k_dft2<32>, grid, dim3(256), lds, s, in, count, out);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace srmra

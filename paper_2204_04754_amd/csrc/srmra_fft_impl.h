@@ -1,0 +1,106 @@
+// 2-D discrete Fourier transforms of L x L images (L in {8, 16, 32}) by teams
+// of L threads: a team's thread r holds row r (then column r) of the image as
+// L complex values in registers and runs an iterative radix-2
+// decimation-in-time transform on it; rows and columns meet through the
+// team's LDS buffer (pitch L + 1 complex, conflict-free for both).  A team
+// sits inside one wave, so a wave barrier orders its LDS traffic.
+// Forward: X[k] = sum_n x[n] exp(-2 pi i k.n / L); inverse: the conjugate
+// twiddles, unscaled (callers apply 1 / L^2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace srmra {
+namespace fft {
+
+template <int L> struct Log2;
+template <> struct Log2<8> { static constexpr int v = 3; };
+template <> struct Log2<16> { static constexpr int v = 4; };
+template <> struct Log2<32> { static constexpr int v = 5; };
+
+template <int L> __host__ __device__ constexpr int bitrev(int i) {
+    int r = 0;
+    for (int b = 0; b < Log2<L>::v; ++b) r |= ((i >> b) & 1) << (Log2<L>::v - 1 - b);
+    return r;
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {   // a * conj(b)
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+// twiddles tw[j] = exp(-2 pi i j / L), j < L/2, from double-precision sincospi
+template <int L> __device__ __forceinline__ void make_twiddles(float2* tw) {
+    for (int j = threadIdx.x; j < L / 2; j += blockDim.x) {
+        double s, c;
+        sincospi(-2.0 * (double)j / (double)L, &s, &c);
+        tw[j] = make_float2((float)c, (float)s);
+    }
+}
+
+// in-register transform of v[0..L) (natural order in and out)
+template <int L, bool INV>
+__device__ __forceinline__ void fft1(float2 (&v)[L], const float2* __restrict__ tw) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) {
+        const int j = bitrev<L>(i);
+        if (j > i) { const float2 t = v[i]; v[i] = v[j]; v[j] = t; }
+    }
+#pragma unroll
+    for (int half = 1; half < L; half *= 2) {
+        const int step = L / (2 * half);
+#pragma unroll
+        for (int j = 0; j < half; ++j) {
+            float2 w = tw[j * step];
+            if (INV) w.y = -w.y;
+#pragma unroll
+            for (int k = 0; k < L; k += 2 * half) {
+                const float2 a = v[k + j];
+                const float2 b = cmul(v[k + j + half], w);
+                v[k + j] = make_float2(a.x + b.x, a.y + b.y);
+                v[k + j + half] = make_float2(a.x - b.x, a.y - b.y);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void team_sync() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Row transforms of v (this thread's row r), then column transforms through the
+// team buffer buf [L][L + 1]; on return v holds column r of the 2-D transform
+// (v[k] = X[k][r]).
+template <int L, bool INV>
+__device__ __forceinline__ void fft2_rows_then_cols(float2 (&v)[L], float2* buf, int r,
+                                                    const float2* tw) {
+    fft1<L, INV>(v, tw);
+#pragma unroll
+    for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = v[k];
+    team_sync();
+#pragma unroll
+    for (int k = 0; k < L; ++k) v[k] = buf[k * (L + 1) + r];
+    team_sync();
+    fft1<L, INV>(v, tw);
+}
+
+// Column transforms of v (this thread's column c: v[k] = x[k][c]), then row
+// transforms through buf; on return v holds row c of the 2-D transform.
+template <int L, bool INV>
+__device__ __forceinline__ void fft2_cols_then_rows(float2 (&v)[L], float2* buf, int c,
+                                                    const float2* tw) {
+    fft1<L, INV>(v, tw);
+#pragma unroll
+    for (int k = 0; k < L; ++k) buf[k * (L + 1) + c] = v[k];
+    team_sync();
+#pragma unroll
+    for (int k = 0; k < L; ++k) v[k] = buf[c * (L + 1) + k];
+    team_sync();
+    fft1<L, INV>(v, tw);
+}
+
+}  // namespace fft
+}  // namespace srmra

@@ -36,7 +36,7 @@ def test_header_declares_the_entry_points():
               "srmra_plan_execute", "srmra_plan_destroy", "srmra_em_step_passes",
               "srmra_project_gaussian", "srmra_project_workspace_bytes", "srmra_prepare_observations_ex",
               "srmra_shift_error", "srmra_shift_error_workspace_bytes",
-              "srmra_moments", "srmra_moments_workspace_bytes",
+              "srmra_moments", "srmra_moments_workspace_bytes", "srmra_dft2",
               "srmra_status_string"]:
         assert n in names
 
@@ -211,3 +211,15 @@ def test_moments_host_validation(L):
     assert L.srmra_moments(y, 0, 32, m1, m2, w, nb, None) == B.SRMRA_EINVAL
     assert L.srmra_moments(y, 1000, 31, m1, m2, w, nb, None) == B.SRMRA_EINVAL
     assert L.srmra_moments(y, 1000, 32, m1, m2, w, nb - 1, None) == B.SRMRA_EWORKSPACE
+
+
+def test_fft_route_shapes():
+    """SRMRA_FP32_FFT: L_low 8, 16, 32 only; the plan calls do not take it."""
+    from paper_2204_04754_amd import binding as B
+    for ll in (8, 16, 32):
+        assert B.srmra_em_step_workspace_bytes(1000, ll, 2, "fp32_fft") > 0
+        assert B.srmra_prepared_bytes(1000, ll, 2, "fp32_fft") >= 1000 * ll * ll * 8
+        assert B.srmra_em_step_passes(1000, ll, 2, "fp32_fft") == 2
+    for ll in (12, 24, 48, 64):
+        assert B.srmra_em_step_workspace_bytes(1000, ll, 2, "fp32_fft") == 0
+    assert B.srmra_plan_form(B.SRMRA_FP32_FFT, 32) == -1

@@ -1,0 +1,61 @@
+"""GPU parity of the FFT route (SRMRA_FP32_FFT): the batched 2-D DFT against
+numpy.fft, and the EM step against the FP64 oracle (the same step as the
+dense forms, computed through products of DFTs)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import em_oracle as O  # noqa: E402
+from paper_2204_04754_amd import binding as B  # noqa: E402
+from paper_2204_04754_amd import synth  # noqa: E402
+from tests.gpu_helpers import check_step, gpu_step, rel  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("L", [8, 16, 32])
+def test_dft2_matches_numpy(L):
+    x = np.random.default_rng(L).standard_normal((37, L, L)).astype(np.float32)
+    out = torch.empty((37, L, L, 2), dtype=torch.float32, device="cuda")
+    B.srmra_dft2(torch.as_tensor(x).cuda(), 37, L, out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    ref = np.fft.fft2(x.astype(np.float64))
+    assert rel(g[..., 0] + 1j * g[..., 1], ref) < 2e-6
+
+
+SHAPES = [(16, 2, 37), (32, 2, 29), (64, 2, 17), (64, 4, 11), (96, 3, 5), (128, 4, 9),
+          (32, 1, 7), (32, 4, 53), (48, 3, 13)]
+
+
+@pytest.mark.parametrize("Lh,K,N", SHAPES)
+def test_fft_step_matches_oracle(Lh, K, N):
+    inst = synth.make_instance(Lh, K, N, 2.0, config=90, instance=Lh * 10 + K)
+    rng = np.random.default_rng(Lh + K)
+    lr = np.log(np.stack([rng.dirichlet(np.ones(Lh)), rng.dirichlet(np.ones(Lh))])).astype(np.float32)
+    g = gpu_step(inst.y, inst.x0, lr, 2.0, K, "fp32_fft")
+    ref = O.em_step(inst.y, inst.x0, lr, 2.0, K, return_details=True)
+    check_step(inst.y, inst.x0, lr, 2.0, K, g, ref)
+    assert rel(g["c"], ref["c"]) < 1e-4 and rel(g["b"], ref["b"]) < 1e-4
+
+
+def test_fft_trajectory_and_determinism():
+    inst = synth.workload("lh16_k2_n1000")
+    x, lr = inst.x0, inst.log_rho0
+    for it in range(10):
+        g = gpu_step(inst.y, x, lr, inst.sigma, inst.K, "fp32_fft")
+        ref = O.em_step(inst.y, x, lr, inst.sigma, inst.K)
+        ex, er = check_step(inst.y, x, lr, inst.sigma, inst.K, g, ref)
+        print(f"it {it} x {ex:.2e} rho {er:.2e}")
+        x, lr = g["x_new"].astype(np.float32), g["log_rho_new"].astype(np.float32)
+    a = gpu_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, 2, "fp32_fft")
+    b = gpu_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, 2, "fp32_fft")
+    for k in ("x_new", "rho_new", "loglik", "ll_obs", "b", "c"):
+        assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
