@@ -83,6 +83,8 @@ def parse():
                     help="target oracle time on the host for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--extra-forms", default="fp32_fft",
+                    help="comma-separated forms also timed beside the main one (single mode)")
     ap.add_argument("--mode", default="single",
                     choices=["single", "batched", "serve", "errors", "projected", "moments"],
                     help="single: one instance (default); batched: 64-instance mix, 20 iterations "
@@ -504,6 +506,15 @@ def main():
             phase_ms=br["phase_ms"], obs_prep=br["prep"])
         print(f"[bench] {args.baseline_precision}: {br['ms_per_step']:.2f} ms/step",
               file=sys.stderr, flush=True)
+    from paper_2204_04754_amd import binding as B
+    for extra in [f for f in args.extra_forms.split(",") if f]:
+        if extra in forms or B.srmra_em_step_workspace_bytes(inst.N, inst.Ll, inst.K, extra) == 0:
+            continue
+        er = run_form(inst, extra, max(2, args.steps // 2), 1)
+        del er["job"]
+        forms[extra] = dict(pairs_per_s=pairs / (er["ms_per_step"] * 1e-3), ms_per_step=er["ms_per_step"],
+                            phase_ms=er["phase_ms"], obs_prep=er["prep"])
+        print(f"[bench] {extra}: {er['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
     # roofline of the dominant kernel (phase 3): the single pass where the
