@@ -41,6 +41,9 @@ hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* cen
                             void* prep_extra, hipStream_t s);
 size_t bf16_prepared_extra(int LL, int64_t N);
 size_t bf16_xb_bytes(int LL, int KK);
+size_t bf16_yt_bytes(int LL, int64_t N);
+bool bf16_supported(int LL);
+int bf16_parts(int LL, int KK);
 hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, hipStream_t s);
 // projection of Alg. 2 (srmra_project.hip)
 size_t project_workspace_bytes(int Lh);
@@ -164,7 +167,7 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     g.n_cg = (g.KK + g.cpb - 1) / g.cpb;
     // pass-1 partials per observation: one per component group, or per component
     // pair for the BF16 form (two waves of a block hold different pairs)
-    g.n_part = is_bf16(prec) ? (g.KK + 1) / 2 : (prec == SRMRA_FP32_FFT ? 1 : g.n_cg);   // 1 for the single pass
+    g.n_part = is_bf16(prec) ? bf16_parts(LL, g.KK) : (prec == SRMRA_FP32_FFT ? 1 : g.n_cg);   // 1 for the single pass
     g.prep_sum_off = align_up(sizeof(double) * (size_t)N);
     g.prep_mu_off = g.prep_sum_off + align_up(sizeof(double) * (size_t)N);
     g.prep_extra_off = g.prep_mu_off + kAlign;
@@ -499,7 +502,7 @@ namespace {
 
 int form_of(int precision, int LL) {
     if (is_bf16(precision)) {
-        if (LL != 24 && LL != 32) return FORM_MFMA;
+        if (!bf16_supported(LL)) return FORM_MFMA;
         return precision == SRMRA_BF16_SPLIT4 ? FORM_BF16X4 : FORM_BF16;
     }
     return precision == SRMRA_FP32_MFMA ? FORM_MFMA : FORM_VALU;
@@ -521,6 +524,10 @@ bool is_bf16_form(int f) { return f == FORM_BF16 || f == FORM_BF16X4; }
 int64_t default_chunk(const Geom& g) {
     const double per_obs = (double)g.cpb * g.LL * g.LL * (double)g.LL * g.LL;
     int64_t c = (int64_t)(268435456.0 / per_obs);
+    // one-component items (BF16 at L_low 48 and 64): about 4 items per CU over
+    // the instance, so that the per-chunk partials (chunks x K^2 x L_low^2)
+    // stay small
+    if (g.cpb == 1 && is_bf16(g.prec)) c = std::max<int64_t>(c, (g.N * g.KK + 1023) / 1024);
     if (c < g.ntile) c = g.ntile;
     return c;
 }
@@ -549,9 +556,8 @@ void fill_desc(srmra_plan* P, int i, int par, InstDesc& d, char* ws) {
     p.fuse_wc = g.fuse_wc;
     if (is_bf16_form(P->form[i])) {
         const char* e = (const char*)pr.prep + g.prep_extra_off;
-        const size_t yt = (size_t)g.N * 2 * g.LL * 32 * 2;
         d.yT = (const __bf16*)e;
-        d.yo = (const __bf16*)(e + align_up(yt));
+        d.yo = (const __bf16*)(e + align_up(bf16_yt_bytes(g.LL, g.N)));
     }
     const bool flip = par == 1;
     d.x = flip ? pr.x_new : pr.x;
@@ -656,11 +662,17 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         ClassLaunch& C = P->classes[cls];
         C.lds1 = std::max(C.lds1, g.lds1);
         C.lds2 = std::max(C.lds2, g.lds2);
-        for (int ch = 0; ch < g.n_chunks; ++ch) {
-            const int64_t nobs = std::min<int64_t>(g.chunk_obs, g.N - (int64_t)ch * g.chunk_obs);
-            const double cst = (double)nobs * g.cpb * (double)g.LL * g.LL * g.LL * g.LL *
-                               (f == FORM_VALU ? 2.0 : (f == FORM_BF16 ? 0.5 : (f == FORM_BF16X4 ? 0.67 : 1.0)));
-            for (int cg = 0; cg < g.n_cg; ++cg) costs.push_back({cls, cst, make_int4(i, ch, cg, 0)});
+        // one-component items are listed component-major, so that the blocks
+        // running at one time share few components' B fragments in L2
+        const bool comp_major = g.cpb == 1 && is_bf16_form(f);
+        for (int a = 0; a < (comp_major ? g.n_cg : g.n_chunks); ++a) {
+            for (int b = 0; b < (comp_major ? g.n_chunks : g.n_cg); ++b) {
+                const int ch = comp_major ? b : a, cg = comp_major ? a : b;
+                const int64_t nobs = std::min<int64_t>(g.chunk_obs, g.N - (int64_t)ch * g.chunk_obs);
+                const double cst = (double)nobs * g.cpb * (double)g.LL * g.LL * g.LL * g.LL *
+                                   (f == FORM_VALU ? 2.0 : (f == FORM_BF16 ? 0.5 : (f == FORM_BF16X4 ? 0.67 : 1.0)));
+                costs.push_back({cls, cst, make_int4(i, ch, cg, 0)});
+            }
         }
         for (int c = 0; c < g.KK; ++c) P->pack_items.push_back(make_int2(i, c));
         for (int k = 0; k < g.n_ll; ++k)

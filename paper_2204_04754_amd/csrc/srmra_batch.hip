@@ -8,7 +8,7 @@
 // own register allocation; a single kernel switching over all bodies spills.)
 #include "srmra_aux_impl.h"
 #include "srmra_batch.h"
-#include "srmra_bf16_impl.h"
+#include "srmra_bf16w_impl.h"
 #include "srmra_mfma_impl.h"
 #include "srmra_valu_impl.h"
 
@@ -34,7 +34,13 @@ __global__ __launch_bounds__(256) void k_batch_pack_xb(const InstDesc* __restric
     const InstDesc& d = D[it.x];
     if (d.form != FORM_BF16 && d.form != FORM_BF16X4) return;
     uint4* xb = const_cast<uint4*>(d.p.xb);
-    if (d.LL == 24) {
+    if (d.LL == 48 || d.LL == 64) {
+        const int nk = d.LL * (d.LL / 16);
+        for (int e = threadIdx.x >> 6; e < 2 * nk; e += 4) {
+            if (d.LL == 48) b16w::pack_xb_body<48>(d.p, d.x, it.y, e / nk, e % nk, xb);
+            else b16w::pack_xb_body<64>(d.p, d.x, it.y, e / nk, e % nk, xb);
+        }
+    } else if (d.LL == 24) {
         for (int ks = threadIdx.x >> 6; ks < b16::nk<24>(); ks += 4) b16::pack_xb_body<24>(d.p, d.x, it.y, ks, xb);
     } else {
         for (int ks = threadIdx.x >> 6; ks < b16::nk<32>(); ks += 4) b16::pack_xb_body<32>(d.p, d.x, it.y, ks, xb);
@@ -94,8 +100,16 @@ void k_class_pass(const InstDesc* __restrict__ D,
             b16::Prep q;
             q.yT = d.yT;
             q.yo = d.yo;
-            if constexpr (PASS == 1) b16::bf16_pass1_body<LL, NP>(d.p, q, w.y, w.z, lds);
-            else b16::bf16_pass2_body<LL, NP>(d.p, q, w.y, w.z, lds);
+            if constexpr (LL >= 48) {
+                b16w::Prep qw;
+                qw.yT = d.yT;
+                qw.yo = d.yo;
+                if constexpr (PASS == 1) b16w::pass1_body<LL, NP>(d.p, qw, w.y, w.z, lds);
+                else b16w::pass2_body<LL, NP>(d.p, qw, w.y, w.z, lds);
+            } else {
+                if constexpr (PASS == 1) b16::bf16_pass1_body<LL, NP>(d.p, q, w.y, w.z, lds);
+                else b16::bf16_pass2_body<LL, NP>(d.p, q, w.y, w.z, lds);
+            }
         } else if constexpr (FORM == FORM_FUSED) {
             mfma_fused_body<LL>(d.p, w.y, lds);
         } else if constexpr (FORM == FORM_MFMA) {
@@ -118,8 +132,10 @@ SRMRA_CLASS(FORM_VALU, 64)
 SRMRA_CLASS(FORM_MFMA, 8) SRMRA_CLASS(FORM_MFMA, 12) SRMRA_CLASS(FORM_MFMA, 16)
 SRMRA_CLASS(FORM_MFMA, 24) SRMRA_CLASS(FORM_MFMA, 32) SRMRA_CLASS(FORM_MFMA, 48)
 SRMRA_CLASS(FORM_MFMA, 64)
-SRMRA_CLASS(FORM_BF16, 24) SRMRA_CLASS(FORM_BF16, 32)
-SRMRA_CLASS(FORM_BF16X4, 24) SRMRA_CLASS(FORM_BF16X4, 32)
+SRMRA_CLASS(FORM_BF16, 24) SRMRA_CLASS(FORM_BF16, 32) SRMRA_CLASS(FORM_BF16, 48)
+SRMRA_CLASS(FORM_BF16, 64)
+SRMRA_CLASS(FORM_BF16X4, 24) SRMRA_CLASS(FORM_BF16X4, 32) SRMRA_CLASS(FORM_BF16X4, 48)
+SRMRA_CLASS(FORM_BF16X4, 64)
 #undef SRMRA_CLASS
 #define SRMRA_FUSED(L) template __global__ void k_class_pass<2, FORM_FUSED, L>(const InstDesc*, const int4*, int, int*);
 SRMRA_FUSED(8) SRMRA_FUSED(12) SRMRA_FUSED(16) SRMRA_FUSED(24) SRMRA_FUSED(32) SRMRA_FUSED(48)
@@ -136,8 +152,10 @@ const void* class_pass_fn(int pass, int form, int LL) {
     SRMRA_PICK(FORM_MFMA, 8) SRMRA_PICK(FORM_MFMA, 12) SRMRA_PICK(FORM_MFMA, 16)
     SRMRA_PICK(FORM_MFMA, 24) SRMRA_PICK(FORM_MFMA, 32) SRMRA_PICK(FORM_MFMA, 48)
     SRMRA_PICK(FORM_MFMA, 64)
-    SRMRA_PICK(FORM_BF16, 24) SRMRA_PICK(FORM_BF16, 32)
-    SRMRA_PICK(FORM_BF16X4, 24) SRMRA_PICK(FORM_BF16X4, 32)
+    SRMRA_PICK(FORM_BF16, 24) SRMRA_PICK(FORM_BF16, 32) SRMRA_PICK(FORM_BF16, 48)
+    SRMRA_PICK(FORM_BF16, 64)
+    SRMRA_PICK(FORM_BF16X4, 24) SRMRA_PICK(FORM_BF16X4, 32) SRMRA_PICK(FORM_BF16X4, 48)
+    SRMRA_PICK(FORM_BF16X4, 64)
 #undef SRMRA_PICK
     // single pass: no pass-1 kernel
 #define SRMRA_PICK(L) if (form == FORM_FUSED && LL == L) return pass == 2 ? (const void*)k_class_pass<2, FORM_FUSED, L> : nullptr;

@@ -1,5 +1,6 @@
-// BF16 split-precision kernels of the EM step (bodies in srmra_bf16_impl.h).
-#include "srmra_bf16_impl.h"
+// BF16 split-precision kernels of the EM step (bodies in srmra_bf16_impl.h for
+// L_low 24 and 32, srmra_bf16w_impl.h for L_low 48 and 64).
+#include "srmra_bf16w_impl.h"
 
 namespace srmra {
 namespace b16 {
@@ -27,14 +28,70 @@ __global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __rest
 
 }  // namespace b16
 
+namespace b16w {
+
+// Single-problem launches run a 1-D grid in which each XCD (blocks b with the
+// same b mod 8) takes a contiguous range of (component, chunk) items,
+// component-major, so the blocks resident on one XCD share one or two
+// components' B fragments (K^2 MiB at Ll = 64) in that XCD's L2.
+__device__ __forceinline__ bool xcd_item(const StepArgs& p, int per_xcd, int& chunk, int& comp) {
+    const int b = blockIdx.x;
+    const int idx = (b & 7) * per_xcd + (b >> 3);
+    if (idx >= p.n_chunks * p.KK) return false;
+    comp = idx / p.n_chunks;
+    chunk = idx % p.n_chunks;
+    return true;
+}
+
+template <int LL, int NP>
+__global__ __launch_bounds__(256, 2) void k_score_lse(StepArgs p, Prep q, int per_xcd) {
+    extern __shared__ float lds[];
+    int chunk, comp;
+    if (!xcd_item(p, per_xcd, chunk, comp)) return;
+    pass1_body<LL, NP>(p, q, chunk, comp, lds);
+}
+
+template <int LL, int NP>
+__global__ __launch_bounds__(256, 1) void k_backproject(StepArgs p, Prep q, int per_xcd) {
+    extern __shared__ float lds[];
+    int chunk, comp;
+    if (!xcd_item(p, per_xcd, chunk, comp)) return;
+    pass2_body<LL, NP>(p, q, chunk, comp, lds);
+}
+
+// grid (2 KK, k-steps / 4): block (c, tb1), 4 k-steps per block
+template <int LL>
+__global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __restrict__ x,
+                                                 uint4* __restrict__ xb) {
+    const int ks = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (ks < Geo<LL>::NK) pack_xb_body<LL>(p, x, blockIdx.x >> 1, blockIdx.x & 1, ks, xb);
+}
+
+}  // namespace b16w
+
 
 // ---------------------------------------------------------------- host side
+static bool wide_ll(int LL) { return LL == 48 || LL == 64; }
+bool bf16_supported(int LL) { return LL == 24 || LL == 32 || wide_ll(LL); }
+
+// pass-1 partials per observation: one per component pair (one-tile form) or
+// per (component, tile) (L_low 48 and 64)
+int bf16_parts(int LL, int KK) { return wide_ll(LL) ? 4 * KK : (KK + 1) / 2; }
+
 size_t bf16_xb_bytes(int LL, int KK) {
+    if (wide_ll(LL)) return (size_t)KK * 2 * LL * (LL / 16) * 128 * sizeof(uint4);
     if (LL != 24 && LL != 32) return 0;
     return (size_t)KK * LL * (b16::R1P / 16) * 128 * sizeof(uint4);
 }
 
 hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, hipStream_t s) {
+    if (wide_ll(LL)) {
+        const int nks = LL * (LL / 16);
+        const dim3 grid(2 * p.KK, (nks + 3) / 4);
+        if (LL == 48) hipLaunchKernelGGL(b16w::k_pack_xb<48>, grid, dim3(256), 0, s, p, x, (uint4*)xb);
+        else hipLaunchKernelGGL(b16w::k_pack_xb<64>, grid, dim3(256), 0, s, p, x, (uint4*)xb);
+        return hipGetLastError();
+    }
     const int nks = LL * (b16::R1P / 16);
     const dim3 grid(p.KK, (nks + 3) / 4);
     if (LL == 24) hipLaunchKernelGGL(b16::k_pack_xb<24>, grid, dim3(256), 0, s, p, x, (uint4*)xb);
@@ -43,9 +100,14 @@ hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, h
     return hipGetLastError();
 }
 
+// bytes of the yT planes (the first prepared layout)
+size_t bf16_yt_bytes(int LL, int64_t N) {
+    return (size_t)N * 2 * LL * (wide_ll(LL) ? LL : b16::R1P) * 2;
+}
+
 size_t bf16_prepared_extra(int LL, int64_t N) {
-    if (LL != 24 && LL != 32) return 0;
-    const size_t yt = (size_t)N * 2 * LL * b16::R1P * 2;
+    if (!bf16_supported(LL)) return 0;
+    const size_t yt = bf16_yt_bytes(LL, N);
     const size_t yo = (size_t)((N + 7) / 8) * 2 * LL * LL * 8 * 2;
     return ((yt + 255) / 256) * 256 + ((yo + 255) / 256) * 256;
 }
@@ -53,16 +115,29 @@ size_t bf16_prepared_extra(int LL, int64_t N) {
 static b16::Prep prep_ptrs(const void* prep_extra, int LL, int64_t N) {
     b16::Prep q;
     const char* b = (const char*)prep_extra;
-    const size_t yt = (size_t)N * 2 * LL * b16::R1P * 2;
     q.yT = (const __bf16*)b;
-    q.yo = (const __bf16*)(b + ((yt + 255) / 256) * 256);
+    q.yo = (const __bf16*)(b + ((bf16_yt_bytes(LL, N) + 255) / 256) * 256);
     return q;
+}
+
+template <int LL>
+static hipError_t launch_prep_wide(const float* y, int64_t N, const double* centre, double* ynorm,
+                                   const b16::Prep& q, hipStream_t s) {
+    const size_t lds = b16w::lds_prep<LL>();
+    if (hipFuncSetAttribute((const void*)b16w::k_prep<LL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(b16w::k_prep<LL>, dim3((unsigned)((N + 7) / 8)), dim3(256), lds, s, y, N,
+                       centre, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
+    return hipGetLastError();
 }
 
 hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* centre, double* ynorm,
                             void* prep_extra, hipStream_t s) {
     b16::Prep q = prep_ptrs(prep_extra, LL, N);
     const dim3 grid((unsigned)((N + 7) / 8));
+    if (LL == 48) return launch_prep_wide<48>(y, N, centre, ynorm, q, s);
+    if (LL == 64) return launch_prep_wide<64>(y, N, centre, ynorm, q, s);
     if (LL == 24) hipLaunchKernelGGL(b16::k_prep_bf16<24>, grid, dim3(256), 0, s, y, N, centre, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
     else if (LL == 32) hipLaunchKernelGGL(b16::k_prep_bf16<32>, grid, dim3(256), 0, s, y, N, centre, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
     else return hipErrorInvalidValue;
@@ -86,9 +161,27 @@ static hipError_t launch_bf16_ll(int pass, const StepArgs& p, const b16::Prep& q
     return hipGetLastError();
 }
 
+template <int LL, int NP>
+static hipError_t launch_bf16w_ll(int pass, const StepArgs& p, const b16::Prep& q0, hipStream_t s) {
+    b16w::Prep q;
+    q.yT = q0.yT;
+    q.yo = q0.yo;
+    const int per_xcd = (p.n_chunks * p.KK + 7) / 8;
+    const dim3 grid(8 * per_xcd);
+    const void* f = pass == 1 ? (const void*)b16w::k_score_lse<LL, NP> : (const void*)b16w::k_backproject<LL, NP>;
+    const size_t lds = pass == 1 ? b16w::lds_pass1<LL>() : b16w::lds_pass2<LL>();
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return hipErrorInvalidValue;
+    if (pass == 1) hipLaunchKernelGGL((b16w::k_score_lse<LL, NP>), grid, dim3(256), lds, s, p, q, per_xcd);
+    else hipLaunchKernelGGL((b16w::k_backproject<LL, NP>), grid, dim3(256), lds, s, p, q, per_xcd);
+    return hipGetLastError();
+}
+
 hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
                        hipStream_t s) {
     const b16::Prep q = prep_ptrs(prep_extra, LL, p.N);
+    if (LL == 48) return np == 4 ? launch_bf16w_ll<48, 4>(pass, p, q, s) : launch_bf16w_ll<48, 3>(pass, p, q, s);
+    if (LL == 64) return np == 4 ? launch_bf16w_ll<64, 4>(pass, p, q, s) : launch_bf16w_ll<64, 3>(pass, p, q, s);
     if (LL == 24) return np == 4 ? launch_bf16_ll<24, 4>(pass, p, q, s) : launch_bf16_ll<24, 3>(pass, p, q, s);
     if (LL == 32) return np == 4 ? launch_bf16_ll<32, 4>(pass, p, q, s) : launch_bf16_ll<32, 3>(pass, p, q, s);
     return hipErrorInvalidValue;
@@ -102,10 +195,29 @@ static void bf16_geom_ll(size_t& lds1, size_t& lds2, const void*& f1, const void
     f2 = (const void*)b16::k_backproject_bf16<LL, NP>;
 }
 
+template <int LL, int NP>
+static void bf16w_geom_ll(size_t& lds1, size_t& lds2, const void*& f1, const void*& f2) {
+    lds1 = b16w::lds_pass1<LL>();
+    lds2 = b16w::lds_pass2<LL>();
+    f1 = (const void*)b16w::k_score_lse<LL, NP>;
+    f2 = (const void*)b16w::k_backproject<LL, NP>;
+}
+
 bool bf16_geom(int LL, int np, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
                const void*& f2) {
     cpb = 4;
     nt = 8;
+    if (wide_ll(LL)) {
+        cpb = 1;   // one component per block, one tile per wave
+        if (LL == 48) {
+            if (np == 4) bf16w_geom_ll<48, 4>(lds1, lds2, f1, f2);
+            else bf16w_geom_ll<48, 3>(lds1, lds2, f1, f2);
+        } else {
+            if (np == 4) bf16w_geom_ll<64, 4>(lds1, lds2, f1, f2);
+            else bf16w_geom_ll<64, 3>(lds1, lds2, f1, f2);
+        }
+        return true;
+    }
     if (LL == 24) {
         if (np == 4) bf16_geom_ll<24, 4>(lds1, lds2, f1, f2);
         else bf16_geom_ll<24, 3>(lds1, lds2, f1, f2);

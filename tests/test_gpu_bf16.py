@@ -1,5 +1,5 @@
-"""GPU parity of the BF16 split-precision form (L_low 24 and 32) against the
-FP64 oracle."""
+"""GPU parity of the BF16 split-precision form (L_low 24 and 32 with one 32x32
+tile per score map, 48 and 64 with 2 x 2 tiles) against the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -22,7 +22,9 @@ def _gpu():
 # every component carries at least one observation's worth of posterior mass
 @pytest.mark.parametrize("prec", ["bf16_split3", "bf16_split4"])
 @pytest.mark.parametrize("Lh,K,N,sigma", [(48, 2, 41, 2.0), (64, 2, 27, 2.0), (96, 4, 151, 2.0),
-                                          (128, 4, 133, 2.0), (96, 3, 77, 2.0), (64, 2, 600, 0.7)])
+                                          (128, 4, 133, 2.0), (96, 3, 77, 2.0), (64, 2, 600, 0.7),
+                                          (96, 2, 45, 2.0), (144, 3, 61, 2.0), (128, 2, 40, 2.0),
+                                          (192, 3, 37, 2.0)])
 def test_shapes(Lh, K, N, sigma, prec):
     inst = synth.make_instance(Lh, K, N, sigma, config=60, instance=Lh + K)
     rng = np.random.default_rng(Lh * K)
@@ -56,10 +58,27 @@ def test_precision_workload_subset(sigma, prec):
         lr = g["log_rho_new"].astype(np.float32)
 
 
+def test_wide_tiles_many_chunks():
+    """L_low 64 with a ragged observation count spread over many chunks (one
+    8-observation group each, the last with 3), unnormalised log rho."""
+    inst = synth.make_instance(128, 2, 203, 1.0, config=62)
+    lr = (inst.log_rho0 + np.float32(0.7)).astype(np.float32)
+    g = gpu_step(inst.y, inst.x0, lr, 1.0, 2, "bf16_split3")
+    ref = O.em_step(inst.y, inst.x0, lr, 1.0, 2, return_details=True)
+    ex, er = check_step(inst.y, inst.x0, lr, 1.0, 2, g, ref, u=U_SPLIT)
+    print(f"Lh 128 K 2 N 203: x {ex:.2e} rho {er:.2e}")
+    assert rel(g["c"], ref["c"]) < 1e-4 and rel(g["b"], ref["b"]) < 1e-4
+
+
 def test_deterministic_and_unsupported():
     inst = synth.make_instance(64, 2, 1000, 1.0, config=61)
     a = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 2, "bf16_split3")
     b = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 2, "bf16_split3")
+    for k in ("x_new", "rho_new", "loglik", "ll_obs", "b", "c"):
+        assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+    inst = synth.make_instance(192, 3, 100, 1.0, config=61)
+    a = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 3, "bf16_split3")
+    b = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 3, "bf16_split3")
     for k in ("x_new", "rho_new", "loglik", "ll_obs", "b", "c"):
         assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
     from paper_2204_04754_amd import binding as B
