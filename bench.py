@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--iterations", type=int, default=20)
     ap.add_argument("--rates", default="5,50,200")
     ap.add_argument("--jobs", type=int, default=24)
+    ap.add_argument("--serve-precisions", default="",
+                    help="serve mode: comma-separated forms (default: --precision, fp32_mfma, fp32_plain)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the timed region, run one device-to-device copy of this many MiB "
                          "(reference kernel of known traffic for hardware-counter calibration)")
@@ -435,7 +437,8 @@ def bench_serve(args):
         arr = np.cumsum(r.exponential(1.0 / rate, size=args.jobs))
         pick = [11 if r.random() < 0.1 else int(r.integers(0, 11)) for _ in range(args.jobs)]
         seqs[rate] = (arr, pick)
-    for prec in dict.fromkeys([args.precision, "fp32_mfma", "fp32_plain"]):
+    precs = [p for p in args.serve_precisions.split(",") if p] or [args.precision, "fp32_mfma", "fp32_plain"]
+    for prec in dict.fromkeys([args.precision] + precs):
         for rate in rates:
             arr, pick = seqs[rate]
             jobs = []
