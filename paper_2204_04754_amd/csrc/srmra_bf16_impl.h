@@ -172,6 +172,46 @@ __device__ __forceinline__ void score(const StepArgs& p, const __bf16* ys, const
             // compiler-only barrier: keeps the requests here instead of letting the
             // compiler re-issue them next to their use (no instruction, no wait)
             asm volatile("" ::: "memory");
+            if constexpr (NC == 1 && NO == 8) {
+                // eight observations, one component: the A fragments of two
+                // observations are requested while the products of the previous
+                // two run, and the two accumulators of a pair alternate so that
+                // consecutive products never depend on each other
+                bf16x8 ah[8], al[8];
+                auto load = [&](int o) {
+                    ah[o] = *reinterpret_cast<const bf16x8*>(arow[o] + 16 * j);
+                    al[o] = *reinterpret_cast<const bf16x8*>(arow[o] + LL * PITCH + 16 * j);
+                };
+                load(0);
+                load(1);
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int pr = 0; pr < 4; ++pr) {
+                    const int o = 2 * pr;
+                    if (pr < 3) {
+                        load(o + 2);
+                        load(o + 3);
+                    }
+                    asm volatile("" ::: "memory");
+                    __builtin_amdgcn_sched_barrier(0);
+                    floatx16& a0 = acc[o][0];
+                    floatx16& a1 = acc[o + 1][0];
+                    a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[o], bh[0], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[o + 1], bh[0], a1, 0, 0, 0);
+                    a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[o], bl[0], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[o + 1], bl[0], a1, 0, 0, 0);
+                    a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o], bh[0], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o + 1], bh[0], a1, 0, 0, 0);
+                    if constexpr (NP == 4) {
+                        a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o], bl[0], a0, 0, 0, 0);
+                        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o + 1], bl[0], a1, 0, 0, 0);
+                    }
+                }
+                bh[0] = nh[0];
+                bl[0] = nl[0];
+                continue;
+            }
             bf16x8 ah[NO], al[NO];
 #pragma unroll
             for (int o = 0; o < NO; ++o) {
@@ -337,25 +377,34 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
             }
             split8(w, wh[v], wl[v]);
         }
-        // back-projection for each a1, folded into the wave's b accumulator
+        // back-projection for each a1, folded into the wave's b accumulator;
+        // accumulator rows v with t2 >= Ll (Ll = 24: v >= 12) carry no weight
+        constexpr int NV = LL == 24 ? 12 : 16;
+        constexpr int PF = 4;
         for (int a1 = 0; a1 < LL; ++a1) {
-            // four independent partial sums (v mod 4) so that consecutive MFMAs
-            // do not depend on each other
-            floatx16 zp[4] = {floatx16{0}, floatx16{0}, floatx16{0}, floatx16{0}};
             const __bf16* yrow = yo + a1 * LL * 8;
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                int t2 = acc_row(v, lane);
-                t2 = t2 < LL ? t2 : t2 - LL;
-                int col = q2e + t2;
+            // A fragments requested PF rows v ahead of their products; two
+            // partial sums alternate so that consecutive MFMAs are independent
+            bf16x8 ah[NV], al[NV];
+            auto load_a = [&](int v) {
+                int col = q2e + acc_row(v, lane);
                 col = col >= LL ? col - LL : col;
-                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(yrow + col * 8);
-                const bf16x8 al = *reinterpret_cast<const bf16x8*>(yrow + LL * LL * 8 + col * 8);
-                zp[v & 3] = mfma_split<NP>(ah, al, wh[v], wl[v], zp[v & 3]);
+                ah[v] = *reinterpret_cast<const bf16x8*>(yrow + col * 8);
+                al[v] = *reinterpret_cast<const bf16x8*>(yrow + LL * LL * 8 + col * 8);
+            };
+#pragma unroll
+            for (int v = 0; v < PF; ++v) load_a(v);
+            floatx16 zp[2] = {floatx16{0}, floatx16{0}};
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                if (v + PF < NV) load_a(v + PF);
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+                zp[v & 1] = mfma_split<NP>(ah[v], al[v], wh[v], wl[v], zp[v & 1]);
             }
             floatx16 z;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) z[e] = (zp[0][e] + zp[1][e]) + (zp[2][e] + zp[3][e]);
+            for (int e = 0; e < 16; ++e) z[e] = zp[0][e] + zp[1][e];
             // z lane holds Z[q2 = acc_row(v)][t1 = j]; b_c[(a1 - t1) % Ll][q2] += Z
             if (j < LL) {
                 int q1 = a1 - j;

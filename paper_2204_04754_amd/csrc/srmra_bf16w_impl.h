@@ -131,30 +131,37 @@ __device__ __forceinline__ void score(const StepArgs& p, const Prep& q, __bf16* 
             const int kn = ks + 1 < G::NK ? ks + 1 : ks;
             const bf16x8 nh = __builtin_bit_cast(bf16x8, bsrc[kn * 128]);
             const bf16x8 nl = __builtin_bit_cast(bf16x8, bsrc[kn * 128 + 64]);
-            // compiler-only barrier: keeps the next fragments' requests here
-            asm volatile("" ::: "memory");
             int col = b2 + t2e;
             col = col >= LL ? col - LL : col;
             const __bf16* arow = st + col * SP + 8 * g;
             bf16x8 ah[8], al[8];
-#pragma unroll
-            for (int o = 0; o < 8; ++o) {
+            auto load = [&](int o) {
                 ah[o] = *reinterpret_cast<const bf16x8*>(arow + (o * 2 * LL) * SP);
                 al[o] = *reinterpret_cast<const bf16x8*>(arow + (o * 2 * LL + LL) * SP);
-            }
+            };
+            load(0);
+            load(1);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int o = 0; o < 8; ++o)
+            for (int pr = 0; pr < 4; ++pr) {
+                const int o = 2 * pr;
+                if (pr < 3) {
+                    load(o + 2);
+                    load(o + 3);
+                }
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
                 acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[o], bh, acc[o], 0, 0, 0);
-#pragma unroll
-            for (int o = 0; o < 8; ++o)
+                acc[o + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[o + 1], bh, acc[o + 1], 0, 0, 0);
                 acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[o], bl, acc[o], 0, 0, 0);
-#pragma unroll
-            for (int o = 0; o < 8; ++o)
+                acc[o + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[o + 1], bl, acc[o + 1], 0, 0, 0);
                 acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o], bh, acc[o], 0, 0, 0);
-            if constexpr (NP == 4) {
-#pragma unroll
-                for (int o = 0; o < 8; ++o)
+                acc[o + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o + 1], bh, acc[o + 1], 0, 0, 0);
+                if constexpr (NP == 4) {
                     acc[o] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o], bl, acc[o], 0, 0, 0);
+                    acc[o + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[o + 1], bl, acc[o + 1], 0, 0, 0);
+                }
             }
             bh = nh;
             bl = nl;
@@ -214,6 +221,40 @@ __device__ __forceinline__ void pass1_body(const StepArgs& p, const Prep& q, int
     }
 }
 
+// Z[q2][t1] of one row a1 (staged Yo row yrow) over the first NV accumulator
+// rows v of the wave's w fragments: Z = sum_v A_v W_v, A_v[q2][(t2, o)] =
+// y_o[a1][(q2 + t2) % Ll].  The A fragments (both planes) are requested PF rows
+// v ahead of their products so that the LDS latency is covered.
+template <int LL, int NP, int NV>
+__device__ __forceinline__ floatx16 bp_rows(const __bf16* yrow, int q2e, int tb2, const bf16x8 (&wh)[16],
+                                            const bf16x8 (&wl)[16]) {
+    constexpr int PF = 4;
+    const int lane = threadIdx.x & 63;
+    bf16x8 ah[NV], al[NV];
+    auto load_a = [&](int v) {
+        const int t2 = 32 * tb2 + acc_row(v, lane);
+        int col = q2e + t2;
+        col = col >= LL ? col - LL : col;
+        ah[v] = *reinterpret_cast<const bf16x8*>(yrow + col * 8);
+        al[v] = *reinterpret_cast<const bf16x8*>(yrow + YR * LL * 8 + col * 8);
+    };
+#pragma unroll
+    for (int v = 0; v < PF; ++v) load_a(v);
+    floatx16 zp[2] = {floatx16{0}, floatx16{0}};
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        if (v + PF < NV) load_a(v + PF);
+        // compiler-only barriers: the request stays PF rows ahead of its use
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        zp[v & 1] = b16::mfma_split<NP>(ah[v], al[v], wh[v], wl[v], zp[v & 1]);
+    }
+    floatx16 z;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) z[e] = zp[0][e] + zp[1][e];
+    return z;
+}
+
 // ============================================================================
 // Pass 2: posterior weights of the wave's tile, back-projection and posterior
 // mass; per-chunk partials of component comp.
@@ -237,7 +278,8 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const Prep& q, int
 #pragma unroll
     for (int v = 0; v < 16; ++v) cnt[v] = 0.f;
     // rows t2 >= Ll of the second t2-tile (Ll = 48: v >= 8) carry no weight
-    const int nv = (LL < 64 && tb2 == 1) ? 8 * ((LL - 32) / 16) : 16;
+    const int nv = (LL < 64 && tb2 == 1) ? 8 : 16;
+    static_assert(LL == 48 || LL == 64, "two 32-wide tiles per axis");
     const int64_t c0 = (int64_t)chunk * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
     for (int64_t o0 = c0; o0 < c1; o0 += 8) {
@@ -272,21 +314,12 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const Prep& q, int
                 for (int qb = 0; qb < 2; ++qb) {
                     const int q2 = 32 * qb + j;
                     const int q2e = q2 < LL ? q2 : q2 - LL;
-                    floatx16 zp[4] = {floatx16{0}, floatx16{0}, floatx16{0}, floatx16{0}};
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        if (v >= nv) break;
-                        const int t2 = 32 * tb2 + acc_row(v, lane);
-                        int col = q2e + t2;
-                        col = col >= LL ? col - LL : col;
-                        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(yrow + col * 8);
-                        const bf16x8 al = *reinterpret_cast<const bf16x8*>(yrow + YR * LL * 8 + col * 8);
-                        zp[v & 3] = b16::mfma_split<NP>(ah, al, wh[v], wl[v], zp[v & 3]);
-                    }
-                    floatx16 z;
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) z[e] = (zp[0][e] + zp[1][e]) + (zp[2][e] + zp[3][e]);
-                    // lane holds Z[q2 = 32 qb + acc_row(v)][t1]; b_c[(a1 - t1) % Ll][q2] += Z
+                    const floatx16 z = nv == 16 ? bp_rows<LL, NP, 16>(yrow, q2e, tb2, wh, wl)
+                                                : bp_rows<LL, NP, (LL < 64 ? 8 : 16)>(yrow, q2e, tb2, wh, wl);
+                    // lane holds Z[q2 = 32 qb + acc_row(v)][t1]; b_c[(a1 - t1) % Ll][q2] += Z.
+                    // LDS adds without return: the accumulator is private to the
+                    // wave, the lanes of one add hit distinct words and one wave's
+                    // LDS operations complete in order, so the sums are deterministic
                     if (t1ok) {
                         int q1 = a1 - t1;
                         q1 = q1 < 0 ? q1 + LL : q1;
