@@ -49,11 +49,14 @@ HBM_PEAK = 8.0e12   # B/s
 # reports null until its counters are taken again.
 _MFMA_SRC = ("srmra_common.h", "srmra_mfma_impl.h", "srmra_mfma.hip")
 _BF16_SRC = ("srmra_common.h", "srmra_bf16_impl.h", "srmra_bf16.hip")
+_BF16W_SRC = ("srmra_common.h", "srmra_bf16_impl.h", "srmra_bf16w_impl.h", "srmra_bf16.hip")
 TRAFFIC = {
     ("lh64_k2_n100000", "fp32_mfma", "k_fused_mfma<32>"):
         dict(bytes=428061491, src=_MFMA_SRC, sha="afe068a4c07ebf90"),
     ("lh128_k4_n200000_s0.5", "bf16_split3", "k_backproject_bf16<32, 3>"):
-        dict(bytes=1667245261, src=_BF16_SRC, sha="b388cb12823a5049"),
+        dict(bytes=1667599104, src=_BF16_SRC, sha="74bec3308467ac0f"),
+    ("lh256_k4_n20000", "bf16_split3", "b16w::k_backproject<64, 3>"):
+        dict(bytes=7659694336, src=_BF16W_SRC, sha="eeed951a3ba32ebd"),
 }
 
 
@@ -543,6 +546,10 @@ def main():
         kname = f"k_fused_{KNAME[args.precision]}{targ}"
         alg_flop = 4.0 * Ll2 * pairs
         issued_flop = alg_flop * prod
+    elif args.precision in PRODUCTS and inst.Ll >= 48:   # BF16 split with 2 x 2 tiles
+        kname = f"b16w::k_backproject{targ}"
+        alg_flop = 2.0 * Ll2 * pairs
+        issued_flop = 4.0 * Ll2 * pairs * prod
     else:
         kname = f"k_backproject_{KNAME[args.precision]}{targ}"
         alg_flop = 2.0 * Ll2 * pairs

@@ -24,7 +24,8 @@ def _gpu():
 @pytest.mark.parametrize("Lh,K,N,sigma", [(48, 2, 41, 2.0), (64, 2, 27, 2.0), (96, 4, 151, 2.0),
                                           (128, 4, 133, 2.0), (96, 3, 77, 2.0), (64, 2, 600, 0.7),
                                           (96, 2, 45, 2.0), (144, 3, 61, 2.0), (128, 2, 40, 2.0),
-                                          (192, 3, 37, 2.0)])
+                                          (192, 3, 37, 2.0), (48, 1, 50, 2.0), (64, 1, 33, 2.0),
+                                          (24, 1, 19, 2.0)])
 def test_shapes(Lh, K, N, sigma, prec):
     inst = synth.make_instance(Lh, K, N, sigma, config=60, instance=Lh + K)
     rng = np.random.default_rng(Lh * K)
