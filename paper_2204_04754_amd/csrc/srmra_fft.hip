@@ -1,14 +1,15 @@
 // FFT route of the EM step (SRMRA_FP32_FFT, L_low in {8, 16, 32}): the same
-// step as the dense forms, with both contractions as products in the 2-D DFT
+// step as the dense forms, with the contractions as products in the 2-D DFT
 // domain of the L_low grid.  With (R_t v)[n] = v[n - t]:
 //   score     S_{i,c}[t] = sum_n y_i[n] x_c[n - t]      = IDFT(Y_i . conj(X_c))[t]
 //   back-proj b_c[q]     = sum_i sum_t w_{i,c}[t] y_i[q + t] = IDFT(sum_i Y_i . conj(W_{i,c}))[q]
-//   mass      c_c[t]     = sum_i w_{i,c}[t]              = IDFT(sum_i W_{i,c})[t]
+//   mass      c_c[t]     = sum_i w_{i,c}[t]   (summed directly, no transform)
 // Y_i (DFT of y_i - mu) is prepared once per job; X_c once per step.  Pass 1:
 // team per observation, its (max, sum exp) over all components.  Pass 2: team
 // per component (observations split over TPC teams), w = exp(a - LSE_i), its
-// DFT, and the two frequency-domain sums; per-chunk FP32 partials, summed in
-// FP64 and brought back by a direct FP64 inverse DFT.  One component per
+// DFT, the frequency-domain sum of the back-projection and the spatial sum of
+// w; per-chunk FP32 partials, summed in FP64, the former brought back by a
+// direct FP64 inverse DFT.  One component per
 // transform: packing two real signals into one complex transform would give a
 // component of little posterior mass the rounding error of its heavier
 // partner.  The transforms are the in-register team FFTs of srmra_fft_impl.h
@@ -28,8 +29,12 @@ template <int L> constexpr size_t lds_bytes() {
     return sizeof(float2) * ((size_t)Geo<L>::TEAMS * Geo<L>::BUF + L / 2);
 }
 
-// ---- per job: Y_i = DFT(y_i - mu), [N][L][L] complex (k1-major)
-template <int L>
+// ---- per job: Y_i = DFT(y_i - mu), [N][L][L] complex.  TRANSPOSED: stored in
+// pairs along k2, Yp[i][k2 / 2][k1][k2 % 2] = Y_i[k1][k2], so that the thread
+// of a team that holds row k1 of Y_i reads two elements per 16-byte load and
+// the team's lanes read consecutive 16-byte words; otherwise natural order
+// Y[i][k1][k2].
+template <int L, bool TRANSPOSED>
 __device__ __forceinline__ void prep_y_body(const float* __restrict__ y, int64_t N,
                                             const double* __restrict__ centre,
                                             float2* __restrict__ yhat) {
@@ -43,21 +48,35 @@ __device__ __forceinline__ void prep_y_body(const float* __restrict__ y, int64_t
     const int64_t i = (int64_t)blockIdx.x * Geo<L>::TEAMS + team;
     if (i >= N) return;   // whole teams leave together (a team lies in one wave)
     float2 v[L];
+    if constexpr (TRANSPOSED) {
+        // thread r: column r of y_i in, row r of Y_i out (both coalesced over the team)
 #pragma unroll
-    for (int k = 0; k < L; ++k) v[k] = make_float2(y[(i * L + r) * L + k] - mu, 0.f);
-    fft2_rows_then_cols<L, false>(v, buf, r, tw);
+        for (int k = 0; k < L; ++k) v[k] = make_float2(y[(i * L + k) * L + r] - mu, 0.f);
+        fft2_cols_then_rows<L, false>(v, buf, r, tw);
+    } else {
 #pragma unroll
-    for (int k = 0; k < L; ++k) yhat[(i * L + k) * L + r] = v[k];
+        for (int k = 0; k < L; ++k) v[k] = make_float2(y[(i * L + r) * L + k] - mu, 0.f);
+        fft2_rows_then_cols<L, false>(v, buf, r, tw);
+    }
+    if constexpr (TRANSPOSED) {   // v[k] = Y_i[r][k]
+        float4* d = reinterpret_cast<float4*>(yhat) + i * (L / 2) * L + r;
+#pragma unroll
+        for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
+    } else {                      // v[k] = Y_i[k][r]
+#pragma unroll
+        for (int k = 0; k < L; ++k) yhat[(i * L + k) * L + r] = v[k];
+    }
 }
 
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_prep_y(const float* __restrict__ y, int64_t N,
                                                     const double* __restrict__ centre,
                                                     float2* __restrict__ yhat) {
-    prep_y_body<L>(y, N, centre, yhat);
+    prep_y_body<L, true>(y, N, centre, yhat);
 }
 
-// ---- per step: X_c = DFT(x_c - mu), [KK][L][L]; one block (first L threads) per component
+// ---- per step: X_c = DFT(x_c - mu), stored in pairs along k2 like Y:
+// Xp[c][k2 / 2][k1][k2 % 2] = X_c[k1][k2]; one block (first L threads) per component
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_pack_x(const float* __restrict__ x, int K,
                                                     const double* __restrict__ centre,
@@ -71,11 +90,12 @@ __global__ __launch_bounds__(256) void k_fft_pack_x(const float* __restrict__ x,
     const float mu = centre_of(centre);
     float2 v[L];
 #pragma unroll
-    for (int k = 0; k < L; ++k)
-        v[k] = make_float2(x[(int64_t)(c1 + r * K) * Lh + (c2 + k * K)] - mu, 0.f);
-    fft2_rows_then_cols<L, false>(v, sh, r, tw);
+    for (int k = 0; k < L; ++k)   // column r of x_c: v[k] = x_c[k][r]
+        v[k] = make_float2(x[(int64_t)(c1 + k * K) * Lh + (c2 + r * K)] - mu, 0.f);
+    fft2_cols_then_rows<L, false>(v, sh, r, tw);   // v[k] = X_c[r][k]
+    float4* d = reinterpret_cast<float4*>(xhat) + (int64_t)c * (L / 2) * L + r;
 #pragma unroll
-    for (int k = 0; k < L; ++k) xhat[((int64_t)c * L + k) * L + r] = v[k];
+    for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
 }
 
 // score column r of (observation o, component c): s[k] = a at (t1 = k, t2 = r)
@@ -84,10 +104,15 @@ __device__ __forceinline__ void score_column(const StepArgs& p, const float2* __
                                              const float2* __restrict__ xhat, int64_t o, int c,
                                              float2* buf, int r, const float2* tw, float (&s)[L]) {
     float2 v[L];
-    const float2* yr = yhat + (o * L + r) * L;
-    const float2* xr = xhat + ((int64_t)c * L + r) * L;
+    // row r of Y_o conj(X_c) from the paired layouts: elements k, k + 1 at [k / 2][r]
+    const float4* yr = reinterpret_cast<const float4*>(yhat) + o * (L / 2) * L + r;
+    const float4* xr = reinterpret_cast<const float4*>(xhat) + (int64_t)c * (L / 2) * L + r;
 #pragma unroll
-    for (int k = 0; k < L; ++k) v[k] = cmulc(yr[k], xr[k]);
+    for (int k = 0; k < L; k += 2) {
+        const float4 a = yr[(k / 2) * L], b = xr[(k / 2) * L];
+        v[k] = cmulc(make_float2(a.x, a.y), make_float2(b.x, b.y));
+        v[k + 1] = cmulc(make_float2(a.z, a.w), make_float2(b.z, b.w));
+    }
     fft2_rows_then_cols<L, true>(v, buf, r, tw);
     const float sc = p.inv_s2 / (float)(L * L);
     const float* bet = p.betaT + (int64_t)c * (L * L) + r * L;   // betaT[c][t2 = r][t1]
@@ -139,15 +164,15 @@ __global__ __launch_bounds__(256) void k_fft_pass1(StepArgs p, const float2* __r
     }
 }
 
-// ---- pass 2: per component group, the frequency-domain sums over the chunk.
-// Component group g holds CG components, TPC = TEAMS / CG teams each
-// (observations split over them); partials [chunk][c][k1][k2] of
-// sum_i Y_i conj(W_i) (bpart) and sum_i W_i (cpart), as float2.
+// ---- pass 2: per component group, the sums over the chunk.  Component group
+// g holds CG components, TPC = TEAMS / CG teams each (observations split over
+// them); partials [chunk][c][k1][k2] of sum_i Y_i conj(W_i) (bpart, float2)
+// and [chunk][c][t1][t2] of sum_i w_i (cpart, float).
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __restrict__ yhat,
                                                    const float2* __restrict__ xhat, int TPC,
                                                    float2* __restrict__ bpart,
-                                                   float2* __restrict__ cpart) {
+                                                   float* __restrict__ cpart) {
     extern __shared__ float2 sh[];
     float2* tw = sh + Geo<L>::TEAMS * Geo<L>::BUF;
     make_twiddles<L>(tw);
@@ -160,9 +185,10 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
     const int64_t chunk = blockIdx.x;
     const int64_t c0 = chunk * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    float2 ab[L], ac[L];
+    float2 ab[L];
+    float acw[L];   // posterior mass at (t1 = k, t2 = r)
 #pragma unroll
-    for (int k = 0; k < L; ++k) { ab[k] = make_float2(0.f, 0.f); ac[k] = ab[k]; }
+    for (int k = 0; k < L; ++k) { ab[k] = make_float2(0.f, 0.f); acw[k] = 0.f; }
     if (active) {
         for (int64_t o = c0 + u; o < c1; o += TPC) {
             float s[L];
@@ -170,15 +196,20 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
             const float lse = p.lse[o];
             float2 v[L];
 #pragma unroll
-            for (int k = 0; k < L; ++k)
-                v[k] = make_float2(s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f, 0.f);   // w[k][r]
-            fft2_cols_then_rows<L, false>(v, buf, r, tw);                              // W[r][k]
-            const float2* yr = yhat + (o * L + r) * L;
-#pragma unroll
             for (int k = 0; k < L; ++k) {
-                const float2 t = cmulc(yr[k], v[k]);
-                ab[k].x += t.x; ab[k].y += t.y;
-                ac[k].x += v[k].x; ac[k].y += v[k].y;
+                const float w = s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;   // w[t1 = k][t2 = r]
+                acw[k] += w;
+                v[k] = make_float2(w, 0.f);
+            }
+            fft2_cols_then_rows<L, false>(v, buf, r, tw);                              // W[r][k]
+            const float4* yr = reinterpret_cast<const float4*>(yhat) + o * (L / 2) * L + r;   // Y_o[r][k], k + 1
+#pragma unroll
+            for (int k = 0; k < L; k += 2) {
+                const float4 a = yr[(k / 2) * L];
+                const float2 t0 = cmulc(make_float2(a.x, a.y), v[k]);
+                const float2 t1 = cmulc(make_float2(a.z, a.w), v[k + 1]);
+                ab[k].x += t0.x; ab[k].y += t0.y;
+                ab[k + 1].x += t1.x; ab[k + 1].y += t1.y;
             }
         }
     }
@@ -186,46 +217,46 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
     for (int plane = 0; plane < 2; ++plane) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = plane == 0 ? ab[k] : ac[k];
+        for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = plane == 0 ? ab[k] : make_float2(acw[k], 0.f);
         __syncthreads();
         if (active && u == 0) {
-            float2* dst = (plane == 0 ? bpart : cpart) + ((chunk * p.KK + c) * L + r) * L;
             for (int k = 0; k < L; ++k) {
                 float2 t = make_float2(0.f, 0.f);
                 for (int j = 0; j < TPC; ++j) {
                     const float2 e = sh[(team + j) * Geo<L>::BUF + r * (L + 1) + k];
                     t.x += e.x; t.y += e.y;
                 }
-                dst[k] = t;
+                if (plane == 0) bpart[((chunk * p.KK + c) * L + r) * L + k] = t;   // [k1 = r][k2 = k]
+                else cpart[((chunk * p.KK + c) * L + k) * L + r] = t.x;            // [t1 = k][t2 = r]
             }
         }
     }
 }
 
-// ---- FP64 sums of the partials over chunks: [KK][L][L] complex doubles
+// ---- FP64 sums of the partials over chunks: the back-projection's transform
+// [KK][L][L] complex, the posterior mass [KK][t1][t2] real (final)
 __global__ __launch_bounds__(256) void k_fft_reduce(const float2* __restrict__ bpart,
-                                                    const float2* __restrict__ cpart, int n_chunks,
+                                                    const float* __restrict__ cpart, int n_chunks,
                                                     int per, double2* __restrict__ bh,
-                                                    double2* __restrict__ ch) {
+                                                    double* __restrict__ csum) {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= per) return;
-    double2 sb = make_double2(0.0, 0.0), sc = sb;
+    double2 sb = make_double2(0.0, 0.0);
+    double sc = 0.0;
     for (int k = 0; k < n_chunks; ++k) {
-        const float2 b = bpart[(int64_t)k * per + e], c = cpart[(int64_t)k * per + e];
+        const float2 b = bpart[(int64_t)k * per + e];
         sb.x += b.x; sb.y += b.y;
-        sc.x += c.x; sc.y += c.y;
+        sc += cpart[(int64_t)k * per + e];
     }
     bh[e] = sb;
-    ch[e] = sc;
+    csum[e] = sc;
 }
 
-// ---- direct FP64 inverse DFT: bsum[c][q1 L + q2], csum[c][t1 L + t2] (the
-// layouts the finalize kernel reads); grid (ceil(L^2 / 256), KK)
+// ---- direct FP64 inverse DFT of the back-projection: bsum[c][q1 L + q2] (the
+// layout the finalize kernel reads); grid (ceil(L^2 / 256), KK)
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_idft(const double2* __restrict__ bh,
-                                                  const double2* __restrict__ ch,
-                                                  double* __restrict__ bsum,
-                                                  double* __restrict__ csum) {
+                                                  double* __restrict__ bsum) {
     __shared__ double cs[L], sn[L];
     if (threadIdx.x < L) sincospi(2.0 * (double)threadIdx.x / (double)L, &sn[threadIdx.x], &cs[threadIdx.x]);
     __syncthreads();
@@ -234,25 +265,21 @@ __global__ __launch_bounds__(256) void k_fft_idft(const double2* __restrict__ bh
     if (q >= L * L) return;
     const int q1 = q / L, q2 = q % L;
     const double2* B = bh + (int64_t)c * L * L;
-    const double2* C = ch + (int64_t)c * L * L;
-    double rb = 0.0, rc = 0.0;
+    double rb = 0.0;
     for (int k1 = 0; k1 < L; ++k1)
         for (int k2 = 0; k2 < L; ++k2) {
             const int m = (k1 * q1 + k2 * q2) % L;   // exp(+2 pi i m / L)
-            const double2 b = B[k1 * L + k2], cc = C[k1 * L + k2];
+            const double2 b = B[k1 * L + k2];
             rb += b.x * cs[m] - b.y * sn[m];
-            rc += cc.x * cs[m] - cc.y * sn[m];
         }
-    const double inv = 1.0 / (double)(L * L);
-    bsum[(int64_t)c * L * L + q] = rb * inv;
-    csum[(int64_t)c * L * L + q] = rc * inv;
+    bsum[(int64_t)c * L * L + q] = rb * (1.0 / (double)(L * L));
 }
 
 // ---- batched forward DFT of real images (utility): out[i][k1][k2]
 template <int L>
 __global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int64_t count,
                                               float2* __restrict__ out) {
-    prep_y_body<L>(in, count, nullptr, out);
+    prep_y_body<L, false>(in, count, nullptr, out);
 }
 
 }  // namespace fft
@@ -312,15 +339,15 @@ static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, con
             const int tpc = fft_tpc(L, p.KK);
             (void)hipFuncSetAttribute((const void*)fft::k_fft_pass2<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             hipLaunchKernelGGL(fft::k_fft_pass2<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lds, s, p,
-                               (const float2*)yhat, (const float2*)xhat, tpc, (float2*)bpart, (float2*)cpart);
+                               (const float2*)yhat, (const float2*)xhat, tpc, (float2*)bpart, (float*)cpart);
             break;
         }
         case 4: {
             const int per = p.KK * L * L;
             hipLaunchKernelGGL(fft::k_fft_reduce, dim3((per + 255) / 256), dim3(256), 0, s, (const float2*)bpart,
-                               (const float2*)cpart, p.n_chunks, per, (double2*)bh, (double2*)ch);
+                               (const float*)cpart, p.n_chunks, per, (double2*)bh, csum);
             hipLaunchKernelGGL(fft::k_fft_idft<L>, dim3((L * L + 255) / 256, p.KK), dim3(256), 0, s,
-                               (const double2*)bh, (const double2*)ch, bsum, csum);
+                               (const double2*)bh, bsum);
             break;
         }
     }
