@@ -385,7 +385,7 @@ def bench_errors(args):
 
     cases = [("lh128_k4_n200000_s0.5", True), ("lh128_k4_n200000_s2", True),
              ("lh128_k4_n200000_unit_s0.25", True), ("lh128_k4_n200000_unit_s0.25", False)]
-    precs = ["fp32_plain", "fp32_mfma", "bf16_split3", "bf16_split4"]
+    precs = ["fp32_plain", "fp32_mfma", "bf16_split3", "bf16_split4", "fp32_fft"]
     rows = []
     cores = len(os.sched_getaffinity(0))
     for name, centre in cases:
