@@ -101,3 +101,23 @@ def test_unit_range_images(centre):
     print(f"centre {centre}: x {ex:.2e} rho {er:.2e} loglik {ell:.2e}")
     if centre:
         check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, 4, g, ref, u=U_SPLIT)
+
+
+@pytest.mark.parametrize("prec", ["bf16_split3", "bf16_split4"])
+def test_largest_supported_grid(prec):
+    """L_high 1024 (L_low 64, K 16: K^2 = 256 components, the library's limits)
+    in the 2 x 2-tile form.  The oracle's loop over 2^20 shifts is too slow
+    here, so properties that hold at any size are checked: posteriors sum to
+    1, rho rows sum to 1, loglik is the sum of its terms, x' is a posterior
+    average of observed values (or keeps x), and the result is deterministic."""
+    N = 5
+    inst = synth.make_instance(1024, 16, N, 30.0, config=54)
+    g = gpu_step(inst.y, inst.x0, inst.log_rho0, 30.0, 16, prec)
+    assert abs(g["c"].sum() - N) <= 1e-5 * N
+    assert np.allclose(g["rho_new"].sum(axis=1), 1.0, atol=1e-6)
+    assert abs(g["loglik"] - g["ll_obs"].sum()) <= 1e-5 * abs(g["loglik"])
+    assert np.all(np.isfinite(g["x_new"]))
+    assert g["x_new"].min() >= min(inst.y.min(), inst.x0.min()) - 1e-3
+    assert g["x_new"].max() <= max(inst.y.max(), inst.x0.max()) + 1e-3
+    h = gpu_step(inst.y, inst.x0, inst.log_rho0, 30.0, 16, prec)
+    assert np.array_equal(g["x_new"], h["x_new"]) and g["loglik"] == h["loglik"]

@@ -59,3 +59,46 @@ def test_fft_trajectory_and_determinism():
     b = gpu_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, 2, "fp32_fft")
     for k in ("x_new", "rho_new", "loglik", "ll_obs", "b", "c"):
         assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+
+
+def test_fft_delta_prior():
+    """N = 1 and a delta prior: all posterior mass on s0; the sampled pixels
+    take the observation's values (through the FP32 transforms: to 1e-5) and
+    every other pixel keeps x exactly (its posterior mass is an exact zero,
+    summed in the shift domain)."""
+    Lh, K = 32, 2
+    inst = synth.make_instance(Lh, K, 1, 0.5, config=52)
+    lr = np.full((2, Lh), -np.inf, dtype=np.float32)
+    s0 = (5, 9)
+    lr[0, s0[0]] = 0.0
+    lr[1, s0[1]] = 0.0
+    g = gpu_step(inst.y, inst.x0, lr, 0.5, K, "fp32_fft")
+    ref = O.em_step(inst.y, inst.x0, lr, 0.5, K)
+    rows, cols = O.shift_downsample_indices(Lh, K, *s0)
+    expect = inst.x0.astype(np.float64).copy()
+    expect[np.ix_(rows, cols)] = inst.y[0]
+    keep = np.ones_like(expect, dtype=bool)
+    keep[np.ix_(rows, cols)] = False
+    assert np.array_equal(g["x_new"][keep], expect[keep])
+    np.testing.assert_allclose(g["x_new"], expect, rtol=0, atol=1e-5)
+    np.testing.assert_allclose(g["rho_new"], ref["rho_new"], atol=0)
+    assert abs(g["loglik"] - ref["loglik"]) < 1e-3 * abs(ref["loglik"])
+
+
+def test_fft_largest_grid():
+    """L_low 32 with K 16 (K^2 = 256 components, the library's limit): the
+    oracle's loop over 2^18 shifts is slow here, so properties that hold at
+    any size are checked (posteriors sum to 1, rho rows sum to 1, loglik is
+    the sum of its terms, x' a posterior average of observed values or x,
+    determinism)."""
+    N = 7
+    inst = synth.make_instance(512, 16, N, 20.0, config=91)
+    g = gpu_step(inst.y, inst.x0, inst.log_rho0, 20.0, 16, "fp32_fft")
+    assert abs(g["c"].sum() - N) <= 1e-5 * N
+    assert np.allclose(g["rho_new"].sum(axis=1), 1.0, atol=1e-6)
+    assert abs(g["loglik"] - g["ll_obs"].sum()) <= 1e-5 * abs(g["loglik"])
+    assert np.all(np.isfinite(g["x_new"]))
+    assert g["x_new"].min() >= min(inst.y.min(), inst.x0.min()) - 1e-3
+    assert g["x_new"].max() <= max(inst.y.max(), inst.x0.max()) + 1e-3
+    h = gpu_step(inst.y, inst.x0, inst.log_rho0, 20.0, 16, "fp32_fft")
+    assert np.array_equal(g["x_new"], h["x_new"]) and g["loglik"] == h["loglik"]
