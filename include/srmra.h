@@ -218,7 +218,13 @@ int srmra_plan_form(int precision, int L_low);
 
 /* Build a plan (host only, no device work).  `probs` is copied.  On success
  * *plan is set and *workspace_bytes receives the device workspace size that
- * srmra_plan_upload / srmra_plan_execute need.  Returns SRMRA_OK or an error. */
+ * srmra_plan_upload / srmra_plan_execute need.  Returns SRMRA_OK or an error.
+ * A plan with more than one (form, L_low) class also owns two helper streams
+ * (default priority, non-blocking) and six events, created here on the
+ * current device and released by srmra_plan_destroy: srmra_plan_execute forks
+ * the classes of each pass onto them and joins them back to the caller's
+ * stream (graph-capturable), so the plan must be executed on that device.
+ * If they cannot be created the classes run one after another instead. */
 int srmra_plan_create(const srmra_problem* probs, int count, int precision,
                       srmra_plan** plan, size_t* workspace_bytes);
 

@@ -496,6 +496,21 @@ struct srmra_plan {
     int parity = 0;
     bool uploaded = false;
     const void* uploaded_ws = nullptr;
+    // helper streams (default priority) and events on which the classes of one
+    // pass run concurrently; created with the plan on the current device
+    hipStream_t aux[kAuxStreams] = {};
+    hipEvent_t fork[2] = {};
+    hipEvent_t join[2][kAuxStreams] = {};
+    bool concurrent = false;
+    ~srmra_plan() {
+        for (int a = 0; a < kAuxStreams; ++a)
+            if (aux[a]) (void)hipStreamDestroy(aux[a]);
+        for (int q = 0; q < 2; ++q) {
+            if (fork[q]) (void)hipEventDestroy(fork[q]);
+            for (int a = 0; a < kAuxStreams; ++a)
+                if (join[q][a]) (void)hipEventDestroy(join[q][a]);
+        }
+    }
 };
 
 namespace {
@@ -717,6 +732,20 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         C.blocks1 = f1 ? cus * occupancy(f1, C.lds1) : 0;
         C.blocks2 = cus * occupancy(class_pass_fn(2, C.form, C.LL), C.lds2);
     }
+    // helper streams for concurrent classes (without them the classes run one
+    // after another on the caller's stream)
+    if (P->classes.size() > 1) {
+        bool ok = true;
+        for (int a = 0; a < kAuxStreams && ok; ++a)
+            ok = hipStreamCreateWithFlags(&P->aux[a], hipStreamNonBlocking) == hipSuccess;
+        for (int q = 0; q < 2 && ok; ++q) {
+            ok = hipEventCreateWithFlags(&P->fork[q], hipEventDisableTiming) == hipSuccess;
+            for (int a = 0; a < kAuxStreams && ok; ++a)
+                ok = hipEventCreateWithFlags(&P->join[q][a], hipEventDisableTiming) == hipSuccess;
+        }
+        P->concurrent = ok;
+        if (!ok) (void)hipGetLastError();
+    }
     *plan = P;
     *workspace_bytes = P->total;
     return SRMRA_OK;
@@ -789,6 +818,11 @@ int srmra_plan_execute(srmra_plan* plan, void* workspace, size_t workspace_bytes
     L.n_inst = n;
     L.n_class = (int)plan->classes.size();
     for (int k = 0; k < L.n_class; ++k) L.cls[k] = plan->classes[k];
+    for (int a = 0; a < kAuxStreams; ++a) L.aux[a] = plan->concurrent ? plan->aux[a] : nullptr;
+    for (int q = 0; q < 2; ++q) {
+        L.fork[q] = plan->fork[q];
+        for (int a = 0; a < kAuxStreams; ++a) L.join[q][a] = plan->join[q][a];
+    }
     if (batch_enqueue(L, stream) != hipSuccess) return SRMRA_EDEVICE;
     plan->parity ^= 1;
     return SRMRA_OK;

@@ -32,6 +32,7 @@ struct ClassLaunch {
 };
 
 constexpr int kMaxClasses = 16;
+constexpr int kAuxStreams = 2;   // helper streams a plan runs classes on beside the caller's
 
 struct BatchLaunch {
     const InstDesc* desc;        // device, n_inst entries
@@ -42,6 +43,13 @@ struct BatchLaunch {
     int* counters;               // 2 per class
     int n_pack, n_combine, n_combine_late, n_reduce, n_inst, n_class;
     ClassLaunch cls[kMaxClasses];
+    // classes of one pass run concurrently: class k on the caller's stream when
+    // k % (kAuxStreams + 1) == 0, else on aux[k % (kAuxStreams + 1) - 1], forked
+    // from and joined back to the caller's stream through events (null: all on
+    // the caller's stream)
+    hipStream_t aux[kAuxStreams];
+    hipEvent_t fork[2];
+    hipEvent_t join[2][kAuxStreams];
 };
 
 hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s);

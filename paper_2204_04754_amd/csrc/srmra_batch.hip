@@ -168,7 +168,14 @@ hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, L.counters, 2 * L.n_class);
     hipLaunchKernelGGL(k_batch_pack, dim3(L.n_pack), dim3(256), 0, s, L.desc, L.pack_items);
     hipLaunchKernelGGL(k_batch_pack_xb, dim3(L.n_pack), dim3(256), 0, s, L.desc, L.pack_items);
+    const bool par = L.aux[0] != nullptr && L.n_class > 1;
     for (int pass = 1; pass <= 2; ++pass) {
+        // fork: the helper streams wait for everything enqueued so far
+        if (par) {
+            if (hipEventRecord(L.fork[pass - 1], s) != hipSuccess) return hipErrorUnknown;
+            for (int a = 0; a < kAuxStreams; ++a)
+                if (hipStreamWaitEvent(L.aux[a], L.fork[pass - 1], 0) != hipSuccess) return hipErrorUnknown;
+        }
         for (int k = 0; k < L.n_class; ++k) {
             const ClassLaunch& c = L.cls[k];
             if (pass == 1 && c.form == FORM_FUSED) continue;
@@ -179,9 +186,18 @@ hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
             int n = c.n_items;
             int* counter = L.counters + 2 * k + (pass - 1);
             void* args[] = {(void*)&desc, (void*)&items, (void*)&n, (void*)&counter};
+            const int lane = k % (kAuxStreams + 1);
+            hipStream_t sk = (par && lane > 0) ? L.aux[lane - 1] : s;
             const hipError_t e = hipLaunchKernel(f, dim3(pass == 1 ? c.blocks1 : c.blocks2), dim3(256), args,
-                                                 pass == 1 ? c.lds1 : c.lds2, s);
+                                                 pass == 1 ? c.lds1 : c.lds2, sk);
             if (e != hipSuccess) return e;
+        }
+        // join: the caller's stream waits for every helper stream
+        if (par) {
+            for (int a = 0; a < kAuxStreams; ++a) {
+                if (hipEventRecord(L.join[pass - 1][a], L.aux[a]) != hipSuccess) return hipErrorUnknown;
+                if (hipStreamWaitEvent(s, L.join[pass - 1][a], 0) != hipSuccess) return hipErrorUnknown;
+            }
         }
         if (pass == 1 && L.n_combine > 0)
             hipLaunchKernelGGL(k_batch_combine, dim3(L.n_combine), dim3(256), 0, s, L.desc, L.combine_items);
