@@ -86,7 +86,7 @@ def parse():
                     help="target oracle time on the host for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--extra-forms", default="fp32_fft",
+    ap.add_argument("--extra-forms", default="bf16_split3,fp32_fft",
                     help="comma-separated forms also timed beside the main one (single mode)")
     ap.add_argument("--mode", default="single",
                     choices=["single", "batched", "serve", "errors", "projected", "moments"],
