@@ -75,7 +75,7 @@ typedef enum {
     SRMRA_FP32_MFMA = 1,      /* FP32 matrix cores (v_mfma_f32_32x32x2 / 16x16x4)   */
     SRMRA_BF16_SPLIT3 = 2,    /* BF16 matrix cores, operands split v = hi + lo,
                                  products hi*hi + hi*lo + lo*hi, FP32 accumulate;
-                                 L_low in {24, 32, 48, 64} (others return
+                                 L_low in {16, 24, 32, 48, 64} (others return
                                  SRMRA_EUNSUPPORTED in the single-problem calls)    */
     SRMRA_BF16_SPLIT4 = 3,    /* as SRMRA_BF16_SPLIT3 plus the lo*lo product        */
     SRMRA_FP32_FFT = 4        /* FFT route: both contractions as products of 2-D
@@ -213,7 +213,7 @@ typedef struct srmra_plan srmra_plan;
 
 /* The precision an instance of this L_low runs in within a plan of the given
  * precision: SRMRA_BF16_SPLIT3 / SRMRA_BF16_SPLIT4 plans run L_low outside
- * {24, 32, 48, 64} in SRMRA_FP32_MFMA.  Returns -1 for unsupported arguments. */
+ * {16, 24, 32, 48, 64} in SRMRA_FP32_MFMA.  Returns -1 for unsupported arguments. */
 int srmra_plan_form(int precision, int L_low);
 
 /* Build a plan (host only, no device work).  `probs` is copied.  On success

@@ -33,8 +33,8 @@ bool mfma_geom(int LL, int& cpw, int& nt, size_t& lds1, size_t& lds2, const void
 bool mfma_fused_geom(int LL, int KK, int& wc, int& nt, size_t& lds, const void*& f);
 bool valu_geom(int LL, int KK, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
                const void*& f2);
-bool bf16_geom(int LL, int np, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
-               const void*& f2);
+bool bf16_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds1, size_t& lds2,
+               const void*& f1, const void*& f2);
 hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
                        hipStream_t s);
 hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* centre, double* ynorm,
@@ -149,7 +149,7 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
             f2 = ff;
         }
     } else if (is_bf16(prec)) {
-        ok = bf16_geom(LL, split_products(prec), g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
+        ok = bf16_geom(LL, g.KK, split_products(prec), g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
     } else if (prec == SRMRA_FP32_FFT) {
         // pass 1: a team per observation over all components; pass 2: component
         // groups of CG = teams / tpc components

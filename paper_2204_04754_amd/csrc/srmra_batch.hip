@@ -8,7 +8,7 @@
 // own register allocation; a single kernel switching over all bodies spills.)
 #include "srmra_aux_impl.h"
 #include "srmra_batch.h"
-#include "srmra_bf16w_impl.h"
+#include "srmra_bf16s_impl.h"
 #include "srmra_mfma_impl.h"
 #include "srmra_valu_impl.h"
 
@@ -34,7 +34,9 @@ __global__ __launch_bounds__(256) void k_batch_pack_xb(const InstDesc* __restric
     const InstDesc& d = D[it.x];
     if (d.form != FORM_BF16 && d.form != FORM_BF16X4) return;
     uint4* xb = const_cast<uint4*>(d.p.xb);
-    if (d.LL == 48 || d.LL == 64) {
+    if (d.LL == 16) {
+        for (int ks = threadIdx.x >> 6; ks < b16s::NK; ks += 4) b16s::pack_xb_body(d.p, d.x, it.y, ks, xb);
+    } else if (d.LL == 48 || d.LL == 64) {
         const int nk = d.LL * (d.LL / 16);
         for (int e = threadIdx.x >> 6; e < 2 * nk; e += 4) {
             if (d.LL == 48) b16w::pack_xb_body<48>(d.p, d.x, it.y, e / nk, e % nk, xb);
@@ -76,7 +78,7 @@ __global__ __launch_bounds__(1024) void k_batch_finalize(const InstDesc* __restr
 // from the class's cost-sorted list through an atomic counter and leaves the
 // loop once the counter passes the item count (every wave reaches the exit).
 template <int PASS, int FORM, int LL>
-__global__ __launch_bounds__(256, ((PASS == 1 && (FORM == FORM_BF16 || FORM == FORM_BF16X4)) ||
+__global__ __launch_bounds__(256, ((PASS == 1 && (FORM == FORM_BF16 || FORM == FORM_BF16X4) && LL != 16) ||
                                    (PASS == 2 && FORM == FORM_MFMA && LL >= 16 && LL <= 32) ||
                                    (PASS == 2 && FORM == FORM_FUSED && LL >= 16 && LL <= 24)) ? 2 : 1)
 void k_class_pass(const InstDesc* __restrict__ D,
@@ -100,7 +102,13 @@ void k_class_pass(const InstDesc* __restrict__ D,
             b16::Prep q;
             q.yT = d.yT;
             q.yo = d.yo;
-            if constexpr (LL >= 48) {
+            if constexpr (LL == 16) {
+                b16s::Prep qs;
+                qs.yT = d.yT;
+                qs.yo = d.yo;
+                if constexpr (PASS == 1) b16s::pass1_body<NP>(d.p, qs, w.y, w.z, lds);
+                else b16s::pass2_body<NP>(d.p, qs, w.y, w.z, lds);
+            } else if constexpr (LL >= 48) {
                 b16w::Prep qw;
                 qw.yT = d.yT;
                 qw.yo = d.yo;
@@ -132,10 +140,10 @@ SRMRA_CLASS(FORM_VALU, 64)
 SRMRA_CLASS(FORM_MFMA, 8) SRMRA_CLASS(FORM_MFMA, 12) SRMRA_CLASS(FORM_MFMA, 16)
 SRMRA_CLASS(FORM_MFMA, 24) SRMRA_CLASS(FORM_MFMA, 32) SRMRA_CLASS(FORM_MFMA, 48)
 SRMRA_CLASS(FORM_MFMA, 64)
-SRMRA_CLASS(FORM_BF16, 24) SRMRA_CLASS(FORM_BF16, 32) SRMRA_CLASS(FORM_BF16, 48)
-SRMRA_CLASS(FORM_BF16, 64)
-SRMRA_CLASS(FORM_BF16X4, 24) SRMRA_CLASS(FORM_BF16X4, 32) SRMRA_CLASS(FORM_BF16X4, 48)
-SRMRA_CLASS(FORM_BF16X4, 64)
+SRMRA_CLASS(FORM_BF16, 16) SRMRA_CLASS(FORM_BF16, 24) SRMRA_CLASS(FORM_BF16, 32)
+SRMRA_CLASS(FORM_BF16, 48) SRMRA_CLASS(FORM_BF16, 64)
+SRMRA_CLASS(FORM_BF16X4, 16) SRMRA_CLASS(FORM_BF16X4, 24) SRMRA_CLASS(FORM_BF16X4, 32)
+SRMRA_CLASS(FORM_BF16X4, 48) SRMRA_CLASS(FORM_BF16X4, 64)
 #undef SRMRA_CLASS
 #define SRMRA_FUSED(L) template __global__ void k_class_pass<2, FORM_FUSED, L>(const InstDesc*, const int4*, int, int*);
 SRMRA_FUSED(8) SRMRA_FUSED(12) SRMRA_FUSED(16) SRMRA_FUSED(24) SRMRA_FUSED(32) SRMRA_FUSED(48)
@@ -152,10 +160,10 @@ const void* class_pass_fn(int pass, int form, int LL) {
     SRMRA_PICK(FORM_MFMA, 8) SRMRA_PICK(FORM_MFMA, 12) SRMRA_PICK(FORM_MFMA, 16)
     SRMRA_PICK(FORM_MFMA, 24) SRMRA_PICK(FORM_MFMA, 32) SRMRA_PICK(FORM_MFMA, 48)
     SRMRA_PICK(FORM_MFMA, 64)
-    SRMRA_PICK(FORM_BF16, 24) SRMRA_PICK(FORM_BF16, 32) SRMRA_PICK(FORM_BF16, 48)
-    SRMRA_PICK(FORM_BF16, 64)
-    SRMRA_PICK(FORM_BF16X4, 24) SRMRA_PICK(FORM_BF16X4, 32) SRMRA_PICK(FORM_BF16X4, 48)
-    SRMRA_PICK(FORM_BF16X4, 64)
+    SRMRA_PICK(FORM_BF16, 16) SRMRA_PICK(FORM_BF16, 24) SRMRA_PICK(FORM_BF16, 32)
+    SRMRA_PICK(FORM_BF16, 48) SRMRA_PICK(FORM_BF16, 64)
+    SRMRA_PICK(FORM_BF16X4, 16) SRMRA_PICK(FORM_BF16X4, 24) SRMRA_PICK(FORM_BF16X4, 32)
+    SRMRA_PICK(FORM_BF16X4, 48) SRMRA_PICK(FORM_BF16X4, 64)
 #undef SRMRA_PICK
     // single pass: no pass-1 kernel
 #define SRMRA_PICK(L) if (form == FORM_FUSED && LL == L) return pass == 2 ? (const void*)k_class_pass<2, FORM_FUSED, L> : nullptr;

@@ -1,6 +1,7 @@
 // BF16 split-precision kernels of the EM step (bodies in srmra_bf16_impl.h for
-// L_low 24 and 32, srmra_bf16w_impl.h for L_low 48 and 64).
-#include "srmra_bf16w_impl.h"
+// L_low 24 and 32, srmra_bf16w_impl.h for L_low 48 and 64, srmra_bf16s_impl.h
+// for L_low 16).
+#include "srmra_bf16s_impl.h"
 
 namespace srmra {
 namespace b16 {
@@ -69,22 +70,53 @@ __global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __rest
 
 }  // namespace b16w
 
+namespace b16s {
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_score_lse(StepArgs p, Prep q) {
+    extern __shared__ float lds[];
+    pass1_body<NP>(p, q, blockIdx.x, blockIdx.y, lds);
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_backproject(StepArgs p, Prep q) {
+    extern __shared__ float lds[];
+    pass2_body<NP>(p, q, blockIdx.x, blockIdx.y, lds);
+}
+
+// grid (KK, 2): 4 k-steps per block
+__global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __restrict__ x,
+                                                 uint4* __restrict__ xb) {
+    const int ks = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (ks < NK) pack_xb_body(p, x, blockIdx.x, ks, xb);
+}
+
+}  // namespace b16s
+
 
 // ---------------------------------------------------------------- host side
 static bool wide_ll(int LL) { return LL == 48 || LL == 64; }
-bool bf16_supported(int LL) { return LL == 24 || LL == 32 || wide_ll(LL); }
+bool bf16_supported(int LL) { return LL == 16 || LL == 24 || LL == 32 || wide_ll(LL); }
 
-// pass-1 partials per observation: one per component pair (one-tile form) or
-// per (component, tile) (L_low 48 and 64)
-int bf16_parts(int LL, int KK) { return wide_ll(LL) ? 4 * KK : (KK + 1) / 2; }
+// pass-1 partials per observation: one per component pair (one-tile form), per
+// (component, tile) (L_low 48 and 64) or per group of 4 components (L_low 16)
+int bf16_parts(int LL, int KK) {
+    if (LL == 16) return (KK + 3) / 4;
+    return wide_ll(LL) ? 4 * KK : (KK + 1) / 2;
+}
 
 size_t bf16_xb_bytes(int LL, int KK) {
+    if (LL == 16) return (size_t)KK * b16s::NK * 128 * sizeof(uint4);
     if (wide_ll(LL)) return (size_t)KK * 2 * LL * (LL / 16) * 128 * sizeof(uint4);
     if (LL != 24 && LL != 32) return 0;
     return (size_t)KK * LL * (b16::R1P / 16) * 128 * sizeof(uint4);
 }
 
 hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, hipStream_t s) {
+    if (LL == 16) {
+        hipLaunchKernelGGL(b16s::k_pack_xb, dim3(p.KK, 2), dim3(256), 0, s, p, x, (uint4*)xb);
+        return hipGetLastError();
+    }
     if (wide_ll(LL)) {
         const int nks = LL * (LL / 16);
         const dim3 grid(2 * p.KK, (nks + 3) / 4);
@@ -102,7 +134,7 @@ hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, h
 
 // bytes of the yT planes (the first prepared layout)
 size_t bf16_yt_bytes(int LL, int64_t N) {
-    return (size_t)N * 2 * LL * (wide_ll(LL) ? LL : b16::R1P) * 2;
+    return (size_t)N * 2 * LL * ((wide_ll(LL) || LL == 16) ? LL : b16::R1P) * 2;
 }
 
 size_t bf16_prepared_extra(int LL, int64_t N) {
@@ -136,6 +168,7 @@ hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* cen
                             void* prep_extra, hipStream_t s) {
     b16::Prep q = prep_ptrs(prep_extra, LL, N);
     const dim3 grid((unsigned)((N + 7) / 8));
+    if (LL == 16) return launch_prep_wide<16>(y, N, centre, ynorm, q, s);   // same layouts, one r1 slice
     if (LL == 48) return launch_prep_wide<48>(y, N, centre, ynorm, q, s);
     if (LL == 64) return launch_prep_wide<64>(y, N, centre, ynorm, q, s);
     if (LL == 24) hipLaunchKernelGGL(b16::k_prep_bf16<24>, grid, dim3(256), 0, s, y, N, centre, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
@@ -177,9 +210,25 @@ static hipError_t launch_bf16w_ll(int pass, const StepArgs& p, const b16::Prep& 
     return hipGetLastError();
 }
 
+template <int NP>
+static hipError_t launch_bf16s(int pass, const StepArgs& p, const b16::Prep& q0, hipStream_t s) {
+    b16s::Prep q;
+    q.yT = q0.yT;
+    q.yo = q0.yo;
+    const dim3 grid(p.n_chunks, p.n_cg);
+    const void* f = pass == 1 ? (const void*)b16s::k_score_lse<NP> : (const void*)b16s::k_backproject<NP>;
+    const size_t lds = pass == 1 ? b16s::lds_pass1() : b16s::lds_pass2();
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return hipErrorInvalidValue;
+    if (pass == 1) hipLaunchKernelGGL((b16s::k_score_lse<NP>), grid, dim3(256), lds, s, p, q);
+    else hipLaunchKernelGGL((b16s::k_backproject<NP>), grid, dim3(256), lds, s, p, q);
+    return hipGetLastError();
+}
+
 hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
                        hipStream_t s) {
     const b16::Prep q = prep_ptrs(prep_extra, LL, p.N);
+    if (LL == 16) return np == 4 ? launch_bf16s<4>(pass, p, q, s) : launch_bf16s<3>(pass, p, q, s);
     if (LL == 48) return np == 4 ? launch_bf16w_ll<48, 4>(pass, p, q, s) : launch_bf16w_ll<48, 3>(pass, p, q, s);
     if (LL == 64) return np == 4 ? launch_bf16w_ll<64, 4>(pass, p, q, s) : launch_bf16w_ll<64, 3>(pass, p, q, s);
     if (LL == 24) return np == 4 ? launch_bf16_ll<24, 4>(pass, p, q, s) : launch_bf16_ll<24, 3>(pass, p, q, s);
@@ -203,10 +252,20 @@ static void bf16w_geom_ll(size_t& lds1, size_t& lds2, const void*& f1, const voi
     f2 = (const void*)b16w::k_backproject<LL, NP>;
 }
 
-bool bf16_geom(int LL, int np, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
-               const void*& f2) {
+bool bf16_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds1, size_t& lds2,
+               const void*& f1, const void*& f2) {
     cpb = 4;
     nt = 8;
+    if (LL == 16) {
+        const int wc = b16s::wc_of(KK);
+        cpb = 4 * wc;
+        nt = 8 * (4 / wc);
+        lds1 = b16s::lds_pass1();
+        lds2 = b16s::lds_pass2();
+        f1 = np == 4 ? (const void*)b16s::k_score_lse<4> : (const void*)b16s::k_score_lse<3>;
+        f2 = np == 4 ? (const void*)b16s::k_backproject<4> : (const void*)b16s::k_backproject<3>;
+        return true;
+    }
     if (wide_ll(LL)) {
         cpb = 1;   // one component per block, one tile per wave
         if (LL == 48) {

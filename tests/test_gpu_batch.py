@@ -42,7 +42,7 @@ def test_mixed_batch_matches_oracle(prec):
         inst = d["inst"]
         g = be.results(j)
         ref = O.em_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, return_details=True)
-        u = U_SPLIT if (prec.startswith("bf16") and inst.Ll in (24, 32, 48, 64)) else U32
+        u = U_SPLIT if (prec.startswith("bf16") and inst.Ll in (16, 24, 32, 48, 64)) else U32
         check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, u=u)
 
 
@@ -98,7 +98,7 @@ def test_autotuned_batch_matches_oracle():
     for t in be.tuning:
         assert t["form"] in (B.SRMRA_BF16_SPLIT3, B.SRMRA_FP32_MFMA) and t["item_obs"] > 0
         if t["form"] == B.SRMRA_BF16_SPLIT3:
-            assert t["L_low"] in (24, 32, 48, 64)
+            assert t["L_low"] in (16, 24, 32, 48, 64)
         form[(t["L_low"], t["K"])] = t["form"]
     assert len(be.tune_report) >= len(classes)
     be.step()

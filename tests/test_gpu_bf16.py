@@ -1,5 +1,6 @@
 """GPU parity of the BF16 split-precision form (L_low 24 and 32 with one 32x32
-tile per score map, 48 and 64 with 2 x 2 tiles) against the FP64 oracle."""
+tile per score map, 48 and 64 with 2 x 2 tiles, 16 with one 16x16 tile)
+against the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -25,7 +26,9 @@ def _gpu():
                                           (128, 4, 133, 2.0), (96, 3, 77, 2.0), (64, 2, 600, 0.7),
                                           (96, 2, 45, 2.0), (144, 3, 61, 2.0), (128, 2, 40, 2.0),
                                           (192, 3, 37, 2.0), (48, 1, 50, 2.0), (64, 1, 33, 2.0),
-                                          (24, 1, 19, 2.0)])
+                                          (24, 1, 19, 2.0), (32, 2, 45, 2.0), (48, 3, 101, 2.0),
+                                          (64, 4, 133, 2.0), (16, 1, 13, 2.0), (80, 5, 203, 2.0),
+                                          (32, 2, 700, 0.7)])
 def test_shapes(Lh, K, N, sigma, prec):
     inst = synth.make_instance(Lh, K, N, sigma, config=60, instance=Lh + K)
     rng = np.random.default_rng(Lh * K)
@@ -83,7 +86,7 @@ def test_deterministic_and_unsupported():
     for k in ("x_new", "rho_new", "loglik", "ll_obs", "b", "c"):
         assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
     from paper_2204_04754_amd import binding as B
-    assert B.srmra_em_step_workspace_bytes(100, 16, 2, "bf16_split3") == 0
+    assert B.srmra_em_step_workspace_bytes(100, 12, 2, "bf16_split3") == 0
 
 
 @pytest.mark.parametrize("centre", [True, False])
