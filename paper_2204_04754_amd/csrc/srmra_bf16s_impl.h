@@ -98,8 +98,11 @@ __device__ __forceinline__ void stage_yo(const Prep& q, int64_t N, int64_t o0, i
 }
 
 // Scores of the wave's 8 observations (staged slots obase..obase+7) x 4
-// components (global indices cg[0..3], clamped).
-template <int NP>
+// components (global indices cg[0..3], clamped).  PF: request the next
+// k-step's B fragments before this k-step's products (pass 1; in pass 2 the
+// extra registers would spill).  Either way every accumulator sees the same
+// products in the same order.
+template <int NP, bool PF>
 __device__ __forceinline__ void score(const StepArgs& p, const __bf16* st, int obase, const int (&cg)[4],
                                       floatx4 (&acc)[8][4]) {
     const int lane = threadIdx.x & 63;
@@ -111,12 +114,28 @@ __device__ __forceinline__ void score(const StepArgs& p, const __bf16* st, int o
     const uint4* bsrc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) bsrc[c] = p.xb + (int64_t)cg[c] * NK * 128 + lane;
+    bf16x8 pbh[4], pbl[4];   // PF: the fragments of the coming k-step
+    if constexpr (PF) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            pbh[c] = __builtin_bit_cast(bf16x8, bsrc[c][0]);
+            pbl[c] = __builtin_bit_cast(bf16x8, bsrc[c][64]);
+        }
+    }
     for (int ks = 0; ks < NK; ++ks) {
         bf16x8 bh[4], bl[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            bh[c] = __builtin_bit_cast(bf16x8, bsrc[c][ks * 128]);
-            bl[c] = __builtin_bit_cast(bf16x8, bsrc[c][ks * 128 + 64]);
+            if constexpr (PF) {
+                bh[c] = pbh[c];
+                bl[c] = pbl[c];
+                const int kn = ks + 1 < NK ? ks + 1 : ks;   // the last step re-reads its own
+                pbh[c] = __builtin_bit_cast(bf16x8, bsrc[c][kn * 128]);
+                pbl[c] = __builtin_bit_cast(bf16x8, bsrc[c][kn * 128 + 64]);
+            } else {
+                bh[c] = __builtin_bit_cast(bf16x8, bsrc[c][ks * 128]);
+                bl[c] = __builtin_bit_cast(bf16x8, bsrc[c][ks * 128 + 64]);
+            }
         }
         const int b2 = 2 * ks + (kg >> 1);
         const int col = (b2 + t2) & (LL - 1);
@@ -203,7 +222,7 @@ __device__ __forceinline__ void pass1_body(const StepArgs& p, const Prep& q, int
         __syncthreads();
         if (!active) continue;
         floatx4 acc[8][4];
-        score<NP>(p, st, 8 * wo, cgc, acc);
+        score<NP, true>(p, st, 8 * wo, cgc, acc);
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             const int64_t oi = o0 + 8 * wo + o;
@@ -262,7 +281,7 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const Prep& q, int
         bf16x8 wh[4][4], wl[4][4];   // [component][v]: B fragments over k = (t2, o)
         if (active) {
             floatx4 acc[8][4];
-            score<NP>(p, st, 8 * wo, cgc, acc);
+            score<NP, false>(p, st, 8 * wo, cgc, acc);
             float lse[8];
 #pragma unroll
             for (int o = 0; o < 8; ++o) {

@@ -136,6 +136,9 @@ WORKLOADS = {
     "lh128_k4_n200000_s2": dict(Lh=128, K=4, N=200_000, sigma=2.0, config=2, instance=1),
     # the serving mix's large job: Lh 256, K 4, Ll 64, N 2e4, sigma 1
     "lh256_k4_n20000": dict(Lh=256, K=4, N=20_000, sigma=1.0, config=4, instance=999),
+    # single-shape measurements of the batched mix's L_low 16 and 48 classes
+    "lh64_k4_n200000": dict(Lh=64, K=4, N=200_000, sigma=1.0, config=5),
+    "lh96_k2_n50000": dict(Lh=96, K=2, N=50_000, sigma=1.0, config=5, instance=1),
     # robustness variant: the precision-study image min-max scaled to [0, 1]
     # (mean near 0.5), sigma 0.25 (the middle of the paper's noise levels)
     "lh128_k4_n200000_unit_s0.25": dict(Lh=128, K=4, N=200_000, sigma=0.25, config=2,
