@@ -55,7 +55,7 @@ int fft_tpc(int LL, int KK);
 size_t fft_lds(int LL);
 const void* fft_pass2_fn(int LL);
 hipError_t launch_fft(int LL, int what, const StepArgs& p, const float* x, const float* y,
-                      void* yhat, void* xhat, void* bpart, void* cpart, void* bh, void* ch,
+                      void* yhat, void* xhat, void* bpart, void* cpart, void* bh,
                       double* bsum, double* csum, hipStream_t s);
 hipError_t launch_dft2(int L, const float* in, int64_t count, float2* out, hipStream_t s);
 // reconstruction error (srmra_quality.hip)
@@ -120,7 +120,7 @@ struct Geom {
     size_t lds1 = 0, lds2 = 0;
     // workspace offsets
     size_t o_prep = 0, o_part = 0, o_lse = 0, o_xt2 = 0, o_beta = 0, o_bpart = 0, o_cpart = 0,
-           o_llpart = 0, o_bsum = 0, o_csum = 0, o_xb = 0, o_xhat = 0, o_bh = 0, o_ch = 0, total = 0;
+           o_llpart = 0, o_bsum = 0, o_csum = 0, o_xb = 0, o_xhat = 0, o_bh = 0, total = 0;
 };
 
 int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
@@ -203,7 +203,6 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     if (prec == SRMRA_FP32_FFT) {
         g.o_xhat = take(sizeof(float2) * (size_t)g.KK * LL * LL);
         g.o_bh = take(2 * sizeof(double) * (size_t)g.KK * LL * LL);
-        g.o_ch = take(2 * sizeof(double) * (size_t)g.KK * LL * LL);
     }
     g.total = off;
     return SRMRA_OK;
@@ -275,7 +274,7 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
         void* yhat = (void*)((const char*)prep_extra);
         auto fft = [&](int what) {
             return launch_fft(LL, what, p, x, y, yhat, ws + g.o_xhat, ws + g.o_bpart, ws + g.o_cpart,
-                              ws + g.o_bh, ws + g.o_ch, (double*)(ws + g.o_bsum),
+                              ws + g.o_bh, (double*)(ws + g.o_bsum),
                               (double*)(ws + g.o_csum), stream);
         };
         if (fft(1) != hipSuccess) return SRMRA_EDEVICE;
@@ -396,7 +395,7 @@ static int enqueue_prepare(const Geom& g, const float* y, char* prep, int centre
         p.N = g.N;
         p.centre = centre;
         if (launch_fft(g.LL, 0, p, nullptr, y, prep + g.prep_extra_off, nullptr, nullptr, nullptr,
-                       nullptr, nullptr, nullptr, nullptr, stream) != hipSuccess)
+                       nullptr, nullptr, nullptr, stream) != hipSuccess)
             return SRMRA_EDEVICE;
     }
     return SRMRA_OK;

@@ -316,7 +316,7 @@ const void* fft_pass2_fn(int LL) {
 template <int L>
 static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, const float* y,
                                 void* yhat, void* xhat, void* bpart, void* cpart, void* bh,
-                                void* ch, double* bsum, double* csum, hipStream_t s) {
+                                double* bsum, double* csum, hipStream_t s) {
     const size_t lds = fft::lds_bytes<L>();
     const int teams = 256 / L;
     switch (what) {
@@ -355,12 +355,12 @@ static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, con
 }
 
 hipError_t launch_fft(int LL, int what, const StepArgs& p, const float* x, const float* y,
-                      void* yhat, void* xhat, void* bpart, void* cpart, void* bh, void* ch,
+                      void* yhat, void* xhat, void* bpart, void* cpart, void* bh,
                       double* bsum, double* csum, hipStream_t s) {
     switch (LL) {
-        case 8: return fft_launch_ll<8>(what, p, x, y, yhat, xhat, bpart, cpart, bh, ch, bsum, csum, s);
-        case 16: return fft_launch_ll<16>(what, p, x, y, yhat, xhat, bpart, cpart, bh, ch, bsum, csum, s);
-        case 32: return fft_launch_ll<32>(what, p, x, y, yhat, xhat, bpart, cpart, bh, ch, bsum, csum, s);
+        case 8: return fft_launch_ll<8>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
+        case 16: return fft_launch_ll<16>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
+        case 32: return fft_launch_ll<32>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
     }
     return hipErrorInvalidValue;
 }
