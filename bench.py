@@ -555,8 +555,11 @@ def main():
         alg_flop = 2.0 * Ll2 * pairs
         issued_flop = 4.0 * Ll2 * pairs * prod
     achieved = alg_flop / (k_ms * 1e-3)
+    traffic = traffic_bytes((args.workload, args.precision, kname))
     roof = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": traffic_bytes((args.workload, args.precision, kname)),
+            "frac": achieved / peak, "traffic": traffic,
+            # the same kernel against the HBM roofline (counter bytes / duration / 8 TB/s)
+            "hbm_frac": None if traffic is None else traffic / (k_ms * 1e-3) / HBM_PEAK,
             "kernel": kname, "kernel_ms": k_ms, "passes": n_pass,
             "issued_frac": issued_flop / (k_ms * 1e-3) / peak}
     if n_pass == 2:
