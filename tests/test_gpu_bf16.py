@@ -124,3 +124,28 @@ def test_largest_supported_grid(prec):
     assert g["x_new"].max() <= max(inst.y.max(), inst.x0.max()) + 1e-3
     h = gpu_step(inst.y, inst.x0, inst.log_rho0, 30.0, 16, prec)
     assert np.array_equal(g["x_new"], h["x_new"]) and g["loglik"] == h["loglik"]
+
+
+@pytest.mark.parametrize("Lh,K", [(32, 2), (48, 2), (64, 2), (96, 2), (128, 2)])
+def test_single_observation_delta_prior(Lh, K):
+    """N = 1 (one partial 8-observation group) and a delta prior at every
+    BF16 tile layout (L_low 16, 24, 32, 48, 64): the posterior is exactly 1 at
+    s0, so the sampled pixels take the observation's values up to the split's
+    residual (2^-17 relative per operand) and every other pixel keeps x
+    exactly."""
+    inst = synth.make_instance(Lh, K, 1, 0.5, config=63, instance=Lh)
+    lr = np.full((2, Lh), -np.inf, dtype=np.float32)
+    s0 = (5, 9)
+    lr[0, s0[0]] = 0.0
+    lr[1, s0[1]] = 0.0
+    g = gpu_step(inst.y, inst.x0, lr, 0.5, K, "bf16_split3")
+    ref = O.em_step(inst.y, inst.x0, lr, 0.5, K)
+    rows, cols = O.shift_downsample_indices(Lh, K, *s0)
+    expect = inst.x0.astype(np.float64).copy()
+    expect[np.ix_(rows, cols)] = inst.y[0]
+    keep = np.ones_like(expect, dtype=bool)
+    keep[np.ix_(rows, cols)] = False
+    assert np.array_equal(g["x_new"][keep], expect[keep])
+    np.testing.assert_allclose(g["x_new"], expect, rtol=0, atol=1e-4 * np.abs(inst.y).max())
+    np.testing.assert_allclose(g["rho_new"], ref["rho_new"], atol=0)
+    assert abs(g["loglik"] - ref["loglik"]) < 1e-3 * abs(ref["loglik"])
