@@ -35,6 +35,7 @@ bool valu_geom(int LL, int KK, int& cpb, int& nt, size_t& lds1, size_t& lds2, co
                const void*& f2);
 bool bf16_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds1, size_t& lds2,
                const void*& f1, const void*& f2);
+bool bf16_fused_geom(int LL, int KK, int np, size_t& lds, const void*& f);
 hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
                        hipStream_t s);
 hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* centre, double* ynorm,
@@ -114,6 +115,7 @@ struct Geom {
     int64_t N = 0;
     int cpb = 0, n_cg = 0, n_part = 0, ntile = 0, n_chunks = 0, n_ll = 0;
     int fuse_wc = 0;   // FP32 MFMA single pass: component groups per block (0: two passes)
+    int fuse_bf16 = 0; // BF16 split single pass (all components in one workgroup)
     // prepared buffer: [||y_i - mu||^2 N doubles][sum_i N doubles][mu][BF16 planes]
     size_t prep_bytes = 0, prep_sum_off = 0, prep_mu_off = 0, prep_extra_off = 0;
     int64_t chunk_obs = 0;
@@ -150,6 +152,15 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
         }
     } else if (is_bf16(prec)) {
         ok = bf16_geom(LL, g.KK, split_products(prec), g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
+        size_t lds = 0;
+        const void* ff = nullptr;
+        if (ok && bf16_fused_geom(LL, g.KK, split_products(prec), lds, ff)) {
+            g.fuse_bf16 = 1;
+            g.lds1 = 0;
+            g.lds2 = lds;
+            f1 = nullptr;
+            f2 = ff;
+        }
     } else if (prec == SRMRA_FP32_FFT) {
         // pass 1: a team per observation over all components; pass 2: component
         // groups of CG = teams / tpc components
@@ -167,7 +178,8 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     g.n_cg = (g.KK + g.cpb - 1) / g.cpb;
     // pass-1 partials per observation: one per component group, or per component
     // pair for the BF16 form (two waves of a block hold different pairs)
-    g.n_part = is_bf16(prec) ? bf16_parts(LL, g.KK) : (prec == SRMRA_FP32_FFT ? 1 : g.n_cg);   // 1 for the single pass
+    g.n_part = g.fuse_bf16 ? 1 : (is_bf16(prec) ? bf16_parts(LL, g.KK)
+                                                : (prec == SRMRA_FP32_FFT ? 1 : g.n_cg));   // 1 for the single pass
     g.prep_sum_off = align_up(sizeof(double) * (size_t)N);
     g.prep_mu_off = g.prep_sum_off + align_up(sizeof(double) * (size_t)N);
     g.prep_extra_off = g.prep_mu_off + kAlign;
@@ -306,11 +318,13 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
                            g.n_part, g.N, ynorm, p.inv_2s2, p.lse, (double*)(ws + g.o_llpart), ll_obs);
         return hipGetLastError();
     };
-    if (g.fuse_wc) {
+    if (g.fuse_wc || g.fuse_bf16) {
         // single pass; its (max, sum) per observation feed the log-likelihood after it
         mark(2);
         mark(3);
-        if (launch_mfma(LL, 3, p, stream) != hipSuccess) return SRMRA_EDEVICE;
+        if ((g.fuse_wc ? launch_mfma(LL, 3, p, stream)
+                       : launch_bf16(LL, split_products(g.prec), 3, p, prep_extra, stream)) != hipSuccess)
+            return SRMRA_EDEVICE;
         mark(4);
         if (combine() != hipSuccess) return SRMRA_EDEVICE;
     } else {
@@ -362,7 +376,7 @@ int srmra_em_step_passes(int64_t N, int L_low, int K, int precision) {
     Geom g;
     const int st = make_geom(N, L_low, K, precision, false, g);
     if (st != SRMRA_OK) return st;
-    return g.fuse_wc ? 1 : 2;   // the FFT route makes two passes
+    return (g.fuse_wc || g.fuse_bf16) ? 1 : 2;   // the FFT route makes two passes
 }
 
 size_t srmra_prepared_bytes(int64_t N, int L_low, int K, int precision) {
@@ -517,7 +531,7 @@ namespace {
 int form_of(int precision, int LL) {
     if (is_bf16(precision)) {
         if (!bf16_supported(LL)) return FORM_MFMA;
-        return precision == SRMRA_BF16_SPLIT4 ? FORM_BF16X4 : FORM_BF16;
+        return precision == SRMRA_BF16_SPLIT4 ? FORM_BF16X4 : FORM_BF16;   // (single pass: below)
     }
     return precision == SRMRA_FP32_MFMA ? FORM_MFMA : FORM_VALU;
 }
@@ -525,13 +539,15 @@ int form_of(int precision, int LL) {
 // the precision a batched form runs in
 int prec_of_form(int f) {
     switch (f) {
-        case FORM_BF16: return SRMRA_BF16_SPLIT3;
-        case FORM_BF16X4: return SRMRA_BF16_SPLIT4;
+        case FORM_BF16: case FORM_BF16F: return SRMRA_BF16_SPLIT3;
+        case FORM_BF16X4: case FORM_BF16X4F: return SRMRA_BF16_SPLIT4;
         case FORM_VALU: return SRMRA_FP32_PLAIN;
     }
     return SRMRA_FP32_MFMA;
 }
-bool is_bf16_form(int f) { return f == FORM_BF16 || f == FORM_BF16X4; }
+bool is_bf16_form(int f) { return f == FORM_BF16 || f == FORM_BF16X4 || f == FORM_BF16F || f == FORM_BF16X4F; }
+// forms with no pass-1 launch (their log-likelihood combine runs after pass 2)
+bool single_pass_form(int f) { return f == FORM_FUSED || f == FORM_BF16F || f == FORM_BF16X4F; }
 
 // observations per work item: about 2^28 multiply-adds (shape-only, so an
 // instance's partition does not depend on the rest of the batch)
@@ -659,6 +675,7 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, item_obs > 0 ? item_obs : default_chunk(g0));
         if (pr.prep_bytes < g.prep_bytes) { delete P; return SRMRA_EWORKSPACE; }
         if (f == FORM_MFMA && g.fuse_wc) f = FORM_FUSED;
+        if (g.fuse_bf16) f = f == FORM_BF16X4 ? FORM_BF16X4F : FORM_BF16F;
         P->geoms.push_back(g);
         P->form.push_back(f);
         int cls = -1;
@@ -684,13 +701,14 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
                 const int ch = comp_major ? b : a, cg = comp_major ? a : b;
                 const int64_t nobs = std::min<int64_t>(g.chunk_obs, g.N - (int64_t)ch * g.chunk_obs);
                 const double cst = (double)nobs * g.cpb * (double)g.LL * g.LL * g.LL * g.LL *
-                                   (f == FORM_VALU ? 2.0 : (f == FORM_BF16 ? 0.5 : (f == FORM_BF16X4 ? 0.67 : 1.0)));
+                                   (f == FORM_VALU ? 2.0 : (f == FORM_BF16 ? 0.5 : (f == FORM_BF16X4 ? 0.67 :
+                                    (f == FORM_BF16F ? 0.35 : (f == FORM_BF16X4F ? 0.45 : 1.0)))));
                 costs.push_back({cls, cst, make_int4(i, ch, cg, 0)});
             }
         }
         for (int c = 0; c < g.KK; ++c) P->pack_items.push_back(make_int2(i, c));
         for (int k = 0; k < g.n_ll; ++k)
-            (f == FORM_FUSED ? combine_late : P->combine_items).push_back(make_int2(i, k));
+            (single_pass_form(f) ? combine_late : P->combine_items).push_back(make_int2(i, k));
         const int per = g.KK * g.LL * g.LL;
         for (int k = 0; k < (per + 255) / 256; ++k) P->reduce_items.push_back(make_int2(i, k));
     }

@@ -6,7 +6,9 @@ namespace srmra {
 
 // FORM_FUSED: FP32 MFMA single pass (no pass-1 launch; the log-likelihood
 // combine of these instances runs after pass 2)
-enum { FORM_VALU = 0, FORM_MFMA = 1, FORM_BF16 = 2, FORM_FUSED = 3, FORM_BF16X4 = 4 };
+// FORM_BF16F / FORM_BF16X4F: the BF16 split single pass (3 / 4 products)
+enum { FORM_VALU = 0, FORM_MFMA = 1, FORM_BF16 = 2, FORM_FUSED = 3, FORM_BF16X4 = 4, FORM_BF16F = 5,
+       FORM_BF16X4F = 6 };
 
 struct InstDesc {
     StepArgs p;                  // per-instance step arguments (workspace pointers set)

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_batch_pack_xb(const InstDesc* __restric
                                                        const int2* __restrict__ items) {
     const int2 it = items[blockIdx.x];
     const InstDesc& d = D[it.x];
-    if (d.form != FORM_BF16 && d.form != FORM_BF16X4) return;
+    if (d.form != FORM_BF16 && d.form != FORM_BF16X4 && d.form != FORM_BF16F && d.form != FORM_BF16X4F) return;
     uint4* xb = const_cast<uint4*>(d.p.xb);
     if (d.LL == 16) {
         for (int ks = threadIdx.x >> 6; ks < b16s::NK; ks += 4) b16s::pack_xb_body(d.p, d.x, it.y, ks, xb);
@@ -118,6 +118,12 @@ void k_class_pass(const InstDesc* __restrict__ D,
                 if constexpr (PASS == 1) b16::bf16_pass1_body<LL, NP>(d.p, q, w.y, w.z, lds);
                 else b16::bf16_pass2_body<LL, NP>(d.p, q, w.y, w.z, lds);
             }
+        } else if constexpr (FORM == FORM_BF16F || FORM == FORM_BF16X4F) {
+            constexpr int NP = FORM == FORM_BF16X4F ? 4 : 3;
+            b16::Prep q;
+            q.yT = d.yT;
+            q.yo = d.yo;
+            b16::bf16_pass2_body<LL, NP, true>(d.p, q, w.y, 0, lds);
         } else if constexpr (FORM == FORM_FUSED) {
             mfma_fused_body<LL>(d.p, w.y, lds);
         } else if constexpr (FORM == FORM_MFMA) {
@@ -145,6 +151,10 @@ SRMRA_CLASS(FORM_BF16, 48) SRMRA_CLASS(FORM_BF16, 64)
 SRMRA_CLASS(FORM_BF16X4, 16) SRMRA_CLASS(FORM_BF16X4, 24) SRMRA_CLASS(FORM_BF16X4, 32)
 SRMRA_CLASS(FORM_BF16X4, 48) SRMRA_CLASS(FORM_BF16X4, 64)
 #undef SRMRA_CLASS
+#define SRMRA_BF16F(F, L) template __global__ void k_class_pass<2, F, L>(const InstDesc*, const int4*, int, int*);
+SRMRA_BF16F(FORM_BF16F, 24) SRMRA_BF16F(FORM_BF16F, 32)
+SRMRA_BF16F(FORM_BF16X4F, 24) SRMRA_BF16F(FORM_BF16X4F, 32)
+#undef SRMRA_BF16F
 #define SRMRA_FUSED(L) template __global__ void k_class_pass<2, FORM_FUSED, L>(const InstDesc*, const int4*, int, int*);
 SRMRA_FUSED(8) SRMRA_FUSED(12) SRMRA_FUSED(16) SRMRA_FUSED(24) SRMRA_FUSED(32) SRMRA_FUSED(48)
 SRMRA_FUSED(64)
@@ -169,6 +179,10 @@ const void* class_pass_fn(int pass, int form, int LL) {
 #define SRMRA_PICK(L) if (form == FORM_FUSED && LL == L) return pass == 2 ? (const void*)k_class_pass<2, FORM_FUSED, L> : nullptr;
     SRMRA_PICK(8) SRMRA_PICK(12) SRMRA_PICK(16) SRMRA_PICK(24) SRMRA_PICK(32) SRMRA_PICK(48) SRMRA_PICK(64)
 #undef SRMRA_PICK
+#define SRMRA_PICK(F, L) if (form == F && LL == L) return pass == 2 ? (const void*)k_class_pass<2, F, L> : nullptr;
+    SRMRA_PICK(FORM_BF16F, 24) SRMRA_PICK(FORM_BF16F, 32)
+    SRMRA_PICK(FORM_BF16X4F, 24) SRMRA_PICK(FORM_BF16X4F, 32)
+#undef SRMRA_PICK
     return nullptr;
 }
 
@@ -186,7 +200,7 @@ hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
         }
         for (int k = 0; k < L.n_class; ++k) {
             const ClassLaunch& c = L.cls[k];
-            if (pass == 1 && c.form == FORM_FUSED) continue;
+            if (pass == 1 && (c.form == FORM_FUSED || c.form == FORM_BF16F || c.form == FORM_BF16X4F)) continue;
             const void* f = class_pass_fn(pass, c.form, c.LL);
             if (!f) return hipErrorInvalidValue;
             const InstDesc* desc = L.desc;

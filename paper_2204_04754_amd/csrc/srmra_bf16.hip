@@ -19,6 +19,13 @@ __global__ __launch_bounds__(256) void k_backproject_bf16(StepArgs p, Prep q) {
     bf16_pass2_body<LL, NP>(p, q, blockIdx.x, blockIdx.y, lds);
 }
 
+// single pass (K^2 <= 4): grid (chunks)
+template <int LL, int NP>
+__global__ __launch_bounds__(256) void k_fused_bf16(StepArgs p, Prep q) {
+    extern __shared__ float lds[];
+    bf16_pass2_body<LL, NP, true>(p, q, blockIdx.x, 0, lds);
+}
+
 // x as MFMA B fragments: grid (KK, k-steps / 4), 256 threads (4 k-steps per block)
 template <int LL>
 __global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __restrict__ x,
@@ -75,14 +82,15 @@ namespace b16s {
 template <int NP>
 __global__ __launch_bounds__(256) void k_score_lse(StepArgs p, Prep q) {
     extern __shared__ float lds[];
-    pass1_body<NP>(p, q, blockIdx.x, blockIdx.y, lds);
+    b16s::pass1_body<NP>(p, q, blockIdx.x, blockIdx.y, lds);
 }
 
 template <int NP>
 __global__ __launch_bounds__(256) void k_backproject(StepArgs p, Prep q) {
     extern __shared__ float lds[];
-    pass2_body<NP>(p, q, blockIdx.x, blockIdx.y, lds);
+    b16s::pass2_body<NP>(p, q, blockIdx.x, blockIdx.y, lds);
 }
+
 
 // grid (KK, 2): 4 k-steps per block
 __global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __restrict__ x,
@@ -179,6 +187,14 @@ hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* cen
 
 template <int LL, int NP>
 static hipError_t launch_bf16_ll(int pass, const StepArgs& p, const b16::Prep& q, hipStream_t s) {
+    if (pass == 3) {
+        const size_t lds = b16::lds_fused<LL>();
+        if (hipFuncSetAttribute((const void*)b16::k_fused_bf16<LL, NP>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((b16::k_fused_bf16<LL, NP>), dim3(p.n_chunks), dim3(256), lds, s, p, q);
+        return hipGetLastError();
+    }
     const dim3 grid(p.n_chunks, p.n_cg);
     if (pass == 1) {
         const size_t lds = b16::lds_pass1<LL>();
@@ -250,6 +266,26 @@ static void bf16w_geom_ll(size_t& lds1, size_t& lds2, const void*& f1, const voi
     lds2 = b16w::lds_pass2<LL>();
     f1 = (const void*)b16w::k_score_lse<LL, NP>;
     f2 = (const void*)b16w::k_backproject<LL, NP>;
+}
+
+// The single pass when one workgroup holds all K^2 components of its
+// observations: L_low 24 / 32 with K^2 <= 4.  (At L_low 16 a single pass that
+// keeps the scores of 8 observations x 4 components across the block's
+// (max, sum) exchange spilled registers and measured no faster than the two
+// passes, slower inside the batched form; L_low 16 keeps two passes.)
+bool bf16_fused_geom(int LL, int KK, int np, size_t& lds, const void*& f) {
+    if ((LL == 24 || LL == 32) && KK <= 4) {
+        if (LL == 24) {
+            lds = b16::lds_fused<24>();
+            f = np == 4 ? (const void*)b16::k_fused_bf16<24, 4> : (const void*)b16::k_fused_bf16<24, 3>;
+        } else {
+            lds = b16::lds_fused<32>();
+            f = np == 4 ? (const void*)b16::k_fused_bf16<32, 4> : (const void*)b16::k_fused_bf16<32, 3>;
+        }
+        return true;
+    }
+    (void)np;
+    return false;
 }
 
 bool bf16_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds1, size_t& lds2,

@@ -323,10 +323,49 @@ __device__ __forceinline__ void bf16_pass1_body(const StepArgs& p, const Prep& q
     }
 }
 
+// Log-sum-exp of 8 observations over the components of a block from the waves'
+// own (max, sum exp) pairs, exchanged through LDS (red: [waves][8] float2).
+// Every wave of the block calls it (two barriers); the caller's wave stores
+// its pair at slot `slot` and combines slots base + k * stride, k < nslot,
+// for which use(k) holds, in that order.  The combined pair is also written as
+// the observation's single partial (its log-likelihood term is formed from it
+// later) by the `writer` waves, and the value returned is the one the combine
+// kernel forms from that pair.
+template <typename Use>
+__device__ __forceinline__ void block_lse(const StepArgs& p, const float (&mw)[8], const float (&sw)[8],
+                                          int slot, int base, int stride, int nslot, int64_t obs0,
+                                          int64_t c1, bool writer, Use use, float2* red, float (&lse)[8]) {
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int o = 0; o < 8; ++o) red[slot * 8 + o] = make_float2(mw[o], sw[o]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+        float m = -INFINITY;
+        for (int k = 0; k < nslot; ++k)
+            if (use(k)) m = fmaxf(m, red[(base + k * stride) * 8 + o].x);
+        double sum = 0.0;
+        if (m > -INFINITY) {
+            for (int k = 0; k < nslot; ++k) {
+                if (!use(k)) continue;
+                const float2 e = red[(base + k * stride) * 8 + o];
+                if (e.x > -INFINITY) sum += (double)e.y * exp((double)e.x - (double)m);
+            }
+        }
+        const float sf = (float)sum;
+        lse[o] = m > -INFINITY ? (float)((double)m + log((double)sf)) : 0.f;
+        if (writer && lane == 0 && obs0 + o < c1) p.part[obs0 + o] = make_float2(m, sf);
+    }
+    __syncthreads();   // red is rewritten by the next group
+}
+
 // ============================================================================
 // Pass 2.  Block = 8 observations x 4 components; wave w owns component
-// cg*4 + w for all 8 observations.
-template <int LL, int NP>
+// cg*4 + w for all 8 observations.  FUSED (K^2 <= 4, one component group):
+// the single pass -- LSE from the block's own scores instead of pass 1.
+template <int LL, int NP, bool FUSED = false>
 __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q, int chunk_i, int cg,
                                                 float* lds) {
     using G = Geo<LL>;
@@ -357,8 +396,47 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
         // posterior weights, posterior mass, BF16 hi/lo fragments over k = (t2, o)
         bf16x8 wh[16], wl[16];
         float lse[8];
+        if constexpr (FUSED) {
+            // this wave's (max, sum exp) per observation, then the 4 waves combined
+            float mw[8], sw[8];
 #pragma unroll
-        for (int o = 0; o < 8; ++o) lse[o] = (o0 + o < p.N) ? p.lse[o0 + o] : 0.f;
+            for (int o = 0; o < 8; ++o) {
+                mw[o] = -INFINITY;
+                sw[o] = 0.f;
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int t2 = acc_row(v, lane);
+                const bool sok = cok && t2 < LL && j < LL;
+                const float bet = sok ? p.betaT[(int64_t)comp * (LL * LL) + t2 * LL + j] : 0.f;
+#pragma unroll
+                for (int o = 0; o < 8; ++o)
+                    if (sok && o0 + o < p.N) mw[o] = fmaxf(mw[o], acc[o][0][v] * p.inv_s2 + bet);
+            }
+#pragma unroll
+            for (int o = 0; o < 8; ++o)
+                for (int off = 32; off > 0; off >>= 1) mw[o] = fmaxf(mw[o], __shfl_xor(mw[o], off));
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int t2 = acc_row(v, lane);
+                const bool sok = cok && t2 < LL && j < LL;
+                const float bet = sok ? p.betaT[(int64_t)comp * (LL * LL) + t2 * LL + j] : 0.f;
+#pragma unroll
+                for (int o = 0; o < 8; ++o) {
+                    const float a = acc[o][0][v] * p.inv_s2 + bet;
+                    if (sok && o0 + o < p.N && a > -INFINITY) sw[o] += fast_exp(a - mw[o]);
+                }
+            }
+#pragma unroll
+            for (int o = 0; o < 8; ++o)
+                for (int off = 32; off > 0; off >>= 1) sw[o] += __shfl_xor(sw[o], off);
+            float2* red = reinterpret_cast<float2*>(yo + 2 * LL * LL * 8);
+            block_lse(p, mw, sw, wave, 0, 1, 4, o0, p.N, wave == 0,
+                      [&](int k) { return k < p.KK; }, red, lse);
+        } else {
+#pragma unroll
+            for (int o = 0; o < 8; ++o) lse[o] = (o0 + o < p.N) ? p.lse[o0 + o] : 0.f;
+        }
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int t2 = acc_row(v, lane);
@@ -520,6 +598,8 @@ template <int LL> constexpr size_t lds_pass2() {
     return sizeof(float) * (4 * LL * G::BP) +
            sizeof(__bf16) * (8 * 2 * LL * PITCH + 2 * LL * LL * 8);
 }
+// the single pass: pass 2's LDS plus the (max, sum) exchange
+template <int LL> constexpr size_t lds_fused() { return lds_pass2<LL>() + sizeof(float2) * 4 * 8; }
 
 }  // namespace b16
 }  // namespace srmra

@@ -112,7 +112,8 @@ def test_pass_count_query():
     assert B.srmra_em_step_passes(200000, 32, 4, "fp32_mfma") == 2
     assert B.srmra_em_step_passes(20000, 64, 4, "fp32_mfma") == 2
     assert B.srmra_em_step_passes(100000, 32, 2, "fp32_plain") == 2
-    assert B.srmra_em_step_passes(100000, 32, 2, "bf16_split3") == 2
+    assert B.srmra_em_step_passes(100000, 32, 2, "bf16_split3") == 1   # one workgroup holds K^2 = 4
+    assert B.srmra_em_step_passes(200000, 32, 4, "bf16_split3") == 2
     with pytest.raises(B.SrmraError):
         B.srmra_em_step_passes(1000, 20, 2, "fp32_mfma")
 
