@@ -53,6 +53,7 @@ hipError_t launch_project(const float* x_in, float* x_out, int Lh, float* sigma_
 // FFT route (srmra_fft.hip)
 bool fft_supported(int LL);
 int fft_tpc(int LL, int KK);
+int fft_teams(int LL);
 size_t fft_lds(int LL);
 const void* fft_pass2_fn(int LL);
 hipError_t launch_fft(int LL, int what, const StepArgs& p, const float* x, const float* y,
@@ -166,7 +167,7 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
         // groups of CG = teams / tpc components
         ok = fft_supported(LL);
         if (ok) {
-            const int teams = 256 / LL;
+            const int teams = fft_teams(LL);
             g.cpb = teams / fft_tpc(LL, g.KK);   // components per pass-2 block
             g.ntile = teams;
             g.lds1 = g.lds2 = fft_lds(LL);

@@ -98,26 +98,41 @@ __global__ __launch_bounds__(256) void k_fft_pack_x(const float* __restrict__ x,
     for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
 }
 
-// score column r of (observation o, component c): s[k] = a at (t1 = k, t2 = r)
+// ---- the two passes: a team of 2L lanes per image (lane pair (r, h): r the
+// row or column, h which half of it), TEAMS_H teams per block
+template <int L> struct GeoP {
+    static constexpr int TEAMS = 256 / (2 * L);
+    static constexpr int BUF = L * (L + 1);   // float2 per team buffer
+};
+template <int L> constexpr size_t lds_pairs() {
+    return sizeof(float2) * ((size_t)GeoP<L>::TEAMS * GeoP<L>::BUF + L / 2);
+}
+
+// Scores of (observation o, component c) for pair (r, h): s[k] = a at
+// (t1 = (L/2) h + k, t2 = r).  Row r of Y_o conj(X_c) enters as its samples
+// 2m + h, for which the team's lanes read consecutive words of the paired
+// layouts.
 template <int L>
-__device__ __forceinline__ void score_column(const StepArgs& p, const float2* __restrict__ yhat,
-                                             const float2* __restrict__ xhat, int64_t o, int c,
-                                             float2* buf, int r, const float2* tw, float (&s)[L]) {
-    float2 v[L];
-    // row r of Y_o conj(X_c) from the paired layouts: elements k, k + 1 at [k / 2][r]
-    const float4* yr = reinterpret_cast<const float4*>(yhat) + o * (L / 2) * L + r;
-    const float4* xr = reinterpret_cast<const float4*>(xhat) + (int64_t)c * (L / 2) * L + r;
+__device__ __forceinline__ void score_pair(const StepArgs& p, const float2* __restrict__ yhat,
+                                           const float2* __restrict__ xhat, int64_t o, int c,
+                                           float2* buf, int r, int h, const float2* tw, float (&s)[L / 2]) {
+    float2 v[L / 2];
+    const float2* yr = yhat + ((int64_t)o * (L / 2) * L + r) * 2 + h;   // Y_o[r][2m + h] at yr[2 L m]
+    const float2* xr = xhat + ((int64_t)c * (L / 2) * L + r) * 2 + h;
 #pragma unroll
-    for (int k = 0; k < L; k += 2) {
-        const float4 a = yr[(k / 2) * L], b = xr[(k / 2) * L];
-        v[k] = cmulc(make_float2(a.x, a.y), make_float2(b.x, b.y));
-        v[k + 1] = cmulc(make_float2(a.z, a.w), make_float2(b.z, b.w));
-    }
-    fft2_rows_then_cols<L, true>(v, buf, r, tw);
+    for (int m = 0; m < L / 2; ++m) v[m] = cmulc(yr[2 * L * m], xr[2 * L * m]);
+    fft_pair_dit<L, true>(v, h, tw);                       // v[k] = row r, n2 = (L/2) h + k
+#pragma unroll
+    for (int k = 0; k < L / 2; ++k) buf[r * (L + 1) + (L / 2) * h + k] = v[k];
+    team_sync();
+#pragma unroll
+    for (int m = 0; m < L / 2; ++m) v[m] = buf[(2 * m + h) * (L + 1) + r];   // column r, rows 2m + h
+    team_sync();
+    fft_pair_dit<L, true>(v, h, tw);                       // v[k] = S[(L/2) h + k][r]
     const float sc = p.inv_s2 / (float)(L * L);
-    const float* bet = p.betaT + (int64_t)c * (L * L) + r * L;   // betaT[c][t2 = r][t1]
+    const float* bet = p.betaT + (int64_t)c * (L * L) + r * L + (L / 2) * h;   // betaT[c][t2 = r][t1]
 #pragma unroll
-    for (int k = 0; k < L; ++k) s[k] = v[k].x * sc + bet[k];
+    for (int k = 0; k < L / 2; ++k) s[k] = v[k].x * sc + bet[k];
 }
 
 __device__ __forceinline__ void lse_merge(float& m, float& s, float m2, float s2) {
@@ -128,39 +143,43 @@ __device__ __forceinline__ void lse_merge(float& m, float& s, float m2, float s2
     m = mn;
 }
 
-// ---- pass 1: (max, sum exp) of every observation over all components
+// ---- pass 1: (max, sum exp) of every observation over all components.  Grid
+// (chunks, component groups) like pass 2: the gridDim.y blocks of a chunk
+// share its observations, so that pass 1 fills the device as pass 2 does.
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_pass1(StepArgs p, const float2* __restrict__ yhat,
                                                    const float2* __restrict__ xhat) {
     extern __shared__ float2 sh[];
-    float2* tw = sh + Geo<L>::TEAMS * Geo<L>::BUF;
+    float2* tw = sh + GeoP<L>::TEAMS * GeoP<L>::BUF;
     make_twiddles<L>(tw);
     __syncthreads();
-    const int team = threadIdx.x / L, r = threadIdx.x % L;
-    float2* buf = sh + team * Geo<L>::BUF;
+    const int team = threadIdx.x / (2 * L), lt = threadIdx.x % (2 * L);
+    const int r = lt >> 1, h = lt & 1;
+    float2* buf = sh + team * GeoP<L>::BUF;
     const int64_t c0 = (int64_t)blockIdx.x * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    for (int64_t o = c0 + team; o < c1; o += Geo<L>::TEAMS) {
+    for (int64_t o = c0 + team + (int64_t)GeoP<L>::TEAMS * blockIdx.y; o < c1;
+         o += (int64_t)GeoP<L>::TEAMS * gridDim.y) {
         float m = -INFINITY, sm = 0.f;
         for (int c = 0; c < p.KK; ++c) {
-            float s[L];
-            score_column<L>(p, yhat, xhat, o, c, buf, r, tw, s);
+            float s[L / 2];
+            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, s);
             float mc = -INFINITY;
 #pragma unroll
-            for (int k = 0; k < L; ++k) mc = fmaxf(mc, s[k]);
+            for (int k = 0; k < L / 2; ++k) mc = fmaxf(mc, s[k]);
             float sc = 0.f;
             if (mc > -INFINITY) {
 #pragma unroll
-                for (int k = 0; k < L; ++k) sc += s[k] > -INFINITY ? __expf(s[k] - mc) : 0.f;
+                for (int k = 0; k < L / 2; ++k) sc += s[k] > -INFINITY ? __expf(s[k] - mc) : 0.f;
             }
             lse_merge(m, sm, mc, sc);
         }
-        // team reduction (the team is L consecutive lanes of one wave)
-        for (int off = L / 2; off > 0; off >>= 1) {
+        // team reduction (the team is 2L consecutive lanes of one wave)
+        for (int off = L; off > 0; off >>= 1) {
             const float m2 = __shfl_xor(m, off), s2 = __shfl_xor(sm, off);
             lse_merge(m, sm, m2, s2);
         }
-        if (r == 0) p.part[o] = make_float2(m, sm);
+        if (lt == 0) p.part[o] = make_float2(m, sm);
     }
 }
 
@@ -174,37 +193,47 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
                                                    float2* __restrict__ bpart,
                                                    float* __restrict__ cpart) {
     extern __shared__ float2 sh[];
-    float2* tw = sh + Geo<L>::TEAMS * Geo<L>::BUF;
+    float2* tw = sh + GeoP<L>::TEAMS * GeoP<L>::BUF;
     make_twiddles<L>(tw);
     __syncthreads();
-    const int team = threadIdx.x / L, r = threadIdx.x % L;
-    float2* buf = sh + team * Geo<L>::BUF;
-    const int CG = Geo<L>::TEAMS / TPC;
+    const int team = threadIdx.x / (2 * L), lt = threadIdx.x % (2 * L);
+    const int r = lt >> 1, h = lt & 1;
+    float2* buf = sh + team * GeoP<L>::BUF;
+    const int CG = GeoP<L>::TEAMS / TPC;
     const int c = blockIdx.y * CG + team / TPC, u = team % TPC;
     const bool active = c < p.KK;
     const int64_t chunk = blockIdx.x;
     const int64_t c0 = chunk * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    float2 ab[L];
-    float acw[L];   // posterior mass at (t1 = k, t2 = r)
+    float2 ab[L / 2];   // sum of Y conj(W) at (k1 = r, k2 = (L/2) h + k)
+    float acw[L / 2];   // posterior mass at (t1 = (L/2) h + k, t2 = r)
 #pragma unroll
-    for (int k = 0; k < L; ++k) { ab[k] = make_float2(0.f, 0.f); acw[k] = 0.f; }
+    for (int k = 0; k < L / 2; ++k) { ab[k] = make_float2(0.f, 0.f); acw[k] = 0.f; }
     if (active) {
         for (int64_t o = c0 + u; o < c1; o += TPC) {
-            float s[L];
-            score_column<L>(p, yhat, xhat, o, c, buf, r, tw, s);
+            float s[L / 2];
+            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, s);
             const float lse = p.lse[o];
-            float2 v[L];
+            float2 v[L / 2];
 #pragma unroll
-            for (int k = 0; k < L; ++k) {
-                const float w = s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;   // w[t1 = k][t2 = r]
+            for (int k = 0; k < L / 2; ++k) {
+                const float w = s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;
                 acw[k] += w;
                 v[k] = make_float2(w, 0.f);
             }
-            fft2_cols_then_rows<L, false>(v, buf, r, tw);                              // W[r][k]
-            const float4* yr = reinterpret_cast<const float4*>(yhat) + o * (L / 2) * L + r;   // Y_o[r][k], k + 1
+            // column t2 = r (its half (L/2) h..), transformed along t1, then the rows
+            fft_pair_dif<L, false>(v, h, tw);                    // v[k] = k1 = 2k + h, column r
 #pragma unroll
-            for (int k = 0; k < L; k += 2) {
+            for (int k = 0; k < L / 2; ++k) buf[(2 * k + h) * (L + 1) + r] = v[k];
+            team_sync();
+#pragma unroll
+            for (int m = 0; m < L / 2; ++m) v[m] = buf[r * (L + 1) + 2 * m + h];   // row k1 = r, n2 = 2m + h
+            team_sync();
+            fft_pair_dit<L, false>(v, h, tw);                    // v[k] = W[r][(L/2) h + k]
+            // Y_o[r][(L/2) h + k], k and k + 1 in one 16-byte word of the paired layout
+            const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)o * (L / 2) + (L / 4) * h) * L + r;
+#pragma unroll
+            for (int k = 0; k < L / 2; k += 2) {
                 const float4 a = yr[(k / 2) * L];
                 const float2 t0 = cmulc(make_float2(a.x, a.y), v[k]);
                 const float2 t1 = cmulc(make_float2(a.z, a.w), v[k + 1]);
@@ -214,20 +243,22 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
         }
     }
     // sum the TPC teams of each component in a fixed order, one plane at a time
+    // (each lane keeps its own L/2 slots of the team buffer)
     for (int plane = 0; plane < 2; ++plane) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = plane == 0 ? ab[k] : make_float2(acw[k], 0.f);
+        for (int k = 0; k < L / 2; ++k)
+            buf[lt * (L / 2) + k] = plane == 0 ? ab[k] : make_float2(acw[k], 0.f);
         __syncthreads();
         if (active && u == 0) {
-            for (int k = 0; k < L; ++k) {
+            for (int k = 0; k < L / 2; ++k) {
                 float2 t = make_float2(0.f, 0.f);
                 for (int j = 0; j < TPC; ++j) {
-                    const float2 e = sh[(team + j) * Geo<L>::BUF + r * (L + 1) + k];
+                    const float2 e = sh[(team + j) * GeoP<L>::BUF + lt * (L / 2) + k];
                     t.x += e.x; t.y += e.y;
                 }
-                if (plane == 0) bpart[((chunk * p.KK + c) * L + r) * L + k] = t;   // [k1 = r][k2 = k]
-                else cpart[((chunk * p.KK + c) * L + k) * L + r] = t.x;            // [t1 = k][t2 = r]
+                if (plane == 0) bpart[((chunk * p.KK + c) * L + r) * L + (L / 2) * h + k] = t;   // [k1][k2]
+                else cpart[((chunk * p.KK + c) * L + (L / 2) * h + k) * L + r] = t.x;            // [t1][t2]
             }
         }
     }
@@ -287,19 +318,22 @@ __global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int6
 // ---------------------------------------------------------------- host side
 bool fft_supported(int LL) { return LL == 8 || LL == 16 || LL == 32; }
 
-// teams per component in pass 2 for KK components (a power of 2 dividing TEAMS)
+// teams of the two passes per block (2 LL lanes each)
+int fft_teams(int LL) { return 256 / (2 * LL); }
+
+// teams per component in pass 2 for KK components (a power of 2 dividing the teams)
 int fft_tpc(int LL, int KK) {
-    const int teams = 256 / LL;
+    const int teams = fft_teams(LL);
     int tpc = 1;
     while (tpc * 2 <= teams && KK * tpc * 2 <= teams) tpc *= 2;
     return tpc;
 }
 
-size_t fft_lds(int LL) {
+size_t fft_lds(int LL) {   // the two passes
     switch (LL) {
-        case 8: return fft::lds_bytes<8>();
-        case 16: return fft::lds_bytes<16>();
-        case 32: return fft::lds_bytes<32>();
+        case 8: return fft::lds_pairs<8>();
+        case 16: return fft::lds_pairs<16>();
+        case 32: return fft::lds_pairs<32>();
     }
     return 0;
 }
@@ -317,7 +351,8 @@ template <int L>
 static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, const float* y,
                                 void* yhat, void* xhat, void* bpart, void* cpart, void* bh,
                                 double* bsum, double* csum, hipStream_t s) {
-    const size_t lds = fft::lds_bytes<L>();
+    const size_t lds = fft::lds_bytes<L>();      // preparation and X: one lane per row
+    const size_t lp = fft::lds_pairs<L>();       // the passes: two lanes per row
     const int teams = 256 / L;
     switch (what) {
         case 0:   // prepare Y
@@ -331,14 +366,14 @@ static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, con
                                (float2*)xhat);
             break;
         case 2:
-            (void)hipFuncSetAttribute((const void*)fft::k_fft_pass1<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(fft::k_fft_pass1<L>, dim3(p.n_chunks), dim3(256), lds, s, p,
+            (void)hipFuncSetAttribute((const void*)fft::k_fft_pass1<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
+            hipLaunchKernelGGL(fft::k_fft_pass1<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lp, s, p,
                                (const float2*)yhat, (const float2*)xhat);
             break;
         case 3: {
             const int tpc = fft_tpc(L, p.KK);
-            (void)hipFuncSetAttribute((const void*)fft::k_fft_pass2<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(fft::k_fft_pass2<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lds, s, p,
+            (void)hipFuncSetAttribute((const void*)fft::k_fft_pass2<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
+            hipLaunchKernelGGL(fft::k_fft_pass2<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lp, s, p,
                                (const float2*)yhat, (const float2*)xhat, tpc, (float2*)bpart, (float*)cpart);
             break;
         }

@@ -14,6 +14,7 @@ namespace srmra {
 namespace fft {
 
 template <int L> struct Log2;
+template <> struct Log2<4> { static constexpr int v = 2; };
 template <> struct Log2<8> { static constexpr int v = 3; };
 template <> struct Log2<16> { static constexpr int v = 4; };
 template <> struct Log2<32> { static constexpr int v = 5; };
@@ -64,6 +65,69 @@ __device__ __forceinline__ void fft1(float2 (&v)[L], const float2* __restrict__ 
             }
         }
     }
+}
+
+// in-register transform of v[0..N) (natural order in and out) with the
+// twiddles of the length-N*TS table tw[j] = exp(-2 pi i j / (N TS)), j < N TS / 2
+template <int N, bool INV, int TS>
+__device__ __forceinline__ void fft1t(float2 (&v)[N], const float2* __restrict__ tw) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int j = bitrev<N>(i);
+        if (j > i) { const float2 t = v[i]; v[i] = v[j]; v[j] = t; }
+    }
+#pragma unroll
+    for (int half = 1; half < N; half *= 2) {
+        const int step = N / (2 * half);
+#pragma unroll
+        for (int j = 0; j < half; ++j) {
+            float2 w = tw[j * step * TS];
+            if (INV) w.y = -w.y;
+#pragma unroll
+            for (int k = 0; k < N; k += 2 * half) {
+                const float2 a = v[k + j];
+                const float2 b = cmul(v[k + j + half], w);
+                v[k + j] = make_float2(a.x + b.x, a.y + b.y);
+                v[k + j + half] = make_float2(a.x - b.x, a.y - b.y);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ float2 shfl_pair(float2 a) {
+    return make_float2(__shfl_xor(a.x, 1), __shfl_xor(a.y, 1));
+}
+
+// A length-L transform held by the two lanes of a pair (h = lane & 1, L / 2
+// values each), tw the length-L table.
+// Decimation in time: v holds the samples x[2m + h]; on return v[k] = X[(L/2) h + k]
+// (X[k] = E[k] + W^k O[k], X[k + L/2] = E[k] - W^k O[k] from the two half transforms).
+template <int L, bool INV>
+__device__ __forceinline__ void fft_pair_dit(float2 (&v)[L / 2], int h, const float2* __restrict__ tw) {
+    fft1t<L / 2, INV, 2>(v, tw);
+#pragma unroll
+    for (int k = 0; k < L / 2; ++k) {
+        const float2 q = shfl_pair(v[k]);
+        const float2 e = h ? q : v[k], o = h ? v[k] : q;
+        float2 w = tw[k];
+        if (INV) w.y = -w.y;
+        const float2 t = cmul(o, w);
+        v[k] = h ? make_float2(e.x - t.x, e.y - t.y) : make_float2(e.x + t.x, e.y + t.y);
+    }
+}
+// Decimation in frequency: v holds the half x[(L/2) h + m]; on return v[k] = X[2k + h]
+// (X[2k] from a + b, X[2k + 1] from (a - b) W^m, a and b the two halves).
+template <int L, bool INV>
+__device__ __forceinline__ void fft_pair_dif(float2 (&v)[L / 2], int h, const float2* __restrict__ tw) {
+#pragma unroll
+    for (int k = 0; k < L / 2; ++k) {
+        const float2 q = shfl_pair(v[k]);
+        const float2 a = h ? q : v[k], b = h ? v[k] : q;
+        float2 w = tw[k];
+        if (INV) w.y = -w.y;
+        v[k] = h ? cmul(make_float2(a.x - b.x, a.y - b.y), w) : make_float2(a.x + b.x, a.y + b.y);
+    }
+    fft1t<L / 2, INV, 2>(v, tw);
 }
 
 __device__ __forceinline__ void team_sync() {
