@@ -550,11 +550,16 @@ bool is_bf16_form(int f) { return f == FORM_BF16 || f == FORM_BF16X4 || f == FOR
 // forms with no pass-1 launch (their log-likelihood combine runs after pass 2)
 bool single_pass_form(int f) { return f == FORM_FUSED || f == FORM_BF16F || f == FORM_BF16X4F; }
 
-// observations per work item: about 2^28 multiply-adds (shape-only, so an
-// instance's partition does not depend on the rest of the batch)
+// observations per work item: about 2^28 multiply-adds, but no fewer than 128
+// chunks per instance while an item keeps 2^24 or more (at small L_low 2^28
+// is thousands of observations, and a class of a few instances would have
+// fewer items than the device has CUs).  Shape-only, so an instance's
+// partition does not depend on the rest of the batch.
 int64_t default_chunk(const Geom& g) {
     const double per_obs = (double)g.cpb * g.LL * g.LL * (double)g.LL * g.LL;
     int64_t c = (int64_t)(268435456.0 / per_obs);
+    const int64_t spread = (g.N + 127) / 128;
+    if (spread < c) c = std::max<int64_t>(spread, (int64_t)(16777216.0 / per_obs));
     // one-component items (BF16 at L_low 48 and 64): about 4 items per CU over
     // the instance, so that the per-chunk partials (chunks x K^2 x L_low^2)
     // stay small

@@ -198,20 +198,26 @@ hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
             for (int a = 0; a < kAuxStreams; ++a)
                 if (hipStreamWaitEvent(L.aux[a], L.fork[pass - 1], 0) != hipSuccess) return hipErrorUnknown;
         }
+        // the single-pass classes (no pass-1 launch, no dependence on the
+        // combine) run in the first phase, beside the pass-1 launches of the
+        // others, so that the second phase holds only two-pass classes
+        int slot = 0;
         for (int k = 0; k < L.n_class; ++k) {
             const ClassLaunch& c = L.cls[k];
-            if (pass == 1 && (c.form == FORM_FUSED || c.form == FORM_BF16F || c.form == FORM_BF16X4F)) continue;
-            const void* f = class_pass_fn(pass, c.form, c.LL);
+            const bool single = c.form == FORM_FUSED || c.form == FORM_BF16F || c.form == FORM_BF16X4F;
+            if (pass == 2 && single) continue;
+            const int kp = single ? 2 : pass;   // which kernel of the class
+            const void* f = class_pass_fn(kp, c.form, c.LL);
             if (!f) return hipErrorInvalidValue;
             const InstDesc* desc = L.desc;
             const int4* items = L.pass_items + c.item0;
             int n = c.n_items;
-            int* counter = L.counters + 2 * k + (pass - 1);
+            int* counter = L.counters + 2 * k + (kp - 1);
             void* args[] = {(void*)&desc, (void*)&items, (void*)&n, (void*)&counter};
-            const int lane = k % (kAuxStreams + 1);
+            const int lane = slot++ % (kAuxStreams + 1);
             hipStream_t sk = (par && lane > 0) ? L.aux[lane - 1] : s;
-            const hipError_t e = hipLaunchKernel(f, dim3(pass == 1 ? c.blocks1 : c.blocks2), dim3(256), args,
-                                                 pass == 1 ? c.lds1 : c.lds2, sk);
+            const hipError_t e = hipLaunchKernel(f, dim3(kp == 1 ? c.blocks1 : c.blocks2), dim3(256), args,
+                                                 kp == 1 ? c.lds1 : c.lds2, sk);
             if (e != hipSuccess) return e;
         }
         // join: the caller's stream waits for every helper stream
