@@ -234,7 +234,8 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision,
  * precision `form` -- the plan's own precision, or SRMRA_FP32_MFMA in a
  * BF16 split plan -- with `item_obs` observations per work item
  * (rounded up to the form's observation tile; 0 keeps the default of about
- * 2^28 multiply-adds per item).  Entries of another precision are ignored;
+ * 2^28 multiply-adds per item, smaller -- down to 2^24 -- where that leaves
+ * the problem fewer than 128 items per component group).  Entries of another precision are ignored;
  * the first matching entry wins.  A problem's result depends on its own
  * entry only (form and partition), never on the rest of the plan. */
 typedef struct srmra_tuning {

@@ -8,7 +8,8 @@ the fastest:
   accuracy target; which is faster depends on the shape), otherwise the plan's
   own precision;
 * observations per work item, as multiples of the library's default (about
-  2^28 multiply-adds per item): smaller items balance the persistent launch
+  2^28 multiply-adds per item, down to 2^24 where that gives a problem fewer
+  than 128 chunks): smaller items balance the persistent launch
   better, larger ones write fewer per-chunk partials.
 
 Timing runs one EM step of the class alone per candidate, on scratch copies of
