@@ -155,6 +155,25 @@ def test_tuning_table_validated_on_host(L):
     assert B.srmra_plan_default_item_obs(1000, 32, 2, "fp32_mfma") > 0
 
 
+def test_default_item_size_spreads_small_shapes():
+    """The plan's default work item is about 2^28 multiply-adds, but a problem
+    whose items would then be few (small L_low) is cut into about 128 chunks,
+    with no item below 2^24 multiply-adds; the partition depends on the
+    problem's own shape only."""
+    import math
+
+    from paper_2204_04754_amd import binding as B
+    # L_low 8, K 4: 2^28 multiply-adds would be thousands of observations
+    for N in (5000, 27500, 50000):
+        item = B.srmra_plan_default_item_obs(N, 8, 4, "fp32_mfma")
+        assert 100 <= math.ceil(N / item) <= 128 or item * 16 * 8 ** 4 <= 2 ** 24 * 1.01, (N, item)
+    assert B.srmra_plan_default_item_obs(50000, 12, 4, "fp32_mfma") <= math.ceil(50000 / 100)
+    # large L_low: the 2^28 item already gives many chunks and is kept
+    big = B.srmra_plan_default_item_obs(50000, 32, 2, "bf16_split3")
+    assert big == B.srmra_plan_default_item_obs(500000, 32, 2, "bf16_split3")
+    assert math.ceil(50000 / big) > 128
+
+
 def test_split4_precision_accepted():
     """SRMRA_BF16_SPLIT4 has the same shapes, preparation and workspace as the
     3-product form, and the same L_low restriction."""
