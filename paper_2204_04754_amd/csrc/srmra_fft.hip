@@ -1,4 +1,4 @@
-// FFT route of the EM step (SRMRA_FP32_FFT, L_low in {8, 16, 32}): the same
+// FFT route of the EM step (SRMRA_FP32_FFT, L_low in {8, 16, 32, 64}): the same
 // step as the dense forms, with the contractions as products in the 2-D DFT
 // domain of the L_low grid.  With (R_t v)[n] = v[n - t]:
 //   score     S_{i,c}[t] = sum_n y_i[n] x_c[n - t]      = IDFT(Y_i . conj(X_c))[t]
@@ -99,13 +99,15 @@ __global__ __launch_bounds__(256) void k_fft_pack_x(const float* __restrict__ x,
 }
 
 // ---- the two passes: a team of 2L lanes per image (lane pair (r, h): r the
-// row or column, h which half of it), TEAMS_H teams per block
+// row or column, h which half of it), TEAMS teams per block; at L = 64 a team
+// is two waves (pair_sync is then the block barrier)
 template <int L> struct GeoP {
     static constexpr int TEAMS = 256 / (2 * L);
     static constexpr int BUF = L * (L + 1);   // float2 per team buffer
 };
+// team buffers, the twiddles (L / 2) and one (max, sum) slot per wave
 template <int L> constexpr size_t lds_pairs() {
-    return sizeof(float2) * ((size_t)GeoP<L>::TEAMS * GeoP<L>::BUF + L / 2);
+    return sizeof(float2) * ((size_t)GeoP<L>::TEAMS * GeoP<L>::BUF + L / 2 + 4);
 }
 
 // Scores of (observation o, component c) for pair (r, h): s[k] = a at
@@ -124,10 +126,10 @@ __device__ __forceinline__ void score_pair(const StepArgs& p, const float2* __re
     fft_pair_dit<L, true>(v, h, tw);                       // v[k] = row r, n2 = (L/2) h + k
 #pragma unroll
     for (int k = 0; k < L / 2; ++k) buf[r * (L + 1) + (L / 2) * h + k] = v[k];
-    team_sync();
+    pair_sync<L>();
 #pragma unroll
     for (int m = 0; m < L / 2; ++m) v[m] = buf[(2 * m + h) * (L + 1) + r];   // column r, rows 2m + h
-    team_sync();
+    pair_sync<L>();
     fft_pair_dit<L, true>(v, h, tw);                       // v[k] = S[(L/2) h + k][r]
     const float sc = p.inv_s2 / (float)(L * L);
     const float* bet = p.betaT + (int64_t)c * (L * L) + r * L + (L / 2) * h;   // betaT[c][t2 = r][t1]
@@ -151,6 +153,7 @@ __global__ __launch_bounds__(256) void k_fft_pass1(StepArgs p, const float2* __r
                                                    const float2* __restrict__ xhat) {
     extern __shared__ float2 sh[];
     float2* tw = sh + GeoP<L>::TEAMS * GeoP<L>::BUF;
+    float2* red = tw + L / 2;   // per wave (max, sum), teams wider than a wave
     make_twiddles<L>(tw);
     __syncthreads();
     const int team = threadIdx.x / (2 * L), lt = threadIdx.x % (2 * L);
@@ -158,12 +161,21 @@ __global__ __launch_bounds__(256) void k_fft_pass1(StepArgs p, const float2* __r
     float2* buf = sh + team * GeoP<L>::BUF;
     const int64_t c0 = (int64_t)blockIdx.x * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    for (int64_t o = c0 + team + (int64_t)GeoP<L>::TEAMS * blockIdx.y; o < c1;
-         o += (int64_t)GeoP<L>::TEAMS * gridDim.y) {
+    // ob is the same for every team of the block, so all of them run the
+    // same iterations
+    for (int64_t ob = c0 + (int64_t)GeoP<L>::TEAMS * blockIdx.y; ob < c1;
+         ob += (int64_t)GeoP<L>::TEAMS * gridDim.y) {
+        const int64_t o = ob + team;
+        const bool live = o < c1;
+        // a team inside one wave leaves after its last observation; a wider
+        // one scores a live observation again (result dropped), so that the
+        // block's barriers stay in step
+        if (!kPairWide<L> && !live) break;
+        const int64_t os = live ? o : c1 - 1;
         float m = -INFINITY, sm = 0.f;
         for (int c = 0; c < p.KK; ++c) {
             float s[L / 2];
-            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, s);
+            score_pair<L>(p, yhat, xhat, os, c, buf, r, h, tw, s);
             float mc = -INFINITY;
 #pragma unroll
             for (int k = 0; k < L / 2; ++k) mc = fmaxf(mc, s[k]);
@@ -174,12 +186,22 @@ __global__ __launch_bounds__(256) void k_fft_pass1(StepArgs p, const float2* __r
             }
             lse_merge(m, sm, mc, sc);
         }
-        // team reduction (the team is 2L consecutive lanes of one wave)
-        for (int off = L; off > 0; off >>= 1) {
+        // team reduction: the lanes of a wave by shuffles, then the two waves
+        // of a wider team through LDS
+        for (int off = kPairWide<L> ? 32 : L; off > 0; off >>= 1) {
             const float m2 = __shfl_xor(m, off), s2 = __shfl_xor(sm, off);
             lse_merge(m, sm, m2, s2);
         }
-        if (lt == 0) p.part[o] = make_float2(m, sm);
+        if constexpr (kPairWide<L>) {
+            const int wave = threadIdx.x >> 6;
+            if ((threadIdx.x & 63) == 0) red[wave] = make_float2(m, sm);
+            __syncthreads();
+            if (lt == 0) {
+                const float2 q = red[wave + 1];
+                lse_merge(m, sm, q.x, q.y);
+            }
+        }
+        if (lt == 0 && live) p.part[o] = make_float2(m, sm);
     }
 }
 
@@ -209,15 +231,62 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
     float acw[L / 2];   // posterior mass at (t1 = (L/2) h + k, t2 = r)
 #pragma unroll
     for (int k = 0; k < L / 2; ++k) { ab[k] = make_float2(0.f, 0.f); acw[k] = 0.f; }
-    if (active) {
-        for (int64_t o = c0 + u; o < c1; o += TPC) {
+    // Teams inside one wave take their own observations and leave after the
+    // last one.  A team of two waves runs the block's common number of
+    // iterations even without a component or an observation (clamped operands,
+    // zero weights), so that the block's barriers stay in step.  The loop body
+    // is the same for both (two loops, each kept in the form that compiled to
+    // the faster code for its width).
+    if constexpr (!kPairWide<L>) {
+        if (active) {
+            const int cs = c;
+            const bool live = true;
+            for (int64_t os = c0 + u; os < c1; os += TPC) {
+                float s[L / 2];
+                score_pair<L>(p, yhat, xhat, os, cs, buf, r, h, tw, s);
+                const float lse = p.lse[os];
+                float2 v[L / 2];
+#pragma unroll
+                for (int k = 0; k < L / 2; ++k) {
+                    const float w = live && s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;
+                    acw[k] += w;
+                    v[k] = make_float2(w, 0.f);
+                }
+                // column t2 = r (its half (L/2) h..), transformed along t1, then the rows
+                fft_pair_dif<L, false>(v, h, tw);                    // v[k] = k1 = 2k + h, column r
+#pragma unroll
+                for (int k = 0; k < L / 2; ++k) buf[(2 * k + h) * (L + 1) + r] = v[k];
+                pair_sync<L>();
+#pragma unroll
+                for (int m = 0; m < L / 2; ++m) v[m] = buf[r * (L + 1) + 2 * m + h];   // row k1 = r, n2 = 2m + h
+                pair_sync<L>();
+                fft_pair_dit<L, false>(v, h, tw);                    // v[k] = W[r][(L/2) h + k]
+                // Y_o[r][(L/2) h + k], k and k + 1 in one 16-byte word of the paired layout
+                const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)os * (L / 2) + (L / 4) * h) * L + r;
+#pragma unroll
+                for (int k = 0; k < L / 2; k += 2) {
+                    const float4 a = yr[(k / 2) * L];
+                    const float2 t0 = cmulc(make_float2(a.x, a.y), v[k]);
+                    const float2 t1 = cmulc(make_float2(a.z, a.w), v[k + 1]);
+                    ab[k].x += t0.x; ab[k].y += t0.y;
+                    ab[k + 1].x += t1.x; ab[k + 1].y += t1.y;
+                }
+            }
+        }
+    } else {
+        const int cs = active ? c : p.KK - 1;
+        const int64_t nit = (c1 - c0 + TPC - 1) / TPC;
+        for (int64_t it = 0; it < nit; ++it) {
+            const int64_t o = c0 + u + it * TPC;
+            const bool live = active && o < c1;
+            const int64_t os = o < c1 ? o : c1 - 1;
             float s[L / 2];
-            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, s);
-            const float lse = p.lse[o];
+            score_pair<L>(p, yhat, xhat, os, cs, buf, r, h, tw, s);
+            const float lse = p.lse[os];
             float2 v[L / 2];
 #pragma unroll
             for (int k = 0; k < L / 2; ++k) {
-                const float w = s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;
+                const float w = live && s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;
                 acw[k] += w;
                 v[k] = make_float2(w, 0.f);
             }
@@ -225,13 +294,13 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
             fft_pair_dif<L, false>(v, h, tw);                    // v[k] = k1 = 2k + h, column r
 #pragma unroll
             for (int k = 0; k < L / 2; ++k) buf[(2 * k + h) * (L + 1) + r] = v[k];
-            team_sync();
+            pair_sync<L>();
 #pragma unroll
             for (int m = 0; m < L / 2; ++m) v[m] = buf[r * (L + 1) + 2 * m + h];   // row k1 = r, n2 = 2m + h
-            team_sync();
+            pair_sync<L>();
             fft_pair_dit<L, false>(v, h, tw);                    // v[k] = W[r][(L/2) h + k]
             // Y_o[r][(L/2) h + k], k and k + 1 in one 16-byte word of the paired layout
-            const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)o * (L / 2) + (L / 4) * h) * L + r;
+            const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)os * (L / 2) + (L / 4) * h) * L + r;
 #pragma unroll
             for (int k = 0; k < L / 2; k += 2) {
                 const float4 a = yr[(k / 2) * L];
@@ -316,7 +385,7 @@ __global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int6
 }  // namespace fft
 
 // ---------------------------------------------------------------- host side
-bool fft_supported(int LL) { return LL == 8 || LL == 16 || LL == 32; }
+bool fft_supported(int LL) { return LL == 8 || LL == 16 || LL == 32 || LL == 64; }
 
 // teams of the two passes per block (2 LL lanes each)
 int fft_teams(int LL) { return 256 / (2 * LL); }
@@ -334,6 +403,7 @@ size_t fft_lds(int LL) {   // the two passes
         case 8: return fft::lds_pairs<8>();
         case 16: return fft::lds_pairs<16>();
         case 32: return fft::lds_pairs<32>();
+        case 64: return fft::lds_pairs<64>();
     }
     return 0;
 }
@@ -343,6 +413,7 @@ const void* fft_pass2_fn(int LL) {
         case 8: return (const void*)fft::k_fft_pass2<8>;
         case 16: return (const void*)fft::k_fft_pass2<16>;
         case 32: return (const void*)fft::k_fft_pass2<32>;
+        case 64: return (const void*)fft::k_fft_pass2<64>;
     }
     return nullptr;
 }
@@ -396,6 +467,7 @@ hipError_t launch_fft(int LL, int what, const StepArgs& p, const float* x, const
         case 8: return fft_launch_ll<8>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
         case 16: return fft_launch_ll<16>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
         case 32: return fft_launch_ll<32>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
+        case 64: return fft_launch_ll<64>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
     }
     return hipErrorInvalidValue;
 }
@@ -411,6 +483,11 @@ hipError_t launch_dft2(int L, const float* in, int64_t count, float2* out, hipSt
             lds = fft::lds_bytes<32>();
             (void)hipFuncSetAttribute((const void*)fft::k_dft2<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             hipLaunchKernelGGL(fft::k_dft2<32>, grid, dim3(256), lds, s, in, count, out);
+            break;
+        case 64:
+            lds = fft::lds_bytes<64>();
+            (void)hipFuncSetAttribute((const void*)fft::k_dft2<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(fft::k_dft2<64>, grid, dim3(256), lds, s, in, count, out);
             break;
         default: return hipErrorInvalidValue;
     }

@@ -1,5 +1,5 @@
-// 2-D discrete Fourier transforms of L x L images (L in {8, 16, 32}) by teams
-// of L threads: a team's thread r holds row r (then column r) of the image as
+// 2-D discrete Fourier transforms of L x L images (L in {8, 16, 32, 64}) by
+// teams of L threads: a team's thread r holds row r (then column r) of the image as
 // L complex values in registers and runs an iterative radix-2
 // decimation-in-time transform on it; rows and columns meet through the
 // team's LDS buffer (pitch L + 1 complex, conflict-free for both).  A team
@@ -18,6 +18,7 @@ template <> struct Log2<4> { static constexpr int v = 2; };
 template <> struct Log2<8> { static constexpr int v = 3; };
 template <> struct Log2<16> { static constexpr int v = 4; };
 template <> struct Log2<32> { static constexpr int v = 5; };
+template <> struct Log2<64> { static constexpr int v = 6; };
 
 template <int L> __host__ __device__ constexpr int bitrev(int i) {
     int r = 0;
@@ -133,6 +134,15 @@ __device__ __forceinline__ void fft_pair_dif(float2 (&v)[L / 2], int h, const fl
 __device__ __forceinline__ void team_sync() {
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
     __builtin_amdgcn_wave_barrier();
+}
+
+// A team of 2L lanes (two per row) spans more than one wave for L = 64: its
+// LDS traffic is then ordered by the block barrier, which every team of the
+// block must reach the same number of times.
+template <int L> constexpr bool kPairWide = 2 * L > 64;
+template <int L> __device__ __forceinline__ void pair_sync() {
+    if constexpr (kPairWide<L>) __syncthreads();
+    else team_sync();
 }
 
 // Row transforms of v (this thread's row r), then column transforms through the

@@ -20,7 +20,7 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("L", [8, 16, 32])
+@pytest.mark.parametrize("L", [8, 16, 32, 64])
 def test_dft2_matches_numpy(L):
     x = np.random.default_rng(L).standard_normal((37, L, L)).astype(np.float32)
     out = torch.empty((37, L, L, 2), dtype=torch.float32, device="cuda")
@@ -31,8 +31,11 @@ def test_dft2_matches_numpy(L):
     assert rel(g[..., 0] + 1j * g[..., 1], ref) < 2e-6
 
 
+# L_low 64 (teams of two waves): K 1 (two teams per component), K 2, and K 3
+# (K^2 = 9: the last component group has a team without a component); odd N
+# leaves a team without an observation at the end of a chunk
 SHAPES = [(16, 2, 37), (32, 2, 29), (64, 2, 17), (64, 4, 11), (96, 3, 5), (128, 4, 9),
-          (32, 1, 7), (32, 4, 53), (48, 3, 13)]
+          (32, 1, 7), (32, 4, 53), (48, 3, 13), (64, 1, 9), (128, 2, 5), (192, 3, 13)]
 
 
 @pytest.mark.parametrize("Lh,K,N", SHAPES)

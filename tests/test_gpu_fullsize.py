@@ -31,7 +31,9 @@ def _workload(name):
 
 CASES = [("lh64_k2_n100000", "fp32_mfma"), ("lh64_k2_n100000", "fp32_plain"),
          ("lh128_k4_n200000_s0.5", "bf16_split3"), ("lh128_k4_n200000_s0.5", "fp32_mfma"),
-         ("lh128_k4_n200000_s2", "bf16_split4"), ("lh256_k4_n20000", "bf16_split3")]
+         ("lh128_k4_n200000_s2", "bf16_split4"), ("lh256_k4_n20000", "bf16_split3"),
+         ("lh64_k2_n100000", "fp32_fft"), ("lh128_k4_n200000_s0.5", "fp32_fft"),
+         ("lh256_k4_n20000", "fp32_fft")]
 
 
 @pytest.mark.parametrize("name,prec", CASES)
