@@ -101,7 +101,9 @@ def parse():
     ap.add_argument("--rates", default="5,50,200")
     ap.add_argument("--jobs", type=int, default=24)
     ap.add_argument("--serve-precisions", default="",
-                    help="serve mode: comma-separated forms (default: --precision, fp32_mfma, fp32_plain)")
+                    help="serve mode: comma-separated forms (default: --precision, fp32_mfma, "
+                         "fp32_plain); '<form>+fft' runs jobs at an L_low the FFT route supports "
+                         "through it and the rest in <form>")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the timed region, run one device-to-device copy of this many MiB "
                          "(reference kernel of known traffic for hardware-counter calibration)")
@@ -449,7 +451,9 @@ def bench_serve(args):
                 inst = pool[pick[k]]
                 jobs.append(Job(k, inst.y, inst.K, inst.sigma, inst.x0, inst.log_rho0,
                                 iterations=args.iterations, arrival=float(arr[k])))
-            ex = GPUExecutor(precision=prec)
+            # "<precision>+fft": jobs at an L_low the FFT route supports take it
+            base, _, extra = prec.partition("+")
+            ex = GPUExecutor(precision=base, fft=extra == "fft")
             rep = serve(jobs, ex, hbm_budget=200 << 30, max_slots=64)
             summ = rep.summary()
             results[f"{prec}@{rate:g}"] = summ

@@ -26,7 +26,7 @@ from __future__ import annotations
 import time
 from collections import deque
 from dataclasses import dataclass, field
-from typing import Callable, Deque, Dict, List, Optional
+from typing import Callable, Deque, Dict, List, Optional, Tuple
 
 import numpy as np
 
@@ -132,9 +132,12 @@ class Scheduler:
 
 
 class GPUExecutor:
-    """Device side of the server: per-job buffers and the batched plan."""
+    """Device side of the server: per-job buffers and the batched plan.  With
+    fft=True a job whose L_low the FFT route supports is advanced by its own
+    FFT-route step (srmra_em_step_prepared, SRMRA_FP32_FFT) on the same stream
+    after the plan, which holds the other jobs."""
 
-    def __init__(self, precision="fp32_mfma", device="cuda"):
+    def __init__(self, precision="fp32_mfma", device="cuda", fft=False):
         import torch
 
         from . import binding as B
@@ -142,15 +145,25 @@ class GPUExecutor:
         self.B = B
         self.device = torch.device(device)
         self.precision = B._prec(precision)
+        self.fft = bool(fft)
         self.buf: Dict[int, dict] = {}
         self.plan = None
         self.plan_ids: Optional[tuple] = None
         self.workspace = None
 
+    def _form(self, job_or_buf) -> Tuple[int, bool]:
+        """(precision the job runs in, whether by its own FFT-route step)."""
+        B = self.B
+        Ll, K = (job_or_buf.Ll, job_or_buf.K) if isinstance(job_or_buf, Job) else \
+            (job_or_buf["L_low"], job_or_buf["K"])
+        if self.fft and B.srmra_em_step_workspace_bytes(1, Ll, K, B.SRMRA_FP32_FFT) > 0:
+            return B.SRMRA_FP32_FFT, True
+        return B.srmra_plan_form(self.precision, Ll), False
+
     def footprint(self, job: Job) -> int:
         B = self.B
         Ll, K, N = job.Ll, job.K, job.N
-        form = B.srmra_plan_form(self.precision, Ll)
+        form, _ = self._form(job)
         if form < 0:
             return 1 << 62
         Lh = K * Ll
@@ -161,12 +174,14 @@ class GPUExecutor:
         torch, B = self.torch, self.B
         f = dict(device=self.device, dtype=torch.float32)
         y = torch.as_tensor(np.ascontiguousarray(job.y, np.float32)).to(self.device)
-        form = B.srmra_plan_form(self.precision, job.Ll)
+        form, own = self._form(job)
         prep = B.empty_bytes(B.srmra_prepared_bytes(job.N, job.Ll, job.K, form), self.device)
         B.srmra_prepare_observations(y, job.N, job.Ll, job.K, form, prep)
         Lh = job.K * job.Ll
+        ws = B.empty_bytes(B.srmra_em_step_workspace_bytes(job.N, job.Ll, job.K, form), self.device) \
+            if own else None
         self.buf[job.job_id] = dict(
-            y=y, prep=prep, N=job.N, L_low=job.Ll, K=job.K, sigma=job.sigma,
+            y=y, prep=prep, N=job.N, L_low=job.Ll, K=job.K, sigma=job.sigma, own=own, ws=ws,
             xa=torch.as_tensor(np.asarray(job.x0, np.float32)).to(**f).contiguous(),
             xb=torch.empty((Lh, Lh), **f),
             la=torch.as_tensor(np.asarray(job.log_rho0, np.float32)).to(**f).contiguous(),
@@ -187,15 +202,24 @@ class GPUExecutor:
     def tick(self, ids: List[int]) -> Dict[int, float]:
         """One EM step of every job in `ids`; returns each job's loglik."""
         torch, B = self.torch, self.B
-        key = tuple(ids)
-        if key != self.plan_ids or self.plan is None:
+        planned = [i for i in ids if not self.buf[i]["own"]]
+        key = tuple(planned)
+        if planned and (key != self.plan_ids or self.plan is None):
             if self.plan is not None:
                 self.plan.close()
-            self.plan = B.Plan([self._problem(self.buf[i]) for i in ids], self.precision)
+            self.plan = B.Plan([self._problem(self.buf[i]) for i in planned], self.precision)
             self.workspace = B.empty_bytes(self.plan.workspace_bytes, self.device)
             self.plan.upload(self.workspace)
             self.plan_ids = key
-        self.plan.execute(self.workspace)
+        if planned:
+            self.plan.execute(self.workspace)
+        for i in ids:
+            b = self.buf[i]
+            if b["own"]:
+                q = self._problem(b)
+                B.srmra_em_step_prepared(q["y"], q["prep"], q["N"], q["L_low"], q["K"], q["x"],
+                                         q["log_rho"], q["sigma"], q["x_new"], q["rho_new"],
+                                         q["log_rho_new"], q["loglik"], B.SRMRA_FP32_FFT, b["ws"], None)
         for i in ids:
             self.buf[i]["cur"] ^= 1
         lls = torch.cat([self.buf[i]["loglik"] for i in ids]).cpu().numpy()

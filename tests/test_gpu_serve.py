@@ -60,10 +60,14 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16_split3"])
+@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16_split3", "bf16_split3+fft"])
 def test_served_alone_equals_in_mix(prec):
+    """With "+fft" the L_low 16 and 32 jobs take the FFT route by their own
+    steps and the L_low 24 jobs share the plan."""
+    prec, _, extra = prec.partition("+")
+    fft = extra == "fft"
     clock = TickClock(0.01)
-    ex = TimedExecutor(clock, precision=prec)
+    ex = TimedExecutor(clock, precision=prec, fft=fft)
     rep = serve(_jobs(nan_job=4), ex, hbm_budget=1 << 34, max_slots=4, clock=clock, sleep=clock.sleep)
     st = {j.job_id: j for j in rep.jobs}
     assert st[4].state == FAILED
@@ -71,7 +75,7 @@ def test_served_alone_equals_in_mix(prec):
     for j in (0, 1, 2, 3, 5):
         assert st[j].state == DONE
         c2 = TickClock(0.01)
-        alone_ex = TimedExecutor(c2, precision=prec)
+        alone_ex = TimedExecutor(c2, precision=prec, fft=fft)
         job = _jobs()[j]
         job.arrival = 0.0
         r2 = serve([job], alone_ex, hbm_budget=1 << 34, max_slots=4, clock=c2, sleep=c2.sleep)
@@ -79,3 +83,26 @@ def test_served_alone_equals_in_mix(prec):
         b = st[j].result
         for k in ("x", "log_rho", "rho", "loglik"):
             assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (j, k)
+
+
+def test_fft_served_job_equals_its_own_steps():
+    """A job routed to the FFT route by the server gets bitwise the result of
+    the same number of single-problem FFT-route steps (EMJob)."""
+    from paper_2204_04754_amd.em import EMJob
+    j = 2                                              # Lh 64, K 2: L_low 32
+    clock = TickClock(0.01)
+    ex = TimedExecutor(clock, precision="bf16_split3", fft=True)
+    job = _jobs()[j]
+    job.arrival = 0.0
+    rep = serve([job], ex, hbm_budget=1 << 34, max_slots=4, clock=clock, sleep=clock.sleep)
+    got = rep.jobs[0].result
+    Lh, K, N, s = SHAPES[j]
+    inst = synth.make_instance(Lh, K, N, s, config=80, instance=j)
+    em = EMJob(inst.y, K, s, inst.x0, inst.log_rho0, precision="fp32_fft")
+    for _ in range(job.iterations):
+        r = em.step()
+    torch.cuda.synchronize()
+    assert np.array_equal(got["x"], em.x_current.cpu().numpy())
+    assert np.array_equal(got["log_rho"], em.log_rho_current.cpu().numpy())
+    assert np.array_equal(got["rho"], r.rho_new.cpu().numpy())
+    assert got["loglik"] == float(r.loglik.item())
