@@ -98,16 +98,15 @@ __global__ __launch_bounds__(256) void k_fft_pack_x(const float* __restrict__ x,
     for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
 }
 
-// ---- the two passes: a team of 2L lanes per image (lane pair (r, h): r the
-// row or column, h which half of it), TEAMS teams per block; at L = 64 a team
-// is two waves (pair_sync is then the block barrier)
+// ---- the two passes at L <= 32: a team of 2L lanes (inside one wave) per
+// image (lane pair (r, h): r the row or column, h which half of it), TEAMS
+// teams per block
 template <int L> struct GeoP {
     static constexpr int TEAMS = 256 / (2 * L);
     static constexpr int BUF = L * (L + 1);   // float2 per team buffer
 };
-// team buffers, the twiddles (L / 2) and one (max, sum) slot per wave
 template <int L> constexpr size_t lds_pairs() {
-    return sizeof(float2) * ((size_t)GeoP<L>::TEAMS * GeoP<L>::BUF + L / 2 + 4);
+    return sizeof(float2) * ((size_t)GeoP<L>::TEAMS * GeoP<L>::BUF + L / 2);
 }
 
 // Scores of (observation o, component c) for pair (r, h): s[k] = a at
@@ -126,10 +125,10 @@ __device__ __forceinline__ void score_pair(const StepArgs& p, const float2* __re
     fft_pair_dit<L, true>(v, h, tw);                       // v[k] = row r, n2 = (L/2) h + k
 #pragma unroll
     for (int k = 0; k < L / 2; ++k) buf[r * (L + 1) + (L / 2) * h + k] = v[k];
-    pair_sync<L>();
+    team_sync();
 #pragma unroll
     for (int m = 0; m < L / 2; ++m) v[m] = buf[(2 * m + h) * (L + 1) + r];   // column r, rows 2m + h
-    pair_sync<L>();
+    team_sync();
     fft_pair_dit<L, true>(v, h, tw);                       // v[k] = S[(L/2) h + k][r]
     const float sc = p.inv_s2 / (float)(L * L);
     const float* bet = p.betaT + (int64_t)c * (L * L) + r * L + (L / 2) * h;   // betaT[c][t2 = r][t1]
@@ -153,7 +152,6 @@ __global__ __launch_bounds__(256) void k_fft_pass1(StepArgs p, const float2* __r
                                                    const float2* __restrict__ xhat) {
     extern __shared__ float2 sh[];
     float2* tw = sh + GeoP<L>::TEAMS * GeoP<L>::BUF;
-    float2* red = tw + L / 2;   // per wave (max, sum), teams wider than a wave
     make_twiddles<L>(tw);
     __syncthreads();
     const int team = threadIdx.x / (2 * L), lt = threadIdx.x % (2 * L);
@@ -161,21 +159,12 @@ __global__ __launch_bounds__(256) void k_fft_pass1(StepArgs p, const float2* __r
     float2* buf = sh + team * GeoP<L>::BUF;
     const int64_t c0 = (int64_t)blockIdx.x * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    // ob is the same for every team of the block, so all of them run the
-    // same iterations
-    for (int64_t ob = c0 + (int64_t)GeoP<L>::TEAMS * blockIdx.y; ob < c1;
-         ob += (int64_t)GeoP<L>::TEAMS * gridDim.y) {
-        const int64_t o = ob + team;
-        const bool live = o < c1;
-        // a team inside one wave leaves after its last observation; a wider
-        // one scores a live observation again (result dropped), so that the
-        // block's barriers stay in step
-        if (!kPairWide<L> && !live) break;
-        const int64_t os = live ? o : c1 - 1;
+    for (int64_t o = c0 + team + (int64_t)GeoP<L>::TEAMS * blockIdx.y; o < c1;
+         o += (int64_t)GeoP<L>::TEAMS * gridDim.y) {
         float m = -INFINITY, sm = 0.f;
         for (int c = 0; c < p.KK; ++c) {
             float s[L / 2];
-            score_pair<L>(p, yhat, xhat, os, c, buf, r, h, tw, s);
+            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, s);
             float mc = -INFINITY;
 #pragma unroll
             for (int k = 0; k < L / 2; ++k) mc = fmaxf(mc, s[k]);
@@ -186,22 +175,12 @@ __global__ __launch_bounds__(256) void k_fft_pass1(StepArgs p, const float2* __r
             }
             lse_merge(m, sm, mc, sc);
         }
-        // team reduction: the lanes of a wave by shuffles, then the two waves
-        // of a wider team through LDS
-        for (int off = kPairWide<L> ? 32 : L; off > 0; off >>= 1) {
+        // team reduction (the team is 2L consecutive lanes of one wave)
+        for (int off = L; off > 0; off >>= 1) {
             const float m2 = __shfl_xor(m, off), s2 = __shfl_xor(sm, off);
             lse_merge(m, sm, m2, s2);
         }
-        if constexpr (kPairWide<L>) {
-            const int wave = threadIdx.x >> 6;
-            if ((threadIdx.x & 63) == 0) red[wave] = make_float2(m, sm);
-            __syncthreads();
-            if (lt == 0) {
-                const float2 q = red[wave + 1];
-                lse_merge(m, sm, q.x, q.y);
-            }
-        }
-        if (lt == 0 && live) p.part[o] = make_float2(m, sm);
+        if (lt == 0) p.part[o] = make_float2(m, sm);
     }
 }
 
@@ -231,62 +210,15 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
     float acw[L / 2];   // posterior mass at (t1 = (L/2) h + k, t2 = r)
 #pragma unroll
     for (int k = 0; k < L / 2; ++k) { ab[k] = make_float2(0.f, 0.f); acw[k] = 0.f; }
-    // Teams inside one wave take their own observations and leave after the
-    // last one.  A team of two waves runs the block's common number of
-    // iterations even without a component or an observation (clamped operands,
-    // zero weights), so that the block's barriers stay in step.  The loop body
-    // is the same for both (two loops, each kept in the form that compiled to
-    // the faster code for its width).
-    if constexpr (!kPairWide<L>) {
-        if (active) {
-            const int cs = c;
-            const bool live = true;
-            for (int64_t os = c0 + u; os < c1; os += TPC) {
-                float s[L / 2];
-                score_pair<L>(p, yhat, xhat, os, cs, buf, r, h, tw, s);
-                const float lse = p.lse[os];
-                float2 v[L / 2];
-#pragma unroll
-                for (int k = 0; k < L / 2; ++k) {
-                    const float w = live && s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;
-                    acw[k] += w;
-                    v[k] = make_float2(w, 0.f);
-                }
-                // column t2 = r (its half (L/2) h..), transformed along t1, then the rows
-                fft_pair_dif<L, false>(v, h, tw);                    // v[k] = k1 = 2k + h, column r
-#pragma unroll
-                for (int k = 0; k < L / 2; ++k) buf[(2 * k + h) * (L + 1) + r] = v[k];
-                pair_sync<L>();
-#pragma unroll
-                for (int m = 0; m < L / 2; ++m) v[m] = buf[r * (L + 1) + 2 * m + h];   // row k1 = r, n2 = 2m + h
-                pair_sync<L>();
-                fft_pair_dit<L, false>(v, h, tw);                    // v[k] = W[r][(L/2) h + k]
-                // Y_o[r][(L/2) h + k], k and k + 1 in one 16-byte word of the paired layout
-                const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)os * (L / 2) + (L / 4) * h) * L + r;
-#pragma unroll
-                for (int k = 0; k < L / 2; k += 2) {
-                    const float4 a = yr[(k / 2) * L];
-                    const float2 t0 = cmulc(make_float2(a.x, a.y), v[k]);
-                    const float2 t1 = cmulc(make_float2(a.z, a.w), v[k + 1]);
-                    ab[k].x += t0.x; ab[k].y += t0.y;
-                    ab[k + 1].x += t1.x; ab[k + 1].y += t1.y;
-                }
-            }
-        }
-    } else {
-        const int cs = active ? c : p.KK - 1;
-        const int64_t nit = (c1 - c0 + TPC - 1) / TPC;
-        for (int64_t it = 0; it < nit; ++it) {
-            const int64_t o = c0 + u + it * TPC;
-            const bool live = active && o < c1;
-            const int64_t os = o < c1 ? o : c1 - 1;
+    if (active) {
+        for (int64_t o = c0 + u; o < c1; o += TPC) {
             float s[L / 2];
-            score_pair<L>(p, yhat, xhat, os, cs, buf, r, h, tw, s);
-            const float lse = p.lse[os];
+            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, s);
+            const float lse = p.lse[o];
             float2 v[L / 2];
 #pragma unroll
             for (int k = 0; k < L / 2; ++k) {
-                const float w = live && s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;
+                const float w = s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;
                 acw[k] += w;
                 v[k] = make_float2(w, 0.f);
             }
@@ -294,13 +226,13 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
             fft_pair_dif<L, false>(v, h, tw);                    // v[k] = k1 = 2k + h, column r
 #pragma unroll
             for (int k = 0; k < L / 2; ++k) buf[(2 * k + h) * (L + 1) + r] = v[k];
-            pair_sync<L>();
+            team_sync();
 #pragma unroll
             for (int m = 0; m < L / 2; ++m) v[m] = buf[r * (L + 1) + 2 * m + h];   // row k1 = r, n2 = 2m + h
-            pair_sync<L>();
+            team_sync();
             fft_pair_dit<L, false>(v, h, tw);                    // v[k] = W[r][(L/2) h + k]
             // Y_o[r][(L/2) h + k], k and k + 1 in one 16-byte word of the paired layout
-            const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)os * (L / 2) + (L / 4) * h) * L + r;
+            const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)o * (L / 2) + (L / 4) * h) * L + r;
 #pragma unroll
             for (int k = 0; k < L / 2; k += 2) {
                 const float4 a = yr[(k / 2) * L];
@@ -330,6 +262,141 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
                 else cpart[((chunk * p.KK + c) * L + (L / 2) * h + k) * L + r] = t.x;            // [t1][t2]
             }
         }
+    }
+}
+
+// ---- L_low 64: one team per block, four lanes per row (lane 4r + q holds a
+// quarter of row r, see fft_quad_dit / fft_quad_dif), so a lane keeps 16
+// complex values of an image; the LDS transposes are ordered by the block
+// barrier, and every thread of the block belongs to the one team.
+namespace quad {
+constexpr int L = 64, NV = L / 4;
+constexpr int BUF = L * (L + 1);
+// team buffer, the twiddles (L / 2) and one (max, sum) slot per wave
+constexpr size_t lds() { return sizeof(float2) * ((size_t)BUF + L / 2 + 4); }
+
+// scores of (observation o, component c) for lane (r, q): s[k] = a at
+// (t1 = 16 quad_block(q) + k, t2 = r)
+__device__ __forceinline__ void score(const StepArgs& p, const float2* __restrict__ yhat,
+                                      const float2* __restrict__ xhat, int64_t o, int c, float2* buf,
+                                      int r, int q, int bq, const float2* tw, float (&s)[NV]) {
+    float2 v[NV];
+    // Y_o[r][4m + q] of the paired layout [k2 / 2][k1][k2 % 2] at yr[4 L m]
+    const float2* yr = yhat + (((int64_t)o * (L / 2) + (q >> 1)) * L + r) * 2 + (q & 1);
+    const float2* xr = xhat + (((int64_t)c * (L / 2) + (q >> 1)) * L + r) * 2 + (q & 1);
+#pragma unroll
+    for (int m = 0; m < NV; ++m) v[m] = cmulc(yr[4 * L * m], xr[4 * L * m]);
+    fft_quad_dit<L, true>(v, q, tw);                       // v[k] = row r, n2 = 16 bq + k
+#pragma unroll
+    for (int k = 0; k < NV; ++k) buf[r * (L + 1) + 16 * bq + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NV; ++m) v[m] = buf[(4 * m + q) * (L + 1) + r];   // column r, rows 4m + q
+    __syncthreads();
+    fft_quad_dit<L, true>(v, q, tw);                       // v[k] = S[16 bq + k][r]
+    const float sc = p.inv_s2 / (float)(L * L);
+    const float* bet = p.betaT + (int64_t)c * (L * L) + r * L + 16 * bq;   // betaT[c][t2 = r][t1]
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = v[k].x * sc + bet[k];
+}
+}  // namespace quad
+
+// pass 1 at L_low 64: block (chunk, y) takes the chunk's observations y,
+// y + gridDim.y, ... (the same for all its threads)
+__global__ __launch_bounds__(256) void k_fft_pass1_q(StepArgs p, const float2* __restrict__ yhat,
+                                                     const float2* __restrict__ xhat) {
+    using namespace quad;
+    extern __shared__ float2 sh[];
+    float2* tw = sh + BUF;
+    float2* red = tw + L / 2;
+    make_twiddles<L>(tw);
+    __syncthreads();
+    const int lt = threadIdx.x, r = lt >> 2, q = lt & 3, bq = quad_block(q);
+    const int64_t c0 = (int64_t)blockIdx.x * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    for (int64_t o = c0 + blockIdx.y; o < c1; o += gridDim.y) {
+        float m = -INFINITY, sm = 0.f;
+        for (int c = 0; c < p.KK; ++c) {
+            float s[NV];
+            score(p, yhat, xhat, o, c, sh, r, q, bq, tw, s);
+            float mc = -INFINITY;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) mc = fmaxf(mc, s[k]);
+            float sc = 0.f;
+            if (mc > -INFINITY) {
+#pragma unroll
+                for (int k = 0; k < NV; ++k) sc += s[k] > -INFINITY ? __expf(s[k] - mc) : 0.f;
+            }
+            lse_merge(m, sm, mc, sc);
+        }
+        // the lanes of each wave by shuffles, then the four waves through LDS
+        for (int off = 32; off > 0; off >>= 1) {
+            const float m2 = __shfl_xor(m, off), s2 = __shfl_xor(sm, off);
+            lse_merge(m, sm, m2, s2);
+        }
+        if ((lt & 63) == 0) red[lt >> 6] = make_float2(m, sm);
+        __syncthreads();
+        if (lt == 0) {
+            for (int w = 1; w < 4; ++w) lse_merge(m, sm, red[w].x, red[w].y);
+            p.part[o] = make_float2(m, sm);
+        }
+    }
+}
+
+// pass 2 at L_low 64: block (chunk, c), one component; partials written directly
+__global__ __launch_bounds__(256) void k_fft_pass2_q(StepArgs p, const float2* __restrict__ yhat,
+                                                     const float2* __restrict__ xhat, int /*TPC*/,
+                                                     float2* __restrict__ bpart,
+                                                     float* __restrict__ cpart) {
+    using namespace quad;
+    extern __shared__ float2 sh[];
+    float2* tw = sh + BUF;
+    make_twiddles<L>(tw);
+    __syncthreads();
+    const int lt = threadIdx.x, r = lt >> 2, q = lt & 3, bq = quad_block(q);
+    const int c = blockIdx.y;
+    const int64_t chunk = blockIdx.x;
+    const int64_t c0 = chunk * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    float2 ab[NV];   // sum of Y conj(W) at (k1 = r, k2 = 16 bq + k)
+    float acw[NV];   // posterior mass at (t1 = 16 bq + k, t2 = r)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) { ab[k] = make_float2(0.f, 0.f); acw[k] = 0.f; }
+    for (int64_t o = c0; o < c1; ++o) {
+        float s[NV];
+        score(p, yhat, xhat, o, c, sh, r, q, bq, tw, s);
+        const float lse = p.lse[o];
+        float2 v[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const float w = s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;
+            acw[k] += w;
+            v[k] = make_float2(w, 0.f);
+        }
+        // column t2 = r (its block 16 bq..), transformed along t1, then the rows
+        fft_quad_dif<L, false>(v, q, tw);                  // v[k] = k1 = 4k + q, column r
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[(4 * k + q) * (L + 1) + r] = v[k];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < NV; ++m) v[m] = sh[r * (L + 1) + 4 * m + q];   // row k1 = r, n2 = 4m + q
+        __syncthreads();
+        fft_quad_dit<L, false>(v, q, tw);                  // v[k] = W[r][16 bq + k]
+        // Y_o[r][16 bq + k], k and k + 1 in one 16-byte word of the paired layout
+        const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)o * (L / 2) + 8 * bq) * L + r;
+#pragma unroll
+        for (int k = 0; k < NV; k += 2) {
+            const float4 a = yr[(k / 2) * L];
+            const float2 t0 = cmulc(make_float2(a.x, a.y), v[k]);
+            const float2 t1 = cmulc(make_float2(a.z, a.w), v[k + 1]);
+            ab[k].x += t0.x; ab[k].y += t0.y;
+            ab[k + 1].x += t1.x; ab[k + 1].y += t1.y;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        bpart[((chunk * p.KK + c) * L + r) * L + 16 * bq + k] = ab[k];      // [k1][k2]
+        cpart[((chunk * p.KK + c) * L + 16 * bq + k) * L + r] = acw[k];     // [t1][t2]
     }
 }
 
@@ -387,8 +454,9 @@ __global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int6
 // ---------------------------------------------------------------- host side
 bool fft_supported(int LL) { return LL == 8 || LL == 16 || LL == 32 || LL == 64; }
 
-// teams of the two passes per block (2 LL lanes each)
-int fft_teams(int LL) { return 256 / (2 * LL); }
+// teams of the two passes per block (2 LL lanes each; at LL 64 one team of
+// four lanes per row)
+int fft_teams(int LL) { return LL == 64 ? 1 : 256 / (2 * LL); }
 
 // teams per component in pass 2 for KK components (a power of 2 dividing the teams)
 int fft_tpc(int LL, int KK) {
@@ -403,7 +471,7 @@ size_t fft_lds(int LL) {   // the two passes
         case 8: return fft::lds_pairs<8>();
         case 16: return fft::lds_pairs<16>();
         case 32: return fft::lds_pairs<32>();
-        case 64: return fft::lds_pairs<64>();
+        case 64: return fft::quad::lds();
     }
     return 0;
 }
@@ -413,7 +481,7 @@ const void* fft_pass2_fn(int LL) {
         case 8: return (const void*)fft::k_fft_pass2<8>;
         case 16: return (const void*)fft::k_fft_pass2<16>;
         case 32: return (const void*)fft::k_fft_pass2<32>;
-        case 64: return (const void*)fft::k_fft_pass2<64>;
+        case 64: return (const void*)fft::k_fft_pass2_q;
     }
     return nullptr;
 }
@@ -423,7 +491,7 @@ static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, con
                                 void* yhat, void* xhat, void* bpart, void* cpart, void* bh,
                                 double* bsum, double* csum, hipStream_t s) {
     const size_t lds = fft::lds_bytes<L>();      // preparation and X: one lane per row
-    const size_t lp = fft::lds_pairs<L>();       // the passes: two lanes per row
+    const size_t lp = L == 64 ? fft::quad::lds() : fft::lds_pairs<L>();   // the passes
     const int teams = 256 / L;
     switch (what) {
         case 0:   // prepare Y
@@ -436,16 +504,19 @@ static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, con
             hipLaunchKernelGGL(fft::k_fft_pack_x<L>, dim3(p.KK), dim3(256), lds, s, x, p.K, p.centre,
                                (float2*)xhat);
             break;
-        case 2:
-            (void)hipFuncSetAttribute((const void*)fft::k_fft_pass1<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
-            hipLaunchKernelGGL(fft::k_fft_pass1<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lp, s, p,
-                               (const float2*)yhat, (const float2*)xhat);
+        case 2: {
+            auto f = L == 64 ? fft::k_fft_pass1_q : fft::k_fft_pass1<L == 64 ? 32 : L>;
+            (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
+            hipLaunchKernelGGL(f, dim3(p.n_chunks, p.n_cg), dim3(256), lp, s, p, (const float2*)yhat,
+                               (const float2*)xhat);
             break;
+        }
         case 3: {
             const int tpc = fft_tpc(L, p.KK);
-            (void)hipFuncSetAttribute((const void*)fft::k_fft_pass2<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
-            hipLaunchKernelGGL(fft::k_fft_pass2<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lp, s, p,
-                               (const float2*)yhat, (const float2*)xhat, tpc, (float2*)bpart, (float*)cpart);
+            auto f = L == 64 ? fft::k_fft_pass2_q : fft::k_fft_pass2<L == 64 ? 32 : L>;
+            (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
+            hipLaunchKernelGGL(f, dim3(p.n_chunks, p.n_cg), dim3(256), lp, s, p, (const float2*)yhat,
+                               (const float2*)xhat, tpc, (float2*)bpart, (float*)cpart);
             break;
         }
         case 4: {

@@ -131,19 +131,73 @@ __device__ __forceinline__ void fft_pair_dif(float2 (&v)[L / 2], int h, const fl
     fft1t<L / 2, INV, 2>(v, tw);
 }
 
+// ---- four lanes per row (L = 64): lane q of a row holds a quarter of it.
+__device__ __forceinline__ float2 shfl_x(float2 a, int mask) {
+    return make_float2(__shfl_xor(a.x, mask), __shfl_xor(a.y, mask));
+}
+// the block of L/4 outputs (decimation in time) or inputs (in frequency) of lane q:
+// q with its two bits swapped
+__device__ __forceinline__ int quad_block(int q) { return ((q & 1) << 1) | (q >> 1); }
+
+// Decimation in time over the four lanes of a row: v holds x[4m + q]; on return
+// v[j] = X[(L/4) quad_block(q) + j].  Each lane transforms its quarter, then
+// two radix-2 stages across lanes: q with q ^ 2 form the length-L/2 transforms
+// E_p of the samples 2n + p (p = q & 1; lane q < 2 keeps E_p[j], lane q >= 2
+// E_p[j + L/4]), and q with q ^ 1 form X[k] = E_0[k] +- W_L^k E_1[k].
+template <int L, bool INV>
+__device__ __forceinline__ void fft_quad_dit(float2 (&v)[L / 4], int q, const float2* __restrict__ tw) {
+    constexpr int N = L / 4;
+    fft1t<N, INV, 4>(v, tw);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const float2 o = shfl_x(v[j], 2);
+        const float2 lo = q < 2 ? v[j] : o, hi = q < 2 ? o : v[j];
+        float2 w = tw[2 * j];                     // W_{L/2}^j
+        if (INV) w.y = -w.y;
+        const float2 t = cmul(hi, w);
+        v[j] = q < 2 ? make_float2(lo.x + t.x, lo.y + t.y) : make_float2(lo.x - t.x, lo.y - t.y);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const float2 o = shfl_x(v[j], 1);
+        const float2 e0 = (q & 1) ? o : v[j], e1 = (q & 1) ? v[j] : o;
+        float2 w = tw[N * (q >> 1) + j];          // W_L^k, k = (L/4)(q >> 1) + j
+        if (INV) w.y = -w.y;
+        const float2 t = cmul(e1, w);
+        v[j] = (q & 1) ? make_float2(e0.x - t.x, e0.y - t.y) : make_float2(e0.x + t.x, e0.y + t.y);
+    }
+}
+// Decimation in frequency, the mirror: v holds x[(L/4) quad_block(q) + j]; on
+// return v[j] = X[4j + q].  q with q ^ 1 split n and n + L/2 into the sums
+// (even outputs) and the twiddled differences (odd outputs), q with q ^ 2 do
+// the same within each length-L/2 sequence, then each lane transforms its quarter.
+template <int L, bool INV>
+__device__ __forceinline__ void fft_quad_dif(float2 (&v)[L / 4], int q, const float2* __restrict__ tw) {
+    constexpr int N = L / 4;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const float2 o = shfl_x(v[j], 1);
+        const float2 a = (q & 1) ? o : v[j], b = (q & 1) ? v[j] : o;
+        float2 w = tw[N * (q >> 1) + j];          // W_L^n, n = (L/4)(q >> 1) + j
+        if (INV) w.y = -w.y;
+        v[j] = (q & 1) ? cmul(make_float2(a.x - b.x, a.y - b.y), w) : make_float2(a.x + b.x, a.y + b.y);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const float2 o = shfl_x(v[j], 2);
+        const float2 a = (q >> 1) ? o : v[j], b = (q >> 1) ? v[j] : o;
+        float2 w = tw[2 * j];                     // W_{L/2}^j
+        if (INV) w.y = -w.y;
+        v[j] = (q >> 1) ? cmul(make_float2(a.x - b.x, a.y - b.y), w) : make_float2(a.x + b.x, a.y + b.y);
+    }
+    fft1t<N, INV, 4>(v, tw);
+}
+
 __device__ __forceinline__ void team_sync() {
     __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
     __builtin_amdgcn_wave_barrier();
 }
 
-// A team of 2L lanes (two per row) spans more than one wave for L = 64: its
-// LDS traffic is then ordered by the block barrier, which every team of the
-// block must reach the same number of times.
-template <int L> constexpr bool kPairWide = 2 * L > 64;
-template <int L> __device__ __forceinline__ void pair_sync() {
-    if constexpr (kPairWide<L>) __syncthreads();
-    else team_sync();
-}
 
 // Row transforms of v (this thread's row r), then column transforms through the
 // team buffer buf [L][L + 1]; on return v holds column r of the 2-D transform
