@@ -253,7 +253,7 @@ def bench_batched(args):
         forms[key] = dict(pairs_per_s=pairs / (ms * 1e-3), ms_per_step=ms, iterations_in_graph=iters)
         if tune:
             forms[key]["tune_seconds"] = be.tune_seconds
-            tuning[key] = [dict(L_low=t["L_low"], K=t["K"], form=t["form"], item_obs=t["item_obs"])
+            tuning[key] = [dict(L_low=t["L_low"], K=t["K"], form=t["form"], item_obs=t["item_obs"], tile=t.get("tile", 0))
                            for t in be.tuning]
         print(f"[bench] batched {key}: {ms:.2f} ms/step", file=sys.stderr, flush=True)
         del g, be

@@ -235,19 +235,25 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision,
  * BF16 split plan -- with `item_obs` observations per work item
  * (rounded up to the form's observation tile; 0 keeps the default of about
  * 2^28 multiply-adds per item, smaller -- down to 2^24 -- where that leaves
- * the problem fewer than 128 items per component group).  Entries of another precision are ignored;
- * the first matching entry wins.  A problem's result depends on its own
- * entry only (form and partition), never on the rest of the plan. */
+ * the problem fewer than 128 items per component group), and with the block
+ * tile `tile` where the form has a choice: for the BF16 split at L_low 16,
+ * the component slots WC of a workgroup (1, 2 or 4: a workgroup covers
+ * 32 / WC observations and 4 WC components); 0 keeps the default (WC from
+ * K^2).  Entries of another precision are ignored; the first matching entry
+ * wins.  A problem's result depends on its own entry only (form, partition
+ * and tile), never on the rest of the plan. */
 typedef struct srmra_tuning {
     int precision;
     int L_low, K;
     int form;
     int64_t item_obs;
+    int tile;
 } srmra_tuning;
 
 /* srmra_plan_create with a tuning table (`table` may be NULL when n_table is
- * 0, which is srmra_plan_create).  SRMRA_EINVAL for a negative item_obs or a
- * form the plan's precision does not allow; SRMRA_EUNSUPPORTED for a BF16
+ * 0, which is srmra_plan_create).  SRMRA_EINVAL for a negative item_obs, a
+ * tile other than 0 where the entry's form and L_low have no choice or a tile
+ * outside that choice, or a form the plan's precision does not allow; SRMRA_EUNSUPPORTED for a BF16
  * entry at an L_low without a BF16 kernel.  The prepared buffer of every
  * problem must suit the form it runs in (a BF16 split preparation also
  * serves SRMRA_FP32_MFMA). */

@@ -10,7 +10,11 @@ the fastest:
 * observations per work item, as multiples of the library's default (about
   2^28 multiply-adds per item, down to 2^24 where that gives a problem fewer
   than 128 chunks): smaller items balance the persistent launch
-  better, larger ones write fewer per-chunk partials.
+  better, larger ones write fewer per-chunk partials;
+* the block tile where the form has a choice (the BF16 split at L_low 16: a
+  workgroup of 32 / WC observations x 4 WC components, WC in {1, 2, 4}),
+  timed at the default item size before the item sizes are swept at the best
+  tile.
 
 Timing runs one EM step of the class alone per candidate, on scratch copies of
 the iterates (the problems' own iterates are left unchanged), with HIP events
@@ -36,6 +40,13 @@ def candidate_forms(precision: int, L_low: int) -> List[int]:
     if base in (B.SRMRA_BF16_SPLIT3, B.SRMRA_BF16_SPLIT4):
         return [base, B.SRMRA_FP32_MFMA]
     return [base]
+
+
+def candidate_tiles(form: int, L_low: int) -> List[int]:
+    """Block tiles the form offers at this L_low (0: the library's default only)."""
+    if form in (B.SRMRA_BF16_SPLIT3, B.SRMRA_BF16_SPLIT4) and L_low == 16:
+        return [1, 2, 4]
+    return [0]
 
 
 def _scratch(pr: dict) -> dict:
@@ -87,15 +98,26 @@ def tune(problems: Sequence[dict], precision, scales=SCALES, reps: int = 3, warm
         for form in candidate_forms(p, Ll):
             base = B.srmra_plan_default_item_obs(n_max, Ll, K, form)
             seen = set()
+
+            def trial(item, tile):
+                nonlocal best
+                entry = dict(precision=p, L_low=Ll, K=K, form=form, item_obs=item, tile=tile)
+                ms = _time_plan(scratch, p, entry, reps, warmup, stream)
+                report.append(dict(entry, ms=ms, problems=len(idx)))
+                if best is None or ms < best[0]:
+                    best = (ms, entry)
+                return ms
+
+            tiles = candidate_tiles(form, Ll)
+            tile = tiles[0]
+            if len(tiles) > 1:
+                tile = min(tiles, key=lambda t: trial(base, t))
+                seen.add(base)
             for sc in scales:
                 item = max(1, int(round(base * sc)))
                 if item in seen:
                     continue
                 seen.add(item)
-                entry = dict(precision=p, L_low=Ll, K=K, form=form, item_obs=item)
-                ms = _time_plan(scratch, p, entry, reps, warmup, stream)
-                report.append(dict(entry, ms=ms, problems=len(idx)))
-                if best is None or ms < best[0]:
-                    best = (ms, entry)
+                trial(item, tile)
         table.append(best[1])
     return table, report

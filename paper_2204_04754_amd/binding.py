@@ -57,7 +57,7 @@ class srmra_problem(ctypes.Structure):
 
 class srmra_tuning(ctypes.Structure):
     _fields_ = [("precision", _int), ("L_low", _int), ("K", _int), ("form", _int),
-                ("item_obs", _i64)]
+                ("item_obs", _i64), ("tile", _int)]
 
 
 def lib():
@@ -260,7 +260,7 @@ class Plan:
     """Owner of an srmra_plan* (host object) plus the problem structs."""
 
     def __init__(self, problems: Sequence[dict], precision, tuning: Optional[Sequence[dict]] = None):
-        """tuning: entries {precision, L_low, K, form, item_obs} (srmra_tuning)."""
+        """tuning: entries {precision, L_low, K, form, item_obs[, tile]} (srmra_tuning)."""
         arr = (srmra_problem * len(problems))()
         for k, pr in enumerate(problems):
             s = arr[k]
@@ -283,6 +283,7 @@ class Plan:
                 tab[k].precision = _prec(t["precision"])
                 tab[k].L_low = int(t["L_low"]); tab[k].K = int(t["K"])
                 tab[k].form = _prec(t["form"]); tab[k].item_obs = int(t["item_obs"])
+                tab[k].tile = int(t.get("tile", 0))
             _check(lib().srmra_plan_create_tuned(arr, len(problems), _prec(precision), tab,
                                                  len(tuning), ctypes.byref(h), ctypes.byref(ws)),
                    "srmra_plan_create_tuned")

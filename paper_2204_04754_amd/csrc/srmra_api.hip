@@ -33,7 +33,7 @@ bool mfma_geom(int LL, int& cpw, int& nt, size_t& lds1, size_t& lds2, const void
 bool mfma_fused_geom(int LL, int KK, int& wc, int& nt, size_t& lds, const void*& f);
 bool valu_geom(int LL, int KK, int& cpb, int& nt, size_t& lds1, size_t& lds2, const void*& f1,
                const void*& f2);
-bool bf16_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds1, size_t& lds2,
+bool bf16_geom(int LL, int KK, int np, int tile, int& cpb, int& nt, size_t& lds1, size_t& lds2,
                const void*& f1, const void*& f2);
 bool bf16_fused_geom(int LL, int KK, int np, size_t& lds, const void*& f);
 hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
@@ -127,7 +127,7 @@ struct Geom {
 };
 
 int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
-              int64_t chunk_override = 0) {
+              int64_t chunk_override = 0, int tile = 0) {
     if (N < 1 || N > (int64_t)INT32_MAX || K < 1 || LL < 1) return SRMRA_EINVAL;
     if (!supported_ll(LL)) return SRMRA_EUNSUPPORTED;
     if ((int64_t)K * LL > 4096 || K * K > 256) return SRMRA_EUNSUPPORTED;
@@ -152,7 +152,7 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
             f2 = ff;
         }
     } else if (is_bf16(prec)) {
-        ok = bf16_geom(LL, g.KK, split_products(prec), g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
+        ok = bf16_geom(LL, g.KK, split_products(prec), tile, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
         size_t lds = 0;
         const void* ff = nullptr;
         if (ok && bf16_fused_geom(LL, g.KK, split_products(prec), lds, ff)) {
@@ -644,6 +644,9 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         const srmra_tuning& t = table[k];
         if (t.item_obs < 0) return SRMRA_EINVAL;
         if (t.precision != precision) continue;
+        // a block tile only where the form has a choice (BF16 split at L_low 16)
+        if (t.tile != 0 && !(is_bf16(t.form) && t.L_low == 16 && (t.tile == 1 || t.tile == 2 || t.tile == 4)))
+            return SRMRA_EINVAL;
         const bool ok = t.form == precision || (is_bf16(precision) && t.form == SRMRA_FP32_MFMA);
         if (!ok) return SRMRA_EINVAL;
         if (is_bf16(t.form) && !is_bf16_form(form_of(t.form, t.L_low))) return SRMRA_EUNSUPPORTED;
@@ -665,20 +668,22 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         if (st != SRMRA_OK) { delete P; return st; }
         int f = form_of(precision, pr.L_low);
         int64_t item_obs = 0;
+        int tile = 0;
         for (int k = 0; k < n_table; ++k) {   // first matching entry wins
             const srmra_tuning& t = table[k];
             if (t.precision == precision && t.L_low == pr.L_low && t.K == pr.K) {
                 f = form_of(t.form, pr.L_low);
                 item_obs = t.item_obs;
+                tile = t.tile;
                 break;
             }
         }
         const int fprec = prec_of_form(f);
         Geom g0;
-        st = make_geom(pr.N, pr.L_low, pr.K, fprec, false, g0);
+        st = make_geom(pr.N, pr.L_low, pr.K, fprec, false, g0, 0, tile);
         if (st != SRMRA_OK) { delete P; return st; }
         Geom g;
-        make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, item_obs > 0 ? item_obs : default_chunk(g0));
+        make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, item_obs > 0 ? item_obs : default_chunk(g0), tile);
         if (pr.prep_bytes < g.prep_bytes) { delete P; return SRMRA_EWORKSPACE; }
         if (f == FORM_MFMA && g.fuse_wc) f = FORM_FUSED;
         if (g.fuse_bf16) f = f == FORM_BF16X4 ? FORM_BF16X4F : FORM_BF16F;

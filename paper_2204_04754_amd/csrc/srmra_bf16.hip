@@ -288,12 +288,15 @@ bool bf16_fused_geom(int LL, int KK, int np, size_t& lds, const void*& f) {
     return false;
 }
 
-bool bf16_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds1, size_t& lds2,
+bool bf16_geom(int LL, int KK, int np, int tile, int& cpb, int& nt, size_t& lds1, size_t& lds2,
                const void*& f1, const void*& f2) {
     cpb = 4;
     nt = 8;
+    // tile: the block layout where the form has a choice (L_low 16: component
+    // slots WC in {1, 2, 4}); 0 = the default
+    if (tile != 0 && !(LL == 16 && (tile == 1 || tile == 2 || tile == 4))) return false;
     if (LL == 16) {
-        const int wc = b16s::wc_of(KK);
+        const int wc = tile ? tile : b16s::wc_of(KK);
         cpb = 4 * wc;
         nt = 8 * (4 / wc);
         lds1 = b16s::lds_pass1();

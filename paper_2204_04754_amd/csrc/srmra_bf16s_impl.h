@@ -70,8 +70,12 @@ __device__ __forceinline__ void pack_xb_body(const StepArgs& p, const float* __r
     dst[64 + lane] = __builtin_bit_cast(uint4, l);
 }
 
-// block layout for K^2 components: component slots per block 4 WC
+// block layout: WC component slots of 4 components per block (WC in {1, 2, 4};
+// a block then covers 8 (4 / WC) observations and 4 WC components).  The
+// default for K^2 components; the plan's tuning table may pick another, and
+// the kernels read it from p.cpb = 4 WC.
 __host__ __device__ inline int wc_of(int KK) { return KK <= 4 ? 1 : (KK <= 8 ? 2 : 4); }
+__device__ __forceinline__ int wc_in(const StepArgs& p) { return p.cpb >> 2; }
 
 // yT of the block's observations [o0, o0 + 8 WO) into LDS st[o][plane][col][SP]
 __device__ __forceinline__ void stage_yT(const Prep& q, int64_t N, int64_t o0, int nob, __bf16* st) {
@@ -190,7 +194,7 @@ __device__ __forceinline__ void lane_bias(const StepArgs& p, const int (&cgl)[4]
 // = observation slot wo, component slot wc.
 __device__ __forceinline__ void wave_slots(const StepArgs& p, int cgroup, int& wo, int& wc, int (&cgl)[4],
                                            int (&cgc)[4], int& WO) {
-    const int WC = wc_of(p.KK);
+    const int WC = wc_in(p);
     WO = 4 / WC;
     const int wave = threadIdx.x >> 6;
     wo = wave % WO;
@@ -215,7 +219,7 @@ __device__ __forceinline__ void pass1_body(const StepArgs& p, const Prep& q, int
     const int nob = 8 * WO;
     const int64_t c0 = (int64_t)chunk * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    const int slot = cgroup * wc_of(p.KK) + wc;           // partial index of this wave's components
+    const int slot = cgroup * wc_in(p) + wc;              // partial index of this wave's components
     for (int64_t o0 = c0; o0 < c1; o0 += nob) {
         __syncthreads();
         stage_yT(q, p.N, o0, nob, st);
@@ -339,7 +343,7 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const Prep& q, int
     }
     __syncthreads();
     // per-chunk partials: the WO waves of each component slot summed in order
-    const int WC = wc_of(p.KK);
+    const int WC = wc_in(p);
     for (int e = threadIdx.x; e < WC * 4 * LL * LL; e += 256) {
         const int s = e / (4 * LL * LL), r = e % (4 * LL * LL);   // s = component slot wc
         const int c = r / (LL * LL), qq = r % (LL * LL);

@@ -133,8 +133,10 @@ def test_tuning_table_validated_on_host(L):
 
     def create(precision, entries):
         tab = (B.srmra_tuning * len(entries))()
-        for k, (prec, ll, K, form, item) in enumerate(entries):
+        for k, e in enumerate(entries):
+            prec, ll, K, form, item = e[:5]
             tab[k].precision, tab[k].L_low, tab[k].K, tab[k].form, tab[k].item_obs = prec, ll, K, form, item
+            tab[k].tile = e[5] if len(e) > 5 else 0
         h, ws = ctypes.c_void_p(), ctypes.c_size_t()
         st = L.srmra_plan_create_tuned(prob, 1, precision, tab, len(entries), ctypes.byref(h), ctypes.byref(ws))
         if st == B.SRMRA_OK:
@@ -152,6 +154,14 @@ def test_tuning_table_validated_on_host(L):
     assert create(BF, [(BF, 32, 2, F32, 100)]) == B.SRMRA_OK
     assert create(BF, [(F32, 32, 2, F32, 100)]) == B.SRMRA_OK       # other precision: ignored
     assert create(F32, [(F32, 32, 2, F32, 37)]) == B.SRMRA_OK
+    # block tiles: only the BF16 split at L_low 16 has a choice (WC in {1, 2, 4})
+    p.L_low, p.K = 16, 2
+    for wc in (1, 2, 4):
+        assert create(BF, [(BF, 16, 2, BF, 0, wc)]) == B.SRMRA_OK
+    assert create(BF, [(BF, 16, 2, BF, 0, 3)]) == B.SRMRA_EINVAL
+    assert create(BF, [(BF, 16, 2, F32, 0, 2)]) == B.SRMRA_EINVAL     # FP32 MFMA: no choice
+    assert create(BF, [(BF, 32, 2, BF, 0, 2)]) == B.SRMRA_EINVAL      # L_low 32: no choice
+    assert create(F32, [(F32, 16, 2, F32, 0, 1)]) == B.SRMRA_EINVAL
     assert B.srmra_plan_default_item_obs(1000, 32, 2, "fp32_mfma") > 0
 
 

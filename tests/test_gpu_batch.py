@@ -132,3 +132,24 @@ def test_tuning_entry_selects_form_and_partition():
     for k in ("x_new", "rho_new", "log_rho_new", "loglik"):
         assert np.array_equal(np.asarray(ra[k]), np.asarray(rb[k])), k
     assert np.max(np.abs(ra["x_new"] - rc["x_new"])) < 1e-4 * np.max(np.abs(rc["x_new"]))
+
+
+@pytest.mark.parametrize("tile", [1, 2, 4])
+def test_bf16_block_tile_at_l16_matches_oracle(tile):
+    """Every block tile of the BF16 split at L_low 16 (a workgroup of 32 / WC
+    observations x 4 WC components) gives the step to the split's bound, with
+    K^2 = 4, 9 and 16 components (idle component slots where 4 WC > K^2) and a
+    ragged N."""
+    from paper_2204_04754_amd import binding as B
+    shapes = [(32, 2, 203, 0.9), (48, 3, 157, 1.1), (64, 4, 131, 1.3)]
+    ins = _instances(shapes, config=75)
+    tab = [dict(precision=B.SRMRA_BF16_SPLIT3, L_low=16, K=K, form=B.SRMRA_BF16_SPLIT3, item_obs=0, tile=tile)
+           for (_, K, _, _) in shapes]
+    be = BatchedEM(ins, precision="bf16_split3", tuning=tab)
+    be.step()
+    torch.cuda.synchronize()
+    for j, d in enumerate(ins):
+        inst = d["inst"]
+        g = be.results(j)
+        ref = O.em_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, return_details=True)
+        check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, u=U_SPLIT)
