@@ -31,11 +31,10 @@ def test_dft2_matches_numpy(L):
     assert rel(g[..., 0] + 1j * g[..., 1], ref) < 2e-6
 
 
-# L_low 64 (teams of two waves): K 1 (two teams per component), K 2, and K 3
-# (K^2 = 9: the last component group has a team without a component); odd N
-# leaves a team without an observation at the end of a chunk
+# L_low 64 (one team of four lanes per row per block): K 1, 2 and 3, odd N,
+# and N = 1
 SHAPES = [(16, 2, 37), (32, 2, 29), (64, 2, 17), (64, 4, 11), (96, 3, 5), (128, 4, 9),
-          (32, 1, 7), (32, 4, 53), (48, 3, 13), (64, 1, 9), (128, 2, 5), (192, 3, 13)]
+          (32, 1, 7), (32, 4, 53), (48, 3, 13), (64, 1, 9), (128, 2, 5), (192, 3, 13), (64, 1, 1)]
 
 
 @pytest.mark.parametrize("Lh,K,N", SHAPES)
@@ -88,14 +87,15 @@ def test_fft_delta_prior():
     assert abs(g["loglik"] - ref["loglik"]) < 1e-3 * abs(ref["loglik"])
 
 
-def test_fft_largest_grid():
-    """L_low 32 with K 16 (K^2 = 256 components, the library's limit): the
-    oracle's loop over 2^18 shifts is slow here, so properties that hold at
-    any size are checked (posteriors sum to 1, rho rows sum to 1, loglik is
-    the sum of its terms, x' a posterior average of observed values or x,
-    determinism)."""
+@pytest.mark.parametrize("Lh", [512, 1024])
+def test_fft_largest_grid(Lh):
+    """L_low 32 and 64 with K 16 (K^2 = 256 components, the library's limit;
+    Lh 1024 is the largest grid): the oracle's loop over Lh^2 shifts is slow
+    here, so properties that hold at any size are checked (posteriors sum to
+    1, rho rows sum to 1, loglik is the sum of its terms, x' a posterior
+    average of observed values or x, determinism)."""
     N = 7
-    inst = synth.make_instance(512, 16, N, 20.0, config=91)
+    inst = synth.make_instance(Lh, 16, N, 20.0, config=91)
     g = gpu_step(inst.y, inst.x0, inst.log_rho0, 20.0, 16, "fp32_fft")
     assert abs(g["c"].sum() - N) <= 1e-5 * N
     assert np.allclose(g["rho_new"].sum(axis=1), 1.0, atol=1e-6)
