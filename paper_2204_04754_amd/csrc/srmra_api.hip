@@ -10,6 +10,7 @@
 #include <algorithm>
 
 #include "../../include/srmra.h"
+#include "srmra_aux_impl.h"
 #include "srmra_batch.h"
 #include "srmra_common.h"
 #include "srmra_moments.h"
@@ -337,7 +338,7 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
         mark(4);
     }
     const int per = g.KK * LL * LL;
-    hipLaunchKernelGGL(k_reduce_partials, dim3((per + 255) / 256), dim3(256), 0, stream,
+    hipLaunchKernelGGL(k_reduce_partials, dim3((per + kReduceElems - 1) / kReduceElems), dim3(256), 0, stream,
                        (const float*)p.bpart, (const float*)p.cpart, g.n_chunks, per,
                        (double*)(ws + g.o_bsum), (double*)(ws + g.o_csum));
     if (hipGetLastError() != hipSuccess) return SRMRA_EDEVICE;
@@ -721,7 +722,7 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         for (int k = 0; k < g.n_ll; ++k)
             (single_pass_form(f) ? combine_late : P->combine_items).push_back(make_int2(i, k));
         const int per = g.KK * g.LL * g.LL;
-        for (int k = 0; k < (per + 255) / 256; ++k) P->reduce_items.push_back(make_int2(i, k));
+        for (int k = 0; k < (per + kReduceElems - 1) / kReduceElems; ++k) P->reduce_items.push_back(make_int2(i, k));
     }
     P->n_combine_early = (int)P->combine_items.size();
     P->combine_items.insert(P->combine_items.end(), combine_late.begin(), combine_late.end());

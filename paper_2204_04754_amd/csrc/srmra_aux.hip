@@ -42,7 +42,8 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const float* __restrict
                                                          int n_chunks, int per_chunk,
                                                          double* __restrict__ bsum,
                                                          double* __restrict__ csum) {
-    reduce_partials_body(bpart, cpart, n_chunks, per_chunk, bsum, csum, blockIdx.x);
+    __shared__ double red[512];
+    reduce_partials_body(bpart, cpart, n_chunks, per_chunk, bsum, csum, blockIdx.x, red);
 }
 
 __global__ __launch_bounds__(1024) void k_finalize(const double* __restrict__ bsum,

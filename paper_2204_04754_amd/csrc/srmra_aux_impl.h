@@ -154,20 +154,42 @@ __device__ __forceinline__ void lse_combine_body(const float2* __restrict__ part
 
 // ---------------------------------------------------------------- a5: finalize
 // Stage 1: FP64 sums of the per-chunk partials, one thread per (component, index).
+// FP64 reduction of per-chunk partials: elements per workgroup (its 256
+// threads form 256 / kReduceElems slices, each summing every slice-th chunk)
+constexpr int kReduceElems = 32;
+constexpr int kReduceSlices = 256 / kReduceElems;
+
+// Workgroup blk takes elements [kReduceElems blk, +kReduceElems); slice s of
+// its threads sums the chunks s, s + kReduceSlices, ... in order, and the slice
+// sums are added in slice order: a fixed order, independent of scheduling.
+// red: 2 x 256 doubles of LDS.
 __device__ __forceinline__ void reduce_partials_body(const float* __restrict__ bpart,
                                                      const float* __restrict__ cpart,
                                                      int n_chunks, int per_chunk,
                                                      double* __restrict__ bsum,
-                                                     double* __restrict__ csum, int blk) {
-    const int e = blk * 256 + threadIdx.x;
-    if (e >= per_chunk) return;
+                                                     double* __restrict__ csum, int blk,
+                                                     double* red) {
+    const int le = threadIdx.x % kReduceElems, sl = threadIdx.x / kReduceElems;
+    const int e = blk * kReduceElems + le;
     double sb = 0.0, sc = 0.0;
-    for (int k = 0; k < n_chunks; ++k) {
-        sb += (double)bpart[(int64_t)k * per_chunk + e];
-        sc += (double)cpart[(int64_t)k * per_chunk + e];
+    if (e < per_chunk) {
+        for (int k = sl; k < n_chunks; k += kReduceSlices) {
+            sb += (double)bpart[(int64_t)k * per_chunk + e];
+            sc += (double)cpart[(int64_t)k * per_chunk + e];
+        }
     }
-    bsum[e] = sb;
-    csum[e] = sc;
+    red[threadIdx.x] = sb;
+    red[256 + threadIdx.x] = sc;
+    __syncthreads();
+    if (sl == 0 && e < per_chunk) {
+        double tb = 0.0, tc = 0.0;
+        for (int s = 0; s < kReduceSlices; ++s) {
+            tb += red[s * kReduceElems + le];
+            tc += red[256 + s * kReduceElems + le];
+        }
+        bsum[e] = tb;
+        csum[e] = tc;
+    }
 }
 
 // Stage 2 (one block): A_c = sum_t c_(c,t); x_new[c1 + q1 K][c2 + q2 K] = b_c[q]/A_c + mu

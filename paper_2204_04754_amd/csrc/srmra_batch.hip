@@ -60,10 +60,11 @@ __global__ __launch_bounds__(256) void k_batch_combine(const InstDesc* __restric
 
 __global__ __launch_bounds__(256) void k_batch_reduce(const InstDesc* __restrict__ D,
                                                       const int2* __restrict__ items) {
+    __shared__ double red[512];
     const int2 it = items[blockIdx.x];
     const InstDesc& d = D[it.x];
     reduce_partials_body(d.p.bpart, d.p.cpart, d.p.n_chunks, d.p.KK * d.LL * d.LL, d.bsum, d.csum,
-                         it.y);
+                         it.y, red);
 }
 
 __global__ __launch_bounds__(1024) void k_batch_finalize(const InstDesc* __restrict__ D) {

@@ -14,6 +14,7 @@
 // component of little posterior mass the rounding error of its heavier
 // partner.  The transforms are the in-register team FFTs of srmra_fft_impl.h
 // (O(L^2 log L) per pair instead of the dense 4 L^4).
+#include "srmra_aux_impl.h"
 #include "srmra_common.h"
 #include "srmra_fft_impl.h"
 
@@ -406,17 +407,34 @@ __global__ __launch_bounds__(256) void k_fft_reduce(const float2* __restrict__ b
                                                     const float* __restrict__ cpart, int n_chunks,
                                                     int per, double2* __restrict__ bh,
                                                     double* __restrict__ csum) {
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= per) return;
+    // the chunk slices of reduce_partials_body, for complex b
+    __shared__ double red[3 * 256];
+    const int le = threadIdx.x % kReduceElems, sl = threadIdx.x / kReduceElems;
+    const int e = blockIdx.x * kReduceElems + le;
     double2 sb = make_double2(0.0, 0.0);
     double sc = 0.0;
-    for (int k = 0; k < n_chunks; ++k) {
-        const float2 b = bpart[(int64_t)k * per + e];
-        sb.x += b.x; sb.y += b.y;
-        sc += cpart[(int64_t)k * per + e];
+    if (e < per) {
+        for (int k = sl; k < n_chunks; k += kReduceSlices) {
+            const float2 b = bpart[(int64_t)k * per + e];
+            sb.x += b.x; sb.y += b.y;
+            sc += cpart[(int64_t)k * per + e];
+        }
     }
-    bh[e] = sb;
-    csum[e] = sc;
+    red[threadIdx.x] = sb.x;
+    red[256 + threadIdx.x] = sb.y;
+    red[512 + threadIdx.x] = sc;
+    __syncthreads();
+    if (sl == 0 && e < per) {
+        double2 tb = make_double2(0.0, 0.0);
+        double tc = 0.0;
+        for (int s = 0; s < kReduceSlices; ++s) {
+            tb.x += red[s * kReduceElems + le];
+            tb.y += red[256 + s * kReduceElems + le];
+            tc += red[512 + s * kReduceElems + le];
+        }
+        bh[e] = tb;
+        csum[e] = tc;
+    }
 }
 
 // ---- direct FP64 inverse DFT of the back-projection: bsum[c][q1 L + q2] (the
@@ -521,7 +539,7 @@ static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, con
         }
         case 4: {
             const int per = p.KK * L * L;
-            hipLaunchKernelGGL(fft::k_fft_reduce, dim3((per + 255) / 256), dim3(256), 0, s, (const float2*)bpart,
+            hipLaunchKernelGGL(fft::k_fft_reduce, dim3((per + kReduceElems - 1) / kReduceElems), dim3(256), 0, s, (const float2*)bpart,
                                (const float*)cpart, p.n_chunks, per, (double2*)bh, csum);
             hipLaunchKernelGGL(fft::k_fft_idft<L>, dim3((L * L + 255) / 256, p.KK), dim3(256), 0, s,
                                (const double2*)bh, bsum);
