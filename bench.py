@@ -54,9 +54,9 @@ TRAFFIC = {
     ("lh64_k2_n100000", "fp32_mfma", "k_fused_mfma<32>"):
         dict(bytes=428061491, src=_MFMA_SRC, sha="afe068a4c07ebf90"),
     ("lh128_k4_n200000_s0.5", "bf16_split3", "k_backproject_bf16<32, 3>"):
-        dict(bytes=1679487898, src=_BF16_SRC, sha="62873be3e1f50c4f"),
+        dict(bytes=1667584512, src=_BF16_SRC, sha="6ff1042a104f29b1"),
     ("lh256_k4_n20000", "bf16_split3", "b16w::k_backproject<64, 3>"):
-        dict(bytes=7701069517, src=_BF16W_SRC, sha="a561b2f34204f5b9"),
+        dict(bytes=7369647616, src=_BF16W_SRC, sha="f7205148b449a689"),
 }
 
 
