@@ -253,10 +253,10 @@ typedef struct srmra_tuning {
 /* srmra_plan_create with a tuning table (`table` may be NULL when n_table is
  * 0, which is srmra_plan_create).  SRMRA_EINVAL for a negative item_obs, a
  * tile other than 0 where the entry's form and L_low have no choice or a tile
- * outside that choice, or a form the plan's precision does not allow; SRMRA_EUNSUPPORTED for a BF16
- * entry at an L_low without a BF16 kernel.  The prepared buffer of every
- * problem must suit the form it runs in (a BF16 split preparation also
- * serves SRMRA_FP32_MFMA). */
+ * outside that choice, or a form the plan's precision does not allow;
+ * SRMRA_EUNSUPPORTED for a BF16 entry at an L_low without a BF16 kernel.  The
+ * prepared buffer of every problem must suit the form it runs in (a BF16
+ * split preparation also serves SRMRA_FP32_MFMA). */
 int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision,
                             const srmra_tuning* table, int n_table,
                             srmra_plan** plan, size_t* workspace_bytes);
