@@ -9,7 +9,7 @@
 // per component (observations split over TPC teams), w = exp(a - LSE_i), its
 // DFT, the frequency-domain sum of the back-projection and the spatial sum of
 // w; per-chunk FP32 partials, summed in FP64, the former brought back by a
-// direct FP64 inverse DFT.  One component per
+// separable FP64 inverse DFT.  One component per
 // transform: packing two real signals into one complex transform would give a
 // component of little posterior mass the rounding error of its heavier
 // partner.  The transforms are the in-register team FFTs of srmra_fft_impl.h
@@ -437,27 +437,43 @@ __global__ __launch_bounds__(256) void k_fft_reduce(const float2* __restrict__ b
     }
 }
 
-// ---- direct FP64 inverse DFT of the back-projection: bsum[c][q1 L + q2] (the
-// layout the finalize kernel reads); grid (ceil(L^2 / 256), KK)
+// ---- FP64 inverse DFT of the back-projection, one workgroup per component,
+// separable: T[k1][q2] = sum_k2 B[k1][k2] w^(k2 q2) into LDS, then
+// bsum[c][q1 L + q2] = Re sum_k1 T[k1][q2] w^(k1 q1) / L^2 (w = exp(2 pi i / L);
+// the layout the finalize kernel reads).  Dynamic LDS: idft_lds<L>() bytes.
+template <int L> constexpr size_t idft_lds() { return sizeof(double2) * L * L + 2 * sizeof(double) * L; }
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_idft(const double2* __restrict__ bh,
                                                   double* __restrict__ bsum) {
-    __shared__ double cs[L], sn[L];
+    extern __shared__ double2 T[];                       // [L][L]
+    double* cs = reinterpret_cast<double*>(T + L * L);   // [L]
+    double* sn = cs + L;                                 // [L]
     if (threadIdx.x < L) sincospi(2.0 * (double)threadIdx.x / (double)L, &sn[threadIdx.x], &cs[threadIdx.x]);
     __syncthreads();
-    const int c = blockIdx.y;
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    if (q >= L * L) return;
-    const int q1 = q / L, q2 = q % L;
+    const int c = blockIdx.x;
     const double2* B = bh + (int64_t)c * L * L;
-    double rb = 0.0;
-    for (int k1 = 0; k1 < L; ++k1)
+    for (int e = threadIdx.x; e < L * L; e += 256) {
+        const int k1 = e / L, q2 = e % L;
+        double re = 0.0, im = 0.0;
         for (int k2 = 0; k2 < L; ++k2) {
-            const int m = (k1 * q1 + k2 * q2) % L;   // exp(+2 pi i m / L)
+            const int m = (k2 * q2) & (L - 1);
             const double2 b = B[k1 * L + k2];
-            rb += b.x * cs[m] - b.y * sn[m];
+            re += b.x * cs[m] - b.y * sn[m];
+            im += b.x * sn[m] + b.y * cs[m];
         }
-    bsum[(int64_t)c * L * L + q] = rb * (1.0 / (double)(L * L));
+        T[e] = make_double2(re, im);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < L * L; e += 256) {
+        const int q1 = e / L, q2 = e % L;
+        double re = 0.0;
+        for (int k1 = 0; k1 < L; ++k1) {
+            const int m = (k1 * q1) & (L - 1);
+            const double2 t = T[k1 * L + q2];
+            re += t.x * cs[m] - t.y * sn[m];
+        }
+        bsum[(int64_t)c * L * L + e] = re * (1.0 / (double)(L * L));
+    }
 }
 
 // ---- batched forward DFT of real images (utility): out[i][k1][k2]
@@ -541,7 +557,9 @@ static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, con
             const int per = p.KK * L * L;
             hipLaunchKernelGGL(fft::k_fft_reduce, dim3((per + kReduceElems - 1) / kReduceElems), dim3(256), 0, s, (const float2*)bpart,
                                (const float*)cpart, p.n_chunks, per, (double2*)bh, csum);
-            hipLaunchKernelGGL(fft::k_fft_idft<L>, dim3((L * L + 255) / 256, p.KK), dim3(256), 0, s,
+            (void)hipFuncSetAttribute((const void*)fft::k_fft_idft<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)fft::idft_lds<L>());
+            hipLaunchKernelGGL(fft::k_fft_idft<L>, dim3(p.KK), dim3(256), fft::idft_lds<L>(), s,
                                (const double2*)bh, bsum);
             break;
         }
