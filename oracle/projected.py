@@ -12,7 +12,7 @@ It follows Alg. 2 (projected EM) of the paper (Shani, Tirer, Giryes, Bendory,
   em_oracle.em_step), then x <- D(x, sigma_t), then update sigma_t
 * sigma_t = 2^(-1/10) sigma_(t-1), sigma_1 = 1          -- eq. (decaying_function)
 
-Readings (the paper's denoiser, BM3D, is outside this build):
+Readings (the paper's denoiser, BM3D, is not implemented here):
 
 P1  D(x, s) is a circular Gaussian blur of x whose standard deviation, in
     pixels of the L_high grid, is the denoiser's noise level s: out[m] =
