@@ -128,17 +128,30 @@ def m_step_sums(Y, w: np.ndarray, K: int):
     return b, a, c
 
 
-def em_step(Y, x, log_rho, sigma: float, K: int, chunk: int = 256,
-            return_details: bool = False):
-    """One unprojected EM step from theta_t = (x, rho) (Sec. 2, EM paragraph).
+def em_sums(Y, x, log_rho, sigma: float, K: int, chunk: int = 256,
+            magnitudes: bool = False, g=None) -> dict:
+    """The E-step and the sums of the M-step over a set of observations
+    (Sec. 2, eq. (likelihood_EM), eq. (weights_EM) and the sums inside
+    eq. (x_EM) and eq. (rho_EM)).
 
-    Y: [N, Ll, Ll]; x: [Lh, Lh]; log_rho: [2, Lh] (row 0 = log rho1 on axis 0,
-    row 1 = log rho2 on axis 1).  Observations are processed in chunks; this is
-    exact because the per-observation normaliser only involves that
-    observation and every other quantity is a sum over observations.
-
-    Returns dict(x_new [Lh,Lh], rho_new [2,Lh], loglik, lse [N]) and, with
-    return_details, also b, a, c (see m_step_sums)."""
+    Observations are processed in chunks; this is exact because the
+    per-observation normaliser only involves that observation and every other
+    quantity is a sum over observations.  Sums of disjoint sets of
+    observations combine with merge_sums.  Returns dict(b, a, c [Lh, Lh],
+    lse [N]) and, with magnitudes, the sizes that bound a computation of the
+    same step at lower precision:
+      b_abs  the back-projection of |y_i| (so |b| <= b_abs);
+      w_max  per pixel, the largest single weight w^{i,s} among all (i, s)
+             that sample it;
+    and, given g (one non-negative scale per observation), the same sums with
+    the weights w^{i,s} replaced by w^{i,s} (1 - w^{i,s}) g_i:
+      v1     the back-projection of |y_i| with these weights,
+      v0     the diagonal of A with these weights,
+      c1     per shift, the sum over observations of these weights.
+    If every log-joint term of observation i carries an error of at most
+    g_i (in any direction), a weight normalised over s moves by a factor
+    exp(e) with |e| <= 2 g_i (1 - w^{i,s}); v1, v0 and c1 are the first-order
+    sizes of the resulting changes of b, A and c."""
     Y = _f64(Y)
     x = _f64(x)
     log_rho = _f64(log_rho)
@@ -150,6 +163,12 @@ def em_step(Y, x, log_rho, sigma: float, K: int, chunk: int = 256,
     a = np.zeros((Lh, Lh))
     c = np.zeros((Lh, Lh))
     lse = np.empty(N)
+    out = dict(b=b, a=a, c=c, lse=lse)
+    if magnitudes:
+        out.update(b_abs=np.zeros((Lh, Lh)), w_max=np.zeros((Lh, Lh)))
+        if g is not None:
+            g = _f64(g)
+            out.update(v1=np.zeros((Lh, Lh)), v0=np.zeros((Lh, Lh)), c1=np.zeros((Lh, Lh)))
     for lo in range(0, N, chunk):
         hi = min(N, lo + chunk)
         L = log_joint(Y[lo:hi], x, log_rho[0], log_rho[1], sigma, K)
@@ -159,14 +178,66 @@ def em_step(Y, x, log_rho, sigma: float, K: int, chunk: int = 256,
         b += bb
         a += aa
         c += cc
+        if magnitudes:
+            out["b_abs"] += m_step_sums(np.abs(Y[lo:hi]), w, K)[0]
+            wm = w.max(axis=0)
+            w_max = out["w_max"]
+            for s1 in range(Lh):
+                for s2 in range(Lh):
+                    rows, cols = shift_downsample_indices(Lh, K, s1, s2)
+                    w_max[np.ix_(rows, cols)] = np.maximum(w_max[np.ix_(rows, cols)], wm[s1, s2])
+            if g is not None:
+                wg = w * (1.0 - w) * g[lo:hi, None, None]
+                v1, v0, c1 = m_step_sums(np.abs(Y[lo:hi]), wg, K)
+                out["v1"] += v1
+                out["v0"] += v0
+                out["c1"] += c1
+    return out
+
+
+def merge_sums(parts) -> dict:
+    """Combine em_sums of consecutive disjoint sets of observations (in order):
+    the sums add, w_max takes the larger value, lse concatenates."""
+    out = {k: parts[0][k].copy() for k in parts[0]}
+    for p in parts[1:]:
+        for k in ("b", "a", "c", "b_abs", "v1", "v0", "c1"):
+            if k in out:
+                out[k] += p[k]
+        if "w_max" in out:
+            out["w_max"] = np.maximum(out["w_max"], p["w_max"])
+    out["lse"] = np.concatenate([p["lse"] for p in parts])
+    return out
+
+
+def em_finish(x, sums: dict) -> dict:
+    """The M-step from the sums: eq. (x_EM) and eq. (rho_EM), and the
+    log-likelihood eq. (likelihood_EM) at the input parameters (reading R6)."""
+    x = _f64(x)
+    b, a, c = sums["b"], sums["a"], sums["c"]
     # eq. (x_EM): A is diagonal here (reading R1), so A x = b is solved per pixel.
     x_new = np.where(a > 0, b / np.where(a > 0, a, 1.0), x)     # reading R8
     # eq. (rho_EM) with the product form (reading R3).
     tot = c.sum()
     rho_new = np.stack([c.sum(axis=1) / tot, c.sum(axis=0) / tot])
-    out = dict(x_new=x_new, rho_new=rho_new, loglik=float(lse.sum()), lse=lse)
+    return dict(x_new=x_new, rho_new=rho_new, loglik=float(sums["lse"].sum()), lse=sums["lse"])
+
+
+def em_step(Y, x, log_rho, sigma: float, K: int, chunk: int = 256,
+            return_details: bool = False, return_magnitudes: bool = False, g=None):
+    """One unprojected EM step from theta_t = (x, rho) (Sec. 2, EM paragraph).
+
+    Y: [N, Ll, Ll]; x: [Lh, Lh]; log_rho: [2, Lh] (row 0 = log rho1 on axis 0,
+    row 1 = log rho2 on axis 1).
+
+    Returns dict(x_new [Lh,Lh], rho_new [2,Lh], loglik, lse [N]) and, with
+    return_details, also b, a, c (see m_step_sums); with return_magnitudes
+    also the magnitudes of em_sums (v1, v0, c1 when g is given)."""
+    sums = em_sums(Y, x, log_rho, sigma, K, chunk=chunk, magnitudes=return_magnitudes, g=g)
+    out = em_finish(x, sums)
     if return_details:
-        out.update(b=b, a=a, c=c)
+        out.update(b=sums["b"], a=sums["a"], c=sums["c"])
+    if return_magnitudes:
+        out.update({k: sums[k] for k in ("b_abs", "w_max", "v1", "v0", "c1") if k in sums})
     return out
 
 
