@@ -21,7 +21,7 @@ __global__ void k_obs_sums(const float*, int64_t, int, double*);
 __global__ void k_centre(const double*, int64_t, int, int, double*);
 __global__ void k_obs_norms(const float*, int64_t, int, const double*, double*);
 __global__ void k_pack_x(const float*, const float*, int, int, double, const double*, float*, float*);
-__global__ void k_lse_combine(const float2*, int, int64_t, const double*, double, float*, double*,
+__global__ void k_lse_combine(const float2*, int, int64_t, const double*, double, float2*, double*,
                               float*);
 __global__ void k_reduce_partials(const float*, const float*, int, int, double*, double*);
 __global__ void k_finalize(const double*, const double*, int, int, const float*, const double*,
@@ -36,7 +36,7 @@ bool valu_geom(int LL, int KK, int& cpb, int& nt, size_t& lds1, size_t& lds2, co
                const void*& f2);
 bool bf16_geom(int LL, int KK, int np, int tile, int& cpb, int& nt, size_t& lds1, size_t& lds2,
                const void*& f1, const void*& f2);
-bool bf16_fused_geom(int LL, int KK, int np, size_t& lds, const void*& f);
+bool bf16_fused_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds, const void*& f);
 hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
                        hipStream_t s);
 hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* centre, double* ynorm,
@@ -105,9 +105,9 @@ int device_cus() {
     return g_dev[dev].cus;
 }
 
-int occupancy(const void* f, size_t lds) {
+int occupancy(const void* f, size_t lds, int threads = 256) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, lds) != hipSuccess || n < 1) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, threads, lds) != hipSuccess || n < 1) n = 1;
     return n;
 }
 
@@ -128,7 +128,7 @@ struct Geom {
 };
 
 int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
-              int64_t chunk_override = 0, int tile = 0) {
+              int64_t chunk_override = 0, int tile = 0, bool plan = false) {
     if (N < 1 || N > (int64_t)INT32_MAX || K < 1 || LL < 1) return SRMRA_EINVAL;
     if (!supported_ll(LL)) return SRMRA_EUNSUPPORTED;
     if ((int64_t)K * LL > 4096 || K * K > 256) return SRMRA_EUNSUPPORTED;
@@ -156,7 +156,9 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
         ok = bf16_geom(LL, g.KK, split_products(prec), tile, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
         size_t lds = 0;
         const void* ff = nullptr;
-        if (ok && bf16_fused_geom(LL, g.KK, split_products(prec), lds, ff)) {
+        // (plans run the single pass only where it fits their 256-thread class kernels)
+        if (ok && tile == 0 && !(plan && g.KK > 4) &&
+            bf16_fused_geom(LL, g.KK, split_products(prec), g.cpb, g.ntile, lds, ff)) {
             g.fuse_bf16 = 1;
             g.lds1 = 0;
             g.lds2 = lds;
@@ -188,7 +190,8 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     g.prep_bytes = g.prep_extra_off + (is_bf16(prec) ? bf16_prepared_extra(LL, N) : 0) +
                    (prec == SRMRA_FP32_FFT ? sizeof(float2) * (size_t)N * LL * LL : 0);
     // one resident wave of blocks over the whole device for the heavier pass
-    const int occ = occupancy(f2, g.lds2);
+    // (the BF16 single pass at K^2 > 4 runs 512-thread workgroups)
+    const int occ = occupancy(f2, g.lds2, (g.fuse_bf16 && g.KK > 4) ? 512 : 256);
     const int64_t target = (int64_t)device_cus() * occ;
     const int64_t tiles = (N + g.ntile - 1) / g.ntile;
     int64_t nch = target / g.n_cg;
@@ -204,7 +207,7 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     g.o_prep = with_norms ? take(g.prep_bytes) : 0;
     g.o_part = take(sizeof(float2) * (size_t)g.n_part * (size_t)N);
-    g.o_lse = take(sizeof(float) * (size_t)N);
+    g.o_lse = take(sizeof(float2) * (size_t)N);
     g.o_xt2 = take(sizeof(float) * (size_t)g.KK * LL * 2 * LL);
     g.o_beta = take(sizeof(float) * (size_t)g.KK * LL * LL);
     const size_t pw = prec == SRMRA_FP32_FFT ? sizeof(float2) : sizeof(float);   // complex partials
@@ -265,7 +268,7 @@ int run_step(const Geom& g, const float* y, const char* prep, const float* x,
     p.betaT = (const float*)(ws + g.o_beta);
     p.xb = is_bf16(g.prec) ? (const uint4*)(ws + g.o_xb) : nullptr;
     p.part = (float2*)(ws + g.o_part);
-    p.lse = (float*)(ws + g.o_lse);
+    p.lse = (float2*)(ws + g.o_lse);
     p.bpart = (float*)(ws + g.o_bpart);
     p.cpart = (float*)(ws + g.o_cpart);
     p.n_chunks = g.n_chunks;
@@ -585,7 +588,7 @@ void fill_desc(srmra_plan* P, int i, int par, InstDesc& d, char* ws) {
     p.betaT = (const float*)(w + g.o_beta);
     p.xb = is_bf16_form(P->form[i]) ? (const uint4*)(w + g.o_xb) : nullptr;
     p.part = (float2*)(w + g.o_part);
-    p.lse = (float*)(w + g.o_lse);
+    p.lse = (float2*)(w + g.o_lse);
     p.bpart = (float*)(w + g.o_bpart);
     p.cpart = (float*)(w + g.o_cpart);
     p.n_chunks = g.n_chunks; p.n_cg = g.n_cg; p.cpb = g.cpb; p.ntile = g.ntile;
@@ -621,7 +624,7 @@ int srmra_plan_form(int precision, int L_low) {
 
 int64_t srmra_plan_default_item_obs(int64_t N, int L_low, int K, int form_precision) {
     Geom g;
-    const int st = make_geom(N, L_low, K, form_precision, false, g);
+    const int st = make_geom(N, L_low, K, form_precision, false, g, 0, 0, true);
     if (st != SRMRA_OK) return st;
     return default_chunk(g);
 }
@@ -681,10 +684,10 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         }
         const int fprec = prec_of_form(f);
         Geom g0;
-        st = make_geom(pr.N, pr.L_low, pr.K, fprec, false, g0, 0, tile);
+        st = make_geom(pr.N, pr.L_low, pr.K, fprec, false, g0, 0, tile, true);
         if (st != SRMRA_OK) { delete P; return st; }
         Geom g;
-        make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, item_obs > 0 ? item_obs : default_chunk(g0), tile);
+        make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, item_obs > 0 ? item_obs : default_chunk(g0), tile, true);
         if (pr.prep_bytes < g.prep_bytes) { delete P; return SRMRA_EWORKSPACE; }
         if (f == FORM_MFMA && g.fuse_wc) f = FORM_FUSED;
         if (g.fuse_bf16) f = f == FORM_BF16X4 ? FORM_BF16X4F : FORM_BF16F;

@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_pack_x(const float* __restrict__ x,
 
 __global__ __launch_bounds__(256) void k_lse_combine(const float2* __restrict__ part, int n_cg,
                                                      int64_t N, const double* __restrict__ ynorm,
-                                                     double inv_2s2, float* __restrict__ lse,
+                                                     double inv_2s2, float2* __restrict__ lse,
                                                      double* __restrict__ llpart,
                                                      float* __restrict__ ll_obs) {
     __shared__ double red[256];

@@ -122,7 +122,7 @@ __device__ __forceinline__ void pack_x_body(const float* __restrict__ x,
 // optionally, l_i itself.
 __device__ __forceinline__ void lse_combine_body(const float2* __restrict__ part, int n_cg,
                                                  int64_t N, const double* __restrict__ ynorm,
-                                                 double inv_2s2, float* __restrict__ lse,
+                                                 double inv_2s2, float2* __restrict__ lse,
                                                  double* __restrict__ llpart,
                                                  float* __restrict__ ll_obs, int64_t blk,
                                                  double* red) {
@@ -139,7 +139,7 @@ __device__ __forceinline__ void lse_combine_body(const float2* __restrict__ part
             }
         }
         const double L = (double)m + log(s);
-        lse[i] = (float)L;
+        lse[i] = make_float2(m, (float)log(s));
         li = L - ynorm[i] * inv_2s2;
         if (ll_obs) ll_obs[i] = (float)li;
     }

@@ -124,7 +124,8 @@ void k_class_pass(const InstDesc* __restrict__ D,
             b16::Prep q;
             q.yT = d.yT;
             q.yo = d.yo;
-            b16::bf16_pass2_body<LL, NP, true>(d.p, q, w.y, 0, lds);
+            if (d.p.KK <= 4) b16::bf16_pass2_body<LL, NP, true>(d.p, q, w.y, 0, lds);
+            else b16::bf16_fused16_body<LL, NP>(d.p, q, w.y, lds);
         } else if constexpr (FORM == FORM_FUSED) {
             mfma_fused_body<LL>(d.p, w.y, lds);
         } else if constexpr (FORM == FORM_MFMA) {

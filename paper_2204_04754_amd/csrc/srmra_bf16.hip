@@ -26,6 +26,13 @@ __global__ __launch_bounds__(256) void k_fused_bf16(StepArgs p, Prep q) {
     bf16_pass2_body<LL, NP, true>(p, q, blockIdx.x, 0, lds);
 }
 
+// single pass at 4 < K^2 <= 16: grid (chunks)
+template <int LL, int NP>
+__global__ __launch_bounds__(F16_NT, 1) void k_fused16_bf16(StepArgs p, Prep q) {
+    extern __shared__ float lds[];
+    bf16_fused16_body<LL, NP>(p, q, blockIdx.x, lds);
+}
+
 // x as MFMA B fragments: grid (KK, k-steps / 4), 256 threads (4 k-steps per block)
 template <int LL>
 __global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __restrict__ x,
@@ -187,6 +194,14 @@ hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* cen
 
 template <int LL, int NP>
 static hipError_t launch_bf16_ll(int pass, const StepArgs& p, const b16::Prep& q, hipStream_t s) {
+    if (pass == 3 && p.KK > 4) {
+        const size_t lds = b16::lds_fused16<LL>();
+        if (hipFuncSetAttribute((const void*)b16::k_fused16_bf16<LL, NP>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL((b16::k_fused16_bf16<LL, NP>), dim3(p.n_chunks), dim3(b16::F16_NT), lds, s, p, q);
+        return hipGetLastError();
+    }
     if (pass == 3) {
         const size_t lds = b16::lds_fused<LL>();
         if (hipFuncSetAttribute((const void*)b16::k_fused_bf16<LL, NP>,
@@ -269,11 +284,25 @@ static void bf16w_geom_ll(size_t& lds1, size_t& lds2, const void*& f1, const voi
 }
 
 // The single pass when one workgroup holds all K^2 components of its
-// observations: L_low 24 / 32 with K^2 <= 4.  (At L_low 16 a single pass that
+// observations: L_low 24 / 32 with K^2 <= 4 (8 observations x 4 components
+// per workgroup) and with 4 < K^2 <= 16 (4 observations x 16 components;
+// cpb and nt are set to that tile).  (At L_low 16 a single pass that
 // keeps the scores of 8 observations x 4 components across the block's
 // (max, sum) exchange spilled registers and measured no faster than the two
 // passes, slower inside the batched form; L_low 16 keeps two passes.)
-bool bf16_fused_geom(int LL, int KK, int np, size_t& lds, const void*& f) {
+bool bf16_fused_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds, const void*& f) {
+    if ((LL == 24 || LL == 32) && KK > 4 && KK <= b16::F16_NCW * b16::F16_NW) {
+        cpb = b16::F16_NCW * b16::F16_NW;
+        nt = b16::F16_NOB;
+        if (LL == 24) {
+            lds = b16::lds_fused16<24>();
+            f = np == 4 ? (const void*)b16::k_fused16_bf16<24, 4> : (const void*)b16::k_fused16_bf16<24, 3>;
+        } else {
+            lds = b16::lds_fused16<32>();
+            f = np == 4 ? (const void*)b16::k_fused16_bf16<32, 4> : (const void*)b16::k_fused16_bf16<32, 3>;
+        }
+        return true;
+    }
     if ((LL == 24 || LL == 32) && KK <= 4) {
         if (LL == 24) {
             lds = b16::lds_fused<24>();

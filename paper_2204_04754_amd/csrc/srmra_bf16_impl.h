@@ -107,11 +107,11 @@ __device__ __forceinline__ void pack_xb_body(const StepArgs& p, const float* __r
     dst[64 + lane] = __builtin_bit_cast(uint4, l);
 }
 
-// yT planes of observations [o0, o0 + 8) into LDS (row pitch PITCH), zeros past N.
-template <int LL>
+// yT planes of observations [o0, o0 + NOB) into LDS (row pitch PITCH), zeros past N.
+template <int LL, int NOB = 8, int NT = 256>
 __device__ __forceinline__ void load_yT(const StepArgs& p, const Prep& q, int64_t o0, __bf16* ys) {
     constexpr int CH = 2 * LL * (R1P / 8);     // 16-byte chunks per observation
-    for (int e = threadIdx.x; e < 8 * CH; e += 256) {
+    for (int e = threadIdx.x; e < NOB * CH; e += NT) {
         const int o = e / CH, r = e % CH;
         const int row = r / (R1P / 8), part = r % (R1P / 8);   // row = plane*LL + col
         uint4 v = make_uint4(0, 0, 0, 0);
@@ -331,31 +331,31 @@ __device__ __forceinline__ void bf16_pass1_body(const StepArgs& p, const Prep& q
 // the observation's single partial (its log-likelihood term is formed from it
 // later) by the `writer` waves, and the value returned is the one the combine
 // kernel forms from that pair.
-template <typename Use>
-__device__ __forceinline__ void block_lse(const StepArgs& p, const float (&mw)[8], const float (&sw)[8],
+template <int NOB, typename Use>
+__device__ __forceinline__ void block_lse(const StepArgs& p, const float (&mw)[NOB], const float (&sw)[NOB],
                                           int slot, int base, int stride, int nslot, int64_t obs0,
-                                          int64_t c1, bool writer, Use use, float2* red, float (&lse)[8]) {
+                                          int64_t c1, bool writer, Use use, float2* red, float2 (&lse)[NOB]) {
     const int lane = threadIdx.x & 63;
     if (lane == 0) {
 #pragma unroll
-        for (int o = 0; o < 8; ++o) red[slot * 8 + o] = make_float2(mw[o], sw[o]);
+        for (int o = 0; o < NOB; ++o) red[slot * NOB + o] = make_float2(mw[o], sw[o]);
     }
     __syncthreads();
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
+    for (int o = 0; o < NOB; ++o) {
         float m = -INFINITY;
         for (int k = 0; k < nslot; ++k)
-            if (use(k)) m = fmaxf(m, red[(base + k * stride) * 8 + o].x);
+            if (use(k)) m = fmaxf(m, red[(base + k * stride) * NOB + o].x);
         double sum = 0.0;
         if (m > -INFINITY) {
             for (int k = 0; k < nslot; ++k) {
                 if (!use(k)) continue;
-                const float2 e = red[(base + k * stride) * 8 + o];
+                const float2 e = red[(base + k * stride) * NOB + o];
                 if (e.x > -INFINITY) sum += (double)e.y * exp((double)e.x - (double)m);
             }
         }
         const float sf = (float)sum;
-        lse[o] = m > -INFINITY ? (float)((double)m + log((double)sf)) : 0.f;
+        lse[o] = m > -INFINITY ? make_float2(m, (float)log((double)sf)) : make_float2(0.f, 0.f);
         if (writer && lane == 0 && obs0 + o < c1) p.part[obs0 + o] = make_float2(m, sf);
     }
     __syncthreads();   // red is rewritten by the next group
@@ -395,7 +395,7 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
         score<LL, 8, 1, NP>(p, ys, oslot, cgl, acc);
         // posterior weights, posterior mass, BF16 hi/lo fragments over k = (t2, o)
         bf16x8 wh[16], wl[16];
-        float lse[8];
+        float2 lse[8];
         if constexpr (FUSED) {
             // this wave's (max, sum exp) per observation, then the 4 waves combined
             float mw[8], sw[8];
@@ -435,7 +435,7 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
                       [&](int k) { return k < p.KK; }, red, lse);
         } else {
 #pragma unroll
-            for (int o = 0; o < 8; ++o) lse[o] = (o0 + o < p.N) ? p.lse[o0 + o] : 0.f;
+            for (int o = 0; o < 8; ++o) lse[o] = (o0 + o < p.N) ? p.lse[o0 + o] : make_float2(0.f, 0.f);
         }
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -448,7 +448,7 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
                 float ww = 0.f;
                 if (sok && o0 + o < p.N) {
                     const float a = acc[o][0][v] * p.inv_s2 + bet;
-                    ww = a > -INFINITY ? fast_exp(a - lse[o]) : 0.f;
+                    ww = a > -INFINITY ? fast_exp((a - lse[o].x) - lse[o].y) : 0.f;
                 }
                 w[o] = ww;
                 cnt[v] += ww;
@@ -511,6 +511,230 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
                 if (t2 < LL) co[j * LL + t2] = cnt[v];
             }
         }
+    }
+}
+
+// ============================================================================
+// Single pass for 4 < K^2 <= 16 (L_low 24, 32): a workgroup of 8 waves holds
+// all K^2 components of groups of 4 observations.  Wave w scores the 4
+// observations against components 2w, 2w + 1 (8 tiles, as a pass-1 wave), the
+// eight waves' (max, sum exp) per observation are combined through LDS into
+// the log-sum-exp, and each wave back-projects its components from its own
+// accumulators.  The back-projection of component c for each a1,
+//   Z[q2][t1] = sum_{t2, o} y_o[a1][(q2 + t2) % Ll] * w_{o,c}[t1][t2],
+// runs over k = (t2, o) in k-steps of two t2 rows x 4 observations: the B
+// fragment of k-step s (lane half g) is the weights of rows
+// 8 (s >> 1) + 4 g + 2 (s & 1) + {0, 1} of the lane's accumulators for the
+// 4 observations, the A fragment the matching values of the staged
+// observations, stored [plane][a1][column][4 observations] (one 8-byte record
+// per column: two records per fragment).  The posterior mass of a
+// (component, shift) is owned by one lane of one wave for the whole chunk and
+// summed into the chunk's partial in global memory group by group (registers
+// and LDS are both full).
+constexpr int F16_NOB = 4;   // observations per group
+constexpr int F16_NCW = 2;   // components per wave
+constexpr int F16_NW = 8;    // waves per workgroup
+constexpr int F16_NT = 64 * F16_NW;
+
+// Yo4 for the 4 observations [o0, o0 + 4) (o0 a multiple of 4): their half
+// of the prepared 8-observation group, both planes, [plane][a1][col][4 obs].
+template <int LL>
+__device__ __forceinline__ void load_yo4(const Prep& q, int64_t o0, __bf16* yo4) {
+    constexpr int CH = 2 * LL * LL;            // 16-byte records (8 obs x bf16) per group
+    const uint4* src = reinterpret_cast<const uint4*>(q.yo + (o0 / 8) * (int64_t)(2 * LL * LL * 8));
+    const int half = (int)((o0 / 4) & 1);
+    uint2* dst = reinterpret_cast<uint2*>(yo4);
+    for (int e = threadIdx.x; e < CH; e += F16_NT) {
+        const uint4 v = src[e];
+        dst[e] = half ? make_uint2(v.z, v.w) : make_uint2(v.x, v.y);
+    }
+}
+
+template <int LL, int NP>
+__device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep& q, int chunk_i,
+                                                  float* lds) {
+    using G = Geo<LL>;
+    constexpr int NOB = F16_NOB, NCW = F16_NCW, NW = F16_NW;
+    float* bacc = lds;                                                  // NW x NCW x Ll x BP
+    __bf16* ys = reinterpret_cast<__bf16*>(bacc + NW * NCW * LL * G::BP);  // NOB x 2 x Ll x PITCH
+    __bf16* yo4 = ys + NOB * 2 * LL * PITCH;                            // 2 x Ll x Ll x NOB
+    float2* red = reinterpret_cast<float2*>(yo4 + 2 * LL * LL * NOB);   // NW x NOB
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j = lane & 31, g = lane >> 5;
+    int comp[NCW], cgl[NCW];
+    bool cok[NCW];
+#pragma unroll
+    for (int c = 0; c < NCW; ++c) {
+        comp[c] = wave * NCW + c;
+        cok[c] = comp[c] < p.KK;
+        cgl[c] = cok[c] ? comp[c] : p.KK - 1;
+    }
+    float* bw = bacc + wave * NCW * LL * G::BP;
+    for (int e = lane; e < NCW * LL * G::BP; e += 64) bw[e] = 0.f;
+    const int oslot[NOB] = {0, 1, 2, 3};
+    const int q2e = j < LL ? j : j - LL;
+    const int64_t chunk = chunk_i;
+    const int64_t c0 = chunk * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    for (int64_t o0 = c0; o0 < c1; o0 += NOB) {
+        __syncthreads();
+        load_yT<LL, NOB, F16_NT>(p, q, o0, ys);
+        load_yo4<LL>(q, o0, yo4);
+        __syncthreads();
+        floatx16 acc[NOB][NCW];
+        score<LL, NOB, NCW, NP>(p, ys, oslot, cgl, acc);
+        // a = S / sigma^2 + beta, formed where it is used (the accumulators are
+        // only read); slots that are not a shift of this observation (rows /
+        // columns past Ll, missing components or observations) are skipped.
+        // The wave's (max, sum exp) per observation:
+        bool ook[NOB];
+#pragma unroll
+        for (int o = 0; o < NOB; ++o) ook[o] = o0 + o < p.N;
+        auto beta_of = [&](int c, int v, bool& sok) {
+            const int t2 = acc_row(v, lane);
+            sok = cok[c] && t2 < LL && j < LL;
+            return sok ? p.betaT[(int64_t)comp[c] * (LL * LL) + t2 * LL + j] : 0.f;
+        };
+        float mw[NOB], sw[NOB];
+#pragma unroll
+        for (int o = 0; o < NOB; ++o) {
+            mw[o] = -INFINITY;
+            sw[o] = 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < NCW; ++c) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                bool sok;
+                const float bet = beta_of(c, v, sok);
+#pragma unroll
+                for (int o = 0; o < NOB; ++o)
+                    if (sok && ook[o]) mw[o] = fmaxf(mw[o], acc[o][c][v] * p.inv_s2 + bet);
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < NOB; ++o)
+            for (int off = 32; off > 0; off >>= 1) mw[o] = fmaxf(mw[o], __shfl_xor(mw[o], off));
+#pragma unroll
+        for (int c = 0; c < NCW; ++c) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                bool sok;
+                const float bet = beta_of(c, v, sok);
+#pragma unroll
+                for (int o = 0; o < NOB; ++o) {
+                    const float a = acc[o][c][v] * p.inv_s2 + bet;
+                    if (sok && ook[o] && a > -INFINITY) sw[o] += fast_exp(a - mw[o]);
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < NOB; ++o)
+            for (int off = 32; off > 0; off >>= 1) sw[o] += __shfl_xor(sw[o], off);
+        float2 lse[NOB];
+        block_lse(p, mw, sw, wave, 0, 1, NW, o0, p.N, wave == 0,
+                  [&](int k) { return k * NCW < p.KK; }, red, lse);
+        // posterior weights and mass of both components, the weights as B
+        // fragments over k = (two t2 rows, 4 obs) (the accumulators are dead
+        // after this), then the back-projection for each a1 (k-steps with t2
+        // rows >= Ll carry no weight: at Ll = 24 the last two are skipped), one
+        // A fragment per k-step serving both components, folded into the
+        // wave's b accumulators
+        bf16x8 wh[NCW][8], wl[NCW][8];
+#pragma unroll
+        for (int c = 0; c < NCW; ++c) {
+            float* co = p.cpart + (chunk * p.KK + comp[c]) * (LL * LL);
+#pragma unroll
+            for (int s8 = 0; s8 < 8; ++s8) {
+                float w[8];
+#pragma unroll
+                for (int r = 0; r < 2; ++r) {
+                    const int v = 2 * s8 + r;
+                    bool sok;
+                    const float bet = beta_of(c, v, sok);
+                    float m = 0.f;
+#pragma unroll
+                    for (int o = 0; o < NOB; ++o) {
+                        const float a = acc[o][c][v] * p.inv_s2 + bet;
+                        const float ww = (sok && ook[o] && a > -INFINITY)
+                                             ? fast_exp((a - lse[o].x) - lse[o].y) : 0.f;
+                        w[4 * r + o] = ww;
+                        m += ww;
+                    }
+                    // the posterior mass of shift (c, t1 = j, t2): this lane's
+                    // running sum over the chunk's groups
+                    if (sok) {
+                        float* cp = co + j * LL + acc_row(v, lane);
+                        *cp = (o0 == c0) ? m : *cp + m;
+                    }
+                }
+                split8(w, wh[c][s8], wl[c][s8]);
+            }
+        }
+        constexpr int NS = LL == 24 ? 6 : 8;
+        constexpr int PF = 2;
+        constexpr int PL = LL * LL;                          // plane stride in records
+        for (int a1 = 0; a1 < LL; ++a1) {
+            const uint2* yrow = reinterpret_cast<const uint2*>(yo4) + a1 * LL;
+            bf16x8 ah[NS], al[NS];
+            auto load_a = [&](int s8) {
+                int k0 = q2e + 8 * (s8 >> 1) + 4 * g + 2 * (s8 & 1);
+                k0 = k0 >= LL ? k0 - LL : k0;
+                const int k1 = k0 + 1 >= LL ? k0 + 1 - LL : k0 + 1;
+                const uint2 h0 = yrow[k0], h1 = yrow[k1];
+                const uint2 l0 = yrow[PL + k0], l1 = yrow[PL + k1];
+                ah[s8] = __builtin_bit_cast(bf16x8, make_uint4(h0.x, h0.y, h1.x, h1.y));
+                al[s8] = __builtin_bit_cast(bf16x8, make_uint4(l0.x, l0.y, l1.x, l1.y));
+            };
+#pragma unroll
+            for (int s8 = 0; s8 < PF; ++s8) load_a(s8);
+            floatx16 z[NCW];
+#pragma unroll
+            for (int c = 0; c < NCW; ++c) z[c] = floatx16{0};
+#pragma unroll
+            for (int s8 = 0; s8 < NS; ++s8) {
+                if (s8 + PF < NS) load_a(s8 + PF);
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int c = 0; c < NCW; ++c)
+                    z[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s8], wh[c][s8], z[c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < NCW; ++c)
+                    z[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[s8], wl[c][s8], z[c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < NCW; ++c)
+                    z[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s8], wh[c][s8], z[c], 0, 0, 0);
+                if constexpr (NP == 4) {
+#pragma unroll
+                    for (int c = 0; c < NCW; ++c)
+                        z[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s8], wl[c][s8], z[c], 0, 0, 0);
+                }
+            }
+            // lane holds Z[q2 = acc_row(v)][t1 = j]; b_c[(a1 - t1) % Ll][q2] += Z
+            if (j < LL) {
+                int q1 = a1 - j;
+                q1 = q1 < 0 ? q1 + LL : q1;
+#pragma unroll
+                for (int c = 0; c < NCW; ++c) {
+                    float* brow = bw + (c * LL + q1) * G::BP;
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int q2 = acc_row(v, lane);
+                        if (q2 < LL) brow[q2] += z[c][v];
+                    }
+                }
+            }
+        }
+    }
+    // ---- this block's partials of b for the wave's components
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NCW; ++c) {
+        if (!cok[c]) continue;
+        const float* bc = bw + c * LL * G::BP;
+        float* bo = p.bpart + (chunk * p.KK + comp[c]) * (LL * LL);
+        for (int e = lane; e < LL * LL; e += 64) bo[e] = bc[(e / LL) * G::BP + (e % LL)];
     }
 }
 
@@ -600,6 +824,13 @@ template <int LL> constexpr size_t lds_pass2() {
 }
 // the single pass: pass 2's LDS plus the (max, sum) exchange
 template <int LL> constexpr size_t lds_fused() { return lds_pass2<LL>() + sizeof(float2) * 4 * 8; }
+// the single pass at 4 < K^2 <= 16
+template <int LL> constexpr size_t lds_fused16() {
+    using G = Geo<LL>;
+    return sizeof(float) * (F16_NW * F16_NCW * LL * G::BP) +
+           sizeof(__bf16) * (F16_NOB * 2 * LL * PITCH + 2 * LL * LL * F16_NOB) +
+           sizeof(float2) * F16_NW * F16_NOB;
+}
 
 }  // namespace b16
 }  // namespace srmra

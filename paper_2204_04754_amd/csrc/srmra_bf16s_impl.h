@@ -286,11 +286,11 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const Prep& q, int
         if (active) {
             floatx4 acc[8][4];
             score<NP, false>(p, st, 8 * wo, cgc, acc);
-            float lse[8];
+            float2 lse[8];
 #pragma unroll
             for (int o = 0; o < 8; ++o) {
                 const int64_t oi = o0 + 8 * wo + o;
-                lse[o] = oi < c1 ? p.lse[oi] : 0.f;
+                lse[o] = oi < c1 ? p.lse[oi] : make_float2(0.f, 0.f);
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c)
@@ -302,7 +302,7 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const Prep& q, int
                         float ww = 0.f;
                         if (o0 + 8 * wo + o < c1) {
                             const float a = acc[o][c][v] * p.inv_s2 + bet[c][v];
-                            ww = a > -INFINITY ? fast_exp(a - lse[o]) : 0.f;
+                            ww = a > -INFINITY ? fast_exp((a - lse[o].x) - lse[o].y) : 0.f;
                         }
                         w[o] = ww;
                         cnt[c][v] += ww;

@@ -285,9 +285,9 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const Prep& q, int
     for (int64_t o0 = c0; o0 < c1; o0 += 8) {
         floatx16 acc[8];
         score<LL, NP>(p, q, st, cc, tb1, tb2, o0, acc);
-        float lse[8];
+        float2 lse[8];
 #pragma unroll
-        for (int o = 0; o < 8; ++o) lse[o] = (o0 + o < p.N) ? p.lse[o0 + o] : 0.f;
+        for (int o = 0; o < 8; ++o) lse[o] = (o0 + o < p.N) ? p.lse[o0 + o] : make_float2(0.f, 0.f);
         bf16x8 wh[16], wl[16];
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -297,7 +297,7 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const Prep& q, int
                 float ww = 0.f;
                 if (cok && o0 + o < p.N) {
                     const float a = acc[o][v] * p.inv_s2 + bet[v];
-                    ww = a > -INFINITY ? fast_exp(a - lse[o]) : 0.f;
+                    ww = a > -INFINITY ? fast_exp((a - lse[o].x) - lse[o].y) : 0.f;
                 }
                 w[o] = ww;
                 cnt[v] += ww;

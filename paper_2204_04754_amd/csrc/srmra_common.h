@@ -55,7 +55,11 @@ struct StepArgs {
     const uint4* xb;         // BF16 form: x as MFMA B fragments [KK][k-step][plane][lane]
     // pass-1 output / pass-2 input
     float2* part;            // [n_cg][N]  (max, sum) of exp over the group's shifts
-    float* lse;              // [N]
+    float2* lse;             // [N] (m_i, l_i): LSE_i = m_i + l_i with m_i the largest
+                             // log-joint term (an FP32 value of the step's own
+                             // arithmetic) and l_i = log sum_s exp(a_is - m_i), so a
+                             // weight exp((a - m_i) - l_i) loses nothing to the
+                             // rounding of a large LSE_i
     // pass-2 outputs
     float* bpart;            // [n_chunks][KK][Ll*Ll]   (q1*Ll + q2)
     float* cpart;            // [n_chunks][KK][Ll*Ll]   (t1*Ll + t2)

@@ -215,11 +215,11 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
         for (int64_t o = c0 + u; o < c1; o += TPC) {
             float s[L / 2];
             score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, s);
-            const float lse = p.lse[o];
+            const float2 lse = p.lse[o];
             float2 v[L / 2];
 #pragma unroll
             for (int k = 0; k < L / 2; ++k) {
-                const float w = s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;
+                const float w = s[k] > -INFINITY ? __expf((s[k] - lse.x) - lse.y) : 0.f;
                 acw[k] += w;
                 v[k] = make_float2(w, 0.f);
             }
@@ -366,11 +366,11 @@ __global__ __launch_bounds__(256) void k_fft_pass2_q(StepArgs p, const float2* _
     for (int64_t o = c0; o < c1; ++o) {
         float s[NV];
         score(p, yhat, xhat, o, c, sh, r, q, bq, tw, s);
-        const float lse = p.lse[o];
+        const float2 lse = p.lse[o];
         float2 v[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-            const float w = s[k] > -INFINITY ? __expf(s[k] - lse) : 0.f;
+            const float w = s[k] > -INFINITY ? __expf((s[k] - lse.x) - lse.y) : 0.f;
             acw[k] += w;
             v[k] = make_float2(w, 0.f);
         }

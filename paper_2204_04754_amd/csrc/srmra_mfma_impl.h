@@ -508,9 +508,10 @@ __device__ __forceinline__ void mfma_pass2_body(const StepArgs& p, int chunk_i, 
         const int64_t wobs_g = o0 + wobs;
         floatx16 acc[2][2];
         score_tiles<LL>(Ys, Xs, wobs, acc);
-        float lse_o[TL::OPW];
+        float2 lse_o[TL::OPW];
 #pragma unroll
-        for (int k = 0; k < TL::OPW; ++k) lse_o[k] = (wobs_g + k < p.N) ? p.lse[wobs_g + k] : 0.f;
+        for (int k = 0; k < TL::OPW; ++k)
+            lse_o[k] = (wobs_g + k < p.N) ? p.lse[wobs_g + k] : make_float2(0.f, 0.f);
         // w = exp(a - lse) in place; accumulate c
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
@@ -520,7 +521,7 @@ __device__ __forceinline__ void mfma_pass2_body(const StepArgs& p, int chunk_i, 
                 for (int v = 0; v < 16; ++v) {
                     int os;
                     const float a = tile_logit<LL>(p, cg, wobs_g, rb, cb, v, acc[rb][cb][v], os);
-                    const float w = a > -INFINITY ? fast_exp(a - lse_o[os]) : 0.f;
+                    const float w = a > -INFINITY ? fast_exp((a - lse_o[os].x) - lse_o[os].y) : 0.f;
                     acc[rb][cb][v] = w;
                     count_tile<LL>(cnt, rb, cb, v, w);
                 }
@@ -632,8 +633,7 @@ __device__ __forceinline__ void mfma_fused_body(const StepArgs& p, int chunk_i, 
                 if (mg > -INFINITY) S += sg * fast_exp(mg - M);
             }
             const bool valid = wobs_g + k < p.N && M > -INFINITY;
-            const float lse = M + __logf(S);
-            scale[k] = valid && mx[k] > -INFINITY ? fast_exp(mx[k] - lse) : 0.f;
+            scale[k] = valid && mx[k] > -INFINITY ? fast_exp((mx[k] - M) - __logf(S)) : 0.f;
             if (valid && wc == 0 && lane == 0) p.part[wobs_g + k] = make_float2(M, S);
         }
         __syncthreads();   // every wave has read the exchange before W is overwritten

@@ -199,7 +199,7 @@ __device__ __forceinline__ void valu_pass2_body(const StepArgs& p, int chunk, in
             for (int o = 0; o < V::NOV; ++o) {
                 const int64_t og_ = o0 + og * V::NOV + o;
                 const bool ook = cok && og_ < p.N;
-                const float l = ook ? p.lse[og_] : 0.f;
+                const float2 l = ook ? p.lse[og_] : make_float2(0.f, 0.f);
                 float* wdst = Ws + ((og * V::NOV + o) * p.cpb + cs) * (LL * LL);
 #pragma unroll
                 for (int uu = 0; uu < 4; ++uu)
@@ -210,7 +210,7 @@ __device__ __forceinline__ void valu_pass2_body(const StepArgs& p, int chunk, in
                         if (ook) {
                             const float a = acc[o][uu][v] * p.inv_s2 +
                                             p.betaT[(int64_t)c * (LL * LL) + t2 * LL + t1];
-                            w = a > -INFINITY ? fast_exp(a - l) : 0.f;
+                            w = a > -INFINITY ? fast_exp((a - l.x) - l.y) : 0.f;
                         }
                         cnt[uu][v] += w;
                         wdst[t1 * LL + t2] = w;

