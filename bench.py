@@ -2,21 +2,26 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--precision P]
 
-Workload (default): Lh 64, K 2, Ll 32, N = 100000 observations, sigma = 1,
-seeded synthetic smooth image, Dirichlet(1) shift distributions.  A "step" is
+Workload (default): the precision study, Lh 128, K 4, Ll 32, N = 200000
+observations, sigma 0.5, seeded synthetic smooth image, Dirichlet(1) shift
+distributions; main form the BF16 split with three products.  A "step" is
 one full EM iteration (pack x + score/log-sum-exp pass + combine +
 posterior/back-projection pass + FP64 M-step), with the observation stack and
-its per-job preparation already resident in HBM.  The main form is timed and
-the plain FP32 (vector ALU) form is timed beside it on the same inputs.
+its per-job preparation already resident in HBM.  Plain FP32 (vector ALU),
+FP32 MFMA, the FFT route and the 4-product split are timed beside it on the
+same inputs, and the single-instance workload (Lh 64, K 2, N 100000, FP32
+MFMA, one pass) is reported as a secondary line.
 
 Prints ONE JSON line.  Also reports:
  * roofline of the dominant kernel (the single pass, or for two-pass shapes
-   the posterior/back-projection pass), its
-   duration measured with HIP events recorded by the library on the step's
-   stream, against the MI355X FP32 matrix peak (157.3 TFLOP/s) or, for the
-   vector-ALU form, the non-packed FP32 vector peak (78.6 TFLOP/s);
- * cpu_baseline: the FP64 oracle on a bounded prefix of the observations, timed
-   on this host, and the GPU's relative error against it on that prefix.
+   the posterior/back-projection pass) and of the score pass, their
+   durations measured with HIP events recorded by the library on the step's
+   stream, against the MI355X peak of the form's arithmetic (BF16 dense
+   2516.6 TFLOP/s, FP32 matrix 157.3 TFLOP/s, or the non-packed FP32 vector
+   rate 78.6 TFLOP/s): algorithmic work (4 Ll^2 flop per observation x shift
+   pair) and issued work (with the score recompute and the split's products);
+ * cpu_baseline: the FP64 oracle on the first 2000 observations, timed on
+   this host, and every GPU form's relative error against it on that subset.
 """
 from __future__ import annotations
 
@@ -55,6 +60,8 @@ TRAFFIC = {
         dict(bytes=428061491, src=_MFMA_SRC, sha="afe068a4c07ebf90"),
     ("lh128_k4_n200000_s0.5", "bf16_split3", "k_backproject_bf16<32, 3>"):
         dict(bytes=1667584512, src=_BF16_SRC, sha="6ff1042a104f29b1"),
+    ("lh128_k4_n200000_s0.5", "bf16_split3", "k_score_lse_bf16<32, 3>"):
+        dict(bytes=855719219, src=_BF16_SRC, sha="6ff1042a104f29b1"),
     ("lh256_k4_n20000", "bf16_split3", "b16w::k_backproject<64, 3>"):
         dict(bytes=7369647616, src=_BF16W_SRC, sha="f7205148b449a689"),
 }
@@ -77,17 +84,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="lh64_k2_n100000")
-    ap.add_argument("--precision", default="fp32_mfma")
+    ap.add_argument("--workload", default="lh128_k4_n200000_s0.5")
+    ap.add_argument("--precision", default="bf16_split3")
     ap.add_argument("--baseline-precision", default="fp32_plain")
-    ap.add_argument("--cpu-sample", type=int, default=0,
+    ap.add_argument("--cpu-sample", type=int, default=2000,
                     help="observations in the oracle sample (0 = sized for --cpu-seconds)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target oracle time on the host for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--extra-forms", default="bf16_split3,fp32_fft",
+    ap.add_argument("--extra-forms", default="fp32_mfma,fp32_fft,bf16_split4",
                     help="comma-separated forms also timed beside the main one (single mode)")
+    ap.add_argument("--secondary-workload", default="lh64_k2_n100000",
+                    help="single mode: a second workload timed in --secondary-precision ('' = none)")
+    ap.add_argument("--secondary-precision", default="fp32_mfma")
     ap.add_argument("--mode", default="single",
                     choices=["single", "batched", "serve", "errors", "projected", "moments"],
                     help="single: one instance (default); batched: 64-instance mix, 20 iterations "
@@ -187,27 +197,99 @@ def oracle_sample_size(inst, seconds):
     return max(n0, int(seconds / max(per_obs, 1e-9)))
 
 
-def cpu_baseline(inst, n_sample, precision):
-    """FP64 oracle on the first n_sample observations; the GPU runs the same
-    prefix for the error figure."""
-    import torch
+def cpu_baseline(inst, n_sample, forms):
+    """FP64 oracle on the first n_sample observations, timed on this host; every
+    GPU form runs the same subset for its error figure (x', rho' norm-wise,
+    loglik relative), flagged against the 1e-4 target."""
     from oracle import em_oracle as O
-    from paper_2204_04754_amd import synth
     from tests.gpu_helpers import gpu_step, rel
 
-    ys = inst.y[:n_sample]
+    ys = np.ascontiguousarray(inst.y[:n_sample])
     cores = len(os.sched_getaffinity(0))
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"]
+                   or [1])
+    except Exception:   # threadpoolctl missing: report the environment's setting
+        blas = int(os.environ.get("OMP_NUM_THREADS", "1"))
     t = time.perf_counter()
     ref = O.em_step(ys, inst.x0, inst.log_rho0, inst.sigma, inst.K)
     dt = time.perf_counter() - t
     pairs = n_sample * inst.Lh * inst.Lh
-    g = gpu_step(ys, inst.x0, inst.log_rho0, inst.sigma, inst.K, precision, debug=False)
-    err = dict(x=rel(g["x_new"], ref["x_new"]), rho=rel(g["rho_new"], ref["rho_new"]),
-               loglik=abs(g["loglik"] - ref["loglik"]) / abs(ref["loglik"]))
-    threads = os.environ.get("OMP_NUM_THREADS")
-    return dict(value=pairs / dt, unit="obs×shift pairs/s", cores=cores, kind="oracle",
-                sample=f"first {n_sample} observations of the workload, one EM step "
-                       f"({dt:.1f} s, FP64 NumPy, BLAS threads={threads or 'default'})"), err
+    errs = {}
+    for prec in forms:
+        g = gpu_step(ys, inst.x0, inst.log_rho0, inst.sigma, inst.K, prec, debug=False)
+        e = dict(x=rel(g["x_new"], ref["x_new"]), rho=rel(g["rho_new"], ref["rho_new"]),
+                 loglik=abs(g["loglik"] - ref["loglik"]) / abs(ref["loglik"]))
+        e["within_1e-4"] = bool(e["x"] <= 1e-4 and e["rho"] <= 1e-4)
+        errs[prec] = e
+    return dict(value=pairs / dt, unit="obs×shift pairs/s", cores=blas, kind="oracle",
+                sample=f"first {n_sample} observations of the workload, one EM step from its seeded "
+                       f"start ({dt:.1f} s; FP64 NumPy: the loop over shifts in one thread, the "
+                       f"M-step products on {blas} BLAS threads; {cores} host cores visible)"), errs
+
+
+def roofline(inst, precision, phase_ms, workload):
+    """Roofline of the dominant kernel (phase 3: the single pass, else the
+    posterior / back-projection pass) and, for two passes, of the score pass
+    (phase 1).  Algorithmic work: 2 Ll^2 flop per pair for the score and as
+    much for the back-projection; issued work adds the pass-2 recompute of the
+    scores and the split's products per multiply-add."""
+    import math
+    from paper_2204_04754_amd import binding as B
+    pairs = inst.pairs_per_step
+    Ll2 = inst.Ll * inst.Ll
+    bound, peak = PEAK[precision]
+    n_pass = B.srmra_em_step_passes(inst.N, inst.Ll, inst.K, precision)
+    prod = float(PRODUCTS.get(precision, 1))
+    targ = f"<{inst.Ll}, {PRODUCTS[precision]}>" if precision in PRODUCTS else f"<{inst.Ll}>"
+    k_ms = phase_ms[3]
+    s_name = None
+    if precision == "fp32_fft":
+        # pass 2: an inverse and a forward complex 2-D FFT of Ll^2 points per
+        # (observation, component) pair, 5 n log2 n flop each
+        kname = f"k_fft_pass2<{inst.Ll}>"
+        alg_flop = inst.N * inst.K * inst.K * 2 * 5.0 * Ll2 * math.log2(Ll2)
+        issued_flop = alg_flop
+    elif n_pass == 1:
+        # the BF16 split's single pass at 4 < K^2 <= 16 is its own kernel
+        wide = precision in PRODUCTS and inst.K * inst.K > 4
+        kname = f"k_fused{'16' if wide else ''}_{KNAME[precision]}{targ}"
+        alg_flop = 4.0 * Ll2 * pairs
+        issued_flop = alg_flop * prod
+    elif precision in PRODUCTS and inst.Ll >= 48:   # BF16 split with 2 x 2 tiles
+        kname = f"b16w::k_backproject{targ}"
+        s_name = f"b16w::k_score_lse{targ}"
+        alg_flop = 2.0 * Ll2 * pairs
+        issued_flop = 4.0 * Ll2 * pairs * prod
+    else:
+        kname = f"k_backproject_{KNAME[precision]}{targ}"
+        s_name = f"k_score_lse_{KNAME[precision]}{targ}"
+        alg_flop = 2.0 * Ll2 * pairs
+        issued_flop = 4.0 * Ll2 * pairs * prod
+    traffic = traffic_bytes((workload, precision, kname))
+    roof = {"bound": bound, "achieved": alg_flop / (k_ms * 1e-3) / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": alg_flop / (k_ms * 1e-3) / peak, "traffic": traffic,
+            # the same kernel against the HBM roofline (counter bytes / duration / 8 TB/s)
+            "hbm_frac": None if traffic is None else traffic / (k_ms * 1e-3) / HBM_PEAK,
+            "kernel": kname, "kernel_ms": k_ms, "passes": n_pass,
+            "issued_frac": issued_flop / (k_ms * 1e-3) / peak}
+    if n_pass == 2:
+        s_ms = phase_ms[1]
+        if precision == "fp32_fft":   # one inverse complex FFT per (observation, component)
+            s_flop = inst.N * inst.K * inst.K * 5.0 * Ll2 * math.log2(Ll2)
+            s_issued = s_flop
+            s_name = f"k_fft_pass1<{inst.Ll}>"
+        else:
+            s_flop = 2.0 * Ll2 * pairs
+            s_issued = s_flop * prod
+        st = traffic_bytes((workload, precision, s_name)) if s_name else None
+        roof["score_pass"] = {"kernel": s_name, "kernel_ms": s_ms,
+                              "achieved": s_flop / (s_ms * 1e-3) / 1e12,
+                              "frac": s_flop / (s_ms * 1e-3) / peak,
+                              "issued_frac": s_issued / (s_ms * 1e-3) / peak, "traffic": st,
+                              "hbm_frac": None if st is None else st / (s_ms * 1e-3) / HBM_PEAK}
+    return roof
 
 
 def bench_batched(args):
@@ -526,57 +608,7 @@ def main():
                             phase_ms=er["phase_ms"], obs_prep=er["prep"])
         print(f"[bench] {extra}: {er['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-
-    # roofline of the dominant kernel (phase 3): the single pass where the
-    # instance's components fit one workgroup (score + back-projection, each
-    # 2 Ll^2 flop per pair), else the posterior / back-projection pass (2 Ll^2
-    # per pair algorithmic; it also re-issues the score).  BF16 split issues 3
-    # products per multiply-add.
-    from paper_2204_04754_amd import binding as B
-    Ll2 = inst.Ll * inst.Ll
-    bound, peak = PEAK[args.precision]
-    n_pass = B.srmra_em_step_passes(inst.N, inst.Ll, inst.K, args.precision)
-    prod = float(PRODUCTS.get(args.precision, 1))
-    targ = f"<{inst.Ll}, {PRODUCTS[args.precision]}>" if args.precision in PRODUCTS else f"<{inst.Ll}>"
-    k_ms = main_r["phase_ms"][3]
-    if args.precision == "fp32_fft":
-        # pass 2: an inverse and a forward complex 2-D FFT of Ll^2 points per
-        # (observation, component) pair, 5 n log2 n flop each
-        import math
-        kname = f"k_fft_pass2<{inst.Ll}>"
-        alg_flop = inst.N * inst.K * inst.K * 2 * 5.0 * Ll2 * math.log2(Ll2)
-        issued_flop = alg_flop
-    elif n_pass == 1:
-        kname = f"k_fused_{KNAME[args.precision]}{targ}"
-        alg_flop = 4.0 * Ll2 * pairs
-        issued_flop = alg_flop * prod
-    elif args.precision in PRODUCTS and inst.Ll >= 48:   # BF16 split with 2 x 2 tiles
-        kname = f"b16w::k_backproject{targ}"
-        alg_flop = 2.0 * Ll2 * pairs
-        issued_flop = 4.0 * Ll2 * pairs * prod
-    else:
-        kname = f"k_backproject_{KNAME[args.precision]}{targ}"
-        alg_flop = 2.0 * Ll2 * pairs
-        issued_flop = 4.0 * Ll2 * pairs * prod
-    achieved = alg_flop / (k_ms * 1e-3)
-    traffic = traffic_bytes((args.workload, args.precision, kname))
-    roof = {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": traffic,
-            # the same kernel against the HBM roofline (counter bytes / duration / 8 TB/s)
-            "hbm_frac": None if traffic is None else traffic / (k_ms * 1e-3) / HBM_PEAK,
-            "kernel": kname, "kernel_ms": k_ms, "passes": n_pass,
-            "issued_frac": issued_flop / (k_ms * 1e-3) / peak}
-    if n_pass == 2:
-        s_ms = main_r["phase_ms"][1]
-        if args.precision == "fp32_fft":   # one inverse complex FFT per (observation, component)
-            import math
-            s_flop = inst.N * inst.K * inst.K * 5.0 * Ll2 * math.log2(Ll2)
-            roof["score_pass"] = {"kernel_ms": s_ms, "frac": s_flop / (s_ms * 1e-3) / peak,
-                                  "issued_frac": s_flop / (s_ms * 1e-3) / peak}
-        else:
-            roof["score_pass"] = {"kernel_ms": s_ms,
-                                  "frac": 2.0 * Ll2 * pairs / (s_ms * 1e-3) / peak,
-                                  "issued_frac": 2.0 * Ll2 * pairs * prod / (s_ms * 1e-3) / peak}
+    roof = roofline(inst, args.precision, main_r["phase_ms"], args.workload)
 
     out = {"metric": METRIC, "value": value, "unit": "obs×shift pairs/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": forms[args.precision]["ms_per_step"],
@@ -598,12 +630,33 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = nb
         del src, dst
+    fastest = min(forms, key=lambda k: forms[k]["ms_per_step"])
+    out["fastest_form"] = {"precision": fastest, "pairs_per_s": forms[fastest]["pairs_per_s"],
+                           "ms_per_step": forms[fastest]["ms_per_step"]}
+    if args.secondary_workload:
+        t = time.perf_counter()
+        inst2 = synth.workload(args.secondary_workload)
+        sr = run_form(inst2, args.secondary_precision, args.steps, args.warmup)
+        del sr["job"]
+        out["secondary"] = {
+            "workload": args.secondary_workload, "precision": args.secondary_precision,
+            "L_high": inst2.Lh, "K": inst2.K, "L_low": inst2.Ll, "N": inst2.N, "sigma": inst2.sigma,
+            "ms_per_step": sr["ms_per_step"],
+            "pairs_per_s": inst2.pairs_per_step / (sr["ms_per_step"] * 1e-3),
+            "roofline": roofline(inst2, args.secondary_precision, sr["phase_ms"], args.secondary_workload)}
+        print(f"[bench] secondary {args.secondary_workload} {args.secondary_precision}: "
+              f"{sr['ms_per_step']:.2f} ms/step ({time.perf_counter() - t:.1f} s)",
+              file=sys.stderr, flush=True)
+        del inst2
     if not args.no_cpu:
         n = args.cpu_sample or oracle_sample_size(inst, args.cpu_seconds)
         n = min(n, inst.N)
-        cb, err = cpu_baseline(inst, n, args.precision)
+        t = time.perf_counter()
+        cb, err = cpu_baseline(inst, n, list(forms))
         out["cpu_baseline"] = cb
         out["rel_err_vs_oracle_on_sample"] = err
+        print(f"[bench] cpu baseline and errors ({time.perf_counter() - t:.1f} s)", file=sys.stderr,
+              flush=True)
     print(json.dumps(out), flush=True)
 
 
