@@ -65,7 +65,9 @@ typedef enum {
     SRMRA_EINVAL = -1,        /* bad argument (null pointer, size, sigma, aliasing) */
     SRMRA_EUNSUPPORTED = -2,  /* shape or precision not built into this library   */
     SRMRA_EWORKSPACE = -3,    /* workspace / prepared buffer too small              */
-    SRMRA_EDEVICE = -4        /* a HIP launch reported an error                     */
+    SRMRA_EDEVICE = -4,       /* a HIP launch reported an error                     */
+    SRMRA_ESCRATCH = -5       /* srmra_em_step_noalloc: the shape needs more than
+                                 SRMRA_SCRATCH_BYTES of workspace                   */
 } srmra_status;
 
 /* Arithmetic of the two dense contractions (score and back-projection).
@@ -116,6 +118,27 @@ int srmra_em_step(const float* y, int64_t N, int L_low, int K,
                   float* x_new, float* rho_new, double* loglik,
                   int precision, void* workspace, size_t workspace_bytes,
                   hipStream_t stream);
+
+/* Allocation-free form of srmra_em_step, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments and results as srmra_em_step
+ * without the workspace: the step's workspace is a fixed array of
+ * SRMRA_SCRATCH_BYTES bytes of device memory inside the library, one per GPU,
+ * held until the process ends.  Returns SRMRA_ESCRATCH, with nothing
+ * enqueued, when srmra_em_step_workspace_bytes(N, L_low, K, precision)
+ * exceeds SRMRA_SCRATCH_BYTES (every FP32 form up to N = 200000 at
+ * L_low 32, K 4; the BF16 split and FFT forms, whose workspace holds the
+ * prepared observations, up to a few thousand observations at L_low 32).
+ * All calls on one GPU share its single array: calls that overlap on one GPU
+ * (other streams, other threads) race and must be ordered by the caller.  The
+ * step writes every part of the array it later reads, so nothing carries over
+ * between calls.  The first call on a device resolves that device's address
+ * of the array.  Results are bitwise those of srmra_em_step. */
+#define SRMRA_SCRATCH_BYTES ((size_t)64 << 20)
+int srmra_em_step_noalloc(const float* y, int64_t N, int L_low, int K,
+                          const float* x, const float* log_rho, float sigma,
+                          float* x_new, float* rho_new, double* loglik,
+                          int precision, hipStream_t stream);
 
 /* Per-job work that does not depend on theta: the intensity offset mu (the
  * mean of all observation pixels, FP64, rounded to FP32), the per-observation

@@ -22,6 +22,8 @@ SRMRA_EINVAL = -1
 SRMRA_EUNSUPPORTED = -2
 SRMRA_EWORKSPACE = -3
 SRMRA_EDEVICE = -4
+SRMRA_ESCRATCH = -5
+SRMRA_SCRATCH_BYTES = 64 << 20   # the library's per-device scratch array (srmra_em_step_noalloc)
 
 SRMRA_FP32_PLAIN = FP32_PLAIN = 0
 SRMRA_FP32_MFMA = FP32_MFMA = 1
@@ -86,6 +88,9 @@ def lib():
             L.srmra_em_step.restype = _int
             L.srmra_em_step.argtypes = [_vp, _i64, _int, _int, _vp, _vp, _f, _vp, _vp, _vp, _int,
                                         _vp, _sz, _vp]
+            L.srmra_em_step_noalloc.restype = _int
+            L.srmra_em_step_noalloc.argtypes = [_vp, _i64, _int, _int, _vp, _vp, _f, _vp, _vp, _vp,
+                                                _int, _vp]
             L.srmra_em_step_prepared.restype = _int
             L.srmra_em_step_prepared.argtypes = [_vp, _vp, _sz, _i64, _int, _int, _vp, _vp, _f,
                                                  _vp, _vp, _vp, _vp, _int, _vp, _sz, _vp]
@@ -213,6 +218,15 @@ def srmra_em_step(y, N, L_low, K, x, log_rho, sigma, x_new, rho_new, loglik, pre
                                _ptr(loglik, torch.float64), _prec(precision), _ptr(workspace),
                                workspace.numel() * workspace.element_size(), _stream(stream)),
            "srmra_em_step")
+
+
+def srmra_em_step_noalloc(y, N, L_low, K, x, log_rho, sigma, x_new, rho_new, loglik, precision,
+                          stream=None) -> None:
+    _check(lib().srmra_em_step_noalloc(_ptr(y, torch.float32), N, L_low, K, _ptr(x, torch.float32),
+                                       _ptr(log_rho, torch.float32), float(sigma),
+                                       _ptr(x_new, torch.float32), _ptr(rho_new, torch.float32),
+                                       _ptr(loglik, torch.float64), _prec(precision),
+                                       _stream(stream)), "srmra_em_step_noalloc")
 
 
 def srmra_em_step_prepared(y, prep, N, L_low, K, x, log_rho, sigma, x_new, rho_new, log_rho_new,

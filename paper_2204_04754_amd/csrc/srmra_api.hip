@@ -365,6 +365,7 @@ const char* srmra_status_string(int status) {
         case SRMRA_EUNSUPPORTED: return "unsupported shape or precision";
         case SRMRA_EWORKSPACE: return "workspace or prepared buffer too small or misaligned";
         case SRMRA_EDEVICE: return "device launch error";
+        case SRMRA_ESCRATCH: return "shape needs more workspace than the library's scratch array";
     }
     return "unknown status";
 }
@@ -497,6 +498,50 @@ int srmra_em_step(const float* y, int64_t N, int L_low, int K, const float* x,
     return srmra_em_step_debug(y, nullptr, 0, N, L_low, K, x, log_rho, sigma, x_new, rho_new,
                                nullptr, loglik, nullptr, nullptr, nullptr, precision, workspace,
                                workspace_bytes, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free step
+namespace {
+// The workspace of srmra_em_step_noalloc: one fixed array per device.  Host
+// code never names it directly (its host-side name is not a device address);
+// it uses the per-device address resolved below.
+static __device__ __align__(256) unsigned char scratch[SRMRA_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch[64] = {};
+
+// This device's address of `scratch`, resolved once per device with that
+// device current; nullptr if the runtime cannot resolve it.
+void* scratch_address() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch[dev] = ptr;
+    }
+    return g_scratch[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int srmra_em_step_noalloc(const float* y, int64_t N, int L_low, int K, const float* x,
+                          const float* log_rho, float sigma, float* x_new, float* rho_new,
+                          double* loglik, int precision, hipStream_t stream) {
+    int st = check_step_args(y, N, L_low, K, x, log_rho, sigma, x_new, rho_new, loglik);
+    if (st != SRMRA_OK) return st;
+    Geom g;
+    st = make_geom(N, L_low, K, precision, true, g);
+    if (st != SRMRA_OK) return st;
+    if (g.total > SRMRA_SCRATCH_BYTES) return SRMRA_ESCRATCH;
+    void* ws = scratch_address();
+    if (!ws) return SRMRA_EDEVICE;
+    return srmra_em_step(y, N, L_low, K, x, log_rho, sigma, x_new, rho_new, loglik, precision, ws,
+                         SRMRA_SCRATCH_BYTES, stream);
 }
 
 // ---------------------------------------------------------------- batched form
