@@ -30,7 +30,9 @@
  *  - every pointer argument except `probs` / `plan` / `workspace_bytes` of the
  *    plan calls is a DEVICE pointer; the caller owns every buffer;
  *  - the library never allocates or frees device memory and never copies
- *    device data to the host; only srmra_plan_upload synchronises (its stream);
+ *    device data to the host, and never synchronises a stream (a plan waits for
+ *    its own earlier descriptor upload before rewriting the pinned host buffer
+ *    that upload reads);
  *  - arguments are validated on the host before anything is enqueued; on an
  *    error return nothing has been enqueued;
  *  - on success all work is enqueued asynchronously on `stream`; execution
@@ -247,7 +249,9 @@ int srmra_plan_form(int precision, int L_low);
  * current device and released by srmra_plan_destroy: srmra_plan_execute forks
  * the classes of each pass onto them and joins them back to the caller's
  * stream (graph-capturable), so the plan must be executed on that device.
- * If they cannot be created the classes run one after another instead. */
+ * If they cannot be created the classes run one after another instead.
+ * srmra_plan_upload also gives the plan one event and a pinned host staging
+ * buffer (hipHostMalloc, host memory), released by srmra_plan_destroy. */
 int srmra_plan_create(const srmra_problem* probs, int count, int precision,
                       srmra_plan** plan, size_t* workspace_bytes);
 
@@ -294,9 +298,12 @@ int srmra_plan_set_iterate(srmra_plan* plan, int index, const float* x,
                            const float* log_rho, float* x_new, float* rho_new,
                            float* log_rho_new);
 
-/* Copy the plan's device descriptors and work lists into `workspace`
- * (hipMemcpyAsync from host memory, then a synchronisation of `stream`: call
- * it outside graph capture).  Resets the ping-pong parity. */
+/* Copy the plan's device descriptors and work lists into `workspace`: they are
+ * written into a pinned host staging buffer that the plan owns and copied with
+ * hipMemcpyAsync on `stream`; the call does not wait for the copies (a later
+ * upload of the same plan, or srmra_plan_destroy, waits for them before
+ * reusing or freeing the staging buffer).  Call it outside graph capture.
+ * Resets the ping-pong parity. */
 int srmra_plan_upload(srmra_plan* plan, void* workspace, size_t workspace_bytes,
                       hipStream_t stream);
 

@@ -128,7 +128,7 @@ struct Geom {
 };
 
 int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
-              int64_t chunk_override = 0, int tile = 0, bool plan = false) {
+              int64_t chunk_override = 0, int tile = 0) {
     if (N < 1 || N > (int64_t)INT32_MAX || K < 1 || LL < 1) return SRMRA_EINVAL;
     if (!supported_ll(LL)) return SRMRA_EUNSUPPORTED;
     if ((int64_t)K * LL > 4096 || K * K > 256) return SRMRA_EUNSUPPORTED;
@@ -156,9 +156,7 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
         ok = bf16_geom(LL, g.KK, split_products(prec), tile, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
         size_t lds = 0;
         const void* ff = nullptr;
-        // (plans run the single pass only where it fits their 256-thread class kernels)
-        if (ok && tile == 0 && !(plan && g.KK > 4) &&
-            bf16_fused_geom(LL, g.KK, split_products(prec), g.cpb, g.ntile, lds, ff)) {
+        if (ok && tile == 0 && bf16_fused_geom(LL, g.KK, split_products(prec), g.cpb, g.ntile, lds, ff)) {
             g.fuse_bf16 = 1;
             g.lds1 = 0;
             g.lds2 = lds;
@@ -565,7 +563,16 @@ struct srmra_plan {
     hipEvent_t fork[2] = {};
     hipEvent_t join[2][kAuxStreams] = {};
     bool concurrent = false;
+    // pinned host staging of the descriptors and work lists, read by the
+    // asynchronous copies of the last upload until `staged` completes
+    void* staging = nullptr;
+    size_t staging_bytes = 0;
+    hipEvent_t staged = nullptr;
+    bool staged_pending = false;
     ~srmra_plan() {
+        if (staged_pending) (void)hipEventSynchronize(staged);
+        if (staging) (void)hipHostFree(staging);
+        if (staged) (void)hipEventDestroy(staged);
         for (int a = 0; a < kAuxStreams; ++a)
             if (aux[a]) (void)hipStreamDestroy(aux[a]);
         for (int q = 0; q < 2; ++q) {
@@ -589,15 +596,20 @@ int form_of(int precision, int LL) {
 // the precision a batched form runs in
 int prec_of_form(int f) {
     switch (f) {
-        case FORM_BF16: case FORM_BF16F: return SRMRA_BF16_SPLIT3;
-        case FORM_BF16X4: case FORM_BF16X4F: return SRMRA_BF16_SPLIT4;
+        case FORM_BF16: case FORM_BF16F: case FORM_BF16W: return SRMRA_BF16_SPLIT3;
+        case FORM_BF16X4: case FORM_BF16X4F: case FORM_BF16X4W: return SRMRA_BF16_SPLIT4;
         case FORM_VALU: return SRMRA_FP32_PLAIN;
     }
     return SRMRA_FP32_MFMA;
 }
-bool is_bf16_form(int f) { return f == FORM_BF16 || f == FORM_BF16X4 || f == FORM_BF16F || f == FORM_BF16X4F; }
+bool is_bf16_form(int f) {
+    return f == FORM_BF16 || f == FORM_BF16X4 || f == FORM_BF16F || f == FORM_BF16X4F || f == FORM_BF16W ||
+           f == FORM_BF16X4W;
+}
 // forms with no pass-1 launch (their log-likelihood combine runs after pass 2)
-bool single_pass_form(int f) { return f == FORM_FUSED || f == FORM_BF16F || f == FORM_BF16X4F; }
+bool single_pass_form(int f) {
+    return f == FORM_FUSED || f == FORM_BF16F || f == FORM_BF16X4F || f == FORM_BF16W || f == FORM_BF16X4W;
+}
 
 // observations per work item: about 2^28 multiply-adds, but no fewer than 128
 // chunks per instance while an item keeps 2^24 or more (at small L_low 2^28
@@ -669,7 +681,7 @@ int srmra_plan_form(int precision, int L_low) {
 
 int64_t srmra_plan_default_item_obs(int64_t N, int L_low, int K, int form_precision) {
     Geom g;
-    const int st = make_geom(N, L_low, K, form_precision, false, g, 0, 0, true);
+    const int st = make_geom(N, L_low, K, form_precision, false, g);
     if (st != SRMRA_OK) return st;
     return default_chunk(g);
 }
@@ -729,13 +741,14 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         }
         const int fprec = prec_of_form(f);
         Geom g0;
-        st = make_geom(pr.N, pr.L_low, pr.K, fprec, false, g0, 0, tile, true);
+        st = make_geom(pr.N, pr.L_low, pr.K, fprec, false, g0, 0, tile);
         if (st != SRMRA_OK) { delete P; return st; }
         Geom g;
-        make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, item_obs > 0 ? item_obs : default_chunk(g0), tile, true);
+        make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, item_obs > 0 ? item_obs : default_chunk(g0), tile);
         if (pr.prep_bytes < g.prep_bytes) { delete P; return SRMRA_EWORKSPACE; }
         if (f == FORM_MFMA && g.fuse_wc) f = FORM_FUSED;
-        if (g.fuse_bf16) f = f == FORM_BF16X4 ? FORM_BF16X4F : FORM_BF16F;
+        if (g.fuse_bf16 && g.KK > 4) f = f == FORM_BF16X4 ? FORM_BF16X4W : FORM_BF16W;
+        else if (g.fuse_bf16) f = f == FORM_BF16X4 ? FORM_BF16X4F : FORM_BF16F;
         P->geoms.push_back(g);
         P->form.push_back(f);
         int cls = -1;
@@ -762,7 +775,8 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
                 const int64_t nobs = std::min<int64_t>(g.chunk_obs, g.N - (int64_t)ch * g.chunk_obs);
                 const double cst = (double)nobs * g.cpb * (double)g.LL * g.LL * g.LL * g.LL *
                                    (f == FORM_VALU ? 2.0 : (f == FORM_BF16 ? 0.5 : (f == FORM_BF16X4 ? 0.67 :
-                                    (f == FORM_BF16F ? 0.35 : (f == FORM_BF16X4F ? 0.45 : 1.0)))));
+                                    ((f == FORM_BF16F || f == FORM_BF16W) ? 0.35
+                                     : ((f == FORM_BF16X4F || f == FORM_BF16X4W) ? 0.45 : 1.0)))));
                 costs.push_back({cls, cst, make_int4(i, ch, cg, 0)});
             }
         }
@@ -807,7 +821,7 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
     for (auto& C : P->classes) {
         const void* f1 = class_pass_fn(1, C.form, C.LL);
         C.blocks1 = f1 ? cus * occupancy(f1, C.lds1) : 0;
-        C.blocks2 = cus * occupancy(class_pass_fn(2, C.form, C.LL), C.lds2);
+        C.blocks2 = cus * occupancy(class_pass_fn(2, C.form, C.LL), C.lds2, class_threads(C.form));
     }
     // helper streams for concurrent classes (without them the classes run one
     // after another on the caller's stream)
@@ -845,18 +859,52 @@ int srmra_plan_upload(srmra_plan* plan, void* workspace, size_t workspace_bytes,
     if (workspace_bytes < plan->total) return SRMRA_EWORKSPACE;
     char* ws = (char*)workspace;
     const int n = (int)plan->probs.size();
-    static thread_local std::vector<InstDesc> desc;
-    desc.assign(2 * (size_t)n, InstDesc{});
+    // the descriptors and work lists go through a pinned staging copy owned by
+    // the plan, so the copies are asynchronous; a previous upload's copies
+    // must have left the staging buffer before it is rewritten
+    const size_t b_desc = sizeof(InstDesc) * 2 * (size_t)n;
+    const size_t b_pass = sizeof(int4) * plan->pass_items.size();
+    const size_t b_pack = sizeof(int2) * plan->pack_items.size();
+    const size_t b_comb = sizeof(int2) * plan->combine_items.size();
+    const size_t b_red = sizeof(int2) * plan->reduce_items.size();
+    const size_t need = b_desc + b_pass + b_pack + b_comb + b_red;
+    if (plan->staged_pending && hipEventSynchronize(plan->staged) != hipSuccess) return SRMRA_EDEVICE;
+    plan->staged_pending = false;
+    if (!plan->staged && hipEventCreateWithFlags(&plan->staged, hipEventDisableTiming) != hipSuccess)
+        return SRMRA_EDEVICE;
+    if (plan->staging_bytes < need) {
+        if (plan->staging) (void)hipHostFree(plan->staging);
+        plan->staging = nullptr;
+        plan->staging_bytes = 0;
+        if (hipHostMalloc(&plan->staging, need, hipHostMallocDefault) != hipSuccess) return SRMRA_EDEVICE;
+        plan->staging_bytes = need;
+    }
+    char* h = (char*)plan->staging;
+    InstDesc* desc = (InstDesc*)h;
     for (int par = 0; par < 2; ++par)
-        for (int i = 0; i < n; ++i) fill_desc(plan, i, par, desc[(size_t)par * n + i], ws);
-    hipError_t e = hipMemcpyAsync(ws + plan->o_desc, desc.data(), sizeof(InstDesc) * desc.size(),
-                                  hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_pass, plan->pass_items.data(), sizeof(int4) * plan->pass_items.size(), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_pack, plan->pack_items.data(), sizeof(int2) * plan->pack_items.size(), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_comb, plan->combine_items.data(), sizeof(int2) * plan->combine_items.size(), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_red, plan->reduce_items.data(), sizeof(int2) * plan->reduce_items.size(), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);   // host staging buffers are reused
+        for (int i = 0; i < n; ++i) {
+            desc[(size_t)par * n + i] = InstDesc{};
+            fill_desc(plan, i, par, desc[(size_t)par * n + i], ws);
+        }
+    size_t off = b_desc;
+    auto stage = [&](const void* src, size_t bytes) {
+        memcpy(h + off, src, bytes);
+        const char* p = h + off;
+        off += bytes;
+        return p;
+    };
+    const char* s_pass = stage(plan->pass_items.data(), b_pass);
+    const char* s_pack = stage(plan->pack_items.data(), b_pack);
+    const char* s_comb = stage(plan->combine_items.data(), b_comb);
+    const char* s_red = stage(plan->reduce_items.data(), b_red);
+    hipError_t e = hipMemcpyAsync(ws + plan->o_desc, h, b_desc, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_pass, s_pass, b_pass, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_pack, s_pack, b_pack, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_comb, s_comb, b_comb, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ws + plan->o_red, s_red, b_red, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(plan->staged, stream);
     if (e != hipSuccess) return SRMRA_EDEVICE;
+    plan->staged_pending = true;
     for (auto& C : plan->classes) {
         for (int pass = 1; pass <= 2; ++pass) {
             const void* f = class_pass_fn(pass, C.form, C.LL);   // null: single-pass class, pass 1

@@ -7,8 +7,13 @@ namespace srmra {
 // FORM_FUSED: FP32 MFMA single pass (no pass-1 launch; the log-likelihood
 // combine of these instances runs after pass 2)
 // FORM_BF16F / FORM_BF16X4F: the BF16 split single pass (3 / 4 products)
+// FORM_BF16W / FORM_BF16X4W: the BF16 split single pass at 4 < K^2 <= 16
+// (512-thread workgroups)
 enum { FORM_VALU = 0, FORM_MFMA = 1, FORM_BF16 = 2, FORM_FUSED = 3, FORM_BF16X4 = 4, FORM_BF16F = 5,
-       FORM_BF16X4F = 6 };
+       FORM_BF16X4F = 6, FORM_BF16W = 7, FORM_BF16X4W = 8 };
+
+// threads per workgroup of a class's pass kernels
+inline int class_threads(int form) { return (form == FORM_BF16W || form == FORM_BF16X4W) ? 512 : 256; }
 
 struct InstDesc {
     StepArgs p;                  // per-instance step arguments (workspace pointers set)

@@ -32,7 +32,9 @@ __global__ __launch_bounds__(256) void k_batch_pack_xb(const InstDesc* __restric
                                                        const int2* __restrict__ items) {
     const int2 it = items[blockIdx.x];
     const InstDesc& d = D[it.x];
-    if (d.form != FORM_BF16 && d.form != FORM_BF16X4 && d.form != FORM_BF16F && d.form != FORM_BF16X4F) return;
+    if (d.form != FORM_BF16 && d.form != FORM_BF16X4 && d.form != FORM_BF16F && d.form != FORM_BF16X4F &&
+        d.form != FORM_BF16W && d.form != FORM_BF16X4W)
+        return;
     uint4* xb = const_cast<uint4*>(d.p.xb);
     if (d.LL == 16) {
         for (int ks = threadIdx.x >> 6; ks < b16s::NK; ks += 4) b16s::pack_xb_body(d.p, d.x, it.y, ks, xb);
@@ -124,8 +126,7 @@ void k_class_pass(const InstDesc* __restrict__ D,
             b16::Prep q;
             q.yT = d.yT;
             q.yo = d.yo;
-            if (d.p.KK <= 4) b16::bf16_pass2_body<LL, NP, true>(d.p, q, w.y, 0, lds);
-            else b16::bf16_fused16_body<LL, NP>(d.p, q, w.y, lds);
+            b16::bf16_pass2_body<LL, NP, true>(d.p, q, w.y, 0, lds);
         } else if constexpr (FORM == FORM_FUSED) {
             mfma_fused_body<LL>(d.p, w.y, lds);
         } else if constexpr (FORM == FORM_MFMA) {
@@ -138,6 +139,34 @@ void k_class_pass(const InstDesc* __restrict__ D,
         __syncthreads();
     }
 }
+
+// The BF16 single pass at 4 < K^2 <= 16 (512-thread workgroups), persistent
+// over its class's items like k_class_pass.
+template <int NP, int LL>
+__global__ __launch_bounds__(b16::F16_NT, 1) void k_class_fused16(const InstDesc* __restrict__ D,
+                                                                   const int4* __restrict__ items,
+                                                                   int n_items, int* __restrict__ counter) {
+    extern __shared__ float lds[];
+    int* next = reinterpret_cast<int*>(lds);
+    for (;;) {
+        if (threadIdx.x == 0) *next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = *next;
+        __syncthreads();
+        if (it >= n_items) break;
+        const int4 w = items[it];
+        const InstDesc& d = D[w.x];
+        b16::Prep q;
+        q.yT = d.yT;
+        q.yo = d.yo;
+        b16::bf16_fused16_body<LL, NP>(d.p, q, w.y, lds);
+        __syncthreads();
+    }
+}
+template __global__ void k_class_fused16<3, 24>(const InstDesc*, const int4*, int, int*);
+template __global__ void k_class_fused16<3, 32>(const InstDesc*, const int4*, int, int*);
+template __global__ void k_class_fused16<4, 24>(const InstDesc*, const int4*, int, int*);
+template __global__ void k_class_fused16<4, 32>(const InstDesc*, const int4*, int, int*);
 
 #define SRMRA_CLASS(F, L)                                                                     \
     template __global__ void k_class_pass<1, F, L>(const InstDesc*, const int4*, int, int*);  \
@@ -185,6 +214,10 @@ const void* class_pass_fn(int pass, int form, int LL) {
     SRMRA_PICK(FORM_BF16F, 24) SRMRA_PICK(FORM_BF16F, 32)
     SRMRA_PICK(FORM_BF16X4F, 24) SRMRA_PICK(FORM_BF16X4F, 32)
 #undef SRMRA_PICK
+    if (pass == 2 && form == FORM_BF16W && LL == 24) return (const void*)k_class_fused16<3, 24>;
+    if (pass == 2 && form == FORM_BF16W && LL == 32) return (const void*)k_class_fused16<3, 32>;
+    if (pass == 2 && form == FORM_BF16X4W && LL == 24) return (const void*)k_class_fused16<4, 24>;
+    if (pass == 2 && form == FORM_BF16X4W && LL == 32) return (const void*)k_class_fused16<4, 32>;
     return nullptr;
 }
 
@@ -206,7 +239,8 @@ hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
         int slot = 0;
         for (int k = 0; k < L.n_class; ++k) {
             const ClassLaunch& c = L.cls[k];
-            const bool single = c.form == FORM_FUSED || c.form == FORM_BF16F || c.form == FORM_BF16X4F;
+            const bool single = c.form == FORM_FUSED || c.form == FORM_BF16F || c.form == FORM_BF16X4F ||
+                                c.form == FORM_BF16W || c.form == FORM_BF16X4W;
             if (pass == 2 && single) continue;
             const int kp = single ? 2 : pass;   // which kernel of the class
             const void* f = class_pass_fn(kp, c.form, c.LL);
@@ -218,7 +252,8 @@ hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
             void* args[] = {(void*)&desc, (void*)&items, (void*)&n, (void*)&counter};
             const int lane = slot++ % (kAuxStreams + 1);
             hipStream_t sk = (par && lane > 0) ? L.aux[lane - 1] : s;
-            const hipError_t e = hipLaunchKernel(f, dim3(kp == 1 ? c.blocks1 : c.blocks2), dim3(256), args,
+            const hipError_t e = hipLaunchKernel(f, dim3(kp == 1 ? c.blocks1 : c.blocks2),
+                                                 dim3(class_threads(c.form)), args,
                                                  kp == 1 ? c.lds1 : c.lds2, sk);
             if (e != hipSuccess) return e;
         }
