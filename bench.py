@@ -109,7 +109,12 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="batched mode: skip the autotuned runs")
     ap.add_argument("--iterations", type=int, default=20)
     ap.add_argument("--rates", default="5,50,200")
-    ap.add_argument("--jobs", type=int, default=24)
+    ap.add_argument("--jobs", type=int, default=200,
+                    help="serve mode: jobs per arrival rate for the BF16 forms")
+    ap.add_argument("--jobs-fp32", type=int, default=24,
+                    help="serve mode: jobs per arrival rate for the FP32 forms (about 10x slower)")
+    ap.add_argument("--budget-gb", type=float, default=4.0,
+                    help="serve mode: HBM budget of the extra footprint-admission point (0: none)")
     ap.add_argument("--serve-precisions", default="",
                     help="serve mode: comma-separated forms (default: --precision, fp32_mfma, "
                          "fp32_plain); '<form>+fft' runs jobs at an L_low the FFT route supports "
@@ -504,7 +509,10 @@ def bench_errors(args):
 def bench_serve(args):
     """Poisson arrivals of 20-iteration jobs (90% drawn from the batched mix,
     10% Lh 256, K 4, N 20000), swept over arrival rates; solves/s and p50/p99
-    latency (arrival -> completion) per rate and precision."""
+    latency (arrival -> completion) per rate and precision.  The BF16 forms
+    serve `jobs` jobs per rate, the FP32 forms `jobs_fp32`; one more point runs
+    the main form with a small HBM budget so that admission by footprint
+    holds jobs back."""
     import torch
     from paper_2204_04754_amd import synth
     from paper_2204_04754_amd.serve import GPUExecutor, Job, serve
@@ -517,38 +525,51 @@ def bench_serve(args):
           flush=True)
     rates = [float(r) for r in args.rates.split(",")]
     results = {}
-    # one job sequence per rate (same jobs and arrival times for every precision)
-    seqs = {}
-    for rate in rates:
+
+    def sequence(rate, n):
+        # one job sequence per (rate, count): the same jobs and arrival times
+        # for every precision that serves that many jobs
         r = np.random.default_rng(int(rate * 1000) + 7)
-        arr = np.cumsum(r.exponential(1.0 / rate, size=args.jobs))
-        pick = [11 if r.random() < 0.1 else int(r.integers(0, 11)) for _ in range(args.jobs)]
-        seqs[rate] = (arr, pick)
-    precs = [p for p in args.serve_precisions.split(",") if p] or [args.precision, "fp32_mfma", "fp32_plain"]
-    for prec in dict.fromkeys([args.precision] + precs):
+        arr = np.cumsum(r.exponential(1.0 / rate, size=n))
+        pick = [11 if r.random() < 0.1 else int(r.integers(0, 11)) for _ in range(n)]
+        return arr, pick
+
+    def run(prec, rate, n, budget, key):
+        arr, pick = sequence(rate, n)
+        jobs = []
+        for k in range(n):
+            inst = pool[pick[k]]
+            jobs.append(Job(k, inst.y, inst.K, inst.sigma, inst.x0, inst.log_rho0,
+                            iterations=args.iterations, arrival=float(arr[k])))
+        # "<precision>+fft": jobs at an L_low the FFT route supports take it
+        base, _, extra = prec.partition("+")
+        ex = GPUExecutor(precision=base, fft=extra == "fft")
+        rep = serve(jobs, ex, hbm_budget=budget, max_slots=64)
+        summ = rep.summary()
+        summ.update(jobs_served=n, hbm_budget_gb=budget / 2 ** 30)
+        results[key] = summ
+        print(f"[bench] serve {key}: {summ}", file=sys.stderr, flush=True)
+        del ex
+        torch.cuda.empty_cache()
+
+    precs = [p for p in args.serve_precisions.split(",") if p] or \
+        [args.precision + "+fft", args.precision, "fp32_mfma", "fp32_plain"]
+    for prec in dict.fromkeys(precs):
+        n = args.jobs_fp32 if prec.split("+")[0].startswith("fp32") else args.jobs
         for rate in rates:
-            arr, pick = seqs[rate]
-            jobs = []
-            for k in range(args.jobs):
-                inst = pool[pick[k]]
-                jobs.append(Job(k, inst.y, inst.K, inst.sigma, inst.x0, inst.log_rho0,
-                                iterations=args.iterations, arrival=float(arr[k])))
-            # "<precision>+fft": jobs at an L_low the FFT route supports take it
-            base, _, extra = prec.partition("+")
-            ex = GPUExecutor(precision=base, fft=extra == "fft")
-            rep = serve(jobs, ex, hbm_budget=200 << 30, max_slots=64)
-            summ = rep.summary()
-            results[f"{prec}@{rate:g}"] = summ
-            print(f"[bench] serve {prec} rate {rate:g}/s: {summ}", file=sys.stderr, flush=True)
-            del ex
-            torch.cuda.empty_cache()
-    main_key = f"{args.precision}@{rates[-1]:g}"
+            run(prec, rate, n, 200 << 30, f"{prec}@{rate:g}")
+    if args.budget_gb > 0:
+        rate = rates[len(rates) // 2]
+        run(precs[0], rate, args.jobs, int(args.budget_gb * 2 ** 30),
+            f"{precs[0]}@{rate:g}@budget{args.budget_gb:g}GB")
+    main_key = f"{precs[0]}@{rates[-1]:g}"
     out = {"metric": METRIC, "value": results[main_key]["solves_per_s"], "unit": "solves/s",
            "n_gpus": 1, "steps": args.jobs, "warmup": 0, "ms_per_step": None,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": DTYPE[args.precision], "data": "synthetic",
            "config": {"workload": "serve_poisson_mix", "jobs_per_rate": args.jobs,
-                      "iterations_per_job": args.iterations, "rates": rates},
+                      "jobs_per_rate_fp32": args.jobs_fp32,
+                      "iterations_per_job": args.iterations, "rates": rates, "main": precs[0]},
            "p50_latency_s": results[main_key]["p50_latency_s"],
            "p99_latency_s": results[main_key]["p99_latency_s"], "per_rate": results}
     print(json.dumps(out), flush=True)

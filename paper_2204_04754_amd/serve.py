@@ -8,13 +8,20 @@ until it finishes.  Each scheduler tick:
 1. moves arrived jobs into the FIFO queue (jobs whose footprint exceeds the
    whole HBM budget are rejected at once);
 2. admits queued jobs in order while a slot is free and the job's footprint
-   fits in the free budget (uploads y and runs the per-job preparation);
-3. advances every active job by one EM step with one batched execution (the
-   plan is rebuilt only when the active set changed), so jobs that arrived
-   while others were running share the device with them from this tick on;
-4. retires jobs that reached their iteration count (copies x, rho, loglik to
-   the host, frees the buffers) and jobs whose log-likelihood is not finite
-   (marked failed; the others are unaffected).
+   fits in the free budget: their observations are uploaded and prepared on a
+   side stream, which the step stream waits for (an event) before the job's
+   first step, so the upload overlaps the steps already enqueued;
+3. advances every active job that still needs iterations by one EM step with
+   one batched execution (the plan is rebuilt, and its descriptors uploaded
+   asynchronously, only when that set changed), so jobs that arrived while
+   others were running share the device with them from this tick on;
+4. reads the previous tick's log-likelihoods (copied to pinned host memory
+   behind that tick's work, one tick late, so the host never waits for the
+   tick it has just enqueued): a job whose log-likelihood is not finite
+   fails alone;
+5. a job that has enqueued its last iteration has its result copied to
+   pinned host memory behind it and is retired (buffers released, budget
+   freed) once that copy has completed.
 
 The admission policy (`Scheduler`) is plain Python and is tested on the CPU
 with a fake clock; `GPUExecutor` does the device work through the C ABI.  An
@@ -135,7 +142,13 @@ class GPUExecutor:
     """Device side of the server: per-job buffers and the batched plan.  With
     fft=True a job whose L_low the FFT route supports is advanced by its own
     FFT-route step (srmra_em_step_prepared, SRMRA_FP32_FFT) on the same stream
-    after the plan, which holds the other jobs."""
+    after the plan, which holds the other jobs.
+
+    Interface used by `serve`: footprint(job), admit(job), tick(ids) (enqueue
+    one step of ids; returns the previous tick's {id: loglik}), finish(job)
+    (enqueue the result copy), finished() (jobs whose result is on the host),
+    drop(job) (release a failed job's buffers), flush() (the last tick's
+    log-likelihoods)."""
 
     def __init__(self, precision="fp32_mfma", device="cuda", fft=False):
         import torch
@@ -150,6 +163,12 @@ class GPUExecutor:
         self.plan = None
         self.plan_ids: Optional[tuple] = None
         self.workspace = None
+        self.old_plans: List[tuple] = []
+        self.pending_ll = None          # (ids, pinned host tensor, event) of the last tick
+        self.copies: List[tuple] = []   # (job, pinned results, event)
+        if self.device.type == "cuda":
+            self.stream = torch.cuda.current_stream(self.device)
+            self.side = torch.cuda.Stream(self.device)     # default priority
 
     def _form(self, job_or_buf) -> Tuple[int, bool]:
         """(precision the job runs in, whether by its own FFT-route step)."""
@@ -171,24 +190,32 @@ class GPUExecutor:
                 + B.srmra_em_step_workspace_bytes(N, Ll, K, form) + 4 * (2 * Lh * Lh + 6 * Lh) + 4096)
 
     def admit(self, job: Job) -> None:
+        """Upload and prepare on the side stream; the buffers are allocated
+        there and marked as used by the step stream as well."""
         torch, B = self.torch, self.B
         f = dict(device=self.device, dtype=torch.float32)
-        y = torch.as_tensor(np.ascontiguousarray(job.y, np.float32)).to(self.device)
         form, own = self._form(job)
-        prep = B.empty_bytes(B.srmra_prepared_bytes(job.N, job.Ll, job.K, form), self.device)
-        B.srmra_prepare_observations(y, job.N, job.Ll, job.K, form, prep)
         Lh = job.K * job.Ll
-        ws = B.empty_bytes(B.srmra_em_step_workspace_bytes(job.N, job.Ll, job.K, form), self.device) \
-            if own else None
-        self.buf[job.job_id] = dict(
-            y=y, prep=prep, N=job.N, L_low=job.Ll, K=job.K, sigma=job.sigma, own=own, ws=ws,
-            xa=torch.as_tensor(np.asarray(job.x0, np.float32)).to(**f).contiguous(),
-            xb=torch.empty((Lh, Lh), **f),
-            la=torch.as_tensor(np.asarray(job.log_rho0, np.float32)).to(**f).contiguous(),
-            lb=torch.empty((2, Lh), **f),
-            rho_new=torch.empty((2, Lh), **f),
-            loglik=torch.empty(1, dtype=torch.float64, device=self.device),
-            cur=0)
+        with torch.cuda.stream(self.side):
+            y = torch.as_tensor(np.ascontiguousarray(job.y, np.float32)).to(self.device, non_blocking=True)
+            prep = B.empty_bytes(B.srmra_prepared_bytes(job.N, job.Ll, job.K, form), self.device)
+            B.srmra_prepare_observations(y, job.N, job.Ll, job.K, form, prep, self.side)
+            ws = B.empty_bytes(B.srmra_em_step_workspace_bytes(job.N, job.Ll, job.K, form), self.device) \
+                if own else None
+            b = dict(y=y, prep=prep, N=job.N, L_low=job.Ll, K=job.K, sigma=job.sigma, own=own, ws=ws,
+                     xa=torch.as_tensor(np.asarray(job.x0, np.float32)).to(**f, non_blocking=True),
+                     xb=torch.empty((Lh, Lh), **f),
+                     la=torch.as_tensor(np.asarray(job.log_rho0, np.float32)).to(**f, non_blocking=True),
+                     lb=torch.empty((2, Lh), **f),
+                     rho_new=torch.empty((2, Lh), **f),
+                     loglik=torch.empty(1, dtype=torch.float64, device=self.device),
+                     cur=0, ready=torch.cuda.Event())
+            b["ready"].record(self.side)
+        for k in ("y", "prep", "ws", "xa", "xb", "la", "lb", "rho_new", "loglik"):
+            if b[k] is not None:
+                b[k].record_stream(self.stream)
+        b["waited"] = False
+        self.buf[job.job_id] = b
 
     def _problem(self, b):
         cur = b["cur"]
@@ -200,39 +227,103 @@ class GPUExecutor:
                     rho_new=b["rho_new"], loglik=b["loglik"])
 
     def tick(self, ids: List[int]) -> Dict[int, float]:
-        """One EM step of every job in `ids`; returns each job's loglik."""
+        """Enqueue one EM step of every job in `ids` on the step stream and
+        return the log-likelihoods of the previous tick (waiting for that
+        tick only, never for this one)."""
         torch, B = self.torch, self.B
+        for i in ids:
+            b = self.buf[i]
+            if not b["waited"]:
+                self.stream.wait_event(b["ready"])
+                b["waited"] = True
         planned = [i for i in ids if not self.buf[i]["own"]]
         key = tuple(planned)
         if planned and (key != self.plan_ids or self.plan is None):
             if self.plan is not None:
-                self.plan.close()
+                # released one tick later (its helper streams may still run)
+                self.old_plans.append((self.plan, self.workspace))
             self.plan = B.Plan([self._problem(self.buf[i]) for i in planned], self.precision)
             self.workspace = B.empty_bytes(self.plan.workspace_bytes, self.device)
-            self.plan.upload(self.workspace)
+            self.plan.upload(self.workspace, self.stream)
             self.plan_ids = key
         if planned:
-            self.plan.execute(self.workspace)
+            self.plan.execute(self.workspace, self.stream)
         for i in ids:
             b = self.buf[i]
             if b["own"]:
                 q = self._problem(b)
                 B.srmra_em_step_prepared(q["y"], q["prep"], q["N"], q["L_low"], q["K"], q["x"],
                                          q["log_rho"], q["sigma"], q["x_new"], q["rho_new"],
-                                         q["log_rho_new"], q["loglik"], B.SRMRA_FP32_FFT, b["ws"], None)
+                                         q["log_rho_new"], q["loglik"], B.SRMRA_FP32_FFT, b["ws"],
+                                         self.stream)
         for i in ids:
             self.buf[i]["cur"] ^= 1
-        lls = torch.cat([self.buf[i]["loglik"] for i in ids]).cpu().numpy()
-        return {i: float(v) for i, v in zip(ids, lls)}
+        with torch.cuda.stream(self.stream):
+            ll = torch.cat([self.buf[i]["loglik"] for i in ids])
+            host = torch.empty(ll.shape, dtype=ll.dtype, pin_memory=True)
+            host.copy_(ll, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        prev, self.pending_ll = self.pending_ll, (list(ids), host, ev)
+        out = self._read(prev)
+        # plans replaced before the tick just read have no work left on the device
+        while len(self.old_plans) > 1:
+            p, _ = self.old_plans.pop(0)
+            p.close()
+        return out
 
-    def retire(self, job: Job, keep_result: bool = True) -> None:
-        b = self.buf.pop(job.job_id)
-        if keep_result:
-            x = b["xa"] if b["cur"] == 0 else b["xb"]
-            lr = b["la"] if b["cur"] == 0 else b["lb"]
-            job.result = dict(x=x.cpu().numpy(), log_rho=lr.cpu().numpy(),
-                              rho=b["rho_new"].cpu().numpy(), loglik=float(b["loglik"].item()))
-        self.plan_ids = None   # the active set changes
+    @staticmethod
+    def _read(entry) -> Dict[int, float]:
+        if entry is None:
+            return {}
+        ids, host, ev = entry
+        ev.synchronize()
+        return {i: float(v) for i, v in zip(ids, host.numpy())}
+
+    def flush(self) -> Dict[int, float]:
+        """The last tick's log-likelihoods (waits for that tick)."""
+        prev, self.pending_ll = self.pending_ll, None
+        return self._read(prev)
+
+    def finish(self, job: Job) -> None:
+        """Enqueue the copy of the job's result to pinned host memory behind
+        its last step."""
+        torch = self.torch
+        b = self.buf[job.job_id]
+        x = b["xa"] if b["cur"] == 0 else b["xb"]
+        lr = b["la"] if b["cur"] == 0 else b["lb"]
+        with torch.cuda.stream(self.stream):
+            out = {}
+            for k, t in (("x", x), ("log_rho", lr), ("rho", b["rho_new"]), ("loglik", b["loglik"])):
+                h = torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+                h.copy_(t, non_blocking=True)
+                out[k] = h
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        self.copies.append((job, out, ev))
+
+    def finished(self, wait: bool = False) -> List[Job]:
+        """Jobs whose result copy has completed (all pending ones if wait):
+        their result is set and their buffers released."""
+        done, keep = [], []
+        for job, out, ev in self.copies:
+            if wait or ev.query():
+                ev.synchronize()
+                job.result = dict(x=out["x"].numpy().copy(), log_rho=out["log_rho"].numpy().copy(),
+                                  rho=out["rho"].numpy().copy(), loglik=float(out["loglik"].numpy()[0]))
+                self.buf.pop(job.job_id, None)
+                self.plan_ids = None   # the active set changes
+                done.append(job)
+            else:
+                keep.append((job, out, ev))
+        self.copies = keep
+        return done
+
+    def drop(self, job: Job) -> None:
+        """Release a failed job's buffers (the step stream still orders their
+        reuse after the work already enqueued)."""
+        self.buf.pop(job.job_id, None)
+        self.plan_ids = None
 
 
 @dataclass
@@ -260,12 +351,37 @@ def serve(jobs: List[Job], executor, hbm_budget: int, max_slots: int = 64,
           clock: Callable[[], float] = time.perf_counter, sleep=time.sleep,
           on_tick: Optional[Callable[[int, Scheduler], None]] = None) -> ServeReport:
     """Run the continuous-batching loop until every job is finished.  Job
-    arrival times are relative to the start of the loop."""
+    arrival times are relative to the start of the loop.  The executor returns
+    each tick's log-likelihoods one tick later; a job is finished once its
+    last step is enqueued and its result has reached the host."""
     sched = Scheduler(hbm_budget, max_slots, executor.footprint)
     pending = sorted(jobs, key=lambda j: j.arrival)
     t0 = clock()
     k = 0
     ticks = 0
+    finishing = set()
+
+    def check(lls):
+        now = clock() - t0
+        for i, v in lls.items():
+            j = sched.active.get(i)
+            if j is None or i in finishing or np.isfinite(v):
+                continue
+            executor.drop(j)
+            sched.retire(j, now, failed=True, error="non-finite log-likelihood")
+
+    def collect(wait=False):
+        for j in executor.finished(wait):
+            finishing.discard(j.job_id)
+            now = clock() - t0
+            if j.job_id not in sched.active:
+                continue
+            if not np.isfinite(j.result["loglik"]):
+                j.result = None
+                sched.retire(j, now, failed=True, error="non-finite log-likelihood")
+            else:
+                sched.retire(j, now)
+
     while k < len(pending) or not sched.idle:
         now = clock() - t0
         while k < len(pending) and pending[k].arrival <= now:
@@ -273,23 +389,24 @@ def serve(jobs: List[Job], executor, hbm_budget: int, max_slots: int = 64,
             k += 1
         for j in sched.admit(now):
             executor.admit(j)
-        if sched.active:
-            ids = sorted(sched.active)
-            lls = executor.tick(ids)
+        ids = sorted(i for i, j in sched.active.items() if i not in finishing)
+        if ids:
+            check(executor.tick(ids))
             ticks += 1
-            now = clock() - t0
             for i in ids:
-                j = sched.active[i]
+                j = sched.active.get(i)
+                if j is None:
+                    continue
                 j.iters_done += 1
-                if not np.isfinite(lls[i]):
-                    executor.retire(j, keep_result=False)
-                    sched.retire(j, now, failed=True, error="non-finite log-likelihood")
-                elif j.iters_done >= j.iterations:
-                    executor.retire(j)
-                    sched.retire(j, now)
+                if j.iters_done >= j.iterations:
+                    finishing.add(i)
+                    executor.finish(j)
             if on_tick:
                 on_tick(ticks, sched)
-        elif k < len(pending):
+        else:
+            check(executor.flush())
+        collect(wait=not ids)
+        if not ids and not sched.active and k < len(pending):
             sleep(max(0.0, min(0.05, pending[k].arrival - (clock() - t0))))
     rep = ServeReport(jobs=sched.finished, wall=clock() - t0, ticks=ticks)
     return rep

@@ -19,14 +19,18 @@ class FakeClock:
 
 
 class FakeExecutor:
-    """Footprint = N bytes; a tick costs `tick_s` seconds of fake time; jobs
-    whose y contains NaN report a NaN log-likelihood."""
+    """Footprint = N bytes; a tick costs `tick_s` seconds of fake time and
+    reports its log-likelihoods one tick late (as the GPU executor does);
+    jobs whose y contains NaN report a NaN log-likelihood."""
 
     def __init__(self, clock, tick_s=0.01):
         self.clock = clock
         self.tick_s = tick_s
         self.admitted = []
         self.tick_sets = []
+        self.prev = {}
+        self.copies = []
+        self.dropped = []
 
     def footprint(self, job):
         return job.N
@@ -37,13 +41,26 @@ class FakeExecutor:
     def tick(self, ids):
         self.tick_sets.append(tuple(ids))
         self.clock.t += self.tick_s
-        return {i: (np.nan if self.nan.get(i) else -1.0) for i in ids}
+        out, self.prev = self.prev, {i: (np.nan if self.nan.get(i) else -1.0) for i in ids}
+        return out
+
+    def flush(self):
+        out, self.prev = self.prev, {}
+        return out
 
     nan = {}
 
-    def retire(self, job, keep_result=True):
-        if keep_result:
-            job.result = {"loglik": -1.0}
+    def finish(self, job):
+        self.copies.append(job)
+
+    def finished(self, wait=False):
+        out, self.copies = self.copies, []
+        for j in out:
+            j.result = {"loglik": np.nan if self.nan.get(j.job_id) else -1.0}
+        return out
+
+    def drop(self, job):
+        self.dropped.append(job.job_id)
 
 
 def _job(i, N, arrival=0.0, iters=3, nan=False):
@@ -105,6 +122,7 @@ def test_serve_loop_continuous_batching_and_failure_isolation():
     st = {j.job_id: j for j in rep.jobs}
     assert st[0].state == DONE and st[1].state == DONE and st[3].state == DONE
     assert st[2].state == FAILED and "non-finite" in st[2].error
+    assert ex.dropped == [2]           # its buffers released, the others untouched
     # job 1 arrived while job 0 was running and shared its ticks (continuous batching)
     assert any(0 in t and 1 in t for t in ex.tick_sets)
     assert st[1].t_admit >= 0.025 and st[1].t_admit < 0.05
