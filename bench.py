@@ -57,11 +57,9 @@ _BF16_SRC = ("srmra_common.h", "srmra_bf16_impl.h", "srmra_bf16.hip")
 _BF16W_SRC = ("srmra_common.h", "srmra_bf16_impl.h", "srmra_bf16w_impl.h", "srmra_bf16.hip")
 TRAFFIC = {
     ("lh64_k2_n100000", "fp32_mfma", "k_fused_mfma<32>"):
-        dict(bytes=428061491, src=_MFMA_SRC, sha="afe068a4c07ebf90"),
-    ("lh128_k4_n200000_s0.5", "bf16_split3", "k_backproject_bf16<32, 3>"):
-        dict(bytes=1667584512, src=_BF16_SRC, sha="6ff1042a104f29b1"),
-    ("lh128_k4_n200000_s0.5", "bf16_split3", "k_score_lse_bf16<32, 3>"):
-        dict(bytes=855719219, src=_BF16_SRC, sha="6ff1042a104f29b1"),
+        dict(bytes=428054630, src=_MFMA_SRC, sha="5fe9b8ec41a003f1"),
+    ("lh128_k4_n200000_s0.5", "bf16_split3", "k_fused16_bf16<32, 3>"):
+        dict(bytes=15558068326, src=_BF16_SRC, sha="b870e0741896101a"),
     ("lh256_k4_n20000", "bf16_split3", "b16w::k_backproject<64, 3>"):
         dict(bytes=7369647616, src=_BF16W_SRC, sha="f7205148b449a689"),
 }

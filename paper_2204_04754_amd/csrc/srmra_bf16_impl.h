@@ -529,8 +529,8 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
 // observations, stored [plane][a1][column][4 observations] (one 8-byte record
 // per column: two records per fragment).  The posterior mass of a
 // (component, shift) is owned by one lane of one wave for the whole chunk and
-// summed into the chunk's partial in global memory group by group (registers
-// and LDS are both full).
+// summed into the chunk's partial in global memory group by group, as four
+// 16-byte runs per lane and component (registers and LDS are both full).
 constexpr int F16_NOB = 4;   // observations per group
 constexpr int F16_NCW = 2;   // components per wave
 constexpr int F16_NW = 8;    // waves per workgroup
@@ -641,9 +641,18 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
         // A fragment per k-step serving both components, folded into the
         // wave's b accumulators
         bf16x8 wh[NCW][8], wl[NCW][8];
+        // the lane's posterior masses c[t1 = j][t2 = 8 m + 4 g + 0..3] of a
+        // component are four 16-byte runs of the chunk's partial
+        constexpr int NM = LL == 24 ? 3 : 4;
+        const bool first = o0 == c0;
 #pragma unroll
         for (int c = 0; c < NCW; ++c) {
-            float* co = p.cpart + (chunk * p.KK + comp[c]) * (LL * LL);
+            float4* co = reinterpret_cast<float4*>(p.cpart + (chunk * p.KK + comp[c]) * (LL * LL) + j * LL + 4 * g);
+            const bool own = cok[c] && j < LL;
+            float4 cm[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                cm[m] = (own && !first && m < NM) ? co[2 * m] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int s8 = 0; s8 < 8; ++s8) {
                 float w[8];
@@ -661,15 +670,20 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
                         w[4 * r + o] = ww;
                         m += ww;
                     }
-                    // the posterior mass of shift (c, t1 = j, t2): this lane's
-                    // running sum over the chunk's groups
-                    if (sok) {
-                        float* cp = co + j * LL + acc_row(v, lane);
-                        *cp = (o0 == c0) ? m : *cp + m;
+                    float4& q = cm[v >> 2];
+                    switch (v & 3) {
+                        case 0: q.x += m; break;
+                        case 1: q.y += m; break;
+                        case 2: q.z += m; break;
+                        default: q.w += m; break;
                     }
                 }
                 split8(w, wh[c][s8], wl[c][s8]);
             }
+            // the chunk's running sums, owned by this lane
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+                if (own && m < NM) co[2 * m] = cm[m];
         }
         constexpr int NS = LL == 24 ? 6 : 8;
         constexpr int PF = 2;
