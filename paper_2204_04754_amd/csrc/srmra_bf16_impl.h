@@ -79,7 +79,8 @@ __device__ __forceinline__ floatx16 mfma_split(const bf16x8& ah, const bf16x8& a
 // Number of k-steps (b2, 16-row block of r1) of one score tile.
 template <int LL> constexpr int nk() { return LL * (R1P / 16); }
 
-// x of component c (less the offset mu) as the MFMA B operand of every k-step of the score tile:
+// x of component c (less the offset mu) over sigma^2 as the MFMA B operand of every k-step of
+// the score tile (the tile then accumulates <y, R_t x_c> / sigma^2 directly):
 // lane (t1 = lane & 31, g = lane >> 5) of k-step (b2, jb) holds the 8 values
 // x_c[(16 jb + 8 g + e - t1) mod Ll][b2], e = 0..7, split into BF16 hi and lo.
 // Layout [c][k-step][plane][lane] of 16-byte fragments (one 1 KiB coalesced
@@ -98,7 +99,7 @@ __device__ __forceinline__ void pack_xb_body(const StepArgs& p, const float* __r
     for (int e = 0; e < 8; ++e) {
         int r = 16 * jb + 8 * g + e - t1e;
         r = ((r % LL) + LL) % LL;
-        v[e] = x[(int64_t)(c1 + r * p.K) * p.Lh + (c2 + b2 * p.K)] - mu;
+        v[e] = (x[(int64_t)(c1 + r * p.K) * p.Lh + (c2 + b2 * p.K)] - mu) * p.inv_s2;
     }
     bf16x8 h, l;
     split8(v, h, l);
@@ -129,18 +130,21 @@ __device__ __forceinline__ void load_yo(const Prep& q, int64_t o0, __bf16* yo) {
     for (int e = threadIdx.x; e < CH; e += 256) reinterpret_cast<uint4*>(yo)[e] = src[e];
 }
 
-// Score tiles for NO observations (slots o_slot[k]) x NC components (LDS slots cs[k]).
-template <int LL, int NO, int NC, int NP>
+// Score tiles for NO observations (slots o_slot[k]) x NC components (LDS slots cs[k]),
+// accumulated onto acc (cleared first when ZERO).
+template <int LL, int NO, int NC, int NP, bool ZERO = true>
 __device__ __forceinline__ void score(const StepArgs& p, const __bf16* ys, const int (&oslot)[NO],
                                       const int (&cgl)[NC], floatx16 (&acc)[NO][NC]) {
     constexpr int JS = R1P / 16;
     const int lane = threadIdx.x & 63;
     const int i = lane & 31, g = lane >> 5;
     const int t2e = i < LL ? i : i - LL;
+    if constexpr (ZERO) {
 #pragma unroll
-    for (int o = 0; o < NO; ++o)
+        for (int o = 0; o < NO; ++o)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc[o][c] = floatx16{0};
+            for (int c = 0; c < NC; ++c) acc[o][c] = floatx16{0};
+    }
     // B fragments of this lane for every component: xb[c][ks][plane][lane].
     // Double-buffered in registers: the fragments of k-step ks + 1 are requested
     // before the MFMAs of k-step ks, so their L2 latency overlaps a whole k-step.
@@ -152,6 +156,67 @@ __device__ __forceinline__ void score(const StepArgs& p, const __bf16* ys, const
     for (int c = 0; c < NC; ++c) {
         bh[c] = __builtin_bit_cast(bf16x8, bsrc[c][0]);
         bl[c] = __builtin_bit_cast(bf16x8, bsrc[c][64]);
+    }
+    if constexpr (NC == 2 && NO == 4) {
+        // four observations, two components: observation by observation, the
+        // six (eight) products of one observation alternate between its two
+        // accumulators, and the A fragments of the next observation -- for the
+        // last one, of the first observation of the next k-step -- are requested
+        // before them, so an LDS round trip hides behind six products
+        bf16x8 ah[2], al[2];
+        auto arow_of = [&](int b2, int o) {
+            int col = b2 + t2e;
+            col = col >= LL ? col - LL : col;
+            return ys + (oslot[o] * 2 * LL + col) * PITCH + 8 * g;
+        };
+        auto load = [&](int slot, int b2, int j, int o) {
+            const __bf16* r = arow_of(b2, o);
+            ah[slot] = *reinterpret_cast<const bf16x8*>(r + 16 * j);
+            al[slot] = *reinterpret_cast<const bf16x8*>(r + LL * PITCH + 16 * j);
+        };
+        load(0, 0, 0, 0);
+        for (int b2 = 0; b2 < LL; ++b2) {
+#pragma unroll
+            for (int j = 0; j < JS; ++j) {
+                const int ks = b2 * JS + j;
+                const int kn = ks + 1 < nk<LL>() ? ks + 1 : ks;   // the last step re-reads its own
+                bf16x8 nh[NC], nl[NC];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    nh[c] = __builtin_bit_cast(bf16x8, bsrc[c][kn * 128]);
+                    nl[c] = __builtin_bit_cast(bf16x8, bsrc[c][kn * 128 + 64]);
+                }
+                // the next k-step's (b2, j)
+                const int jn = j + 1 < JS ? j + 1 : 0;
+                const int b2n = j + 1 < JS ? b2 : (b2 + 1 < LL ? b2 + 1 : b2);
+#pragma unroll
+                for (int o = 0; o < NO; ++o) {
+                    const int cur = o & 1;
+                    if (o + 1 < NO) load(cur ^ 1, b2, j, o + 1);
+                    else load(cur ^ 1, b2n, jn, 0);
+                    asm volatile("" ::: "memory");
+                    __builtin_amdgcn_sched_barrier(0);
+                    floatx16& a0 = acc[o][0];
+                    floatx16& a1 = acc[o][1];
+                    a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[cur], bh[0], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[cur], bh[1], a1, 0, 0, 0);
+                    a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[cur], bl[0], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[cur], bl[1], a1, 0, 0, 0);
+                    a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[cur], bh[0], a0, 0, 0, 0);
+                    a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[cur], bh[1], a1, 0, 0, 0);
+                    if constexpr (NP == 4) {
+                        a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[cur], bl[0], a0, 0, 0, 0);
+                        a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[cur], bl[1], a1, 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    bh[c] = nh[c];
+                    bl[c] = nl[c];
+                }
+            }
+        }
+        return;
     }
     for (int b2 = 0; b2 < LL; ++b2) {
         int col = b2 + t2e;
@@ -298,7 +363,7 @@ __device__ __forceinline__ void bf16_pass1_body(const StepArgs& p, const Prep& q
             for (int c = 0; c < 2; ++c) {
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
-                    const float a = ook ? acc[o][c][v] * p.inv_s2 + bet[c][v] : -INFINITY;
+                    const float a = ook ? acc[o][c][v] + bet[c][v] : -INFINITY;
                     acc[o][c][v] = a;
                     mx[o] = fmaxf(mx[o], a);
                 }
@@ -323,40 +388,43 @@ __device__ __forceinline__ void bf16_pass1_body(const StepArgs& p, const Prep& q
     }
 }
 
-// Log-sum-exp of 8 observations over the components of a block from the waves'
-// own (max, sum exp) pairs, exchanged through LDS (red: [waves][8] float2).
-// Every wave of the block calls it (two barriers); the caller's wave stores
-// its pair at slot `slot` and combines slots base + k * stride, k < nslot,
-// for which use(k) holds, in that order.  The combined pair is also written as
+// Log-sum-exp of NOB observations over the components of a block from the
+// waves' own (max, sum exp) pairs, exchanged through LDS (red: [NS waves][NOB]
+// float2).  Every wave of the block calls it (two barriers); wave `slot` stores
+// its pairs, and slots k with use(k) take part.  The combine runs on NOB groups
+// of NS lanes (lane o NS + k holds observation o, slot k): the group's maximum,
+// its terms s_k exp(m_k - m) in FP64 summed over the group in a fixed tree
+// order, taken from the group's first lane.  The combined pair is also written as
 // the observation's single partial (its log-likelihood term is formed from it
-// later) by the `writer` waves, and the value returned is the one the combine
-// kernel forms from that pair.
-template <int NOB, typename Use>
+// later) by the `writer` wave, and lse[o] = (m, log sum) for every observation.
+template <int NOB, int NS, typename Use>
 __device__ __forceinline__ void block_lse(const StepArgs& p, const float (&mw)[NOB], const float (&sw)[NOB],
-                                          int slot, int base, int stride, int nslot, int64_t obs0,
-                                          int64_t c1, bool writer, Use use, float2* red, float2 (&lse)[NOB]) {
+                                          int slot, int64_t obs0, int64_t c1, bool writer, Use use,
+                                          float2* red, float2 (&lse)[NOB]) {
+    static_assert(NOB * NS <= 64 && (NS & (NS - 1)) == 0, "one lane per (observation, slot)");
     const int lane = threadIdx.x & 63;
     if (lane == 0) {
 #pragma unroll
         for (int o = 0; o < NOB; ++o) red[slot * NOB + o] = make_float2(mw[o], sw[o]);
     }
     __syncthreads();
+    const int og = lane / NS, k = lane % NS;
+    const bool act = lane < NOB * NS && use(k);
+    const float2 e = act ? red[k * NOB + og] : make_float2(-INFINITY, 0.f);
+    float m = e.x;
+#pragma unroll
+    for (int off = 1; off < NS; off <<= 1) m = fmaxf(m, __shfl_xor(m, off));
+    double t = (act && e.x > -INFINITY) ? (double)e.y * exp((double)e.x - (double)m) : 0.0;
+#pragma unroll
+    for (int off = 1; off < NS; off <<= 1) t += __shfl_xor(t, off);
+    t = __shfl(t, og * NS);              // the group's first lane's sum, in every lane of it
+    const float sf = (float)t;
+    const float lg = m > -INFINITY ? (float)log((double)sf) : 0.f;
+    if (writer && k == 0 && lane < NOB * NS && obs0 + og < c1) p.part[obs0 + og] = make_float2(m, sf);
 #pragma unroll
     for (int o = 0; o < NOB; ++o) {
-        float m = -INFINITY;
-        for (int k = 0; k < nslot; ++k)
-            if (use(k)) m = fmaxf(m, red[(base + k * stride) * NOB + o].x);
-        double sum = 0.0;
-        if (m > -INFINITY) {
-            for (int k = 0; k < nslot; ++k) {
-                if (!use(k)) continue;
-                const float2 e = red[(base + k * stride) * NOB + o];
-                if (e.x > -INFINITY) sum += (double)e.y * exp((double)e.x - (double)m);
-            }
-        }
-        const float sf = (float)sum;
-        lse[o] = m > -INFINITY ? make_float2(m, (float)log((double)sf)) : make_float2(0.f, 0.f);
-        if (writer && lane == 0 && obs0 + o < c1) p.part[obs0 + o] = make_float2(m, sf);
+        const float mo = __shfl(m, o * NS), lo = __shfl(lg, o * NS);
+        lse[o] = mo > -INFINITY ? make_float2(mo, lo) : make_float2(0.f, 0.f);
     }
     __syncthreads();   // red is rewritten by the next group
 }
@@ -411,7 +479,7 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
                 const float bet = sok ? p.betaT[(int64_t)comp * (LL * LL) + t2 * LL + j] : 0.f;
 #pragma unroll
                 for (int o = 0; o < 8; ++o)
-                    if (sok && o0 + o < p.N) mw[o] = fmaxf(mw[o], acc[o][0][v] * p.inv_s2 + bet);
+                    if (sok && o0 + o < p.N) mw[o] = fmaxf(mw[o], acc[o][0][v] + bet);
             }
 #pragma unroll
             for (int o = 0; o < 8; ++o)
@@ -423,7 +491,7 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
                 const float bet = sok ? p.betaT[(int64_t)comp * (LL * LL) + t2 * LL + j] : 0.f;
 #pragma unroll
                 for (int o = 0; o < 8; ++o) {
-                    const float a = acc[o][0][v] * p.inv_s2 + bet;
+                    const float a = acc[o][0][v] + bet;
                     if (sok && o0 + o < p.N && a > -INFINITY) sw[o] += fast_exp(a - mw[o]);
                 }
             }
@@ -431,8 +499,8 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
             for (int o = 0; o < 8; ++o)
                 for (int off = 32; off > 0; off >>= 1) sw[o] += __shfl_xor(sw[o], off);
             float2* red = reinterpret_cast<float2*>(yo + 2 * LL * LL * 8);
-            block_lse(p, mw, sw, wave, 0, 1, 4, o0, p.N, wave == 0,
-                      [&](int k) { return k < p.KK; }, red, lse);
+            block_lse<8, 4>(p, mw, sw, wave, o0, p.N, wave == 0,
+                            [&](int k) { return k < p.KK; }, red, lse);
         } else {
 #pragma unroll
             for (int o = 0; o < 8; ++o) lse[o] = (o0 + o < p.N) ? p.lse[o0 + o] : make_float2(0.f, 0.f);
@@ -447,7 +515,7 @@ __device__ __forceinline__ void bf16_pass2_body(const StepArgs& p, const Prep& q
             for (int o = 0; o < 8; ++o) {
                 float ww = 0.f;
                 if (sok && o0 + o < p.N) {
-                    const float a = acc[o][0][v] * p.inv_s2 + bet;
+                    const float a = acc[o][0][v] + bet;
                     ww = a > -INFINITY ? fast_exp((a - lse[o].x) - lse[o].y) : 0.f;
                 }
                 w[o] = ww;
@@ -581,20 +649,39 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
         load_yT<LL, NOB, F16_NT>(p, q, o0, ys);
         load_yo4<LL>(q, o0, yo4);
         __syncthreads();
-        floatx16 acc[NOB][NCW];
-        score<LL, NOB, NCW, NP>(p, ys, oslot, cgl, acc);
-        // a = S / sigma^2 + beta, formed where it is used (the accumulators are
-        // only read); slots that are not a shift of this observation (rows /
-        // columns past Ll, missing components or observations) are skipped.
-        // The wave's (max, sum exp) per observation:
+        // the accumulators start from beta and the B fragments carry x / sigma^2,
+        // so the tiles end as the log-joint terms a = <y, R_t x_c> / sigma^2 + beta
         bool ook[NOB];
 #pragma unroll
         for (int o = 0; o < NOB; ++o) ook[o] = o0 + o < p.N;
-        auto beta_of = [&](int c, int v, bool& sok) {
-            const int t2 = acc_row(v, lane);
-            sok = cok[c] && t2 < LL && j < LL;
-            return sok ? p.betaT[(int64_t)comp[c] * (LL * LL) + t2 * LL + j] : 0.f;
-        };
+        // every slot a shift of this observation: L_low 32 (no rows / columns
+        // past L_low), both components and all four observations present
+        const bool full = LL == 32 && cok[0] && cok[1] && ook[NOB - 1];
+        auto slot_ok = [&](int c, int v) { return cok[c] && acc_row(v, lane) < LL && j < LL; };
+        floatx16 acc[NOB][NCW];
+#pragma unroll
+        for (int c = 0; c < NCW; ++c)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const float bet = slot_ok(c, v)
+                    ? p.betaT[(int64_t)comp[c] * (LL * LL) + acc_row(v, lane) * LL + j] : 0.f;
+#pragma unroll
+                for (int o = 0; o < NOB; ++o) acc[o][c][v] = bet;
+            }
+        score<LL, NOB, NCW, NP, false>(p, ys, oslot, cgl, acc);
+        if (!full) {   // masked slots out of every sum below
+#pragma unroll
+            for (int c = 0; c < NCW; ++c)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const bool sok = slot_ok(c, v);
+#pragma unroll
+                    for (int o = 0; o < NOB; ++o)
+                        if (!(sok && ook[o])) acc[o][c][v] = -INFINITY;
+                }
+        }
+        // the wave's (max, sum exp) per observation (a term of -inf adds
+        // exp(-inf) = 0)
         float mw[NOB], sw[NOB];
 #pragma unroll
         for (int o = 0; o < NOB; ++o) {
@@ -602,38 +689,29 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
             sw[o] = 0.f;
         }
 #pragma unroll
-        for (int c = 0; c < NCW; ++c) {
+        for (int c = 0; c < NCW; ++c)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                bool sok;
-                const float bet = beta_of(c, v, sok);
+            for (int v = 0; v < 16; ++v)
 #pragma unroll
-                for (int o = 0; o < NOB; ++o)
-                    if (sok && ook[o]) mw[o] = fmaxf(mw[o], acc[o][c][v] * p.inv_s2 + bet);
-            }
-        }
+                for (int o = 0; o < NOB; ++o) mw[o] = fmaxf(mw[o], acc[o][c][v]);
 #pragma unroll
         for (int o = 0; o < NOB; ++o)
             for (int off = 32; off > 0; off >>= 1) mw[o] = fmaxf(mw[o], __shfl_xor(mw[o], off));
+        float mref[NOB];
 #pragma unroll
-        for (int c = 0; c < NCW; ++c) {
+        for (int o = 0; o < NOB; ++o) mref[o] = mw[o] > -INFINITY ? mw[o] : 0.f;
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                bool sok;
-                const float bet = beta_of(c, v, sok);
+        for (int c = 0; c < NCW; ++c)
 #pragma unroll
-                for (int o = 0; o < NOB; ++o) {
-                    const float a = acc[o][c][v] * p.inv_s2 + bet;
-                    if (sok && ook[o] && a > -INFINITY) sw[o] += fast_exp(a - mw[o]);
-                }
-            }
-        }
+            for (int v = 0; v < 16; ++v)
+#pragma unroll
+                for (int o = 0; o < NOB; ++o) sw[o] += fast_exp(acc[o][c][v] - mref[o]);
 #pragma unroll
         for (int o = 0; o < NOB; ++o)
             for (int off = 32; off > 0; off >>= 1) sw[o] += __shfl_xor(sw[o], off);
         float2 lse[NOB];
-        block_lse(p, mw, sw, wave, 0, 1, NW, o0, p.N, wave == 0,
-                  [&](int k) { return k * NCW < p.KK; }, red, lse);
+        block_lse<NOB, NW>(p, mw, sw, wave, o0, p.N, wave == 0,
+                           [&](int k) { return k * NCW < p.KK; }, red, lse);
         // posterior weights and mass of both components, the weights as B
         // fragments over k = (two t2 rows, 4 obs) (the accumulators are dead
         // after this), then the back-projection for each a1 (k-steps with t2
@@ -659,14 +737,11 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
 #pragma unroll
                 for (int r = 0; r < 2; ++r) {
                     const int v = 2 * s8 + r;
-                    bool sok;
-                    const float bet = beta_of(c, v, sok);
                     float m = 0.f;
 #pragma unroll
                     for (int o = 0; o < NOB; ++o) {
-                        const float a = acc[o][c][v] * p.inv_s2 + bet;
-                        const float ww = (sok && ook[o] && a > -INFINITY)
-                                             ? fast_exp((a - lse[o].x) - lse[o].y) : 0.f;
+                        // an observation past N has lse (0, 0) and only -inf terms
+                        const float ww = fast_exp((acc[o][c][v] - lse[o].x) - lse[o].y);
                         w[4 * r + o] = ww;
                         m += ww;
                     }
