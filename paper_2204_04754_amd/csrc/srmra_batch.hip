@@ -8,7 +8,7 @@
 // own register allocation; a single kernel switching over all bodies spills.)
 #include "srmra_aux_impl.h"
 #include "srmra_batch.h"
-#include "srmra_bf16s_impl.h"
+#include "srmra_bf16n_impl.h"
 #include "srmra_mfma_impl.h"
 #include "srmra_valu_impl.h"
 
@@ -38,6 +38,9 @@ __global__ __launch_bounds__(256) void k_batch_pack_xb(const InstDesc* __restric
     uint4* xb = const_cast<uint4*>(d.p.xb);
     if (d.LL == 16) {
         for (int ks = threadIdx.x >> 6; ks < b16s::NK; ks += 4) b16s::pack_xb_body(d.p, d.x, it.y, ks, xb);
+    } else if (d.LL == 48 && (d.form == FORM_BF16F || d.form == FORM_BF16X4F)) {
+        for (int e = threadIdx.x >> 6; e < b16n::T * b16n::NKS; e += 4)
+            b16n::pack_xb_body(d.p, d.x, it.y, e / b16n::NKS, e % b16n::NKS, xb);
     } else if (d.LL == 48 || d.LL == 64) {
         const int nk = d.LL * (d.LL / 16);
         for (int e = threadIdx.x >> 6; e < 2 * nk; e += 4) {
@@ -83,7 +86,8 @@ __global__ __launch_bounds__(1024) void k_batch_finalize(const InstDesc* __restr
 template <int PASS, int FORM, int LL>
 __global__ __launch_bounds__(256, ((PASS == 1 && (FORM == FORM_BF16 || FORM == FORM_BF16X4) && LL != 16) ||
                                    (PASS == 2 && FORM == FORM_MFMA && LL >= 16 && LL <= 32) ||
-                                   (PASS == 2 && FORM == FORM_FUSED && LL >= 16 && LL <= 24)) ? 2 : 1)
+                                   (PASS == 2 && FORM == FORM_FUSED && LL >= 16 && LL <= 24) ||
+                                   ((FORM == FORM_BF16F || FORM == FORM_BF16X4F) && LL == 48)) ? 2 : 1)
 void k_class_pass(const InstDesc* __restrict__ D,
                                                     const int4* __restrict__ items, int n_items,
                                                     int* __restrict__ counter) {
@@ -123,10 +127,17 @@ void k_class_pass(const InstDesc* __restrict__ D,
             }
         } else if constexpr (FORM == FORM_BF16F || FORM == FORM_BF16X4F) {
             constexpr int NP = FORM == FORM_BF16X4F ? 4 : 3;
-            b16::Prep q;
-            q.yT = d.yT;
-            q.yo = d.yo;
-            b16::bf16_pass2_body<LL, NP, true>(d.p, q, w.y, 0, lds);
+            if constexpr (LL == 48) {
+                b16n::Prep qn;
+                qn.yT = d.yT;
+                qn.yo = d.yo;
+                b16n::fused_body<NP>(d.p, qn, w.y, lds);
+            } else {
+                b16::Prep q;
+                q.yT = d.yT;
+                q.yo = d.yo;
+                b16::bf16_pass2_body<LL, NP, true>(d.p, q, w.y, 0, lds);
+            }
         } else if constexpr (FORM == FORM_FUSED) {
             mfma_fused_body<LL>(d.p, w.y, lds);
         } else if constexpr (FORM == FORM_MFMA) {
@@ -183,8 +194,8 @@ SRMRA_CLASS(FORM_BF16X4, 16) SRMRA_CLASS(FORM_BF16X4, 24) SRMRA_CLASS(FORM_BF16X
 SRMRA_CLASS(FORM_BF16X4, 48) SRMRA_CLASS(FORM_BF16X4, 64)
 #undef SRMRA_CLASS
 #define SRMRA_BF16F(F, L) template __global__ void k_class_pass<2, F, L>(const InstDesc*, const int4*, int, int*);
-SRMRA_BF16F(FORM_BF16F, 24) SRMRA_BF16F(FORM_BF16F, 32)
-SRMRA_BF16F(FORM_BF16X4F, 24) SRMRA_BF16F(FORM_BF16X4F, 32)
+SRMRA_BF16F(FORM_BF16F, 24) SRMRA_BF16F(FORM_BF16F, 32) SRMRA_BF16F(FORM_BF16F, 48)
+SRMRA_BF16F(FORM_BF16X4F, 24) SRMRA_BF16F(FORM_BF16X4F, 32) SRMRA_BF16F(FORM_BF16X4F, 48)
 #undef SRMRA_BF16F
 #define SRMRA_FUSED(L) template __global__ void k_class_pass<2, FORM_FUSED, L>(const InstDesc*, const int4*, int, int*);
 SRMRA_FUSED(8) SRMRA_FUSED(12) SRMRA_FUSED(16) SRMRA_FUSED(24) SRMRA_FUSED(32) SRMRA_FUSED(48)
@@ -211,8 +222,8 @@ const void* class_pass_fn(int pass, int form, int LL) {
     SRMRA_PICK(8) SRMRA_PICK(12) SRMRA_PICK(16) SRMRA_PICK(24) SRMRA_PICK(32) SRMRA_PICK(48) SRMRA_PICK(64)
 #undef SRMRA_PICK
 #define SRMRA_PICK(F, L) if (form == F && LL == L) return pass == 2 ? (const void*)k_class_pass<2, F, L> : nullptr;
-    SRMRA_PICK(FORM_BF16F, 24) SRMRA_PICK(FORM_BF16F, 32)
-    SRMRA_PICK(FORM_BF16X4F, 24) SRMRA_PICK(FORM_BF16X4F, 32)
+    SRMRA_PICK(FORM_BF16F, 24) SRMRA_PICK(FORM_BF16F, 32) SRMRA_PICK(FORM_BF16F, 48)
+    SRMRA_PICK(FORM_BF16X4F, 24) SRMRA_PICK(FORM_BF16X4F, 32) SRMRA_PICK(FORM_BF16X4F, 48)
 #undef SRMRA_PICK
     if (pass == 2 && form == FORM_BF16W && LL == 24) return (const void*)k_class_fused16<3, 24>;
     if (pass == 2 && form == FORM_BF16W && LL == 32) return (const void*)k_class_fused16<3, 32>;

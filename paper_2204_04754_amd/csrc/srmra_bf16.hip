@@ -1,7 +1,7 @@
 // BF16 split-precision kernels of the EM step (bodies in srmra_bf16_impl.h for
 // L_low 24 and 32, srmra_bf16w_impl.h for L_low 48 and 64, srmra_bf16s_impl.h
-// for L_low 16).
-#include "srmra_bf16s_impl.h"
+// for L_low 16, srmra_bf16n_impl.h for the single pass at L_low 48, K^2 <= 4).
+#include "srmra_bf16n_impl.h"
 
 namespace srmra {
 namespace b16 {
@@ -108,9 +108,29 @@ __global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __rest
 
 }  // namespace b16s
 
+namespace b16n {
+
+// single pass at L_low 48, K^2 <= 4: grid (chunks)
+template <int NP>
+__global__ __launch_bounds__(NT, 2) void k_fused(StepArgs p, Prep q) {
+    extern __shared__ float lds[];
+    fused_body<NP>(p, q, blockIdx.x, lds);
+}
+
+// grid (3 KK, k-steps / 4): block (c, tile column C), 4 k-steps per block
+__global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __restrict__ x,
+                                                 uint4* __restrict__ xb) {
+    const int s = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (s < NKS) pack_xb_body(p, x, blockIdx.x / T, blockIdx.x % T, s, xb);
+}
+
+}  // namespace b16n
+
 
 // ---------------------------------------------------------------- host side
 static bool wide_ll(int LL) { return LL == 48 || LL == 64; }
+// L_low 48 with all components in one workgroup: the 16 x 16-tile single pass
+static bool nine_tile(int LL, int KK) { return LL == 48 && KK <= b16n::NW; }
 bool bf16_supported(int LL) { return LL == 16 || LL == 24 || LL == 32 || wide_ll(LL); }
 
 // pass-1 partials per observation: one per component pair (one-tile form), per
@@ -130,6 +150,11 @@ size_t bf16_xb_bytes(int LL, int KK) {
 hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, hipStream_t s) {
     if (LL == 16) {
         hipLaunchKernelGGL(b16s::k_pack_xb, dim3(p.KK, 2), dim3(256), 0, s, p, x, (uint4*)xb);
+        return hipGetLastError();
+    }
+    if (nine_tile(LL, p.KK)) {
+        hipLaunchKernelGGL(b16n::k_pack_xb, dim3(b16n::T * p.KK, (b16n::NKS + 3) / 4), dim3(256), 0, s, p, x,
+                           (uint4*)xb);
         return hipGetLastError();
     }
     if (wide_ll(LL)) {
@@ -256,9 +281,23 @@ static hipError_t launch_bf16s(int pass, const StepArgs& p, const b16::Prep& q0,
     return hipGetLastError();
 }
 
+template <int NP>
+static hipError_t launch_bf16n(const StepArgs& p, const b16::Prep& q0, hipStream_t s) {
+    b16n::Prep q;
+    q.yT = q0.yT;
+    q.yo = q0.yo;
+    const size_t lds = b16n::lds_fused();
+    if (hipFuncSetAttribute((const void*)b16n::k_fused<NP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(b16n::k_fused<NP>, dim3(p.n_chunks), dim3(b16n::NT), lds, s, p, q);
+    return hipGetLastError();
+}
+
 hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
                        hipStream_t s) {
     const b16::Prep q = prep_ptrs(prep_extra, LL, p.N);
+    if (pass == 3 && nine_tile(LL, p.KK)) return np == 4 ? launch_bf16n<4>(p, q, s) : launch_bf16n<3>(p, q, s);
     if (LL == 16) return np == 4 ? launch_bf16s<4>(pass, p, q, s) : launch_bf16s<3>(pass, p, q, s);
     if (LL == 48) return np == 4 ? launch_bf16w_ll<48, 4>(pass, p, q, s) : launch_bf16w_ll<48, 3>(pass, p, q, s);
     if (LL == 64) return np == 4 ? launch_bf16w_ll<64, 4>(pass, p, q, s) : launch_bf16w_ll<64, 3>(pass, p, q, s);
@@ -286,11 +325,19 @@ static void bf16w_geom_ll(size_t& lds1, size_t& lds2, const void*& f1, const voi
 // The single pass when one workgroup holds all K^2 components of its
 // observations: L_low 24 / 32 with K^2 <= 4 (8 observations x 4 components
 // per workgroup) and with 4 < K^2 <= 16 (4 observations x 16 components;
-// cpb and nt are set to that tile).  (At L_low 16 a single pass that
+// cpb and nt are set to that tile); L_low 48 with K^2 <= 4 (4 observations x
+// 4 components on 16 x 16 tiles).  (At L_low 16 a single pass that
 // keeps the scores of 8 observations x 4 components across the block's
 // (max, sum) exchange spilled registers and measured no faster than the two
 // passes, slower inside the batched form; L_low 16 keeps two passes.)
 bool bf16_fused_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds, const void*& f) {
+    if (nine_tile(LL, KK)) {
+        cpb = b16n::NW;
+        nt = b16n::NOB;
+        lds = b16n::lds_fused();
+        f = np == 4 ? (const void*)b16n::k_fused<4> : (const void*)b16n::k_fused<3>;
+        return true;
+    }
     if ((LL == 24 || LL == 32) && KK > 4 && KK <= b16::F16_NCW * b16::F16_NW) {
         cpb = b16::F16_NCW * b16::F16_NW;
         nt = b16::F16_NOB;

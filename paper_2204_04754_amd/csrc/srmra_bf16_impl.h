@@ -130,21 +130,18 @@ __device__ __forceinline__ void load_yo(const Prep& q, int64_t o0, __bf16* yo) {
     for (int e = threadIdx.x; e < CH; e += 256) reinterpret_cast<uint4*>(yo)[e] = src[e];
 }
 
-// Score tiles for NO observations (slots o_slot[k]) x NC components (LDS slots cs[k]),
-// accumulated onto acc (cleared first when ZERO).
-template <int LL, int NO, int NC, int NP, bool ZERO = true>
+// Score tiles for NO observations (slots o_slot[k]) x NC components (LDS slots cs[k]).
+template <int LL, int NO, int NC, int NP>
 __device__ __forceinline__ void score(const StepArgs& p, const __bf16* ys, const int (&oslot)[NO],
                                       const int (&cgl)[NC], floatx16 (&acc)[NO][NC]) {
     constexpr int JS = R1P / 16;
     const int lane = threadIdx.x & 63;
     const int i = lane & 31, g = lane >> 5;
     const int t2e = i < LL ? i : i - LL;
-    if constexpr (ZERO) {
 #pragma unroll
-        for (int o = 0; o < NO; ++o)
+    for (int o = 0; o < NO; ++o)
 #pragma unroll
-            for (int c = 0; c < NC; ++c) acc[o][c] = floatx16{0};
-    }
+        for (int c = 0; c < NC; ++c) acc[o][c] = floatx16{0};
     // B fragments of this lane for every component: xb[c][ks][plane][lane].
     // Double-buffered in registers: the fragments of k-step ks + 1 are requested
     // before the MFMAs of k-step ks, so their L2 latency overlaps a whole k-step.
@@ -649,8 +646,10 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
         load_yT<LL, NOB, F16_NT>(p, q, o0, ys);
         load_yo4<LL>(q, o0, yo4);
         __syncthreads();
-        // the accumulators start from beta and the B fragments carry x / sigma^2,
-        // so the tiles end as the log-joint terms a = <y, R_t x_c> / sigma^2 + beta
+        // the B fragments carry x / sigma^2 and the shift prior is added once the
+        // tiles are complete (accumulators started from beta, of the magnitude of
+        // ||x_c||^2 / 2 sigma^2, would round every FP32 accumulation at that
+        // scale), so the tiles end as the log-joint terms a = <y, R_t x_c> / sigma^2 + beta
         bool ook[NOB];
 #pragma unroll
         for (int o = 0; o < NOB; ++o) ook[o] = o0 + o < p.N;
@@ -659,6 +658,7 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
         const bool full = LL == 32 && cok[0] && cok[1] && ook[NOB - 1];
         auto slot_ok = [&](int c, int v) { return cok[c] && acc_row(v, lane) < LL && j < LL; };
         floatx16 acc[NOB][NCW];
+        score<LL, NOB, NCW, NP>(p, ys, oslot, cgl, acc);
 #pragma unroll
         for (int c = 0; c < NCW; ++c)
 #pragma unroll
@@ -666,9 +666,8 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
                 const float bet = slot_ok(c, v)
                     ? p.betaT[(int64_t)comp[c] * (LL * LL) + acc_row(v, lane) * LL + j] : 0.f;
 #pragma unroll
-                for (int o = 0; o < NOB; ++o) acc[o][c][v] = bet;
+                for (int o = 0; o < NOB; ++o) acc[o][c][v] += bet;
             }
-        score<LL, NOB, NCW, NP, false>(p, ys, oslot, cgl, acc);
         if (!full) {   // masked slots out of every sum below
 #pragma unroll
             for (int c = 0; c < NCW; ++c)

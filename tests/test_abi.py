@@ -119,6 +119,9 @@ def test_pass_count_query():
     assert B.srmra_em_step_passes(5000, 24, 3, "bf16_split4") == 1
     assert B.srmra_em_step_passes(5000, 32, 5, "bf16_split3") == 2
     assert B.srmra_em_step_passes(20000, 64, 4, "bf16_split3") == 2
+    assert B.srmra_em_step_passes(50000, 48, 2, "bf16_split3") == 1   # 16x16 tiles, K^2 = 4
+    assert B.srmra_em_step_passes(50000, 48, 1, "bf16_split4") == 1
+    assert B.srmra_em_step_passes(50000, 48, 3, "bf16_split3") == 2
     with pytest.raises(B.SrmraError):
         B.srmra_em_step_passes(1000, 20, 2, "fp32_mfma")
 

@@ -1,6 +1,6 @@
 """GPU parity of the BF16 split-precision form (L_low 24 and 32 with one 32x32
-tile per score map, 48 and 64 with 2 x 2 tiles, 16 with one 16x16 tile)
-against the FP64 oracle."""
+tile per score map, 48 and 64 with 2 x 2 tiles, 16 with one 16x16 tile, 48 at
+K^2 <= 4 with 3 x 3 tiles of 16x16 in one pass) against the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -27,7 +27,8 @@ def _gpu():
                                           (192, 3, 37, 2.0), (48, 1, 50, 2.0), (64, 1, 33, 2.0),
                                           (24, 1, 19, 2.0), (32, 2, 45, 2.0), (48, 3, 101, 2.0),
                                           (64, 4, 133, 2.0), (16, 1, 13, 2.0), (80, 5, 203, 2.0),
-                                          (32, 2, 700, 0.7)])
+                                          (32, 2, 700, 0.7), (96, 2, 203, 1.0), (96, 2, 402, 0.7),
+                                          (48, 1, 7, 2.0), (96, 2, 4, 1.5)])
 def test_shapes(Lh, K, N, sigma, prec):
     inst = synth.make_instance(Lh, K, N, sigma, config=60, instance=Lh + K)
     rng = np.random.default_rng(Lh * K)
