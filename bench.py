@@ -105,6 +105,8 @@ def parse():
     ap.add_argument("--error-obs", type=int, default=2000,
                     help="errors mode: observations in the subset the oracle runs on")
     ap.add_argument("--no-tune", action="store_true", help="batched mode: skip the autotuned runs")
+    ap.add_argument("--per-class", action="store_true",
+                    help="batched mode: also time each (L_low, K) class of the mix alone, in the main form")
     ap.add_argument("--iterations", type=int, default=20)
     ap.add_argument("--rates", default="5,50,200")
     ap.add_argument("--jobs", type=int, default=200,
@@ -343,6 +345,33 @@ def bench_batched(args):
         print(f"[bench] batched {key}: {ms:.2f} ms/step", file=sys.stderr, flush=True)
         del g, be
         torch.cuda.empty_cache()
+    # each (L_low, K) class alone, in its own plan (the mix runs them concurrently)
+    classes = []
+    if args.per_class:
+        groups = {}
+        for d, e in zip(mix, ins):
+            groups.setdefault((d["Lh"] // d["K"], d["K"]), []).append((d, e))
+        for (ll, k) in sorted(groups):
+            be = BatchedEM([e for _, e in groups[(ll, k)]], precision=args.precision)
+            g = be.capture(2)
+            g.replay()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 2
+            pairs = be.pairs_per_step
+            # the class's algorithmic work (4 L_low^2 flop per pair) at the form's peak, issued
+            # with its products per multiply-add (3 or 4 for the BF16 split)
+            ideal = pairs * 4 * ll * ll * PRODUCTS.get(args.precision, 1) / PEAK[args.precision][1] * 1e3
+            classes.append(dict(L_low=ll, K=k, instances=len(groups[(ll, k)]), pairs=pairs, ms_per_step=ms,
+                                ideal_ms=ideal, frac=ideal / ms))
+            print(f"[bench] class L_low {ll} K {k}: {len(groups[(ll, k)])} instances, {ms:.2f} ms/step, "
+                  f"{100 * ideal / ms:.0f}% of its peak-rate time {ideal:.2f} ms", file=sys.stderr, flush=True)
+            del g, be
+            torch.cuda.empty_cache()
     # the headline batched figure is the main form at its best table
     best = min((k for k in forms if k.split("+")[0] == args.precision), key=lambda k: forms[k]["ms_per_step"])
     main_p = args.precision
@@ -354,7 +383,7 @@ def bench_batched(args):
                       "pairs_per_step": sum(d['N'] * d['Lh'] ** 2 for d in mix),
                       "precision": main_p, "table": "tuned" if best.endswith("+tuned") else "default",
                       "graph_iterations": args.iterations},
-           "forms": forms, "tuning": tuning,
+           "forms": forms, "tuning": tuning, "classes": classes,
            "speedup_vs_plain_fp32": forms[best]["pairs_per_s"] / forms["fp32_plain"]["pairs_per_s"]}
     print(json.dumps(out), flush=True)
 

@@ -401,6 +401,276 @@ __global__ __launch_bounds__(256) void k_fft_pass2_q(StepArgs p, const float2* _
     }
 }
 
+// ---- L_low = 3 * 2^m (12, 24, 48): teams of L lanes, one row (then column) of
+// an image per lane, 64 / L teams in each wave (a team never crosses a wave;
+// the lanes past the last team of a wave idle).  The layouts of Y and X, the
+// partials and the meaning of every sum are those of the power-of-two passes.
+namespace row {
+template <int L> struct G {
+    static constexpr int TPW = 64 / L;          // teams per wave
+    static constexpr int TEAMS = 4 * TPW;       // teams per 256-thread block
+    static constexpr int BUF = L * (L + 1);     // float2 per team transpose buffer
+};
+// [transpose buffers TEAMS x BUF float2][twiddles L float2][masses TEAMS x L x L float]
+template <int L> constexpr size_t lds() {
+    return sizeof(float2) * ((size_t)G<L>::TEAMS * G<L>::BUF + L) + sizeof(float) * (size_t)G<L>::TEAMS * L * L;
+}
+
+// lane -> (team, row r); on: the lane belongs to a team
+template <int L> __device__ __forceinline__ void team_of(int& team, int& r, bool& on) {
+    const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    on = ln < G<L>::TPW * L;
+    team = wave * G<L>::TPW + (on ? ln / L : 0);
+    r = ln % L;
+}
+
+// per job: Y_i = DFT(y_i - mu) in the paired layout Yp[i][k2 / 2][k1][k2 % 2]
+template <int L>
+__global__ __launch_bounds__(256) void k_prep_y(const float* __restrict__ y, int64_t N,
+                                                const double* __restrict__ centre, float2* __restrict__ yhat) {
+    extern __shared__ float2 sh[];
+    float2* tw = sh + G<L>::TEAMS * G<L>::BUF;
+    make_twiddles_n<L, L>(tw);
+    __syncthreads();
+    int team, r;
+    bool on;
+    team_of<L>(team, r, on);
+    const int64_t i = (int64_t)blockIdx.x * G<L>::TEAMS + team;
+    if (!on || i >= N) return;   // no block barrier follows
+    float2* buf = sh + team * G<L>::BUF;
+    const float mu = centre_of(centre);
+    float2 v[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) v[k] = make_float2(y[(i * L + k) * L + r] - mu, 0.f);   // column r
+    fft1m<L, false>(v, tw);
+#pragma unroll
+    for (int k = 0; k < L; ++k) buf[k * (L + 1) + r] = v[k];
+    team_sync();
+#pragma unroll
+    for (int k = 0; k < L; ++k) v[k] = buf[r * (L + 1) + k];   // row k1 = r
+    team_sync();
+    fft1m<L, false>(v, tw);                                     // v[k] = Y_i[r][k]
+    float4* d = reinterpret_cast<float4*>(yhat) + i * (L / 2) * L + r;
+#pragma unroll
+    for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
+}
+
+// per step: X_c = DFT(x_c - mu), paired layout; one team (the first L lanes) per component
+template <int L>
+__global__ __launch_bounds__(256) void k_pack_x(const float* __restrict__ x, int K,
+                                                const double* __restrict__ centre, float2* __restrict__ xhat) {
+    extern __shared__ float2 sh[];
+    float2* tw = sh + G<L>::TEAMS * G<L>::BUF;
+    make_twiddles_n<L, L>(tw);
+    __syncthreads();
+    if (threadIdx.x >= L) return;
+    const int c = blockIdx.x, c1 = c / K, c2 = c % K, Lh = K * L, r = threadIdx.x;
+    const float mu = centre_of(centre);
+    float2 v[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k)   // column r of x_c
+        v[k] = make_float2(x[(int64_t)(c1 + k * K) * Lh + (c2 + r * K)] - mu, 0.f);
+    fft1m<L, false>(v, tw);
+#pragma unroll
+    for (int k = 0; k < L; ++k) sh[k * (L + 1) + r] = v[k];
+    team_sync();
+#pragma unroll
+    for (int k = 0; k < L; ++k) v[k] = sh[r * (L + 1) + k];
+    team_sync();
+    fft1m<L, false>(v, tw);                                     // v[k] = X_c[r][k]
+    float4* d = reinterpret_cast<float4*>(xhat) + (int64_t)c * (L / 2) * L + r;
+#pragma unroll
+    for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
+}
+
+// scores of (observation o, component c) for lane r: s[k] = a at (t1 = k, t2 = r).
+// Row r of Y_o conj(X_c) is inverse-transformed along k2, the team exchanges
+// rows for columns, and column r is inverse-transformed along k1.
+template <int L>
+__device__ __forceinline__ void score(const StepArgs& p, const float2* __restrict__ yhat,
+                                      const float2* __restrict__ xhat, int64_t o, int c, float2* buf, int r,
+                                      const float2* tw, float (&s)[L]) {
+    float2 v[L];
+    const float4* yr = reinterpret_cast<const float4*>(yhat) + (int64_t)o * (L / 2) * L + r;
+    const float4* xr = reinterpret_cast<const float4*>(xhat) + (int64_t)c * (L / 2) * L + r;
+#pragma unroll
+    for (int m = 0; m < L / 2; ++m) {
+        const float4 a = yr[m * L], b = xr[m * L];
+        v[2 * m] = cmulc(make_float2(a.x, a.y), make_float2(b.x, b.y));
+        v[2 * m + 1] = cmulc(make_float2(a.z, a.w), make_float2(b.z, b.w));
+    }
+    fft1m<L, true>(v, tw);                                      // v[n2]: row k1 = r
+#pragma unroll
+    for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = v[k];
+    team_sync();
+#pragma unroll
+    for (int m = 0; m < L; ++m) v[m] = buf[m * (L + 1) + r];   // column n2 = r
+    team_sync();
+    fft1m<L, true>(v, tw);                                      // v[k] = S[k][r]
+    const float sc = p.inv_s2 / (float)(L * L);
+    const float* bet = p.betaT + (int64_t)c * (L * L) + r * L;   // betaT[c][t2 = r][t1]
+#pragma unroll
+    for (int k = 0; k < L; ++k) s[k] = v[k].x * sc + bet[k];
+}
+
+// pass 1: (max, sum exp) of every observation over all components; a team per
+// observation, the chunk's observations split over the gridDim.y blocks of the chunk
+template <int L>
+__global__ __launch_bounds__(256) void k_pass1(StepArgs p, const float2* __restrict__ yhat,
+                                               const float2* __restrict__ xhat) {
+    extern __shared__ float2 sh[];
+    float2* tw = sh + G<L>::TEAMS * G<L>::BUF;
+    make_twiddles_n<L, L>(tw);
+    __syncthreads();
+    int team, r;
+    bool on;
+    team_of<L>(team, r, on);
+    if (!on) return;   // no block barrier follows
+    float2* buf = sh + team * G<L>::BUF;
+    const int64_t c0 = (int64_t)blockIdx.x * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    for (int64_t o = c0 + team + (int64_t)G<L>::TEAMS * blockIdx.y; o < c1;
+         o += (int64_t)G<L>::TEAMS * gridDim.y) {
+        float m = -INFINITY, sm = 0.f;
+        for (int c = 0; c < p.KK; ++c) {
+            float s[L];
+            score<L>(p, yhat, xhat, o, c, buf, r, tw, s);
+            float mc = -INFINITY;
+#pragma unroll
+            for (int k = 0; k < L; ++k) mc = fmaxf(mc, s[k]);
+            float sc = 0.f;
+            if (mc > -INFINITY) {
+#pragma unroll
+                for (int k = 0; k < L; ++k) sc += s[k] > -INFINITY ? __expf(s[k] - mc) : 0.f;
+            }
+            lse_merge(m, sm, mc, sc);
+        }
+        // the team's L lanes merged in lane order by its first lane
+        buf[r] = make_float2(m, sm);
+        team_sync();
+        if (r == 0) {
+            for (int k = 1; k < L; ++k) lse_merge(m, sm, buf[k].x, buf[k].y);
+            p.part[o] = make_float2(m, sm);
+        }
+        team_sync();
+    }
+}
+
+// pass 2: per component group, the sums over the chunk (TPC teams per
+// component, observations split over them): partials of sum_i Y_i conj(W_i)
+// [chunk][c][k1][k2] (complex) and of sum_i w_i [chunk][c][t1][t2]
+template <int L>
+__global__ __launch_bounds__(256) void k_pass2(StepArgs p, const float2* __restrict__ yhat,
+                                               const float2* __restrict__ xhat, int TPC,
+                                               float2* __restrict__ bpart, float* __restrict__ cpart) {
+    extern __shared__ float2 sh[];
+    float2* tw = sh + G<L>::TEAMS * G<L>::BUF;
+    float* mass = reinterpret_cast<float*>(tw + L);              // [team][t1][t2]
+    make_twiddles_n<L, L>(tw);
+    int team, r;
+    bool on;
+    team_of<L>(team, r, on);
+    float2* buf = sh + team * G<L>::BUF;
+    float* mt = mass + team * L * L;
+    const int CG = G<L>::TEAMS / TPC;
+    const int c = blockIdx.y * CG + team / TPC, u = team % TPC;
+    const bool active = on && team < CG * TPC && c < p.KK;
+    if (on) {
+#pragma unroll
+        for (int k = 0; k < L; ++k) mt[k * L + r] = 0.f;
+    }
+    __syncthreads();
+    const int64_t chunk = blockIdx.x;
+    const int64_t c0 = chunk * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    float2 ab[L];   // sum of Y conj(W) at (k1 = r, k2 = k)
+#pragma unroll
+    for (int k = 0; k < L; ++k) ab[k] = make_float2(0.f, 0.f);
+    if (active) {
+        for (int64_t o = c0 + u; o < c1; o += TPC) {
+            float s[L];
+            score<L>(p, yhat, xhat, o, c, buf, r, tw, s);
+            const float2 lse = p.lse[o];
+            float2 v[L];
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const float w = s[k] > -INFINITY ? __expf((s[k] - lse.x) - lse.y) : 0.f;
+                mt[k * L + r] += w;                             // (t1 = k, t2 = r): the lane's own
+                v[k] = make_float2(w, 0.f);
+            }
+            fft1m<L, false>(v, tw);                             // column t2 = r along t1: v[k1]
+#pragma unroll
+            for (int k = 0; k < L; ++k) buf[k * (L + 1) + r] = v[k];
+            team_sync();
+#pragma unroll
+            for (int m = 0; m < L; ++m) v[m] = buf[r * (L + 1) + m];   // row k1 = r
+            team_sync();
+            fft1m<L, false>(v, tw);                             // v[k] = W[r][k]
+            const float4* yr = reinterpret_cast<const float4*>(yhat) + o * (L / 2) * L + r;
+#pragma unroll
+            for (int k = 0; k < L; k += 2) {
+                const float4 a = yr[(k / 2) * L];
+                const float2 t0 = cmulc(make_float2(a.x, a.y), v[k]);
+                const float2 t1 = cmulc(make_float2(a.z, a.w), v[k + 1]);
+                ab[k].x += t0.x; ab[k].y += t0.y;
+                ab[k + 1].x += t1.x; ab[k + 1].y += t1.y;
+            }
+        }
+    }
+    // the TPC teams of each component summed in a fixed order: each team's
+    // back-projection transform goes into its transpose buffer ([k1][k2], pitch
+    // L + 1), then the component's first team adds them up
+    __syncthreads();
+    if (on) {
+#pragma unroll
+        for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = ab[k];
+    }
+    __syncthreads();
+    if (active && u == 0) {
+        for (int k = 0; k < L; ++k) {
+            float2 t = make_float2(0.f, 0.f);
+            float cm = 0.f;
+            for (int j = 0; j < TPC; ++j) {
+                const float2 e = sh[(team + j) * G<L>::BUF + r * (L + 1) + k];
+                t.x += e.x; t.y += e.y;
+                cm += mass[(team + j) * L * L + k * L + r];
+            }
+            bpart[((chunk * p.KK + c) * L + r) * L + k] = t;       // [k1 = r][k2 = k]
+            cpart[((chunk * p.KK + c) * L + k) * L + r] = cm;      // [t1 = k][t2 = r]
+        }
+    }
+}
+
+// batched forward DFT of real images (utility): out[i][k1][k2]
+template <int L>
+__global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int64_t count,
+                                              float2* __restrict__ out) {
+    extern __shared__ float2 sh[];
+    float2* tw = sh + G<L>::TEAMS * G<L>::BUF;
+    make_twiddles_n<L, L>(tw);
+    __syncthreads();
+    int team, r;
+    bool on;
+    team_of<L>(team, r, on);
+    const int64_t i = (int64_t)blockIdx.x * G<L>::TEAMS + team;
+    if (!on || i >= count) return;
+    float2* buf = sh + team * G<L>::BUF;
+    float2 v[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) v[k] = make_float2(in[(i * L + r) * L + k], 0.f);   // row r
+    fft1m<L, false>(v, tw);
+#pragma unroll
+    for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = v[k];
+    team_sync();
+#pragma unroll
+    for (int k = 0; k < L; ++k) v[k] = buf[k * (L + 1) + r];   // column r
+    team_sync();
+    fft1m<L, false>(v, tw);                                     // v[k] = X[k][r]
+#pragma unroll
+    for (int k = 0; k < L; ++k) out[(i * L + k) * L + r] = v[k];
+}
+}  // namespace row
+
 // ---- FP64 sums of the partials over chunks: the back-projection's transform
 // [KK][L][L] complex, the posterior mass [KK][t1][t2] real (final)
 __global__ __launch_bounds__(256) void k_fft_reduce(const float2* __restrict__ bpart,
@@ -456,7 +726,7 @@ __global__ __launch_bounds__(256) void k_fft_idft(const double2* __restrict__ bh
         const int k1 = e / L, q2 = e % L;
         double re = 0.0, im = 0.0;
         for (int k2 = 0; k2 < L; ++k2) {
-            const int m = (k2 * q2) & (L - 1);
+            const int m = (k2 * q2) % L;
             const double2 b = B[k1 * L + k2];
             re += b.x * cs[m] - b.y * sn[m];
             im += b.x * sn[m] + b.y * cs[m];
@@ -468,7 +738,7 @@ __global__ __launch_bounds__(256) void k_fft_idft(const double2* __restrict__ bh
         const int q1 = e / L, q2 = e % L;
         double re = 0.0;
         for (int k1 = 0; k1 < L; ++k1) {
-            const int m = (k1 * q1) & (L - 1);
+            const int m = (k1 * q1) % L;
             const double2 t = T[k1 * L + q2];
             re += t.x * cs[m] - t.y * sn[m];
         }
@@ -486,11 +756,15 @@ __global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int6
 }  // namespace fft
 
 // ---------------------------------------------------------------- host side
-bool fft_supported(int LL) { return LL == 8 || LL == 16 || LL == 32 || LL == 64; }
+static bool mixed_ll(int LL) { return LL == 12 || LL == 24 || LL == 48; }
+bool fft_supported(int LL) { return LL == 8 || LL == 16 || LL == 32 || LL == 64 || mixed_ll(LL); }
 
 // teams of the two passes per block (2 LL lanes each; at LL 64 one team of
-// four lanes per row)
-int fft_teams(int LL) { return LL == 64 ? 1 : 256 / (2 * LL); }
+// four lanes per row; at LL = 3 * 2^m, 64 / LL teams of LL lanes per wave)
+int fft_teams(int LL) {
+    if (mixed_ll(LL)) return 4 * (64 / LL);
+    return LL == 64 ? 1 : 256 / (2 * LL);
+}
 
 // teams per component in pass 2 for KK components (a power of 2 dividing the teams)
 int fft_tpc(int LL, int KK) {
@@ -506,6 +780,9 @@ size_t fft_lds(int LL) {   // the two passes
         case 16: return fft::lds_pairs<16>();
         case 32: return fft::lds_pairs<32>();
         case 64: return fft::quad::lds();
+        case 12: return fft::row::lds<12>();
+        case 24: return fft::row::lds<24>();
+        case 48: return fft::row::lds<48>();
     }
     return 0;
 }
@@ -516,55 +793,102 @@ const void* fft_pass2_fn(int LL) {
         case 16: return (const void*)fft::k_fft_pass2<16>;
         case 32: return (const void*)fft::k_fft_pass2<32>;
         case 64: return (const void*)fft::k_fft_pass2_q;
+        case 12: return (const void*)fft::row::k_pass2<12>;
+        case 24: return (const void*)fft::row::k_pass2<24>;
+        case 48: return (const void*)fft::row::k_pass2<48>;
     }
     return nullptr;
+}
+
+// the passes at L_low = 3 * 2^m (what: 0 prepare Y, 1 X, 2 pass 1, 3 pass 2, 4 reduce)
+template <int L>
+static hipError_t fft_launch_row(int what, const StepArgs& p, const float* x, const float* y,
+                                 void* yhat, void* xhat, void* bpart, void* cpart, hipStream_t s) {
+    using G = fft::row::G<L>;
+    const size_t lds = fft::row::lds<L>();
+    auto attr = [&](const void* f) {
+        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    };
+    switch (what) {
+        case 0:
+            if (attr((const void*)fft::row::k_prep_y<L>) != hipSuccess) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(fft::row::k_prep_y<L>, dim3((unsigned)((p.N + G::TEAMS - 1) / G::TEAMS)), dim3(256),
+                               lds, s, y, p.N, p.centre, (float2*)yhat);
+            break;
+        case 1:
+            if (attr((const void*)fft::row::k_pack_x<L>) != hipSuccess) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(fft::row::k_pack_x<L>, dim3(p.KK), dim3(256), lds, s, x, p.K, p.centre,
+                               (float2*)xhat);
+            break;
+        case 2:
+            if (attr((const void*)fft::row::k_pass1<L>) != hipSuccess) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(fft::row::k_pass1<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lds, s, p,
+                               (const float2*)yhat, (const float2*)xhat);
+            break;
+        case 3:
+            if (attr((const void*)fft::row::k_pass2<L>) != hipSuccess) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(fft::row::k_pass2<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lds, s, p,
+                               (const float2*)yhat, (const float2*)xhat, fft_tpc(L, p.KK), (float2*)bpart,
+                               (float*)cpart);
+            break;
+    }
+    return hipGetLastError();
+}
+
+// the FP64 sums of the partials and the inverse DFT of the back-projection
+template <int L>
+static hipError_t fft_launch_reduce(const StepArgs& p, void* bpart, void* cpart, void* bh, double* bsum,
+                                    double* csum, hipStream_t s) {
+    const int per = p.KK * L * L;
+    hipLaunchKernelGGL(fft::k_fft_reduce, dim3((per + kReduceElems - 1) / kReduceElems), dim3(256), 0, s,
+                       (const float2*)bpart, (const float*)cpart, p.n_chunks, per, (double2*)bh, csum);
+    (void)hipFuncSetAttribute((const void*)fft::k_fft_idft<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)fft::idft_lds<L>());
+    hipLaunchKernelGGL(fft::k_fft_idft<L>, dim3(p.KK), dim3(256), fft::idft_lds<L>(), s, (const double2*)bh,
+                       bsum);
+    return hipGetLastError();
 }
 
 template <int L>
 static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, const float* y,
                                 void* yhat, void* xhat, void* bpart, void* cpart, void* bh,
                                 double* bsum, double* csum, hipStream_t s) {
-    const size_t lds = fft::lds_bytes<L>();      // preparation and X: one lane per row
-    const size_t lp = L == 64 ? fft::quad::lds() : fft::lds_pairs<L>();   // the passes
-    const int teams = 256 / L;
-    switch (what) {
-        case 0:   // prepare Y
-            (void)hipFuncSetAttribute((const void*)fft::k_fft_prep_y<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(fft::k_fft_prep_y<L>, dim3((unsigned)((p.N + teams - 1) / teams)), dim3(256), lds, s,
-                               y, p.N, p.centre, (float2*)yhat);
-            break;
-        case 1:   // X
-            (void)hipFuncSetAttribute((const void*)fft::k_fft_pack_x<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(fft::k_fft_pack_x<L>, dim3(p.KK), dim3(256), lds, s, x, p.K, p.centre,
-                               (float2*)xhat);
-            break;
-        case 2: {
-            auto f = L == 64 ? fft::k_fft_pass1_q : fft::k_fft_pass1<L == 64 ? 32 : L>;
-            (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
-            hipLaunchKernelGGL(f, dim3(p.n_chunks, p.n_cg), dim3(256), lp, s, p, (const float2*)yhat,
-                               (const float2*)xhat);
-            break;
+    if (what == 4) return fft_launch_reduce<L>(p, bpart, cpart, bh, bsum, csum, s);
+    if constexpr (L % 3 == 0) {
+        return fft_launch_row<L>(what, p, x, y, yhat, xhat, bpart, cpart, s);
+    } else {
+        const size_t lds = fft::lds_bytes<L>();      // preparation and X: one lane per row
+        const size_t lp = L == 64 ? fft::quad::lds() : fft::lds_pairs<L>();   // the passes
+        const int teams = 256 / L;
+        switch (what) {
+            case 0:   // prepare Y
+                (void)hipFuncSetAttribute((const void*)fft::k_fft_prep_y<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(fft::k_fft_prep_y<L>, dim3((unsigned)((p.N + teams - 1) / teams)), dim3(256), lds, s,
+                                   y, p.N, p.centre, (float2*)yhat);
+                break;
+            case 1:   // X
+                (void)hipFuncSetAttribute((const void*)fft::k_fft_pack_x<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(fft::k_fft_pack_x<L>, dim3(p.KK), dim3(256), lds, s, x, p.K, p.centre,
+                                   (float2*)xhat);
+                break;
+            case 2: {
+                auto f = L == 64 ? fft::k_fft_pass1_q : fft::k_fft_pass1<L == 64 ? 32 : L>;
+                (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
+                hipLaunchKernelGGL(f, dim3(p.n_chunks, p.n_cg), dim3(256), lp, s, p, (const float2*)yhat,
+                                   (const float2*)xhat);
+                break;
+            }
+            case 3: {
+                const int tpc = fft_tpc(L, p.KK);
+                auto f = L == 64 ? fft::k_fft_pass2_q : fft::k_fft_pass2<L == 64 ? 32 : L>;
+                (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
+                hipLaunchKernelGGL(f, dim3(p.n_chunks, p.n_cg), dim3(256), lp, s, p, (const float2*)yhat,
+                                   (const float2*)xhat, tpc, (float2*)bpart, (float*)cpart);
+                break;
+            }
         }
-        case 3: {
-            const int tpc = fft_tpc(L, p.KK);
-            auto f = L == 64 ? fft::k_fft_pass2_q : fft::k_fft_pass2<L == 64 ? 32 : L>;
-            (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
-            hipLaunchKernelGGL(f, dim3(p.n_chunks, p.n_cg), dim3(256), lp, s, p, (const float2*)yhat,
-                               (const float2*)xhat, tpc, (float2*)bpart, (float*)cpart);
-            break;
-        }
-        case 4: {
-            const int per = p.KK * L * L;
-            hipLaunchKernelGGL(fft::k_fft_reduce, dim3((per + kReduceElems - 1) / kReduceElems), dim3(256), 0, s, (const float2*)bpart,
-                               (const float*)cpart, p.n_chunks, per, (double2*)bh, csum);
-            (void)hipFuncSetAttribute((const void*)fft::k_fft_idft<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)fft::idft_lds<L>());
-            hipLaunchKernelGGL(fft::k_fft_idft<L>, dim3(p.KK), dim3(256), fft::idft_lds<L>(), s,
-                               (const double2*)bh, bsum);
-            break;
-        }
+        return hipGetLastError();
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_fft(int LL, int what, const StepArgs& p, const float* x, const float* y,
@@ -575,6 +899,9 @@ hipError_t launch_fft(int LL, int what, const StepArgs& p, const float* x, const
         case 16: return fft_launch_ll<16>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
         case 32: return fft_launch_ll<32>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
         case 64: return fft_launch_ll<64>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
+        case 12: return fft_launch_ll<12>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
+        case 24: return fft_launch_ll<24>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
+        case 48: return fft_launch_ll<48>(what, p, x, y, yhat, xhat, bpart, cpart, bh, bsum, csum, s);
     }
     return hipErrorInvalidValue;
 }
@@ -596,6 +923,18 @@ hipError_t launch_dft2(int L, const float* in, int64_t count, float2* out, hipSt
             (void)hipFuncSetAttribute((const void*)fft::k_dft2<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             hipLaunchKernelGGL(fft::k_dft2<64>, grid, dim3(256), lds, s, in, count, out);
             break;
+        case 12: case 24: case 48: {
+            const int tm = 4 * (64 / L);
+            const dim3 g((unsigned)((count + tm - 1) / tm));
+            const void* f = L == 12 ? (const void*)fft::row::k_dft2<12>
+                                    : (L == 24 ? (const void*)fft::row::k_dft2<24> : (const void*)fft::row::k_dft2<48>);
+            lds = L == 12 ? fft::row::lds<12>() : (L == 24 ? fft::row::lds<24>() : fft::row::lds<48>());
+            (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (L == 12) hipLaunchKernelGGL(fft::row::k_dft2<12>, g, dim3(256), lds, s, in, count, out);
+            else if (L == 24) hipLaunchKernelGGL(fft::row::k_dft2<24>, g, dim3(256), lds, s, in, count, out);
+            else hipLaunchKernelGGL(fft::row::k_dft2<48>, g, dim3(256), lds, s, in, count, out);
+            break;
+        }
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

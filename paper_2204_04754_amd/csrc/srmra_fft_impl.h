@@ -1,7 +1,8 @@
-// 2-D discrete Fourier transforms of L x L images (L in {8, 16, 32, 64}) by
-// teams of L threads: a team's thread r holds row r (then column r) of the image as
-// L complex values in registers and runs an iterative radix-2
-// decimation-in-time transform on it; rows and columns meet through the
+// 2-D discrete Fourier transforms of L x L images (L in {8, 16, 32, 64}, and
+// L = 3 * 2^m in {12, 24, 48}) by teams of L threads: a team's thread r holds
+// row r (then column r) of the image as L complex values in registers and runs
+// an iterative radix-2 decimation-in-time transform on it (for L = 3 M, one
+// radix-3 step and three length-M transforms); rows and columns meet through the
 // team's LDS buffer (pitch L + 1 complex, conflict-free for both).  A team
 // sits inside one wave, so a wave barrier orders its LDS traffic.
 // Forward: X[k] = sum_n x[n] exp(-2 pi i k.n / L); inverse: the conjugate
@@ -93,6 +94,57 @@ __device__ __forceinline__ void fft1t(float2 (&v)[N], const float2* __restrict__
             }
         }
     }
+}
+
+// twiddles tw[j] = exp(-2 pi i j / L), j < NTW, from double-precision sincospi
+template <int L, int NTW> __device__ __forceinline__ void make_twiddles_n(float2* tw) {
+    for (int j = threadIdx.x; j < NTW; j += blockDim.x) {
+        double s, c;
+        sincospi(-2.0 * (double)j / (double)L, &s, &c);
+        tw[j] = make_float2((float)c, (float)s);
+    }
+}
+
+// In-register transform of v[0..L), L = 3 M with M a power of two (natural
+// order in and out), the twiddle table tw[j] = exp(-2 pi i j / L), j < L.
+// With n = M n1 + n2 and k = k1 + 3 k2 (Cooley-Tukey with factors 3 and M):
+//   X[k1 + 3 k2] = sum_{n2} W_M^{n2 k2} W_L^{n2 k1} sum_{n1} x[M n1 + n2] W_3^{n1 k1}:
+// M three-point transforms, the twiddles W_L^{n2 k1}, then three length-M
+// transforms (whose twiddles W_M^j = W_L^{3 j} are every third table entry).
+// The three-point transform of (a, b, c): X0 = a + (b + c),
+// X1,2 = a - (b + c) / 2 -/+ i (sqrt(3) / 2) (b - c) (signs swapped for the inverse).
+template <int L, bool INV>
+__device__ __forceinline__ void fft1m(float2 (&v)[L], const float2* __restrict__ tw) {
+    constexpr int M = L / 3;
+    constexpr float S3 = 0.866025403784438646763723f;   // sqrt(3) / 2
+    float2 u[3][M];
+#pragma unroll
+    for (int n2 = 0; n2 < M; ++n2) {
+        const float2 a = v[n2], b = v[M + n2], c = v[2 * M + n2];
+        const float2 t1 = make_float2(b.x + c.x, b.y + c.y);
+        const float2 t2 = make_float2(b.x - c.x, b.y - c.y);
+        const float2 m = make_float2(a.x - 0.5f * t1.x, a.y - 0.5f * t1.y);
+        // forward: -i S3 t2; inverse: +i S3 t2
+        const float2 sr = INV ? make_float2(-S3 * t2.y, S3 * t2.x) : make_float2(S3 * t2.y, -S3 * t2.x);
+        u[0][n2] = make_float2(a.x + t1.x, a.y + t1.y);
+        float2 w1 = tw[n2], w2 = tw[2 * n2];
+        if (INV) { w1.y = -w1.y; w2.y = -w2.y; }
+        u[1][n2] = n2 == 0 ? make_float2(m.x + sr.x, m.y + sr.y) : cmul(make_float2(m.x + sr.x, m.y + sr.y), w1);
+        u[2][n2] = n2 == 0 ? make_float2(m.x - sr.x, m.y - sr.y) : cmul(make_float2(m.x - sr.x, m.y - sr.y), w2);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) fft1t<M, INV, 3>(u[k1], tw);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < M; ++k2) v[k1 + 3 * k2] = u[k1][k2];
+}
+
+// the transform of v[0..L) for any supported L (radix 2, or 3 x radix 2)
+template <int L, bool INV>
+__device__ __forceinline__ void fft1any(float2 (&v)[L], const float2* __restrict__ tw) {
+    if constexpr (L % 3 == 0) fft1m<L, INV>(v, tw);
+    else fft1<L, INV>(v, tw);
 }
 
 __device__ __forceinline__ float2 shfl_pair(float2 a) {

@@ -255,12 +255,13 @@ def test_moments_host_validation(L):
 
 
 def test_fft_route_shapes():
-    """SRMRA_FP32_FFT: L_low 8, 16, 32, 64 only; the plan calls do not take it."""
+    """SRMRA_FP32_FFT: every L_low of the library (powers of two and 3 * 2^m);
+    the plan calls do not take it."""
     from paper_2204_04754_amd import binding as B
-    for ll in (8, 16, 32, 64):
+    for ll in (8, 12, 16, 24, 32, 48, 64):
         assert B.srmra_em_step_workspace_bytes(1000, ll, 2, "fp32_fft") > 0
         assert B.srmra_prepared_bytes(1000, ll, 2, "fp32_fft") >= 1000 * ll * ll * 8
         assert B.srmra_em_step_passes(1000, ll, 2, "fp32_fft") == 2
-    for ll in (12, 24, 48):
+    for ll in (20, 40):
         assert B.srmra_em_step_workspace_bytes(1000, ll, 2, "fp32_fft") == 0
     assert B.srmra_plan_form(B.SRMRA_FP32_FFT, 32) == -1

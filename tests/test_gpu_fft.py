@@ -20,7 +20,7 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("L", [8, 16, 32, 64])
+@pytest.mark.parametrize("L", [8, 12, 16, 24, 32, 48, 64])
 def test_dft2_matches_numpy(L):
     x = np.random.default_rng(L).standard_normal((37, L, L)).astype(np.float32)
     out = torch.empty((37, L, L, 2), dtype=torch.float32, device="cuda")
@@ -32,9 +32,12 @@ def test_dft2_matches_numpy(L):
 
 
 # L_low 64 (one team of four lanes per row per block): K 1, 2 and 3, odd N,
-# and N = 1
+# and N = 1; L_low 12, 24 and 48 (radix 3 x 2^m, a lane per row): K 1 to 4,
+# ragged N over the 5, 2 and 1 teams of a wave, and N = 1
 SHAPES = [(16, 2, 37), (32, 2, 29), (64, 2, 17), (64, 4, 11), (96, 3, 5), (128, 4, 9),
-          (32, 1, 7), (32, 4, 53), (48, 3, 13), (64, 1, 9), (128, 2, 5), (192, 3, 13), (64, 1, 1)]
+          (32, 1, 7), (32, 4, 53), (48, 3, 13), (64, 1, 9), (128, 2, 5), (192, 3, 13), (64, 1, 1),
+          (24, 2, 19), (36, 3, 13), (48, 4, 7), (48, 2, 23), (96, 4, 9), (24, 1, 1),
+          (96, 2, 11), (48, 1, 5), (144, 3, 7)]
 
 
 @pytest.mark.parametrize("Lh,K,N", SHAPES)
