@@ -84,7 +84,8 @@ typedef enum {
     SRMRA_BF16_SPLIT4 = 3,    /* as SRMRA_BF16_SPLIT3 plus the lo*lo product        */
     SRMRA_FP32_FFT = 4        /* FFT route: both contractions as products of 2-D
                                  DFTs of the L_low grid (FP32 transforms, FP64 sums
-                                 and inverse); L_low in {8, 16, 32, 64};
+                                 and inverse); L_low in {8, 12, 16, 24, 32, 48, 64}
+                                 (powers of two; 3 * 2^m with a radix-3 step);
                                  single-problem calls only (no plan)                */
 } srmra_precision;
 
@@ -336,7 +337,8 @@ int srmra_project_gaussian(const float* x_in, float* x_out, int L_high,
 /* Batched forward 2-D DFT of real L x L images (the FFT route's transform):
  * out[i][k1][k2] = sum_n in[i][n1][n2] exp(-2 pi i (k1 n1 + k2 n2) / L), FP32
  * complex (interleaved re, im).  in: device [count][L][L] float; out: device
- * [count][L][L] float2.  L in {8, 16, 32, 64}, count >= 1, else SRMRA_EINVAL. */
+ * [count][L][L] float2.  L in {8, 12, 16, 24, 32, 48, 64}, count >= 1, else
+ * SRMRA_EINVAL. */
 int srmra_dft2(const float* in, int64_t count, int L, void* out, hipStream_t stream);
 
 /* Empirical moments of the observations (eq. empiric_MOM, the method of
