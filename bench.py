@@ -315,18 +315,25 @@ def bench_batched(args):
           file=sys.stderr, flush=True)
     forms = {}
     tuning = {}
-    # each form with the library's default partition, then the main form and
-    # FP32 MFMA with the autotuner's table (tuned on this batch; tuning time
-    # reported apart from the timed graph replays)
-    runs = [(args.precision, args.iterations, None), ("fp32_mfma", args.iterations, None),
-            ("fp32_plain", 2, None)]
+    # each form with the library's default partition; the main form with every
+    # class on the FFT route (a table sending each (L_low, K) there); then the
+    # main form and FP32 MFMA with the autotuner's table, the main form also
+    # with the FFT route among the tuner's candidates (tuned on this batch;
+    # tuning time reported apart from the timed graph replays)
+    from paper_2204_04754_amd import binding as B
+    fft_table = [dict(precision=B._prec(args.precision), L_low=ll, K=k, form=B.SRMRA_FP32_FFT, item_obs=0)
+                 for (ll, k) in sorted({(d["Lh"] // d["K"], d["K"]) for d in mix})]
+    runs = [(args.precision, args.iterations, None, False), ("fp32_mfma", args.iterations, None, False),
+            ("fp32_plain", 2, None, False), (args.precision, args.iterations, fft_table, False)]
     if not args.no_tune:
-        runs += [(args.precision, args.iterations, "auto"), ("fp32_mfma", args.iterations, "auto")]
-    for prec, iters, tune in runs:
-        key = prec + ("+tuned" if tune else "")
+        runs += [(args.precision, args.iterations, "auto", False), ("fp32_mfma", args.iterations, "auto", False),
+                 (args.precision, args.iterations, "auto", True)]
+    for prec, iters, tune, fft in runs:
+        key = prec + ("+fft_all" if isinstance(tune, list) else "") + ("+tuned" if tune == "auto" else "") + \
+            ("+fft" if fft else "")
         if key in forms:
             continue
-        be = BatchedEM(ins, precision=prec, tuning=tune)
+        be = BatchedEM(ins, precision=prec, tuning=tune, fft=fft)
         pairs = be.pairs_per_step
         g = be.capture(iters)
         g.replay()                                   # warm-up replay
@@ -338,7 +345,7 @@ def bench_batched(args):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / iters
         forms[key] = dict(pairs_per_s=pairs / (ms * 1e-3), ms_per_step=ms, iterations_in_graph=iters)
-        if tune:
+        if tune == "auto":
             forms[key]["tune_seconds"] = be.tune_seconds
             tuning[key] = [dict(L_low=t["L_low"], K=t["K"], form=t["form"], item_obs=t["item_obs"], tile=t.get("tile", 0))
                            for t in be.tuning]
@@ -378,10 +385,12 @@ def bench_batched(args):
     out = {"metric": METRIC, "value": forms[best]["pairs_per_s"], "unit": "obs×shift pairs/s",
            "n_gpus": 1, "steps": args.iterations, "warmup": args.iterations,
            "ms_per_step": forms[best]["ms_per_step"], "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[main_p], "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None,
+           # classes the table sends to the FFT route compute in FP32
+           "dtype": DTYPE[main_p] + ("+f32" if "fft" in best else ""), "data": "synthetic",
            "config": {"workload": f"batched_mix_{args.instances}", "instances": args.instances,
                       "pairs_per_step": sum(d['N'] * d['Lh'] ** 2 for d in mix),
-                      "precision": main_p, "table": "tuned" if best.endswith("+tuned") else "default",
+                      "precision": main_p, "table": best[len(main_p) + 1:] or "default",
                       "graph_iterations": args.iterations},
            "forms": forms, "tuning": tuning, "classes": classes,
            "speedup_vs_plain_fp32": forms[best]["pairs_per_s"] / forms["fp32_plain"]["pairs_per_s"]}

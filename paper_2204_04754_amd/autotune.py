@@ -6,7 +6,9 @@ the fastest:
 
 * the form: in a BF16 split plan, the BF16 kernels or FP32 MFMA (both meet the
   accuracy target; which is faster depends on the shape), otherwise the plan's
-  own precision;
+  own precision; with fft, also the FFT route where it covers the L_low (its
+  candidates run on FFT preparations of the class's problems, made for the
+  trials);
 * observations per work item, as multiples of the library's default (about
   2^28 multiply-adds per item, down to 2^24 where that gives a problem fewer
   than 128 chunks): smaller items balance the persistent launch
@@ -33,13 +35,14 @@ from . import binding as B
 SCALES = (0.25, 0.5, 1.0, 2.0, 4.0)
 
 
-def candidate_forms(precision: int, L_low: int) -> List[int]:
+def candidate_forms(precision: int, L_low: int, fft: bool = False) -> List[int]:
     base = B.srmra_plan_form(precision, L_low)
     if base < 0:
         raise B.SrmraError(B.SRMRA_EUNSUPPORTED, "autotune")
-    if base in (B.SRMRA_BF16_SPLIT3, B.SRMRA_BF16_SPLIT4):
-        return [base, B.SRMRA_FP32_MFMA]
-    return [base]
+    forms = [base, B.SRMRA_FP32_MFMA] if base in (B.SRMRA_BF16_SPLIT3, B.SRMRA_BF16_SPLIT4) else [base]
+    if fft and B.srmra_em_step_workspace_bytes(1024, L_low, 1, "fp32_fft") > 0:
+        forms.append(B.SRMRA_FP32_FFT)
+    return forms
 
 
 def candidate_tiles(form: int, L_low: int) -> List[int]:
@@ -49,10 +52,15 @@ def candidate_tiles(form: int, L_low: int) -> List[int]:
     return [0]
 
 
-def _scratch(pr: dict) -> dict:
-    """The problem with its own observations and preparation but fresh iterate
-    buffers (copies of the current iterate)."""
+def _scratch(pr: dict, form: int, stream=None) -> dict:
+    """The problem with its own observations, a preparation for `form` (its own
+    when that serves the form) and fresh iterate buffers (copies of the current
+    iterate)."""
     d = dict(pr)
+    if (form == B.SRMRA_FP32_FFT) != (pr.get("prep_form") == B.SRMRA_FP32_FFT):
+        pb = B.srmra_prepared_bytes(pr["N"], pr["L_low"], pr["K"], form)
+        d["prep"] = B.empty_bytes(pb, pr["y"].device)
+        B.srmra_prepare_observations(pr["y"], pr["N"], pr["L_low"], pr["K"], form, d["prep"], stream)
     d["x"] = pr["x"].clone()
     d["log_rho"] = pr["log_rho"].clone()
     d["x_new"] = torch.empty_like(pr["x"])
@@ -81,10 +89,10 @@ def _time_plan(problems, precision, entry, reps, warmup, stream) -> float:
 
 
 def tune(problems: Sequence[dict], precision, scales=SCALES, reps: int = 3, warmup: int = 1,
-         stream=None) -> Tuple[List[dict], List[dict]]:
-    """problems: the batch (dicts with y, prep, N, L_low, K, sigma, x, log_rho,
-    rho_new, loglik, as for binding.Plan); every prepared buffer must suit each
-    candidate form (a BF16 preparation also serves FP32 MFMA).
+         stream=None, fft: bool = False) -> Tuple[List[dict], List[dict]]:
+    """problems: the batch (dicts with y, prep, prep_form, N, L_low, K, sigma, x,
+    log_rho, rho_new, loglik, as for binding.Plan); a BF16 preparation also
+    serves FP32 MFMA, and FFT candidates get preparations of their own.
     Returns (table, report): one srmra_tuning entry per class, and every timing."""
     p = B._prec(precision)
     groups: Dict[Tuple[int, int], List[int]] = OrderedDict()
@@ -92,10 +100,10 @@ def tune(problems: Sequence[dict], precision, scales=SCALES, reps: int = 3, warm
         groups.setdefault((int(pr["L_low"]), int(pr["K"])), []).append(i)
     table, report = [], []
     for (Ll, K), idx in groups.items():
-        scratch = [_scratch(problems[i]) for i in idx]
         n_max = max(int(problems[i]["N"]) for i in idx)
         best = None
-        for form in candidate_forms(p, Ll):
+        for form in candidate_forms(p, Ll, fft):
+            scratch = [_scratch(problems[i], form, stream) for i in idx]
             base = B.srmra_plan_default_item_obs(n_max, Ll, K, form)
             seen = set()
 

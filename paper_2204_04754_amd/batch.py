@@ -12,17 +12,40 @@ import torch
 from . import binding as B
 
 
+def table_form(table, precision: int, L_low: int, K: int) -> Optional[int]:
+    """The form the first matching entry of a tuning table gives (L_low, K), or None."""
+    for t in table or ():
+        if B._prec(t["precision"]) == precision and int(t["L_low"]) == L_low and int(t["K"]) == K:
+            return B._prec(t["form"])
+    return None
+
+
+def prepare(e: dict, form: int, stream=None) -> None:
+    """(Re)prepare problem e's observations for the form it will run in (the FFT
+    route keeps the observations' DFTs, the BF16 split its operand planes; a
+    BF16 preparation also serves FP32 MFMA)."""
+    pb = B.srmra_prepared_bytes(e["N"], e["L_low"], e["K"], form)
+    if pb == 0:
+        raise B.SrmraError(B.SRMRA_EUNSUPPORTED, "prepare")
+    e["prep"] = B.empty_bytes(pb, e["y"].device)
+    B.srmra_prepare_observations(e["y"], e["N"], e["L_low"], e["K"], form, e["prep"], stream)
+    e["prep_form"] = form
+
+
 class BatchedEM:
     def __init__(self, instances: Sequence[dict], precision="fp32_mfma", device="cuda",
-                 stream=None, tuning=None):
+                 stream=None, tuning=None, fft=False):
         """instances: dicts with y [N][Ll][Ll], K, sigma, x0 [Lh][Lh], log_rho0 [2][Lh]
         (NumPy or torch).  tuning: None (library defaults), a list of
-        srmra_tuning entries, or "auto" (run the autotuner on this batch)."""
+        srmra_tuning entries, or "auto" (run the autotuner on this batch; with
+        fft, the FFT route is one of its candidates).  Each problem is prepared
+        for the form its class runs in."""
         self.device = torch.device(device)
         self.precision = B._prec(precision)
         self.stream = stream
         self.inst: List[dict] = []
         f = dict(device=self.device, dtype=torch.float32)
+        table = list(tuning) if tuning and tuning != "auto" else None
         for d in instances:
             y = d["y"]
             y = torch.as_tensor(np.ascontiguousarray(y, np.float32)) if isinstance(y, np.ndarray) else y
@@ -30,19 +53,19 @@ class BatchedEM:
             N, Ll = int(y.shape[0]), int(y.shape[1])
             K = int(d["K"])
             Lh = K * Ll
-            form = B.srmra_plan_form(self.precision, Ll)
+            form = table_form(table, self.precision, Ll, K)
+            if form is None:
+                form = B.srmra_plan_form(self.precision, Ll)
             if form < 0:
                 raise B.SrmraError(B.SRMRA_EUNSUPPORTED, "BatchedEM")
-            pb = B.srmra_prepared_bytes(N, Ll, K, form)
-            prep = B.empty_bytes(pb, self.device)
-            B.srmra_prepare_observations(y, N, Ll, K, form, prep, stream)
-            e = dict(y=y, prep=prep, N=N, L_low=Ll, K=K, Lh=Lh, sigma=float(d["sigma"]), form=form,
+            e = dict(y=y, N=N, L_low=Ll, K=K, Lh=Lh, sigma=float(d["sigma"]), form=form,
                      x=torch.as_tensor(np.asarray(d["x0"], np.float32)).to(**f).contiguous(),
                      x_new=torch.empty((Lh, Lh), **f),
                      log_rho=torch.as_tensor(np.asarray(d["log_rho0"], np.float32)).to(**f).contiguous(),
                      log_rho_new=torch.empty((2, Lh), **f),
                      rho_new=torch.empty((2, Lh), **f),
                      loglik=torch.empty(1, dtype=torch.float64, device=self.device))
+            prepare(e, form, stream)
             self.inst.append(e)
         self.tuning, self.tune_report, self.tune_seconds = None, [], 0.0
         if tuning == "auto":
@@ -50,8 +73,13 @@ class BatchedEM:
 
             from .autotune import tune
             t0 = time.perf_counter()
-            self.tuning, self.tune_report = tune(self.inst, self.precision, stream=stream)
+            self.tuning, self.tune_report = tune(self.inst, self.precision, stream=stream, fft=fft)
             self.tune_seconds = time.perf_counter() - t0
+            for e in self.inst:   # a class the tuner sent to (or from) the FFT route
+                form = table_form(self.tuning, self.precision, e["L_low"], e["K"])
+                if form is not None and (form == B.FP32_FFT) != (e["prep_form"] == B.FP32_FFT):
+                    prepare(e, form, stream)
+                    e["form"] = form
         elif tuning:
             self.tuning = list(tuning)
         self.plan = B.Plan(self.inst, self.precision, tuning=self.tuning)

@@ -552,6 +552,10 @@ struct srmra_plan {
     std::vector<int4> pass_items;
     std::vector<int2> pack_items, combine_items, reduce_items;
     int n_combine_early = 0;   // combine items of two-pass instances (the rest run after pass 2)
+    // reduce_items: n_reduce_plain real-partial items, then n_fft_reduce complex ones
+    // and n_fft_idft inverse DFTs of the FFT-form instances
+    int n_reduce_plain = 0, n_fft_reduce = 0, n_fft_idft = 0;
+    size_t pack_lds = 0, idft_lds = 0;
     size_t o_desc = 0, o_pass = 0, o_pack = 0, o_comb = 0, o_red = 0, o_cnt = 0, total = 0;
     std::vector<ClassLaunch> classes;
     int parity = 0;
@@ -586,6 +590,7 @@ struct srmra_plan {
 namespace {
 
 int form_of(int precision, int LL) {
+    if (precision == SRMRA_FP32_FFT) return fft_supported(LL) ? FORM_FFT : -1;
     if (is_bf16(precision)) {
         if (!bf16_supported(LL)) return FORM_MFMA;
         return precision == SRMRA_BF16_SPLIT4 ? FORM_BF16X4 : FORM_BF16;   // (single pass: below)
@@ -599,6 +604,7 @@ int prec_of_form(int f) {
         case FORM_BF16: case FORM_BF16F: case FORM_BF16W: return SRMRA_BF16_SPLIT3;
         case FORM_BF16X4: case FORM_BF16X4F: case FORM_BF16X4W: return SRMRA_BF16_SPLIT4;
         case FORM_VALU: return SRMRA_FP32_PLAIN;
+        case FORM_FFT: return SRMRA_FP32_FFT;
     }
     return SRMRA_FP32_MFMA;
 }
@@ -611,13 +617,16 @@ bool single_pass_form(int f) {
     return f == FORM_FUSED || f == FORM_BF16F || f == FORM_BF16X4F || f == FORM_BF16W || f == FORM_BF16X4W;
 }
 
-// observations per work item: about 2^28 multiply-adds, but no fewer than 128
+// observations per work item: about 2^28 multiply-adds (or FFT flop), but no fewer than 128
 // chunks per instance while an item keeps 2^24 or more (at small L_low 2^28
 // is thousands of observations, and a class of a few instances would have
 // fewer items than the device has CUs).  Shape-only, so an instance's
 // partition does not depend on the rest of the batch.
 int64_t default_chunk(const Geom& g) {
-    const double per_obs = (double)g.cpb * g.LL * g.LL * (double)g.LL * g.LL;
+    // work per observation and item: L_low^4 multiply-adds per component for the
+    // dense forms, about 40 L_low^2 log2 L_low flop for the FFT route's transforms
+    const double per_obs = (double)g.cpb * (g.prec == SRMRA_FP32_FFT ? 40.0 * g.LL * g.LL * log2((double)g.LL)
+                                                                      : (double)g.LL * g.LL * g.LL * g.LL);
     int64_t c = (int64_t)(268435456.0 / per_obs);
     const int64_t spread = (g.N + 127) / 128;
     if (spread < c) c = std::max<int64_t>(spread, (int64_t)(16777216.0 / per_obs));
@@ -644,6 +653,11 @@ void fill_desc(srmra_plan* P, int i, int par, InstDesc& d, char* ws) {
     p.xt2 = (const float*)(w + g.o_xt2);
     p.betaT = (const float*)(w + g.o_beta);
     p.xb = is_bf16_form(P->form[i]) ? (const uint4*)(w + g.o_xb) : nullptr;
+    if (P->form[i] == FORM_FFT) {
+        d.yhat = (const float2*)((const char*)pr.prep + g.prep_extra_off);
+        d.xhat = (float2*)(w + g.o_xhat);
+        d.bh = (double2*)(w + g.o_bh);
+    }
     p.part = (float2*)(w + g.o_part);
     p.lse = (float2*)(w + g.o_lse);
     p.bpart = (float*)(w + g.o_bpart);
@@ -699,8 +713,9 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
     *plan = nullptr;
     *workspace_bytes = 0;
     if (!valid_prec(precision) || precision == SRMRA_FP32_FFT) return SRMRA_EUNSUPPORTED;
-    // a table entry may only keep the plan's precision or, in a BF16 plan, pick
-    // FP32 MFMA (more accurate); the BF16 form needs an L_low it is built for
+    // a table entry may keep the plan's precision, pick FP32 MFMA in a BF16
+    // plan (more accurate), or pick the FFT route (FP32 transforms, FP64 sums)
+    // where it covers the L_low; the BF16 form needs an L_low it is built for
     for (int k = 0; k < n_table; ++k) {
         const srmra_tuning& t = table[k];
         if (t.item_obs < 0) return SRMRA_EINVAL;
@@ -708,8 +723,10 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         // a block tile only where the form has a choice (BF16 split at L_low 16)
         if (t.tile != 0 && !(is_bf16(t.form) && t.L_low == 16 && (t.tile == 1 || t.tile == 2 || t.tile == 4)))
             return SRMRA_EINVAL;
-        const bool ok = t.form == precision || (is_bf16(precision) && t.form == SRMRA_FP32_MFMA);
+        const bool ok = t.form == precision || (is_bf16(precision) && t.form == SRMRA_FP32_MFMA) ||
+                        t.form == SRMRA_FP32_FFT;
         if (!ok) return SRMRA_EINVAL;
+        if (t.form == SRMRA_FP32_FFT && !fft_supported(t.L_low)) return SRMRA_EUNSUPPORTED;
         if (is_bf16(t.form) && !is_bf16_form(form_of(t.form, t.L_low))) return SRMRA_EUNSUPPORTED;
     }
     srmra_plan* P = new (std::nothrow) srmra_plan;
@@ -718,7 +735,7 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
     P->probs.assign(probs, probs + count);
     struct Cost { int cls; double c; int4 it; };
     std::vector<Cost> costs;
-    std::vector<int2> combine_late;
+    std::vector<int2> combine_late, fft_reduce, fft_idft;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
     for (int i = 0; i < count; ++i) {
@@ -773,10 +790,14 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
             for (int b = 0; b < (comp_major ? g.n_chunks : g.n_cg); ++b) {
                 const int ch = comp_major ? b : a, cg = comp_major ? a : b;
                 const int64_t nobs = std::min<int64_t>(g.chunk_obs, g.N - (int64_t)ch * g.chunk_obs);
-                const double cst = (double)nobs * g.cpb * (double)g.LL * g.LL * g.LL * g.LL *
+                // relative cost (orders the classes, heaviest first, and the items in a class)
+                const double dense = (double)g.LL * g.LL * g.LL * g.LL;
+                const double fftc = 40.0 * g.LL * g.LL * log2((double)g.LL);   // transforms per pair
+                const double cst = (double)nobs * g.cpb *
+                                   (f == FORM_FFT ? fftc : dense *
                                    (f == FORM_VALU ? 2.0 : (f == FORM_BF16 ? 0.5 : (f == FORM_BF16X4 ? 0.67 :
                                     ((f == FORM_BF16F || f == FORM_BF16W) ? 0.35
-                                     : ((f == FORM_BF16X4F || f == FORM_BF16X4W) ? 0.45 : 1.0)))));
+                                     : ((f == FORM_BF16X4F || f == FORM_BF16X4W) ? 0.45 : 1.0))))));
                 costs.push_back({cls, cst, make_int4(i, ch, cg, 0)});
             }
         }
@@ -784,8 +805,19 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         for (int k = 0; k < g.n_ll; ++k)
             (single_pass_form(f) ? combine_late : P->combine_items).push_back(make_int2(i, k));
         const int per = g.KK * g.LL * g.LL;
-        for (int k = 0; k < (per + kReduceElems - 1) / kReduceElems; ++k) P->reduce_items.push_back(make_int2(i, k));
+        for (int k = 0; k < (per + kReduceElems - 1) / kReduceElems; ++k)
+            (f == FORM_FFT ? fft_reduce : P->reduce_items).push_back(make_int2(i, k));
+        if (f == FORM_FFT) {
+            for (int c = 0; c < g.KK; ++c) fft_idft.push_back(make_int2(i, c));
+            P->pack_lds = std::max(P->pack_lds, batch_pack_lds(g.LL));
+            P->idft_lds = std::max(P->idft_lds, batch_idft_lds(g.LL));
+        }
     }
+    P->n_reduce_plain = (int)P->reduce_items.size();
+    P->n_fft_reduce = (int)fft_reduce.size();
+    P->n_fft_idft = (int)fft_idft.size();
+    P->reduce_items.insert(P->reduce_items.end(), fft_reduce.begin(), fft_reduce.end());
+    P->reduce_items.insert(P->reduce_items.end(), fft_idft.begin(), fft_idft.end());
     P->n_combine_early = (int)P->combine_items.size();
     P->combine_items.insert(P->combine_items.end(), combine_late.begin(), combine_late.end());
     // items grouped by class (heaviest class first), largest items first within a class
@@ -905,6 +937,10 @@ int srmra_plan_upload(srmra_plan* plan, void* workspace, size_t workspace_bytes,
     if (e == hipSuccess) e = hipEventRecord(plan->staged, stream);
     if (e != hipSuccess) return SRMRA_EDEVICE;
     plan->staged_pending = true;
+    if (plan->n_fft_idft > 0 &&
+        hipFuncSetAttribute(batch_fft_idft_fn(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan->idft_lds) !=
+            hipSuccess)
+        return SRMRA_EDEVICE;
     for (auto& C : plan->classes) {
         for (int pass = 1; pass <= 2; ++pass) {
             const void* f = class_pass_fn(pass, C.form, C.LL);   // null: single-pass class, pass 1
@@ -939,7 +975,11 @@ int srmra_plan_execute(srmra_plan* plan, void* workspace, size_t workspace_bytes
     L.n_pack = (int)plan->pack_items.size();
     L.n_combine = plan->n_combine_early;
     L.n_combine_late = (int)plan->combine_items.size() - plan->n_combine_early;
-    L.n_reduce = (int)plan->reduce_items.size();
+    L.n_reduce = plan->n_reduce_plain;
+    L.n_fft_reduce = plan->n_fft_reduce;
+    L.n_fft_idft = plan->n_fft_idft;
+    L.pack_lds = plan->pack_lds;
+    L.idft_lds = plan->idft_lds;
     L.n_inst = n;
     L.n_class = (int)plan->classes.size();
     for (int k = 0; k < L.n_class; ++k) L.cls[k] = plan->classes[k];

@@ -9,6 +9,7 @@
 #include "srmra_aux_impl.h"
 #include "srmra_batch.h"
 #include "srmra_bf16n_impl.h"
+#include "srmra_fftp_impl.h"
 #include "srmra_mfma_impl.h"
 #include "srmra_valu_impl.h"
 
@@ -27,11 +28,35 @@ __global__ __launch_bounds__(256) void k_batch_pack(const InstDesc* __restrict__
     pack_x_body(d.x, d.log_rho, d.p.K, d.LL, d.p.inv_2s2, d.p.centre, d.xt2_w, d.beta_w, it.y, red);
 }
 
-// BF16-form instances: x as MFMA B fragments, every k-step of one component
+// the FFT form's X_c = DFT(x_c - mu) of component c (dynamic LDS: an L x (L + 1)
+// transpose buffer and the twiddle table)
+template <int L>
+__device__ __forceinline__ void fft_pack_x(const InstDesc& d, int c, float2* sh) {
+    float2* tw = sh + L * (L + 1);
+    fft::make_twiddles_n<L, L>(tw);
+    __syncthreads();
+    fft::pack_x_body<L>(d.x, d.p.K, d.p.centre, d.xhat, c, sh, tw);
+}
+
+// BF16-form instances: x as MFMA B fragments, every k-step of one component;
+// FFT-form instances: the DFT of one component
 __global__ __launch_bounds__(256) void k_batch_pack_xb(const InstDesc* __restrict__ D,
                                                        const int2* __restrict__ items) {
+    extern __shared__ float2 sh[];
     const int2 it = items[blockIdx.x];
     const InstDesc& d = D[it.x];
+    if (d.form == FORM_FFT) {
+        switch (d.LL) {
+            case 8: fft_pack_x<8>(d, it.y, sh); break;
+            case 12: fft_pack_x<12>(d, it.y, sh); break;
+            case 16: fft_pack_x<16>(d, it.y, sh); break;
+            case 24: fft_pack_x<24>(d, it.y, sh); break;
+            case 32: fft_pack_x<32>(d, it.y, sh); break;
+            case 48: fft_pack_x<48>(d, it.y, sh); break;
+            case 64: fft_pack_x<64>(d, it.y, sh); break;
+        }
+        return;
+    }
     if (d.form != FORM_BF16 && d.form != FORM_BF16X4 && d.form != FORM_BF16F && d.form != FORM_BF16X4F &&
         d.form != FORM_BF16W && d.form != FORM_BF16X4W)
         return;
@@ -70,6 +95,34 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const InstDesc* __restrict
     const InstDesc& d = D[it.x];
     reduce_partials_body(d.p.bpart, d.p.cpart, d.p.n_chunks, d.p.KK * d.LL * d.LL, d.bsum, d.csum,
                          it.y, red);
+}
+
+// the FFT form: FP64 sums of the complex back-projection partials and of the
+// posterior mass over chunks (items (instance, block)), then the FP64 inverse
+// DFT of each component's back-projection (items (instance, component))
+__global__ __launch_bounds__(256) void k_batch_fft_reduce(const InstDesc* __restrict__ D,
+                                                          const int2* __restrict__ items) {
+    __shared__ double red[3 * 256];
+    const int2 it = items[blockIdx.x];
+    const InstDesc& d = D[it.x];
+    fft::reduce_body(reinterpret_cast<const float2*>(d.p.bpart), d.p.cpart, d.p.n_chunks,
+                     d.p.KK * d.LL * d.LL, d.bh, d.csum, it.y, red);
+}
+
+__global__ __launch_bounds__(256) void k_batch_fft_idft(const InstDesc* __restrict__ D,
+                                                        const int2* __restrict__ items) {
+    extern __shared__ double2 T[];
+    const int2 it = items[blockIdx.x];
+    const InstDesc& d = D[it.x];
+    switch (d.LL) {
+        case 8: fft::idft_body<8>(d.bh, d.bsum, it.y, T); break;
+        case 12: fft::idft_body<12>(d.bh, d.bsum, it.y, T); break;
+        case 16: fft::idft_body<16>(d.bh, d.bsum, it.y, T); break;
+        case 24: fft::idft_body<24>(d.bh, d.bsum, it.y, T); break;
+        case 32: fft::idft_body<32>(d.bh, d.bsum, it.y, T); break;
+        case 48: fft::idft_body<48>(d.bh, d.bsum, it.y, T); break;
+        case 64: fft::idft_body<64>(d.bh, d.bsum, it.y, T); break;
+    }
 }
 
 __global__ __launch_bounds__(1024) void k_batch_finalize(const InstDesc* __restrict__ D) {
@@ -138,6 +191,21 @@ void k_class_pass(const InstDesc* __restrict__ D,
                 q.yo = d.yo;
                 b16::bf16_pass2_body<LL, NP, true>(d.p, q, w.y, 0, lds);
             }
+        } else if constexpr (FORM == FORM_FFT) {
+            float2* sh = reinterpret_cast<float2*>(lds);
+            float2* bpart = reinterpret_cast<float2*>(d.p.bpart);
+            if constexpr (LL == 64) {
+                if constexpr (PASS == 1) fft::pass1_quad_body(d.p, d.yhat, d.xhat, w.y, w.z, d.p.n_cg, sh);
+                else fft::pass2_quad_body(d.p, d.yhat, d.xhat, bpart, d.p.cpart, w.y, w.z, sh);
+            } else if constexpr (LL % 3 == 0) {
+                if constexpr (PASS == 1) fft::row::pass1_body<LL>(d.p, d.yhat, d.xhat, w.y, w.z, d.p.n_cg, sh);
+                else fft::row::pass2_body<LL>(d.p, d.yhat, d.xhat, fft::tpc_of(LL, d.p.KK), bpart, d.p.cpart,
+                                              w.y, w.z, sh);
+            } else {
+                if constexpr (PASS == 1) fft::pass1_pairs_body<LL>(d.p, d.yhat, d.xhat, w.y, w.z, d.p.n_cg, sh);
+                else fft::pass2_pairs_body<LL>(d.p, d.yhat, d.xhat, fft::tpc_of(LL, d.p.KK), bpart, d.p.cpart,
+                                               w.y, w.z, sh);
+            }
         } else if constexpr (FORM == FORM_FUSED) {
             mfma_fused_body<LL>(d.p, w.y, lds);
         } else if constexpr (FORM == FORM_MFMA) {
@@ -192,6 +260,8 @@ SRMRA_CLASS(FORM_BF16, 16) SRMRA_CLASS(FORM_BF16, 24) SRMRA_CLASS(FORM_BF16, 32)
 SRMRA_CLASS(FORM_BF16, 48) SRMRA_CLASS(FORM_BF16, 64)
 SRMRA_CLASS(FORM_BF16X4, 16) SRMRA_CLASS(FORM_BF16X4, 24) SRMRA_CLASS(FORM_BF16X4, 32)
 SRMRA_CLASS(FORM_BF16X4, 48) SRMRA_CLASS(FORM_BF16X4, 64)
+SRMRA_CLASS(FORM_FFT, 8) SRMRA_CLASS(FORM_FFT, 12) SRMRA_CLASS(FORM_FFT, 16) SRMRA_CLASS(FORM_FFT, 24)
+SRMRA_CLASS(FORM_FFT, 32) SRMRA_CLASS(FORM_FFT, 48) SRMRA_CLASS(FORM_FFT, 64)
 #undef SRMRA_CLASS
 #define SRMRA_BF16F(F, L) template __global__ void k_class_pass<2, F, L>(const InstDesc*, const int4*, int, int*);
 SRMRA_BF16F(FORM_BF16F, 24) SRMRA_BF16F(FORM_BF16F, 32) SRMRA_BF16F(FORM_BF16F, 48)
@@ -216,6 +286,8 @@ const void* class_pass_fn(int pass, int form, int LL) {
     SRMRA_PICK(FORM_BF16, 48) SRMRA_PICK(FORM_BF16, 64)
     SRMRA_PICK(FORM_BF16X4, 16) SRMRA_PICK(FORM_BF16X4, 24) SRMRA_PICK(FORM_BF16X4, 32)
     SRMRA_PICK(FORM_BF16X4, 48) SRMRA_PICK(FORM_BF16X4, 64)
+    SRMRA_PICK(FORM_FFT, 8) SRMRA_PICK(FORM_FFT, 12) SRMRA_PICK(FORM_FFT, 16) SRMRA_PICK(FORM_FFT, 24)
+    SRMRA_PICK(FORM_FFT, 32) SRMRA_PICK(FORM_FFT, 48) SRMRA_PICK(FORM_FFT, 64)
 #undef SRMRA_PICK
     // single pass: no pass-1 kernel
 #define SRMRA_PICK(L) if (form == FORM_FUSED && LL == L) return pass == 2 ? (const void*)k_class_pass<2, FORM_FUSED, L> : nullptr;
@@ -232,10 +304,14 @@ const void* class_pass_fn(int pass, int form, int LL) {
     return nullptr;
 }
 
+const void* batch_fft_idft_fn() { return (const void*)k_batch_fft_idft; }
+size_t batch_pack_lds(int LL) { return sizeof(float2) * ((size_t)LL * (LL + 1) + LL); }
+size_t batch_idft_lds(int LL) { return sizeof(double2) * (size_t)LL * LL + 2 * sizeof(double) * LL; }
+
 hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, L.counters, 2 * L.n_class);
     hipLaunchKernelGGL(k_batch_pack, dim3(L.n_pack), dim3(256), 0, s, L.desc, L.pack_items);
-    hipLaunchKernelGGL(k_batch_pack_xb, dim3(L.n_pack), dim3(256), 0, s, L.desc, L.pack_items);
+    hipLaunchKernelGGL(k_batch_pack_xb, dim3(L.n_pack), dim3(256), L.pack_lds, s, L.desc, L.pack_items);
     const bool par = L.aux[0] != nullptr && L.n_class > 1;
     for (int pass = 1; pass <= 2; ++pass) {
         // fork: the helper streams wait for everything enqueued so far
@@ -281,7 +357,14 @@ hipError_t batch_enqueue(const BatchLaunch& L, hipStream_t s) {
     if (L.n_combine_late > 0)
         hipLaunchKernelGGL(k_batch_combine, dim3(L.n_combine_late), dim3(256), 0, s, L.desc,
                            L.combine_items + L.n_combine);
-    hipLaunchKernelGGL(k_batch_reduce, dim3(L.n_reduce), dim3(256), 0, s, L.desc, L.reduce_items);
+    if (L.n_reduce > 0)
+        hipLaunchKernelGGL(k_batch_reduce, dim3(L.n_reduce), dim3(256), 0, s, L.desc, L.reduce_items);
+    if (L.n_fft_reduce > 0) {
+        hipLaunchKernelGGL(k_batch_fft_reduce, dim3(L.n_fft_reduce), dim3(256), 0, s, L.desc,
+                           L.reduce_items + L.n_reduce);
+        hipLaunchKernelGGL(k_batch_fft_idft, dim3(L.n_fft_idft), dim3(256), L.idft_lds, s, L.desc,
+                           L.reduce_items + L.n_reduce + L.n_fft_reduce);
+    }
     hipLaunchKernelGGL(k_batch_finalize, dim3(L.n_inst), dim3(1024), 0, s, L.desc);
     return hipGetLastError();
 }

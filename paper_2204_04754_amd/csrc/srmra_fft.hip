@@ -1,73 +1,8 @@
-// FFT route of the EM step (SRMRA_FP32_FFT, L_low in {8, 16, 32, 64}): the same
-// step as the dense forms, with the contractions as products in the 2-D DFT
-// domain of the L_low grid.  With (R_t v)[n] = v[n - t]:
-//   score     S_{i,c}[t] = sum_n y_i[n] x_c[n - t]      = IDFT(Y_i . conj(X_c))[t]
-//   back-proj b_c[q]     = sum_i sum_t w_{i,c}[t] y_i[q + t] = IDFT(sum_i Y_i . conj(W_{i,c}))[q]
-//   mass      c_c[t]     = sum_i w_{i,c}[t]   (summed directly, no transform)
-// Y_i (DFT of y_i - mu) is prepared once per job; X_c once per step.  Pass 1:
-// team per observation, its (max, sum exp) over all components.  Pass 2: team
-// per component (observations split over TPC teams), w = exp(a - LSE_i), its
-// DFT, the frequency-domain sum of the back-projection and the spatial sum of
-// w; per-chunk FP32 partials, summed in FP64, the former brought back by a
-// separable FP64 inverse DFT.  One component per
-// transform: packing two real signals into one complex transform would give a
-// component of little posterior mass the rounding error of its heavier
-// partner.  The transforms are the in-register team FFTs of srmra_fft_impl.h
-// (O(L^2 log L) per pair instead of the dense 4 L^4).
-#include "srmra_aux_impl.h"
-#include "srmra_common.h"
-#include "srmra_fft_impl.h"
+// Kernels of the FFT route (bodies in srmra_fftp_impl.h) and their launches.
+#include "srmra_fftp_impl.h"
 
 namespace srmra {
 namespace fft {
-
-template <int L> struct Geo {
-    static constexpr int TEAMS = 256 / L;
-    static constexpr int BUF = L * (L + 1);   // float2 per team buffer
-};
-
-template <int L> constexpr size_t lds_bytes() {
-    return sizeof(float2) * ((size_t)Geo<L>::TEAMS * Geo<L>::BUF + L / 2);
-}
-
-// ---- per job: Y_i = DFT(y_i - mu), [N][L][L] complex.  TRANSPOSED: stored in
-// pairs along k2, Yp[i][k2 / 2][k1][k2 % 2] = Y_i[k1][k2], so that the thread
-// of a team that holds row k1 of Y_i reads two elements per 16-byte load and
-// the team's lanes read consecutive 16-byte words; otherwise natural order
-// Y[i][k1][k2].
-template <int L, bool TRANSPOSED>
-__device__ __forceinline__ void prep_y_body(const float* __restrict__ y, int64_t N,
-                                            const double* __restrict__ centre,
-                                            float2* __restrict__ yhat) {
-    extern __shared__ float2 sh[];
-    float2* tw = sh + Geo<L>::TEAMS * Geo<L>::BUF;
-    make_twiddles<L>(tw);
-    __syncthreads();
-    const int team = threadIdx.x / L, r = threadIdx.x % L;
-    float2* buf = sh + team * Geo<L>::BUF;
-    const float mu = centre_of(centre);
-    const int64_t i = (int64_t)blockIdx.x * Geo<L>::TEAMS + team;
-    if (i >= N) return;   // whole teams leave together (a team lies in one wave)
-    float2 v[L];
-    if constexpr (TRANSPOSED) {
-        // thread r: column r of y_i in, row r of Y_i out (both coalesced over the team)
-#pragma unroll
-        for (int k = 0; k < L; ++k) v[k] = make_float2(y[(i * L + k) * L + r] - mu, 0.f);
-        fft2_cols_then_rows<L, false>(v, buf, r, tw);
-    } else {
-#pragma unroll
-        for (int k = 0; k < L; ++k) v[k] = make_float2(y[(i * L + r) * L + k] - mu, 0.f);
-        fft2_rows_then_cols<L, false>(v, buf, r, tw);
-    }
-    if constexpr (TRANSPOSED) {   // v[k] = Y_i[r][k]
-        float4* d = reinterpret_cast<float4*>(yhat) + i * (L / 2) * L + r;
-#pragma unroll
-        for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
-    } else {                      // v[k] = Y_i[k][r]
-#pragma unroll
-        for (int k = 0; k < L; ++k) yhat[(i * L + k) * L + r] = v[k];
-    }
-}
 
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_prep_y(const float* __restrict__ y, int64_t N,
@@ -76,355 +11,45 @@ __global__ __launch_bounds__(256) void k_fft_prep_y(const float* __restrict__ y,
     prep_y_body<L, true>(y, N, centre, yhat);
 }
 
-// ---- per step: X_c = DFT(x_c - mu), stored in pairs along k2 like Y:
-// Xp[c][k2 / 2][k1][k2 % 2] = X_c[k1][k2]; one block (first L threads) per component
+// X_c for every component: block c, its first L threads
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_pack_x(const float* __restrict__ x, int K,
                                                     const double* __restrict__ centre,
                                                     float2* __restrict__ xhat) {
     extern __shared__ float2 sh[];
-    float2* tw = sh + Geo<L>::TEAMS * Geo<L>::BUF;
-    make_twiddles<L>(tw);
+    float2* tw = sh + L * (L + 1);
+    make_twiddles_n<L, L>(tw);
     __syncthreads();
-    if (threadIdx.x >= L) return;
-    const int c = blockIdx.x, c1 = c / K, c2 = c % K, Lh = K * L, r = threadIdx.x;
-    const float mu = centre_of(centre);
-    float2 v[L];
-#pragma unroll
-    for (int k = 0; k < L; ++k)   // column r of x_c: v[k] = x_c[k][r]
-        v[k] = make_float2(x[(int64_t)(c1 + k * K) * Lh + (c2 + r * K)] - mu, 0.f);
-    fft2_cols_then_rows<L, false>(v, sh, r, tw);   // v[k] = X_c[r][k]
-    float4* d = reinterpret_cast<float4*>(xhat) + (int64_t)c * (L / 2) * L + r;
-#pragma unroll
-    for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
+    pack_x_body<L>(x, K, centre, xhat, blockIdx.x, sh, tw);
 }
 
-// ---- the two passes at L <= 32: a team of 2L lanes (inside one wave) per
-// image (lane pair (r, h): r the row or column, h which half of it), TEAMS
-// teams per block
-template <int L> struct GeoP {
-    static constexpr int TEAMS = 256 / (2 * L);
-    static constexpr int BUF = L * (L + 1);   // float2 per team buffer
-};
-template <int L> constexpr size_t lds_pairs() {
-    return sizeof(float2) * ((size_t)GeoP<L>::TEAMS * GeoP<L>::BUF + L / 2);
-}
-
-// Scores of (observation o, component c) for pair (r, h): s[k] = a at
-// (t1 = (L/2) h + k, t2 = r).  Row r of Y_o conj(X_c) enters as its samples
-// 2m + h, for which the team's lanes read consecutive words of the paired
-// layouts.
-template <int L>
-__device__ __forceinline__ void score_pair(const StepArgs& p, const float2* __restrict__ yhat,
-                                           const float2* __restrict__ xhat, int64_t o, int c,
-                                           float2* buf, int r, int h, const float2* tw, float (&s)[L / 2]) {
-    float2 v[L / 2];
-    const float2* yr = yhat + ((int64_t)o * (L / 2) * L + r) * 2 + h;   // Y_o[r][2m + h] at yr[2 L m]
-    const float2* xr = xhat + ((int64_t)c * (L / 2) * L + r) * 2 + h;
-#pragma unroll
-    for (int m = 0; m < L / 2; ++m) v[m] = cmulc(yr[2 * L * m], xr[2 * L * m]);
-    fft_pair_dit<L, true>(v, h, tw);                       // v[k] = row r, n2 = (L/2) h + k
-#pragma unroll
-    for (int k = 0; k < L / 2; ++k) buf[r * (L + 1) + (L / 2) * h + k] = v[k];
-    team_sync();
-#pragma unroll
-    for (int m = 0; m < L / 2; ++m) v[m] = buf[(2 * m + h) * (L + 1) + r];   // column r, rows 2m + h
-    team_sync();
-    fft_pair_dit<L, true>(v, h, tw);                       // v[k] = S[(L/2) h + k][r]
-    const float sc = p.inv_s2 / (float)(L * L);
-    const float* bet = p.betaT + (int64_t)c * (L * L) + r * L + (L / 2) * h;   // betaT[c][t2 = r][t1]
-#pragma unroll
-    for (int k = 0; k < L / 2; ++k) s[k] = v[k].x * sc + bet[k];
-}
-
-__device__ __forceinline__ void lse_merge(float& m, float& s, float m2, float s2) {
-    if (m2 == -INFINITY) return;
-    if (m == -INFINITY) { m = m2; s = s2; return; }
-    const float mn = fmaxf(m, m2);
-    s = s * __expf(m - mn) + s2 * __expf(m2 - mn);
-    m = mn;
-}
-
-// ---- pass 1: (max, sum exp) of every observation over all components.  Grid
-// (chunks, component groups) like pass 2: the gridDim.y blocks of a chunk
-// share its observations, so that pass 1 fills the device as pass 2 does.
+// the two passes: grid (chunks, observation splits / component groups)
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_pass1(StepArgs p, const float2* __restrict__ yhat,
                                                    const float2* __restrict__ xhat) {
     extern __shared__ float2 sh[];
-    float2* tw = sh + GeoP<L>::TEAMS * GeoP<L>::BUF;
-    make_twiddles<L>(tw);
-    __syncthreads();
-    const int team = threadIdx.x / (2 * L), lt = threadIdx.x % (2 * L);
-    const int r = lt >> 1, h = lt & 1;
-    float2* buf = sh + team * GeoP<L>::BUF;
-    const int64_t c0 = (int64_t)blockIdx.x * p.chunk_obs;
-    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    for (int64_t o = c0 + team + (int64_t)GeoP<L>::TEAMS * blockIdx.y; o < c1;
-         o += (int64_t)GeoP<L>::TEAMS * gridDim.y) {
-        float m = -INFINITY, sm = 0.f;
-        for (int c = 0; c < p.KK; ++c) {
-            float s[L / 2];
-            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, s);
-            float mc = -INFINITY;
-#pragma unroll
-            for (int k = 0; k < L / 2; ++k) mc = fmaxf(mc, s[k]);
-            float sc = 0.f;
-            if (mc > -INFINITY) {
-#pragma unroll
-                for (int k = 0; k < L / 2; ++k) sc += s[k] > -INFINITY ? __expf(s[k] - mc) : 0.f;
-            }
-            lse_merge(m, sm, mc, sc);
-        }
-        // team reduction (the team is 2L consecutive lanes of one wave)
-        for (int off = L; off > 0; off >>= 1) {
-            const float m2 = __shfl_xor(m, off), s2 = __shfl_xor(sm, off);
-            lse_merge(m, sm, m2, s2);
-        }
-        if (lt == 0) p.part[o] = make_float2(m, sm);
-    }
+    pass1_pairs_body<L>(p, yhat, xhat, blockIdx.x, blockIdx.y, gridDim.y, sh);
 }
-
-// ---- pass 2: per component group, the sums over the chunk.  Component group
-// g holds CG components, TPC = TEAMS / CG teams each (observations split over
-// them); partials [chunk][c][k1][k2] of sum_i Y_i conj(W_i) (bpart, float2)
-// and [chunk][c][t1][t2] of sum_i w_i (cpart, float).
 template <int L>
 __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __restrict__ yhat,
                                                    const float2* __restrict__ xhat, int TPC,
-                                                   float2* __restrict__ bpart,
-                                                   float* __restrict__ cpart) {
+                                                   float2* __restrict__ bpart, float* __restrict__ cpart) {
     extern __shared__ float2 sh[];
-    float2* tw = sh + GeoP<L>::TEAMS * GeoP<L>::BUF;
-    make_twiddles<L>(tw);
-    __syncthreads();
-    const int team = threadIdx.x / (2 * L), lt = threadIdx.x % (2 * L);
-    const int r = lt >> 1, h = lt & 1;
-    float2* buf = sh + team * GeoP<L>::BUF;
-    const int CG = GeoP<L>::TEAMS / TPC;
-    const int c = blockIdx.y * CG + team / TPC, u = team % TPC;
-    const bool active = c < p.KK;
-    const int64_t chunk = blockIdx.x;
-    const int64_t c0 = chunk * p.chunk_obs;
-    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    float2 ab[L / 2];   // sum of Y conj(W) at (k1 = r, k2 = (L/2) h + k)
-    float acw[L / 2];   // posterior mass at (t1 = (L/2) h + k, t2 = r)
-#pragma unroll
-    for (int k = 0; k < L / 2; ++k) { ab[k] = make_float2(0.f, 0.f); acw[k] = 0.f; }
-    if (active) {
-        for (int64_t o = c0 + u; o < c1; o += TPC) {
-            float s[L / 2];
-            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, s);
-            const float2 lse = p.lse[o];
-            float2 v[L / 2];
-#pragma unroll
-            for (int k = 0; k < L / 2; ++k) {
-                const float w = s[k] > -INFINITY ? __expf((s[k] - lse.x) - lse.y) : 0.f;
-                acw[k] += w;
-                v[k] = make_float2(w, 0.f);
-            }
-            // column t2 = r (its half (L/2) h..), transformed along t1, then the rows
-            fft_pair_dif<L, false>(v, h, tw);                    // v[k] = k1 = 2k + h, column r
-#pragma unroll
-            for (int k = 0; k < L / 2; ++k) buf[(2 * k + h) * (L + 1) + r] = v[k];
-            team_sync();
-#pragma unroll
-            for (int m = 0; m < L / 2; ++m) v[m] = buf[r * (L + 1) + 2 * m + h];   // row k1 = r, n2 = 2m + h
-            team_sync();
-            fft_pair_dit<L, false>(v, h, tw);                    // v[k] = W[r][(L/2) h + k]
-            // Y_o[r][(L/2) h + k], k and k + 1 in one 16-byte word of the paired layout
-            const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)o * (L / 2) + (L / 4) * h) * L + r;
-#pragma unroll
-            for (int k = 0; k < L / 2; k += 2) {
-                const float4 a = yr[(k / 2) * L];
-                const float2 t0 = cmulc(make_float2(a.x, a.y), v[k]);
-                const float2 t1 = cmulc(make_float2(a.z, a.w), v[k + 1]);
-                ab[k].x += t0.x; ab[k].y += t0.y;
-                ab[k + 1].x += t1.x; ab[k + 1].y += t1.y;
-            }
-        }
-    }
-    // sum the TPC teams of each component in a fixed order, one plane at a time
-    // (each lane keeps its own L/2 slots of the team buffer)
-    for (int plane = 0; plane < 2; ++plane) {
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < L / 2; ++k)
-            buf[lt * (L / 2) + k] = plane == 0 ? ab[k] : make_float2(acw[k], 0.f);
-        __syncthreads();
-        if (active && u == 0) {
-            for (int k = 0; k < L / 2; ++k) {
-                float2 t = make_float2(0.f, 0.f);
-                for (int j = 0; j < TPC; ++j) {
-                    const float2 e = sh[(team + j) * GeoP<L>::BUF + lt * (L / 2) + k];
-                    t.x += e.x; t.y += e.y;
-                }
-                if (plane == 0) bpart[((chunk * p.KK + c) * L + r) * L + (L / 2) * h + k] = t;   // [k1][k2]
-                else cpart[((chunk * p.KK + c) * L + (L / 2) * h + k) * L + r] = t.x;            // [t1][t2]
-            }
-        }
-    }
+    pass2_pairs_body<L>(p, yhat, xhat, TPC, bpart, cpart, blockIdx.x, blockIdx.y, sh);
 }
-
-// ---- L_low 64: one team per block, four lanes per row (lane 4r + q holds a
-// quarter of row r, see fft_quad_dit / fft_quad_dif), so a lane keeps 16
-// complex values of an image; the LDS transposes are ordered by the block
-// barrier, and every thread of the block belongs to the one team.
-namespace quad {
-constexpr int L = 64, NV = L / 4;
-constexpr int BUF = L * (L + 1);
-// team buffer, the twiddles (L / 2) and one (max, sum) slot per wave
-constexpr size_t lds() { return sizeof(float2) * ((size_t)BUF + L / 2 + 4); }
-
-// scores of (observation o, component c) for lane (r, q): s[k] = a at
-// (t1 = 16 quad_block(q) + k, t2 = r)
-__device__ __forceinline__ void score(const StepArgs& p, const float2* __restrict__ yhat,
-                                      const float2* __restrict__ xhat, int64_t o, int c, float2* buf,
-                                      int r, int q, int bq, const float2* tw, float (&s)[NV]) {
-    float2 v[NV];
-    // Y_o[r][4m + q] of the paired layout [k2 / 2][k1][k2 % 2] at yr[4 L m]
-    const float2* yr = yhat + (((int64_t)o * (L / 2) + (q >> 1)) * L + r) * 2 + (q & 1);
-    const float2* xr = xhat + (((int64_t)c * (L / 2) + (q >> 1)) * L + r) * 2 + (q & 1);
-#pragma unroll
-    for (int m = 0; m < NV; ++m) v[m] = cmulc(yr[4 * L * m], xr[4 * L * m]);
-    fft_quad_dit<L, true>(v, q, tw);                       // v[k] = row r, n2 = 16 bq + k
-#pragma unroll
-    for (int k = 0; k < NV; ++k) buf[r * (L + 1) + 16 * bq + k] = v[k];
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < NV; ++m) v[m] = buf[(4 * m + q) * (L + 1) + r];   // column r, rows 4m + q
-    __syncthreads();
-    fft_quad_dit<L, true>(v, q, tw);                       // v[k] = S[16 bq + k][r]
-    const float sc = p.inv_s2 / (float)(L * L);
-    const float* bet = p.betaT + (int64_t)c * (L * L) + r * L + 16 * bq;   // betaT[c][t2 = r][t1]
-#pragma unroll
-    for (int k = 0; k < NV; ++k) s[k] = v[k].x * sc + bet[k];
-}
-}  // namespace quad
-
-// pass 1 at L_low 64: block (chunk, y) takes the chunk's observations y,
-// y + gridDim.y, ... (the same for all its threads)
 __global__ __launch_bounds__(256) void k_fft_pass1_q(StepArgs p, const float2* __restrict__ yhat,
                                                      const float2* __restrict__ xhat) {
-    using namespace quad;
     extern __shared__ float2 sh[];
-    float2* tw = sh + BUF;
-    float2* red = tw + L / 2;
-    make_twiddles<L>(tw);
-    __syncthreads();
-    const int lt = threadIdx.x, r = lt >> 2, q = lt & 3, bq = quad_block(q);
-    const int64_t c0 = (int64_t)blockIdx.x * p.chunk_obs;
-    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    for (int64_t o = c0 + blockIdx.y; o < c1; o += gridDim.y) {
-        float m = -INFINITY, sm = 0.f;
-        for (int c = 0; c < p.KK; ++c) {
-            float s[NV];
-            score(p, yhat, xhat, o, c, sh, r, q, bq, tw, s);
-            float mc = -INFINITY;
-#pragma unroll
-            for (int k = 0; k < NV; ++k) mc = fmaxf(mc, s[k]);
-            float sc = 0.f;
-            if (mc > -INFINITY) {
-#pragma unroll
-                for (int k = 0; k < NV; ++k) sc += s[k] > -INFINITY ? __expf(s[k] - mc) : 0.f;
-            }
-            lse_merge(m, sm, mc, sc);
-        }
-        // the lanes of each wave by shuffles, then the four waves through LDS
-        for (int off = 32; off > 0; off >>= 1) {
-            const float m2 = __shfl_xor(m, off), s2 = __shfl_xor(sm, off);
-            lse_merge(m, sm, m2, s2);
-        }
-        if ((lt & 63) == 0) red[lt >> 6] = make_float2(m, sm);
-        __syncthreads();
-        if (lt == 0) {
-            for (int w = 1; w < 4; ++w) lse_merge(m, sm, red[w].x, red[w].y);
-            p.part[o] = make_float2(m, sm);
-        }
-    }
+    pass1_quad_body(p, yhat, xhat, blockIdx.x, blockIdx.y, gridDim.y, sh);
 }
-
-// pass 2 at L_low 64: block (chunk, c), one component; partials written directly
 __global__ __launch_bounds__(256) void k_fft_pass2_q(StepArgs p, const float2* __restrict__ yhat,
                                                      const float2* __restrict__ xhat, int /*TPC*/,
-                                                     float2* __restrict__ bpart,
-                                                     float* __restrict__ cpart) {
-    using namespace quad;
+                                                     float2* __restrict__ bpart, float* __restrict__ cpart) {
     extern __shared__ float2 sh[];
-    float2* tw = sh + BUF;
-    make_twiddles<L>(tw);
-    __syncthreads();
-    const int lt = threadIdx.x, r = lt >> 2, q = lt & 3, bq = quad_block(q);
-    const int c = blockIdx.y;
-    const int64_t chunk = blockIdx.x;
-    const int64_t c0 = chunk * p.chunk_obs;
-    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    float2 ab[NV];   // sum of Y conj(W) at (k1 = r, k2 = 16 bq + k)
-    float acw[NV];   // posterior mass at (t1 = 16 bq + k, t2 = r)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) { ab[k] = make_float2(0.f, 0.f); acw[k] = 0.f; }
-    for (int64_t o = c0; o < c1; ++o) {
-        float s[NV];
-        score(p, yhat, xhat, o, c, sh, r, q, bq, tw, s);
-        const float2 lse = p.lse[o];
-        float2 v[NV];
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            const float w = s[k] > -INFINITY ? __expf((s[k] - lse.x) - lse.y) : 0.f;
-            acw[k] += w;
-            v[k] = make_float2(w, 0.f);
-        }
-        // column t2 = r (its block 16 bq..), transformed along t1, then the rows
-        fft_quad_dif<L, false>(v, q, tw);                  // v[k] = k1 = 4k + q, column r
-#pragma unroll
-        for (int k = 0; k < NV; ++k) sh[(4 * k + q) * (L + 1) + r] = v[k];
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < NV; ++m) v[m] = sh[r * (L + 1) + 4 * m + q];   // row k1 = r, n2 = 4m + q
-        __syncthreads();
-        fft_quad_dit<L, false>(v, q, tw);                  // v[k] = W[r][16 bq + k]
-        // Y_o[r][16 bq + k], k and k + 1 in one 16-byte word of the paired layout
-        const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)o * (L / 2) + 8 * bq) * L + r;
-#pragma unroll
-        for (int k = 0; k < NV; k += 2) {
-            const float4 a = yr[(k / 2) * L];
-            const float2 t0 = cmulc(make_float2(a.x, a.y), v[k]);
-            const float2 t1 = cmulc(make_float2(a.z, a.w), v[k + 1]);
-            ab[k].x += t0.x; ab[k].y += t0.y;
-            ab[k + 1].x += t1.x; ab[k + 1].y += t1.y;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        bpart[((chunk * p.KK + c) * L + r) * L + 16 * bq + k] = ab[k];      // [k1][k2]
-        cpart[((chunk * p.KK + c) * L + 16 * bq + k) * L + r] = acw[k];     // [t1][t2]
-    }
+    pass2_quad_body(p, yhat, xhat, bpart, cpart, blockIdx.x, blockIdx.y, sh);
 }
 
-// ---- L_low = 3 * 2^m (12, 24, 48): teams of L lanes, one row (then column) of
-// an image per lane, 64 / L teams in each wave (a team never crosses a wave;
-// the lanes past the last team of a wave idle).  The layouts of Y and X, the
-// partials and the meaning of every sum are those of the power-of-two passes.
 namespace row {
-template <int L> struct G {
-    static constexpr int TPW = 64 / L;          // teams per wave
-    static constexpr int TEAMS = 4 * TPW;       // teams per 256-thread block
-    static constexpr int BUF = L * (L + 1);     // float2 per team transpose buffer
-};
-// [transpose buffers TEAMS x BUF float2][twiddles L float2][masses TEAMS x L x L float]
-template <int L> constexpr size_t lds() {
-    return sizeof(float2) * ((size_t)G<L>::TEAMS * G<L>::BUF + L) + sizeof(float) * (size_t)G<L>::TEAMS * L * L;
-}
-
-// lane -> (team, row r); on: the lane belongs to a team
-template <int L> __device__ __forceinline__ void team_of(int& team, int& r, bool& on) {
-    const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    on = ln < G<L>::TPW * L;
-    team = wave * G<L>::TPW + (on ? ln / L : 0);
-    r = ln % L;
-}
-
-// per job: Y_i = DFT(y_i - mu) in the paired layout Yp[i][k2 / 2][k1][k2 % 2]
 template <int L>
 __global__ __launch_bounds__(256) void k_prep_y(const float* __restrict__ y, int64_t N,
                                                 const double* __restrict__ centre, float2* __restrict__ yhat) {
@@ -455,193 +80,19 @@ __global__ __launch_bounds__(256) void k_prep_y(const float* __restrict__ y, int
     for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
 }
 
-// per step: X_c = DFT(x_c - mu), paired layout; one team (the first L lanes) per component
-template <int L>
-__global__ __launch_bounds__(256) void k_pack_x(const float* __restrict__ x, int K,
-                                                const double* __restrict__ centre, float2* __restrict__ xhat) {
-    extern __shared__ float2 sh[];
-    float2* tw = sh + G<L>::TEAMS * G<L>::BUF;
-    make_twiddles_n<L, L>(tw);
-    __syncthreads();
-    if (threadIdx.x >= L) return;
-    const int c = blockIdx.x, c1 = c / K, c2 = c % K, Lh = K * L, r = threadIdx.x;
-    const float mu = centre_of(centre);
-    float2 v[L];
-#pragma unroll
-    for (int k = 0; k < L; ++k)   // column r of x_c
-        v[k] = make_float2(x[(int64_t)(c1 + k * K) * Lh + (c2 + r * K)] - mu, 0.f);
-    fft1m<L, false>(v, tw);
-#pragma unroll
-    for (int k = 0; k < L; ++k) sh[k * (L + 1) + r] = v[k];
-    team_sync();
-#pragma unroll
-    for (int k = 0; k < L; ++k) v[k] = sh[r * (L + 1) + k];
-    team_sync();
-    fft1m<L, false>(v, tw);                                     // v[k] = X_c[r][k]
-    float4* d = reinterpret_cast<float4*>(xhat) + (int64_t)c * (L / 2) * L + r;
-#pragma unroll
-    for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
-}
-
-// scores of (observation o, component c) for lane r: s[k] = a at (t1 = k, t2 = r).
-// Row r of Y_o conj(X_c) is inverse-transformed along k2, the team exchanges
-// rows for columns, and column r is inverse-transformed along k1.
-template <int L>
-__device__ __forceinline__ void score(const StepArgs& p, const float2* __restrict__ yhat,
-                                      const float2* __restrict__ xhat, int64_t o, int c, float2* buf, int r,
-                                      const float2* tw, float (&s)[L]) {
-    float2 v[L];
-    const float4* yr = reinterpret_cast<const float4*>(yhat) + (int64_t)o * (L / 2) * L + r;
-    const float4* xr = reinterpret_cast<const float4*>(xhat) + (int64_t)c * (L / 2) * L + r;
-#pragma unroll
-    for (int m = 0; m < L / 2; ++m) {
-        const float4 a = yr[m * L], b = xr[m * L];
-        v[2 * m] = cmulc(make_float2(a.x, a.y), make_float2(b.x, b.y));
-        v[2 * m + 1] = cmulc(make_float2(a.z, a.w), make_float2(b.z, b.w));
-    }
-    fft1m<L, true>(v, tw);                                      // v[n2]: row k1 = r
-#pragma unroll
-    for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = v[k];
-    team_sync();
-#pragma unroll
-    for (int m = 0; m < L; ++m) v[m] = buf[m * (L + 1) + r];   // column n2 = r
-    team_sync();
-    fft1m<L, true>(v, tw);                                      // v[k] = S[k][r]
-    const float sc = p.inv_s2 / (float)(L * L);
-    const float* bet = p.betaT + (int64_t)c * (L * L) + r * L;   // betaT[c][t2 = r][t1]
-#pragma unroll
-    for (int k = 0; k < L; ++k) s[k] = v[k].x * sc + bet[k];
-}
-
-// pass 1: (max, sum exp) of every observation over all components; a team per
-// observation, the chunk's observations split over the gridDim.y blocks of the chunk
 template <int L>
 __global__ __launch_bounds__(256) void k_pass1(StepArgs p, const float2* __restrict__ yhat,
                                                const float2* __restrict__ xhat) {
     extern __shared__ float2 sh[];
-    float2* tw = sh + G<L>::TEAMS * G<L>::BUF;
-    make_twiddles_n<L, L>(tw);
-    __syncthreads();
-    int team, r;
-    bool on;
-    team_of<L>(team, r, on);
-    if (!on) return;   // no block barrier follows
-    float2* buf = sh + team * G<L>::BUF;
-    const int64_t c0 = (int64_t)blockIdx.x * p.chunk_obs;
-    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    for (int64_t o = c0 + team + (int64_t)G<L>::TEAMS * blockIdx.y; o < c1;
-         o += (int64_t)G<L>::TEAMS * gridDim.y) {
-        float m = -INFINITY, sm = 0.f;
-        for (int c = 0; c < p.KK; ++c) {
-            float s[L];
-            score<L>(p, yhat, xhat, o, c, buf, r, tw, s);
-            float mc = -INFINITY;
-#pragma unroll
-            for (int k = 0; k < L; ++k) mc = fmaxf(mc, s[k]);
-            float sc = 0.f;
-            if (mc > -INFINITY) {
-#pragma unroll
-                for (int k = 0; k < L; ++k) sc += s[k] > -INFINITY ? __expf(s[k] - mc) : 0.f;
-            }
-            lse_merge(m, sm, mc, sc);
-        }
-        // the team's L lanes merged in lane order by its first lane
-        buf[r] = make_float2(m, sm);
-        team_sync();
-        if (r == 0) {
-            for (int k = 1; k < L; ++k) lse_merge(m, sm, buf[k].x, buf[k].y);
-            p.part[o] = make_float2(m, sm);
-        }
-        team_sync();
-    }
+    pass1_body<L>(p, yhat, xhat, blockIdx.x, blockIdx.y, gridDim.y, sh);
 }
-
-// pass 2: per component group, the sums over the chunk (TPC teams per
-// component, observations split over them): partials of sum_i Y_i conj(W_i)
-// [chunk][c][k1][k2] (complex) and of sum_i w_i [chunk][c][t1][t2]
 template <int L>
 __global__ __launch_bounds__(256) void k_pass2(StepArgs p, const float2* __restrict__ yhat,
                                                const float2* __restrict__ xhat, int TPC,
                                                float2* __restrict__ bpart, float* __restrict__ cpart) {
     extern __shared__ float2 sh[];
-    float2* tw = sh + G<L>::TEAMS * G<L>::BUF;
-    float* mass = reinterpret_cast<float*>(tw + L);              // [team][t1][t2]
-    make_twiddles_n<L, L>(tw);
-    int team, r;
-    bool on;
-    team_of<L>(team, r, on);
-    float2* buf = sh + team * G<L>::BUF;
-    float* mt = mass + team * L * L;
-    const int CG = G<L>::TEAMS / TPC;
-    const int c = blockIdx.y * CG + team / TPC, u = team % TPC;
-    const bool active = on && team < CG * TPC && c < p.KK;
-    if (on) {
-#pragma unroll
-        for (int k = 0; k < L; ++k) mt[k * L + r] = 0.f;
-    }
-    __syncthreads();
-    const int64_t chunk = blockIdx.x;
-    const int64_t c0 = chunk * p.chunk_obs;
-    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    float2 ab[L];   // sum of Y conj(W) at (k1 = r, k2 = k)
-#pragma unroll
-    for (int k = 0; k < L; ++k) ab[k] = make_float2(0.f, 0.f);
-    if (active) {
-        for (int64_t o = c0 + u; o < c1; o += TPC) {
-            float s[L];
-            score<L>(p, yhat, xhat, o, c, buf, r, tw, s);
-            const float2 lse = p.lse[o];
-            float2 v[L];
-#pragma unroll
-            for (int k = 0; k < L; ++k) {
-                const float w = s[k] > -INFINITY ? __expf((s[k] - lse.x) - lse.y) : 0.f;
-                mt[k * L + r] += w;                             // (t1 = k, t2 = r): the lane's own
-                v[k] = make_float2(w, 0.f);
-            }
-            fft1m<L, false>(v, tw);                             // column t2 = r along t1: v[k1]
-#pragma unroll
-            for (int k = 0; k < L; ++k) buf[k * (L + 1) + r] = v[k];
-            team_sync();
-#pragma unroll
-            for (int m = 0; m < L; ++m) v[m] = buf[r * (L + 1) + m];   // row k1 = r
-            team_sync();
-            fft1m<L, false>(v, tw);                             // v[k] = W[r][k]
-            const float4* yr = reinterpret_cast<const float4*>(yhat) + o * (L / 2) * L + r;
-#pragma unroll
-            for (int k = 0; k < L; k += 2) {
-                const float4 a = yr[(k / 2) * L];
-                const float2 t0 = cmulc(make_float2(a.x, a.y), v[k]);
-                const float2 t1 = cmulc(make_float2(a.z, a.w), v[k + 1]);
-                ab[k].x += t0.x; ab[k].y += t0.y;
-                ab[k + 1].x += t1.x; ab[k + 1].y += t1.y;
-            }
-        }
-    }
-    // the TPC teams of each component summed in a fixed order: each team's
-    // back-projection transform goes into its transpose buffer ([k1][k2], pitch
-    // L + 1), then the component's first team adds them up
-    __syncthreads();
-    if (on) {
-#pragma unroll
-        for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = ab[k];
-    }
-    __syncthreads();
-    if (active && u == 0) {
-        for (int k = 0; k < L; ++k) {
-            float2 t = make_float2(0.f, 0.f);
-            float cm = 0.f;
-            for (int j = 0; j < TPC; ++j) {
-                const float2 e = sh[(team + j) * G<L>::BUF + r * (L + 1) + k];
-                t.x += e.x; t.y += e.y;
-                cm += mass[(team + j) * L * L + k * L + r];
-            }
-            bpart[((chunk * p.KK + c) * L + r) * L + k] = t;       // [k1 = r][k2 = k]
-            cpart[((chunk * p.KK + c) * L + k) * L + r] = cm;      // [t1 = k][t2 = r]
-        }
-    }
+    pass2_body<L>(p, yhat, xhat, TPC, bpart, cpart, blockIdx.x, blockIdx.y, sh);
 }
-
-// batched forward DFT of real images (utility): out[i][k1][k2]
 template <int L>
 __global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int64_t count,
                                               float2* __restrict__ out) {
@@ -671,82 +122,22 @@ __global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int6
 }
 }  // namespace row
 
-// ---- FP64 sums of the partials over chunks: the back-projection's transform
-// [KK][L][L] complex, the posterior mass [KK][t1][t2] real (final)
 __global__ __launch_bounds__(256) void k_fft_reduce(const float2* __restrict__ bpart,
                                                     const float* __restrict__ cpart, int n_chunks,
                                                     int per, double2* __restrict__ bh,
                                                     double* __restrict__ csum) {
-    // the chunk slices of reduce_partials_body, for complex b
     __shared__ double red[3 * 256];
-    const int le = threadIdx.x % kReduceElems, sl = threadIdx.x / kReduceElems;
-    const int e = blockIdx.x * kReduceElems + le;
-    double2 sb = make_double2(0.0, 0.0);
-    double sc = 0.0;
-    if (e < per) {
-        for (int k = sl; k < n_chunks; k += kReduceSlices) {
-            const float2 b = bpart[(int64_t)k * per + e];
-            sb.x += b.x; sb.y += b.y;
-            sc += cpart[(int64_t)k * per + e];
-        }
-    }
-    red[threadIdx.x] = sb.x;
-    red[256 + threadIdx.x] = sb.y;
-    red[512 + threadIdx.x] = sc;
-    __syncthreads();
-    if (sl == 0 && e < per) {
-        double2 tb = make_double2(0.0, 0.0);
-        double tc = 0.0;
-        for (int s = 0; s < kReduceSlices; ++s) {
-            tb.x += red[s * kReduceElems + le];
-            tb.y += red[256 + s * kReduceElems + le];
-            tc += red[512 + s * kReduceElems + le];
-        }
-        bh[e] = tb;
-        csum[e] = tc;
-    }
+    reduce_body(bpart, cpart, n_chunks, per, bh, csum, blockIdx.x, red);
 }
 
-// ---- FP64 inverse DFT of the back-projection, one workgroup per component,
-// separable: T[k1][q2] = sum_k2 B[k1][k2] w^(k2 q2) into LDS, then
-// bsum[c][q1 L + q2] = Re sum_k1 T[k1][q2] w^(k1 q1) / L^2 (w = exp(2 pi i / L);
-// the layout the finalize kernel reads).  Dynamic LDS: idft_lds<L>() bytes.
-template <int L> constexpr size_t idft_lds() { return sizeof(double2) * L * L + 2 * sizeof(double) * L; }
+// one workgroup per component; dynamic LDS: idft_lds<L>() bytes
 template <int L>
-__global__ __launch_bounds__(256) void k_fft_idft(const double2* __restrict__ bh,
-                                                  double* __restrict__ bsum) {
-    extern __shared__ double2 T[];                       // [L][L]
-    double* cs = reinterpret_cast<double*>(T + L * L);   // [L]
-    double* sn = cs + L;                                 // [L]
-    if (threadIdx.x < L) sincospi(2.0 * (double)threadIdx.x / (double)L, &sn[threadIdx.x], &cs[threadIdx.x]);
-    __syncthreads();
-    const int c = blockIdx.x;
-    const double2* B = bh + (int64_t)c * L * L;
-    for (int e = threadIdx.x; e < L * L; e += 256) {
-        const int k1 = e / L, q2 = e % L;
-        double re = 0.0, im = 0.0;
-        for (int k2 = 0; k2 < L; ++k2) {
-            const int m = (k2 * q2) % L;
-            const double2 b = B[k1 * L + k2];
-            re += b.x * cs[m] - b.y * sn[m];
-            im += b.x * sn[m] + b.y * cs[m];
-        }
-        T[e] = make_double2(re, im);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < L * L; e += 256) {
-        const int q1 = e / L, q2 = e % L;
-        double re = 0.0;
-        for (int k1 = 0; k1 < L; ++k1) {
-            const int m = (k1 * q1) % L;
-            const double2 t = T[k1 * L + q2];
-            re += t.x * cs[m] - t.y * sn[m];
-        }
-        bsum[(int64_t)c * L * L + e] = re * (1.0 / (double)(L * L));
-    }
+__global__ __launch_bounds__(256) void k_fft_idft(const double2* __restrict__ bh, double* __restrict__ bsum) {
+    extern __shared__ double2 T[];
+    idft_body<L>(bh, bsum, blockIdx.x, T);
 }
 
-// ---- batched forward DFT of real images (utility): out[i][k1][k2]
+// batched forward DFT of real images (utility): out[i][k1][k2]
 template <int L>
 __global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int64_t count,
                                               float2* __restrict__ out) {
@@ -759,20 +150,8 @@ __global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int6
 static bool mixed_ll(int LL) { return LL == 12 || LL == 24 || LL == 48; }
 bool fft_supported(int LL) { return LL == 8 || LL == 16 || LL == 32 || LL == 64 || mixed_ll(LL); }
 
-// teams of the two passes per block (2 LL lanes each; at LL 64 one team of
-// four lanes per row; at LL = 3 * 2^m, 64 / LL teams of LL lanes per wave)
-int fft_teams(int LL) {
-    if (mixed_ll(LL)) return 4 * (64 / LL);
-    return LL == 64 ? 1 : 256 / (2 * LL);
-}
-
-// teams per component in pass 2 for KK components (a power of 2 dividing the teams)
-int fft_tpc(int LL, int KK) {
-    const int teams = fft_teams(LL);
-    int tpc = 1;
-    while (tpc * 2 <= teams && KK * tpc * 2 <= teams) tpc *= 2;
-    return tpc;
-}
+int fft_teams(int LL) { return fft::teams_of(LL); }
+int fft_tpc(int LL, int KK) { return fft::tpc_of(LL, KK); }
 
 size_t fft_lds(int LL) {   // the two passes
     switch (LL) {
@@ -816,9 +195,11 @@ static hipError_t fft_launch_row(int what, const StepArgs& p, const float* x, co
                                lds, s, y, p.N, p.centre, (float2*)yhat);
             break;
         case 1:
-            if (attr((const void*)fft::row::k_pack_x<L>) != hipSuccess) return hipErrorInvalidValue;
-            hipLaunchKernelGGL(fft::row::k_pack_x<L>, dim3(p.KK), dim3(256), lds, s, x, p.K, p.centre,
-                               (float2*)xhat);
+            if (hipFuncSetAttribute((const void*)fft::k_fft_pack_x<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)fft::pack_lds<L>()) != hipSuccess)
+                return hipErrorInvalidValue;
+            hipLaunchKernelGGL(fft::k_fft_pack_x<L>, dim3(p.KK), dim3(256), fft::pack_lds<L>(), s, x, p.K,
+                               p.centre, (float2*)xhat);
             break;
         case 2:
             if (attr((const void*)fft::row::k_pass1<L>) != hipSuccess) return hipErrorInvalidValue;
@@ -867,9 +248,10 @@ static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, con
                                    y, p.N, p.centre, (float2*)yhat);
                 break;
             case 1:   // X
-                (void)hipFuncSetAttribute((const void*)fft::k_fft_pack_x<L>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-                hipLaunchKernelGGL(fft::k_fft_pack_x<L>, dim3(p.KK), dim3(256), lds, s, x, p.K, p.centre,
-                                   (float2*)xhat);
+                (void)hipFuncSetAttribute((const void*)fft::k_fft_pack_x<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)fft::pack_lds<L>());
+                hipLaunchKernelGGL(fft::k_fft_pack_x<L>, dim3(p.KK), dim3(256), fft::pack_lds<L>(), s, x, p.K,
+                                   p.centre, (float2*)xhat);
                 break;
             case 2: {
                 auto f = L == 64 ? fft::k_fft_pass1_q : fft::k_fft_pass1<L == 64 ? 32 : L>;

@@ -30,6 +30,12 @@ Model of the errors (Sec. 2, eq. weights_EM, eq. x_EM, eq. rho_EM):
   term the weights' own rounding above).
 * A weight below the FP32 normal range may be lost entirely: an absolute
   error of up to ETA = 2^-126 per weight, n_c = N Ll^2 weights per pixel.
+* Through the DFTs (the FFT route) the back-projection's error is norm-wise,
+  not relative to each element's own terms: a correlation formed as
+  IDFT(Y conj(W)) has ||error||_2 <= e_prod ||w||_1 ||y||_2 (each transform's
+  error is relative in the 2-norm, and |W| <= ||w||_1 at every frequency), so
+  every element of b_c also gets e_prod max_i ||y_i - mu|| m_c, m_c the
+  component's posterior mass (taken as its largest over the components).
 
 The oracle returns the first-order sums of the weight errors (v1, v0, c1 for
 the scale g, b_abs, w_max), from which every element gets its own bound.
@@ -108,11 +114,19 @@ def elementwise_bounds(ref: dict, x_in, y, precision: str, K: int, centre: bool 
     ymax = float(np.abs(np.asarray(y, np.float64)).max())
     A, xr = ref["a"], ref["x_new"]
     xm = np.abs(xr - centre_offset(y, centre))
+    fft_b = 0.0
+    if precision == "fp32_fft":
+        Lh = K * Ll
+        comp = (-np.arange(Lh)) % K
+        mass = max(float(ref["c"][np.ix_(comp == a, comp == b)].sum()) for a in range(K) for b in range(K))
+        yc = np.asarray(y, np.float64) - centre_offset(y, centre)
+        fft_b = product_error(precision, Ll) * float(np.linalg.norm(yc.reshape(N, -1), axis=1).max()) * mass
     with np.errstate(divide="ignore", invalid="ignore"):
         num = (d2 * (ref["v1"] + (mu + xm) * ref["v0"]) + kappa * (ref["b_abs"] + (mu + xm) * A)
-               + n_c * ETA * (ymax + mu + xm))
+               + n_c * ETA * (ymax + mu + xm) + fft_b)
         tol_x = np.where(A > 0, num / A, np.inf) + 4.0 * U32 * (np.abs(xr) + mu)
-    tol_b = d2 * (ref["v1"] + 2 * mu * ref["v0"]) + kappa * (ref["b_abs"] + 2 * mu * A) + n_c * ETA * (ymax + 2 * mu)
+    tol_b = (d2 * (ref["v1"] + 2 * mu * ref["v0"]) + kappa * (ref["b_abs"] + 2 * mu * A)
+             + n_c * ETA * (ymax + 2 * mu) + fft_b)
     tol_c = d2 * ref["c1"] + kappa * ref["c"] + N * ETA
     tot = ref["c"].sum()
     rho = ref["rho_new"]

@@ -162,3 +162,105 @@ def test_bf16_block_tile_at_l16_matches_oracle(tile):
         g = be.results(j)
         ref = oracle_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K)
         check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, "bf16_split3")
+
+
+# every L_low the FFT route covers: 16 (K 2, 3, 4), 24 (K 2, 4), 8, 32, 48, 64 and 12
+FFT_MIX = MIX + [(36, 3, 41, 1.0)]
+
+
+def _fft_table(mix, prec, only=None):
+    from paper_2204_04754_amd import binding as B
+    classes = sorted({(Lh // K, K) for (Lh, K, _, _) in mix})
+    return [dict(precision=B._prec(prec), L_low=ll, K=K, form=B.SRMRA_FP32_FFT, item_obs=0)
+            for (ll, K) in classes if only is None or ll in only]
+
+
+@pytest.mark.parametrize("prec", ["bf16_split3", "fp32_mfma"])
+def test_fft_classes_match_oracle(prec):
+    """Tuning entries that send every class of a plan to the FFT route: each
+    problem is prepared with its observations' DFTs, its class runs the FFT
+    passes as persistent launches, and the step matches the oracle to the FFT
+    route's bound (two steps, so that the second starts from the first's
+    iterate)."""
+    ins = _instances(FFT_MIX, config=76)
+    be = BatchedEM(ins, precision=prec, tuning=_fft_table(FFT_MIX, prec))
+    be.step()
+    torch.cuda.synchronize()
+    firsts = []
+    for j, d in enumerate(ins):
+        inst = d["inst"]
+        g = be.results(j)
+        ref = oracle_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K)
+        ex, er = check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, g, ref, "fp32_fft")
+        print(f"instance {j} (Lh {inst.Lh}, K {inst.K}, N {inst.N}): x {ex:.2e} rho {er:.2e}")
+        firsts.append(g)
+    be.step()
+    torch.cuda.synchronize()
+    for j, d in enumerate(ins):
+        inst = d["inst"]
+        x1 = firsts[j]["x_new"].astype(np.float32)
+        lr1 = firsts[j]["log_rho_new"].astype(np.float32)
+        ref = oracle_step(inst.y, x1, lr1, inst.sigma, inst.K)
+        check_step(inst.y, x1, lr1, inst.sigma, inst.K, be.results(j), ref, "fp32_fft")
+
+
+def test_fft_class_alone_equals_in_mix_bitwise():
+    """FFT classes beside BF16 ones: an FFT-form problem gives bitwise the same
+    three steps alone as inside the mixed plan."""
+    ins = _instances(FFT_MIX, config=77)
+    tab = _fft_table(FFT_MIX, "bf16_split3", only=(12, 16, 32, 64))
+    mix = BatchedEM(ins, precision="bf16_split3", tuning=tab)
+    for _ in range(3):
+        mix.step()
+    torch.cuda.synchronize()
+    for j in (0, 2, 6, 8, 9):
+        alone = BatchedEM([ins[j]], precision="bf16_split3", tuning=tab)
+        for _ in range(3):
+            alone.step()
+        torch.cuda.synchronize()
+        a, b = alone.results(0), mix.results(j)
+        for k in ("x_new", "rho_new", "log_rho_new", "loglik"):
+            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (j, k)
+
+
+def test_fft_classes_graph_replays_match_eager():
+    ins = _instances(FFT_MIX[:6], config=78)
+    tab = _fft_table(FFT_MIX[:6], "bf16_split3", only=(16, 24))
+    eager = BatchedEM(ins, precision="bf16_split3", tuning=tab)
+    graph_be = BatchedEM(ins, precision="bf16_split3", tuning=tab)
+    T = 2
+    g = graph_be.capture(T)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        g.replay()
+        graph_be.executions += T
+        for _ in range(T):
+            eager.step()
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for j in range(len(ins)):
+            a, b = eager.results(j), graph_be.results(j)
+            for k in ("x_new", "rho_new", "log_rho_new", "loglik"):
+                assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (rep, j, k)
+
+
+def test_autotuner_with_fft_candidates():
+    """With fft the autotuner also times the FFT route; the problems of a class
+    it sends there are re-prepared with their DFTs, and every class matches the
+    oracle to the bound of the form it runs in."""
+    from paper_2204_04754_amd import binding as B
+    ins = _instances(FFT_MIX[:4] + [FFT_MIX[-1]], config=79)
+    be = BatchedEM(ins, precision="bf16_split3", tuning="auto", fft=True)
+    forms = {(t["L_low"], t["K"]): t["form"] for t in be.tuning}
+    assert set(forms.values()) <= {B.SRMRA_BF16_SPLIT3, B.SRMRA_FP32_MFMA, B.SRMRA_FP32_FFT}
+    assert any(r["form"] == B.SRMRA_FP32_FFT for r in be.tune_report)
+    name = {B.SRMRA_BF16_SPLIT3: "bf16_split3", B.SRMRA_FP32_MFMA: "fp32_mfma", B.SRMRA_FP32_FFT: "fp32_fft"}
+    be.step()
+    torch.cuda.synchronize()
+    for j, d in enumerate(ins):
+        inst = d["inst"]
+        ref = oracle_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K)
+        f = name[forms[(inst.Ll, inst.K)]]
+        x_tol = 2e-4 if f.startswith("bf16") and inst.N < 20 else 1e-4
+        check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, be.results(j), ref, f, x_tol=x_tol)
