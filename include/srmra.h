@@ -86,7 +86,9 @@ typedef enum {
                                  DFTs of the L_low grid (FP32 transforms, FP64 sums
                                  and inverse); L_low in {8, 12, 16, 24, 32, 48, 64}
                                  (powers of two; 3 * 2^m with a radix-3 step);
-                                 single-problem calls only (no plan)                */
+                                 single-problem calls, and the classes of a plan
+                                 a tuning entry sends here (not a plan's own
+                                 precision)                                         */
 } srmra_precision;
 
 /* Human-readable text of a status code (static storage). */
@@ -259,11 +261,13 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision,
 /* One entry of a tuning table for srmra_plan_create_tuned (the project's
  * autotuner, paper_2204_04754_amd/autotune.py, measures and writes these).
  * Problems with this (L_low, K) in a plan of precision `precision` run in
- * precision `form` -- the plan's own precision, or SRMRA_FP32_MFMA in a
- * BF16 split plan -- with `item_obs` observations per work item
+ * precision `form` -- the plan's own precision, SRMRA_FP32_MFMA in a BF16
+ * split plan, or SRMRA_FP32_FFT (the FFT route, any plan, at the L_low it
+ * covers) -- with `item_obs` observations per work item
  * (rounded up to the form's observation tile; 0 keeps the default of about
- * 2^28 multiply-adds per item, smaller -- down to 2^24 -- where that leaves
- * the problem fewer than 128 items per component group), and with the block
+ * 2^28 multiply-adds per item -- for the FFT route about 2^28 flop of its
+ * transforms -- smaller, down to 2^24, where that leaves the problem fewer
+ * than 128 items per component group), and with the block
  * tile `tile` where the form has a choice: for the BF16 split at L_low 16,
  * the component slots WC of a workgroup (1, 2 or 4: a workgroup covers
  * 32 / WC observations and 4 WC components); 0 keeps the default (WC from
@@ -282,9 +286,12 @@ typedef struct srmra_tuning {
  * 0, which is srmra_plan_create).  SRMRA_EINVAL for a negative item_obs, a
  * tile other than 0 where the entry's form and L_low have no choice or a tile
  * outside that choice, or a form the plan's precision does not allow;
- * SRMRA_EUNSUPPORTED for a BF16 entry at an L_low without a BF16 kernel.  The
- * prepared buffer of every problem must suit the form it runs in (a BF16
- * split preparation also serves SRMRA_FP32_MFMA). */
+ * SRMRA_EUNSUPPORTED for a BF16 entry at an L_low without a BF16 kernel, or
+ * an FFT entry at an L_low the FFT route does not cover.  The prepared buffer
+ * of every problem must suit the form it runs in (a BF16 split preparation
+ * also serves SRMRA_FP32_MFMA; the FFT route needs an SRMRA_FP32_FFT
+ * preparation, which holds the observations' DFTs); SRMRA_EWORKSPACE if it is
+ * smaller than that form's preparation. */
 int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision,
                             const srmra_tuning* table, int n_table,
                             srmra_plan** plan, size_t* workspace_bytes);
