@@ -358,8 +358,8 @@ def bench_batched(args):
         groups = {}
         for d, e in zip(mix, ins):
             groups.setdefault((d["Lh"] // d["K"], d["K"]), []).append((d, e))
-        for (ll, k) in sorted(groups):
-            be = BatchedEM([e for _, e in groups[(ll, k)]], precision=args.precision)
+        def time_class(members, tuning):
+            be = BatchedEM(members, precision=args.precision, tuning=tuning)
             g = be.capture(2)
             g.replay()
             torch.cuda.synchronize()
@@ -368,17 +368,23 @@ def bench_batched(args):
             g.replay()
             e1.record()
             torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / 2
-            pairs = be.pairs_per_step
+            ms, pairs = e0.elapsed_time(e1) / 2, be.pairs_per_step
+            del g, be
+            torch.cuda.empty_cache()
+            return ms, pairs
+
+        for (ll, k) in sorted(groups):
+            members = [e for _, e in groups[(ll, k)]]
+            ms, pairs = time_class(members, None)
+            ms_fft, _ = time_class(members, [t for t in fft_table if (t["L_low"], t["K"]) == (ll, k)])
             # the class's algorithmic work (4 L_low^2 flop per pair) at the form's peak, issued
             # with its products per multiply-add (3 or 4 for the BF16 split)
             ideal = pairs * 4 * ll * ll * PRODUCTS.get(args.precision, 1) / PEAK[args.precision][1] * 1e3
-            classes.append(dict(L_low=ll, K=k, instances=len(groups[(ll, k)]), pairs=pairs, ms_per_step=ms,
-                                ideal_ms=ideal, frac=ideal / ms))
-            print(f"[bench] class L_low {ll} K {k}: {len(groups[(ll, k)])} instances, {ms:.2f} ms/step, "
-                  f"{100 * ideal / ms:.0f}% of its peak-rate time {ideal:.2f} ms", file=sys.stderr, flush=True)
-            del g, be
-            torch.cuda.empty_cache()
+            classes.append(dict(L_low=ll, K=k, instances=len(members), pairs=pairs, ms_per_step=ms,
+                                ideal_ms=ideal, frac=ideal / ms, fft_ms_per_step=ms_fft))
+            print(f"[bench] class L_low {ll} K {k}: {len(members)} instances, {ms:.2f} ms/step, "
+                  f"{100 * ideal / ms:.0f}% of its peak-rate time {ideal:.2f} ms; FFT route {ms_fft:.2f} ms/step",
+                  file=sys.stderr, flush=True)
     # the headline batched figure is the main form at its best table
     best = min((k for k in forms if k.split("+")[0] == args.precision), key=lambda k: forms[k]["ms_per_step"])
     main_p = args.precision
@@ -577,9 +583,10 @@ def bench_serve(args):
             inst = pool[pick[k]]
             jobs.append(Job(k, inst.y, inst.K, inst.sigma, inst.x0, inst.log_rho0,
                             iterations=args.iterations, arrival=float(arr[k])))
-        # "<precision>+fft": jobs at an L_low the FFT route supports take it
+        # "<precision>+fft": jobs at an L_low the FFT route supports take it by
+        # their own steps; "<precision>+fftplan": inside the plan, as FFT classes
         base, _, extra = prec.partition("+")
-        ex = GPUExecutor(precision=base, fft=extra == "fft")
+        ex = GPUExecutor(precision=base, fft={"fft": True, "fftplan": "plan"}.get(extra, False))
         rep = serve(jobs, ex, hbm_budget=budget, max_slots=64)
         summ = rep.summary()
         summ.update(jobs_served=n, hbm_budget_gb=budget / 2 ** 30)
@@ -589,7 +596,7 @@ def bench_serve(args):
         torch.cuda.empty_cache()
 
     precs = [p for p in args.serve_precisions.split(",") if p] or \
-        [args.precision + "+fft", args.precision, "fp32_mfma", "fp32_plain"]
+        [args.precision + "+fftplan", args.precision + "+fft", args.precision, "fp32_mfma", "fp32_plain"]
     for prec in dict.fromkeys(precs):
         n = args.jobs_fp32 if prec.split("+")[0].startswith("fp32") else args.jobs
         for rate in rates:

@@ -258,6 +258,26 @@ int srmra_plan_form(int precision, int L_low);
 int srmra_plan_create(const srmra_problem* probs, int count, int precision,
                       srmra_plan** plan, size_t* workspace_bytes);
 
+/* Block layouts a tuning entry may ask for (`tile`; 0 keeps the default of
+ * the form and shape):
+ * - BF16 split, L_low 16: 1, 2 or 4 -- the component slots WC of a workgroup
+ *   (32 / WC observations x 4 WC components; the default takes WC from K^2);
+ * - BF16 split, L_low 24 and 32: SRMRA_TILE_FUSED_8OBS (single pass, 8
+ *   observations x 4 components per 256-thread workgroup, K^2 <= 4; the
+ *   default there), SRMRA_TILE_FUSED_4OBS (single pass, 4 observations x 16
+ *   components per 512-thread workgroup, K^2 <= 16; the default for
+ *   4 < K^2 <= 16), SRMRA_TILE_TWO_PASS (one 32x32 tile per score map, the
+ *   scores recomputed by a second pass);
+ * - BF16 split, L_low 48: SRMRA_TILE_16X16 (single pass on 3 x 3 tiles of
+ *   16x16 per score map, K^2 <= 4; the default there), SRMRA_TILE_TWO_PASS
+ *   (2 x 2 tiles of 32x32, two passes);
+ * - FP32 MFMA where its default is the single pass: SRMRA_TILE_TWO_PASS.
+ * Any other (form, L_low, K, tile) is SRMRA_EINVAL. */
+#define SRMRA_TILE_TWO_PASS 8
+#define SRMRA_TILE_FUSED_8OBS 16
+#define SRMRA_TILE_FUSED_4OBS 32
+#define SRMRA_TILE_16X16 64
+
 /* One entry of a tuning table for srmra_plan_create_tuned (the project's
  * autotuner, paper_2204_04754_amd/autotune.py, measures and writes these).
  * Problems with this (L_low, K) in a plan of precision `precision` run in
@@ -267,13 +287,10 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision,
  * (rounded up to the form's observation tile; 0 keeps the default of about
  * 2^28 multiply-adds per item -- for the FFT route about 2^28 flop of its
  * transforms -- smaller, down to 2^24, where that leaves the problem fewer
- * than 128 items per component group), and with the block
- * tile `tile` where the form has a choice: for the BF16 split at L_low 16,
- * the component slots WC of a workgroup (1, 2 or 4: a workgroup covers
- * 32 / WC observations and 4 WC components); 0 keeps the default (WC from
- * K^2).  Entries of another precision are ignored; the first matching entry
- * wins.  A problem's result depends on its own entry only (form, partition
- * and tile), never on the rest of the plan. */
+ * than 128 items per component group), and with the block layout `tile` (see
+ * SRMRA_TILE_* above; 0 keeps the default).  Entries of another precision are
+ * ignored; the first matching entry wins.  A problem's result depends on its
+ * own entry only (form, partition and tile), never on the rest of the plan. */
 typedef struct srmra_tuning {
     int precision;
     int L_low, K;
@@ -284,8 +301,8 @@ typedef struct srmra_tuning {
 
 /* srmra_plan_create with a tuning table (`table` may be NULL when n_table is
  * 0, which is srmra_plan_create).  SRMRA_EINVAL for a negative item_obs, a
- * tile other than 0 where the entry's form and L_low have no choice or a tile
- * outside that choice, or a form the plan's precision does not allow;
+ * tile the entry's form, L_low and K do not offer, or a form the plan's
+ * precision does not allow;
  * SRMRA_EUNSUPPORTED for a BF16 entry at an L_low without a BF16 kernel, or
  * an FFT entry at an L_low the FFT route does not cover.  The prepared buffer
  * of every problem must suit the form it runs in (a BF16 split preparation

@@ -13,10 +13,15 @@ the fastest:
   2^28 multiply-adds per item, down to 2^24 where that gives a problem fewer
   than 128 chunks): smaller items balance the persistent launch
   better, larger ones write fewer per-chunk partials;
-* the block tile where the form has a choice (the BF16 split at L_low 16: a
-  workgroup of 32 / WC observations x 4 WC components, WC in {1, 2, 4}),
-  timed at the default item size before the item sizes are swept at the best
-  tile.
+* the block layout where the form and shape offer a choice (SRMRA_TILE_* of
+  srmra.h): for the BF16 split the matrix-core tile shape at L_low 48 (3 x 3
+  tiles of 16x16 in one pass, or 2 x 2 tiles of 32x32 in two passes), the
+  observations and waves per workgroup at L_low 24 and 32 (a single pass over
+  8 observations x 4 components with 4 waves, or 4 observations x 16
+  components with 8 waves, or two passes) and the component slots at L_low 16
+  (a workgroup of 32 / WC observations x 4 WC components, WC in {1, 2, 4});
+  for FP32 MFMA the single pass or two passes; timed at the default item size
+  before the item sizes are swept at the best layout.
 
 Timing runs one EM step of the class alone per candidate, on scratch copies of
 the iterates (the problems' own iterates are left unchanged), with HIP events
@@ -45,10 +50,20 @@ def candidate_forms(precision: int, L_low: int, fft: bool = False) -> List[int]:
     return forms
 
 
-def candidate_tiles(form: int, L_low: int) -> List[int]:
-    """Block tiles the form offers at this L_low (0: the library's default only)."""
-    if form in (B.SRMRA_BF16_SPLIT3, B.SRMRA_BF16_SPLIT4) and L_low == 16:
-        return [1, 2, 4]
+def candidate_tiles(form: int, L_low: int, K: int) -> List[int]:
+    """Block layouts the form offers at this (L_low, K) ([0]: the default only)."""
+    KK = K * K
+    if form in (B.SRMRA_BF16_SPLIT3, B.SRMRA_BF16_SPLIT4):
+        if L_low == 16:
+            return [1, 2, 4]
+        if L_low in (24, 32):
+            tiles = [B.SRMRA_TILE_FUSED_8OBS] if KK <= 4 else []
+            tiles += [B.SRMRA_TILE_FUSED_4OBS] if KK <= 16 else []
+            return tiles + [B.SRMRA_TILE_TWO_PASS] if tiles else [0]
+        if L_low == 48 and KK <= 4:
+            return [B.SRMRA_TILE_16X16, B.SRMRA_TILE_TWO_PASS]
+    if form == B.SRMRA_FP32_MFMA and B.srmra_em_step_passes(1024, L_low, K, "fp32_mfma") == 1:
+        return [0, B.SRMRA_TILE_TWO_PASS]
     return [0]
 
 
@@ -116,7 +131,7 @@ def tune(problems: Sequence[dict], precision, scales=SCALES, reps: int = 3, warm
                     best = (ms, entry)
                 return ms
 
-            tiles = candidate_tiles(form, Ll)
+            tiles = candidate_tiles(form, Ll, K)
             tile = tiles[0]
             if len(tiles) > 1:
                 tile = min(tiles, key=lambda t: trial(base, t))

@@ -30,6 +30,11 @@ SRMRA_FP32_MFMA = FP32_MFMA = 1
 SRMRA_BF16_SPLIT3 = BF16_SPLIT3 = 2
 SRMRA_BF16_SPLIT4 = BF16_SPLIT4 = 3
 SRMRA_FP32_FFT = FP32_FFT = 4
+# block layouts of a tuning entry (srmra.h SRMRA_TILE_*)
+SRMRA_TILE_TWO_PASS = 8
+SRMRA_TILE_FUSED_8OBS = 16
+SRMRA_TILE_FUSED_4OBS = 32
+SRMRA_TILE_16X16 = 64
 PRECISIONS = {"fp32_plain": FP32_PLAIN, "fp32_mfma": FP32_MFMA, "bf16_split3": BF16_SPLIT3,
               "bf16_split4": BF16_SPLIT4, "fp32_fft": FP32_FFT}
 

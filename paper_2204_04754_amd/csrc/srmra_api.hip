@@ -36,7 +36,7 @@ bool valu_geom(int LL, int KK, int& cpb, int& nt, size_t& lds1, size_t& lds2, co
                const void*& f2);
 bool bf16_geom(int LL, int KK, int np, int tile, int& cpb, int& nt, size_t& lds1, size_t& lds2,
                const void*& f1, const void*& f2);
-bool bf16_fused_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds, const void*& f);
+bool bf16_fused_geom(int LL, int KK, int np, int tile, int& cpb, int& nt, size_t& lds, const void*& f);
 hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
                        hipStream_t s);
 hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* centre, double* ynorm,
@@ -127,6 +127,9 @@ struct Geom {
            o_llpart = 0, o_bsum = 0, o_csum = 0, o_xb = 0, o_xhat = 0, o_bh = 0, total = 0;
 };
 
+// the BF16 single pass with 16 component slots per workgroup (512 threads)
+inline bool bf16_wide_block(const Geom& g) { return g.fuse_bf16 && g.cpb == 16; }
+
 int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
               int64_t chunk_override = 0, int tile = 0) {
     if (N < 1 || N > (int64_t)INT32_MAX || K < 1 || LL < 1) return SRMRA_EINVAL;
@@ -137,13 +140,18 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
     const void* f1 = nullptr;
     const void* f2 = nullptr;
     bool ok;
+    // a block layout other than the default: only where the form offers it
+    if (tile != 0 && prec != SRMRA_FP32_MFMA && !is_bf16(prec)) return SRMRA_EINVAL;
     if (prec == SRMRA_FP32_MFMA) {
+        if (tile != 0 && tile != SRMRA_TILE_TWO_PASS) return SRMRA_EINVAL;
         ok = mfma_geom(LL, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
         // one pass when all components of an observation fit in one block
         int wc = 0, nt = 0;
         size_t lds = 0;
         const void* ff = nullptr;
-        if (ok && mfma_fused_geom(LL, g.KK, wc, nt, lds, ff)) {
+        const bool fused = ok && mfma_fused_geom(LL, g.KK, wc, nt, lds, ff);
+        if (tile == SRMRA_TILE_TWO_PASS && !fused) return SRMRA_EINVAL;   // no choice to make
+        if (fused && tile == 0) {
             g.fuse_wc = wc;
             g.cpb *= wc;
             g.ntile = nt;
@@ -153,10 +161,12 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
             f2 = ff;
         }
     } else if (is_bf16(prec)) {
+        if (!bf16_supported(LL)) return SRMRA_EUNSUPPORTED;
         ok = bf16_geom(LL, g.KK, split_products(prec), tile, g.cpb, g.ntile, g.lds1, g.lds2, f1, f2);
+        if (!ok) return SRMRA_EINVAL;   // a layout this shape does not offer
         size_t lds = 0;
         const void* ff = nullptr;
-        if (ok && tile == 0 && bf16_fused_geom(LL, g.KK, split_products(prec), g.cpb, g.ntile, lds, ff)) {
+        if (bf16_fused_geom(LL, g.KK, split_products(prec), tile, g.cpb, g.ntile, lds, ff)) {
             g.fuse_bf16 = 1;
             g.lds1 = 0;
             g.lds2 = lds;
@@ -189,7 +199,7 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
                    (prec == SRMRA_FP32_FFT ? sizeof(float2) * (size_t)N * LL * LL : 0);
     // one resident wave of blocks over the whole device for the heavier pass
     // (the BF16 single pass at K^2 > 4 runs 512-thread workgroups)
-    const int occ = occupancy(f2, g.lds2, (g.fuse_bf16 && g.KK > 4) ? 512 : 256);
+    const int occ = occupancy(f2, g.lds2, bf16_wide_block(g) ? 512 : 256);
     const int64_t target = (int64_t)device_cus() * occ;
     const int64_t tiles = (N + g.ntile - 1) / g.ntile;
     int64_t nch = target / g.n_cg;
@@ -720,9 +730,12 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         const srmra_tuning& t = table[k];
         if (t.item_obs < 0) return SRMRA_EINVAL;
         if (t.precision != precision) continue;
-        // a block tile only where the form has a choice (BF16 split at L_low 16)
-        if (t.tile != 0 && !(is_bf16(t.form) && t.L_low == 16 && (t.tile == 1 || t.tile == 2 || t.tile == 4)))
-            return SRMRA_EINVAL;
+        // a block layout only where the entry's form and shape offer it
+        if (t.tile != 0) {
+            Geom gt;
+            const int st = make_geom(1024, t.L_low, t.K, t.form, false, gt, 0, t.tile);
+            if (st != SRMRA_OK) return st == SRMRA_EUNSUPPORTED ? st : SRMRA_EINVAL;
+        }
         const bool ok = t.form == precision || (is_bf16(precision) && t.form == SRMRA_FP32_MFMA) ||
                         t.form == SRMRA_FP32_FFT;
         if (!ok) return SRMRA_EINVAL;
@@ -764,7 +777,7 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         make_geom(pr.N, pr.L_low, pr.K, fprec, false, g, item_obs > 0 ? item_obs : default_chunk(g0), tile);
         if (pr.prep_bytes < g.prep_bytes) { delete P; return SRMRA_EWORKSPACE; }
         if (f == FORM_MFMA && g.fuse_wc) f = FORM_FUSED;
-        if (g.fuse_bf16 && g.KK > 4) f = f == FORM_BF16X4 ? FORM_BF16X4W : FORM_BF16W;
+        if (bf16_wide_block(g)) f = f == FORM_BF16X4 ? FORM_BF16X4W : FORM_BF16W;
         else if (g.fuse_bf16) f = f == FORM_BF16X4 ? FORM_BF16X4F : FORM_BF16F;
         P->geoms.push_back(g);
         P->form.push_back(f);

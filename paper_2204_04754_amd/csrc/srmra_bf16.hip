@@ -1,6 +1,7 @@
 // BF16 split-precision kernels of the EM step (bodies in srmra_bf16_impl.h for
 // L_low 24 and 32, srmra_bf16w_impl.h for L_low 48 and 64, srmra_bf16s_impl.h
 // for L_low 16, srmra_bf16n_impl.h for the single pass at L_low 48, K^2 <= 4).
+#include "../../include/srmra.h"
 #include "srmra_bf16n_impl.h"
 
 namespace srmra {
@@ -129,8 +130,9 @@ __global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __rest
 
 // ---------------------------------------------------------------- host side
 static bool wide_ll(int LL) { return LL == 48 || LL == 64; }
-// L_low 48 with all components in one workgroup: the 16 x 16-tile single pass
-static bool nine_tile(int LL, int KK) { return LL == 48 && KK <= b16n::NW; }
+// L_low 48 with all components in one workgroup (cpb 4): the 16 x 16-tile
+// single pass (the two-pass form at L_low 48 takes one component per block)
+static bool nine_tile(int LL, int cpb) { return LL == 48 && cpb == b16n::NW; }
 bool bf16_supported(int LL) { return LL == 16 || LL == 24 || LL == 32 || wide_ll(LL); }
 
 // pass-1 partials per observation: one per component pair (one-tile form), per
@@ -152,7 +154,7 @@ hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, h
         hipLaunchKernelGGL(b16s::k_pack_xb, dim3(p.KK, 2), dim3(256), 0, s, p, x, (uint4*)xb);
         return hipGetLastError();
     }
-    if (nine_tile(LL, p.KK)) {
+    if (nine_tile(LL, p.cpb)) {
         hipLaunchKernelGGL(b16n::k_pack_xb, dim3(b16n::T * p.KK, (b16n::NKS + 3) / 4), dim3(256), 0, s, p, x,
                            (uint4*)xb);
         return hipGetLastError();
@@ -219,7 +221,7 @@ hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* cen
 
 template <int LL, int NP>
 static hipError_t launch_bf16_ll(int pass, const StepArgs& p, const b16::Prep& q, hipStream_t s) {
-    if (pass == 3 && p.KK > 4) {
+    if (pass == 3 && p.cpb == b16::F16_NCW * b16::F16_NW) {   // 16 component slots: 512 threads
         const size_t lds = b16::lds_fused16<LL>();
         if (hipFuncSetAttribute((const void*)b16::k_fused16_bf16<LL, NP>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -297,7 +299,7 @@ static hipError_t launch_bf16n(const StepArgs& p, const b16::Prep& q0, hipStream
 hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
                        hipStream_t s) {
     const b16::Prep q = prep_ptrs(prep_extra, LL, p.N);
-    if (pass == 3 && nine_tile(LL, p.KK)) return np == 4 ? launch_bf16n<4>(p, q, s) : launch_bf16n<3>(p, q, s);
+    if (pass == 3 && nine_tile(LL, p.cpb)) return np == 4 ? launch_bf16n<4>(p, q, s) : launch_bf16n<3>(p, q, s);
     if (LL == 16) return np == 4 ? launch_bf16s<4>(pass, p, q, s) : launch_bf16s<3>(pass, p, q, s);
     if (LL == 48) return np == 4 ? launch_bf16w_ll<48, 4>(pass, p, q, s) : launch_bf16w_ll<48, 3>(pass, p, q, s);
     if (LL == 64) return np == 4 ? launch_bf16w_ll<64, 4>(pass, p, q, s) : launch_bf16w_ll<64, 3>(pass, p, q, s);
@@ -330,15 +332,28 @@ static void bf16w_geom_ll(size_t& lds1, size_t& lds2, const void*& f1, const voi
 // keeps the scores of 8 observations x 4 components across the block's
 // (max, sum) exchange spilled registers and measured no faster than the two
 // passes, slower inside the batched form; L_low 16 keeps two passes.)
-bool bf16_fused_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds, const void*& f) {
-    if (nine_tile(LL, KK)) {
+bool bf16_fused_geom(int LL, int KK, int np, int tile, int& cpb, int& nt, size_t& lds, const void*& f) {
+    // the layout: the default for the shape, or the one the tile asks for
+    const bool small = (LL == 24 || LL == 32) && KK <= 4;
+    const bool wide = (LL == 24 || LL == 32) && KK <= b16::F16_NCW * b16::F16_NW;
+    bool use_nine = false, use_small = false, use_wide = false;
+    if (tile == 0) {
+        use_nine = LL == 48 && KK <= b16n::NW;
+        use_small = small;
+        use_wide = wide && !small;
+    } else {
+        use_nine = tile == SRMRA_TILE_16X16 && LL == 48 && KK <= b16n::NW;
+        use_small = tile == SRMRA_TILE_FUSED_8OBS && small;
+        use_wide = tile == SRMRA_TILE_FUSED_4OBS && wide;
+    }
+    if (use_nine) {
         cpb = b16n::NW;
         nt = b16n::NOB;
         lds = b16n::lds_fused();
         f = np == 4 ? (const void*)b16n::k_fused<4> : (const void*)b16n::k_fused<3>;
         return true;
     }
-    if ((LL == 24 || LL == 32) && KK > 4 && KK <= b16::F16_NCW * b16::F16_NW) {
+    if (use_wide) {
         cpb = b16::F16_NCW * b16::F16_NW;
         nt = b16::F16_NOB;
         if (LL == 24) {
@@ -350,7 +365,7 @@ bool bf16_fused_geom(int LL, int KK, int np, int& cpb, int& nt, size_t& lds, con
         }
         return true;
     }
-    if ((LL == 24 || LL == 32) && KK <= 4) {
+    if (use_small) {
         if (LL == 24) {
             lds = b16::lds_fused<24>();
             f = np == 4 ? (const void*)b16::k_fused_bf16<24, 4> : (const void*)b16::k_fused_bf16<24, 3>;
@@ -369,8 +384,17 @@ bool bf16_geom(int LL, int KK, int np, int tile, int& cpb, int& nt, size_t& lds1
     cpb = 4;
     nt = 8;
     // tile: the block layout where the form has a choice (L_low 16: component
-    // slots WC in {1, 2, 4}); 0 = the default
-    if (tile != 0 && !(LL == 16 && (tile == 1 || tile == 2 || tile == 4))) return false;
+    // slots WC in {1, 2, 4}; L_low 24 / 32 and 48: the single passes the shape
+    // allows, or two passes); 0 = the default
+    if (tile != 0) {
+        bool valid = false;
+        if (LL == 16) valid = tile == 1 || tile == 2 || tile == 4;
+        if (LL == 24 || LL == 32)
+            valid = tile == SRMRA_TILE_TWO_PASS || (tile == SRMRA_TILE_FUSED_8OBS && KK <= 4) ||
+                    (tile == SRMRA_TILE_FUSED_4OBS && KK <= b16::F16_NCW * b16::F16_NW);
+        if (LL == 48) valid = (tile == SRMRA_TILE_TWO_PASS || tile == SRMRA_TILE_16X16) && KK <= b16n::NW;
+        if (!valid) return false;
+    }
     if (LL == 16) {
         const int wc = tile ? tile : b16s::wc_of(KK);
         cpb = 4 * wc;

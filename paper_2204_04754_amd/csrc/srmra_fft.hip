@@ -80,14 +80,16 @@ __global__ __launch_bounds__(256) void k_prep_y(const float* __restrict__ y, int
     for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
 }
 
+// two waves per SIMD where the body fits 256 registers (L 12, 24; L 48 is held
+// to one block per CU by its LDS anyway)
 template <int L>
-__global__ __launch_bounds__(256) void k_pass1(StepArgs p, const float2* __restrict__ yhat,
+__global__ __launch_bounds__(256, L <= 24 ? 2 : 1) void k_pass1(StepArgs p, const float2* __restrict__ yhat,
                                                const float2* __restrict__ xhat) {
     extern __shared__ float2 sh[];
     pass1_body<L>(p, yhat, xhat, blockIdx.x, blockIdx.y, gridDim.y, sh);
 }
 template <int L>
-__global__ __launch_bounds__(256) void k_pass2(StepArgs p, const float2* __restrict__ yhat,
+__global__ __launch_bounds__(256, L <= 24 ? 2 : 1) void k_pass2(StepArgs p, const float2* __restrict__ yhat,
                                                const float2* __restrict__ xhat, int TPC,
                                                float2* __restrict__ bpart, float* __restrict__ cpart) {
     extern __shared__ float2 sh[];

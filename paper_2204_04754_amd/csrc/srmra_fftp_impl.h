@@ -28,12 +28,28 @@ __host__ __device__ inline int teams_of(int L) {
     if (L % 3 == 0) return 4 * (64 / L);
     return L == 64 ? 1 : 256 / (2 * L);
 }
-// teams per component in pass 2 for KK components (a power of 2 dividing the teams)
+// teams per component in pass 2 for KK components: a power of 2 (TPC) with
+// CG = teams / TPC components per block over ceil(KK / CG) component groups,
+// chosen for the largest share KK TPC / (groups x teams) of busy teams, then
+// the fewest groups, then the fewest teams per component: at KK = 9 and 4
+// teams, one component per block on all 4 teams (every team busy) instead of
+// 4 components per block (the last group's block three quarters idle)
 __host__ __device__ inline int tpc_of(int L, int KK) {
     const int teams = teams_of(L);
-    int tpc = 1;
-    while (tpc * 2 <= teams && KK * tpc * 2 <= teams) tpc *= 2;
-    return tpc;
+    int best = 1, best_busy = 0, best_all = 1, best_groups = 1 << 30;
+    for (int tpc = 1; tpc <= teams; tpc *= 2) {
+        const int cg = teams / tpc;
+        const int groups = (KK + cg - 1) / cg;
+        const int busy = KK * tpc, all = groups * teams;
+        const long long lhs = (long long)busy * best_all, rhs = (long long)best_busy * all;
+        if (lhs > rhs || (lhs == rhs && groups < best_groups)) {
+            best = tpc;
+            best_busy = busy;
+            best_all = all;
+            best_groups = groups;
+        }
+    }
+    return best;
 }
 
 template <int L> struct Geo {

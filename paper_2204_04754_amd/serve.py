@@ -142,7 +142,9 @@ class GPUExecutor:
     """Device side of the server: per-job buffers and the batched plan.  With
     fft=True a job whose L_low the FFT route supports is advanced by its own
     FFT-route step (srmra_em_step_prepared, SRMRA_FP32_FFT) on the same stream
-    after the plan, which holds the other jobs.
+    after the plan, which holds the other jobs; with fft="plan" such a job is
+    prepared for the FFT route and advanced inside the plan, whose tuning
+    entries send its (L_low, K) class to the FFT route.
 
     Interface used by `serve`: footprint(job), admit(job), tick(ids) (enqueue
     one step of ids; returns the previous tick's {id: loglik}), finish(job)
@@ -158,7 +160,7 @@ class GPUExecutor:
         self.B = B
         self.device = torch.device(device)
         self.precision = B._prec(precision)
-        self.fft = bool(fft)
+        self.fft = fft if fft == "plan" else bool(fft)
         self.buf: Dict[int, dict] = {}
         self.plan = None
         self.plan_ids: Optional[tuple] = None
@@ -176,7 +178,7 @@ class GPUExecutor:
         Ll, K = (job_or_buf.Ll, job_or_buf.K) if isinstance(job_or_buf, Job) else \
             (job_or_buf["L_low"], job_or_buf["K"])
         if self.fft and B.srmra_em_step_workspace_bytes(1, Ll, K, B.SRMRA_FP32_FFT) > 0:
-            return B.SRMRA_FP32_FFT, True
+            return B.SRMRA_FP32_FFT, self.fft != "plan"
         return B.srmra_plan_form(self.precision, Ll), False
 
     def footprint(self, job: Job) -> int:
@@ -202,7 +204,7 @@ class GPUExecutor:
             B.srmra_prepare_observations(y, job.N, job.Ll, job.K, form, prep, self.side)
             ws = B.empty_bytes(B.srmra_em_step_workspace_bytes(job.N, job.Ll, job.K, form), self.device) \
                 if own else None
-            b = dict(y=y, prep=prep, N=job.N, L_low=job.Ll, K=job.K, sigma=job.sigma, own=own, ws=ws,
+            b = dict(y=y, prep=prep, N=job.N, L_low=job.Ll, K=job.K, sigma=job.sigma, own=own, ws=ws, form=form,
                      xa=torch.as_tensor(np.asarray(job.x0, np.float32)).to(**f, non_blocking=True),
                      xb=torch.empty((Lh, Lh), **f),
                      la=torch.as_tensor(np.asarray(job.log_rho0, np.float32)).to(**f, non_blocking=True),
@@ -242,7 +244,13 @@ class GPUExecutor:
             if self.plan is not None:
                 # released one tick later (its helper streams may still run)
                 self.old_plans.append((self.plan, self.workspace))
-            self.plan = B.Plan([self._problem(self.buf[i]) for i in planned], self.precision)
+            # classes of jobs prepared for the FFT route run there inside the plan
+            fft_classes = sorted({(self.buf[i]["L_low"], self.buf[i]["K"]) for i in planned
+                                  if self.buf[i]["form"] == B.SRMRA_FP32_FFT})
+            table = [dict(precision=self.precision, L_low=ll, K=k, form=B.SRMRA_FP32_FFT, item_obs=0)
+                     for (ll, k) in fft_classes]
+            self.plan = B.Plan([self._problem(self.buf[i]) for i in planned], self.precision,
+                               tuning=table or None)
             self.workspace = B.empty_bytes(self.plan.workspace_bytes, self.device)
             self.plan.upload(self.workspace, self.stream)
             self.plan_ids = key

@@ -264,3 +264,61 @@ def test_autotuner_with_fft_candidates():
         f = name[forms[(inst.Ll, inst.K)]]
         x_tol = 2e-4 if f.startswith("bf16") and inst.N < 20 else 1e-4
         check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, be.results(j), ref, f, x_tol=x_tol)
+
+
+LAYOUTS = {
+    # single pass, 8 observations x 4 components (4 waves): L_low 32 and 24 at K^2 = 4
+    "fused_8obs": [(64, 2, 203, 0.9), (48, 2, 131, 1.1)],
+    # single pass, 4 observations x 16 components (8 waves): also at K^2 = 4 and 1
+    "fused_4obs": [(64, 2, 203, 0.9), (96, 3, 61, 1.2), (48, 2, 131, 1.1), (32, 1, 45, 1.3)],
+    # two passes: L_low 32 (K 2, 3), 24 (K 4) and 48 (2 x 2 tiles of 32x32)
+    "two_pass": [(64, 2, 203, 0.9), (96, 3, 61, 1.2), (96, 4, 37, 1.4), (96, 2, 77, 1.0)],
+    # 3 x 3 tiles of 16x16 at L_low 48 (K 2 and 1)
+    "16x16": [(96, 2, 77, 1.0), (48, 1, 33, 1.5)],
+}
+
+
+@pytest.mark.parametrize("name", sorted(LAYOUTS))
+def test_bf16_layouts_match_oracle(name):
+    """Every block layout a tuning entry can ask of the BF16 split gives the
+    step to the split's bound (ragged N, idle component slots where the
+    layout has more than K^2)."""
+    from paper_2204_04754_amd import binding as B
+    tile = {"fused_8obs": B.SRMRA_TILE_FUSED_8OBS, "fused_4obs": B.SRMRA_TILE_FUSED_4OBS,
+            "two_pass": B.SRMRA_TILE_TWO_PASS, "16x16": B.SRMRA_TILE_16X16}[name]
+    shapes = LAYOUTS[name]
+    ins = _instances(shapes, config=80)
+    tab = [dict(precision=B.SRMRA_BF16_SPLIT3, L_low=Lh // K, K=K, form=B.SRMRA_BF16_SPLIT3, item_obs=0,
+                tile=tile) for (Lh, K, _, _) in shapes]
+    be = BatchedEM(ins, precision="bf16_split3", tuning=tab)
+    be.step()
+    torch.cuda.synchronize()
+    for j, d in enumerate(ins):
+        inst = d["inst"]
+        ref = oracle_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K)
+        check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, be.results(j), ref, "bf16_split3")
+
+
+def test_fp32_two_pass_layout_and_invalid_layouts():
+    """FP32 MFMA two passes where its default is the single pass match the
+    oracle; a layout the shape does not offer is refused."""
+    from paper_2204_04754_amd import binding as B
+    shapes = [(64, 2, 203, 0.9), (32, 4, 91, 1.1)]
+    ins = _instances(shapes, config=81)
+    tab = [dict(precision=B.SRMRA_FP32_MFMA, L_low=Lh // K, K=K, form=B.SRMRA_FP32_MFMA, item_obs=0,
+                tile=B.SRMRA_TILE_TWO_PASS) for (Lh, K, _, _) in shapes]
+    be = BatchedEM(ins, precision="fp32_mfma", tuning=tab)
+    be.step()
+    torch.cuda.synchronize()
+    for j, d in enumerate(ins):
+        inst = d["inst"]
+        ref = oracle_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K)
+        check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, be.results(j), ref, "fp32_mfma")
+    bad = [(32, B.SRMRA_TILE_16X16, 2), (48, B.SRMRA_TILE_FUSED_4OBS, 2), (32, B.SRMRA_TILE_FUSED_8OBS, 3),
+           (48, B.SRMRA_TILE_16X16, 3), (16, B.SRMRA_TILE_TWO_PASS, 2)]
+    for ll, tile, K in bad:
+        one = _instances([(ll * K, K, 40, 1.0)], config=82)
+        with pytest.raises(B.SrmraError):
+            BatchedEM(one, precision="bf16_split3",
+                      tuning=[dict(precision=B.SRMRA_BF16_SPLIT3, L_low=ll, K=K, form=B.SRMRA_BF16_SPLIT3,
+                                   item_obs=0, tile=tile)])

@@ -60,12 +60,13 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16_split3", "bf16_split3+fft"])
+@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16_split3", "bf16_split3+fft", "bf16_split3+fftplan"])
 def test_served_alone_equals_in_mix(prec):
-    """With "+fft" the L_low 16 and 32 jobs take the FFT route by their own
-    steps and the L_low 24 jobs share the plan."""
+    """With "+fft" every job (L_low 16, 24, 32) takes the FFT route by its own
+    steps; with "+fftplan" the jobs take it inside the shared plan, as FFT
+    classes."""
     prec, _, extra = prec.partition("+")
-    fft = extra == "fft"
+    fft = {"fft": True, "fftplan": "plan"}.get(extra, False)
     clock = TickClock(0.01)
     ex = TimedExecutor(clock, precision=prec, fft=fft)
     rep = serve(_jobs(nan_job=4), ex, hbm_budget=1 << 34, max_slots=4, clock=clock, sleep=clock.sleep)
