@@ -620,8 +620,12 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
                                                   float* lds) {
     using G = Geo<LL>;
     constexpr int NOB = F16_NOB, NCW = F16_NCW, NW = F16_NW;
-    float* bacc = lds;                                                  // NW x NCW x Ll x BP
-    __bf16* ys = reinterpret_cast<__bf16*>(bacc + NW * NCW * LL * G::BP);  // NOB x 2 x Ll x PITCH
+    // b accumulator pitch: rows of 16-byte runs, so that a lane adds its four
+    // consecutive q2 of a row in one read-modify-write (the 32 lanes of one
+    // update hit 32 different rows; a pitch of Ll + 4 floats spreads them over the banks)
+    constexpr int BPF = LL + 4;
+    float* bacc = lds;                                                  // NW x NCW x Ll x BPF
+    __bf16* ys = reinterpret_cast<__bf16*>(bacc + NW * NCW * LL * BPF);  // NOB x 2 x Ll x PITCH
     __bf16* yo4 = ys + NOB * 2 * LL * PITCH;                            // 2 x Ll x Ll x NOB
     float2* red = reinterpret_cast<float2*>(yo4 + 2 * LL * LL * NOB);   // NW x NOB
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -634,8 +638,8 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
         cok[c] = comp[c] < p.KK;
         cgl[c] = cok[c] ? comp[c] : p.KK - 1;
     }
-    float* bw = bacc + wave * NCW * LL * G::BP;
-    for (int e = lane; e < NCW * LL * G::BP; e += 64) bw[e] = 0.f;
+    float* bw = bacc + wave * NCW * LL * BPF;
+    for (int e = lane; e < NCW * LL * BPF; e += 64) bw[e] = 0.f;
     const int oslot[NOB] = {0, 1, 2, 3};
     const int q2e = j < LL ? j : j - LL;
     const int64_t chunk = chunk_i;
@@ -799,17 +803,25 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
                         z[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[s8], wl[c][s8], z[c], 0, 0, 0);
                 }
             }
-            // lane holds Z[q2 = acc_row(v)][t1 = j]; b_c[(a1 - t1) % Ll][q2] += Z
+            // lane holds Z[q2 = acc_row(v)][t1 = j] (rows 8 m + 4 g + 0..3 for
+            // v = 4 m .. 4 m + 3); b_c[(a1 - t1) % Ll][q2] += Z, four q2 at a time
             if (j < LL) {
                 int q1 = a1 - j;
                 q1 = q1 < 0 ? q1 + LL : q1;
 #pragma unroll
                 for (int c = 0; c < NCW; ++c) {
-                    float* brow = bw + (c * LL + q1) * G::BP;
+                    float* brow = bw + (c * LL + q1) * BPF + 4 * g;
 #pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        const int q2 = acc_row(v, lane);
-                        if (q2 < LL) brow[q2] += z[c][v];
+                    for (int m = 0; m < 4; ++m) {
+                        if (8 * m + 4 * g < LL) {
+                            float4* d = reinterpret_cast<float4*>(brow + 8 * m);
+                            float4 t = *d;
+                            t.x += z[c][4 * m];
+                            t.y += z[c][4 * m + 1];
+                            t.z += z[c][4 * m + 2];
+                            t.w += z[c][4 * m + 3];
+                            *d = t;
+                        }
                     }
                 }
             }
@@ -820,9 +832,9 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
 #pragma unroll
     for (int c = 0; c < NCW; ++c) {
         if (!cok[c]) continue;
-        const float* bc = bw + c * LL * G::BP;
+        const float* bc = bw + c * LL * BPF;
         float* bo = p.bpart + (chunk * p.KK + comp[c]) * (LL * LL);
-        for (int e = lane; e < LL * LL; e += 64) bo[e] = bc[(e / LL) * G::BP + (e % LL)];
+        for (int e = lane; e < LL * LL; e += 64) bo[e] = bc[(e / LL) * BPF + (e % LL)];
     }
 }
 
@@ -915,7 +927,7 @@ template <int LL> constexpr size_t lds_fused() { return lds_pass2<LL>() + sizeof
 // the single pass at 4 < K^2 <= 16
 template <int LL> constexpr size_t lds_fused16() {
     using G = Geo<LL>;
-    return sizeof(float) * (F16_NW * F16_NCW * LL * G::BP) +
+    return sizeof(float) * (F16_NW * F16_NCW * LL * (LL + 4)) +   // b accumulators (pitch Ll + 4)
            sizeof(__bf16) * (F16_NOB * 2 * LL * PITCH + 2 * LL * LL * F16_NOB) +
            sizeof(float2) * F16_NW * F16_NOB;
 }
