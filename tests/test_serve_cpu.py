@@ -137,25 +137,28 @@ def test_serve_loop_continuous_batching_and_failure_isolation():
 
 def test_executor_routes_fft_jobs_and_sizes_their_footprint():
     """GPUExecutor(fft=True) sends a job at an L_low the FFT route supports
-    (8, 16, 32, 64) to its own FFT-route steps and the rest to the plan in
-    the executor's precision; the footprint counts the route's prepared data
-    and workspace (host-side library queries only: nothing is allocated)."""
+    (every L_low of the library: 8, 12, 16, 24, 32, 48, 64) to its own
+    FFT-route steps, fft="plan" to the FFT route inside the plan, and without
+    fft every job goes to the plan in the executor's precision; the footprint
+    counts the route's prepared data and workspace (host-side library queries
+    only: nothing is allocated)."""
     import pytest
     pytest.importorskip("torch")
     from paper_2204_04754_amd import binding as B
     from paper_2204_04754_amd.serve import GPUExecutor
     ex = GPUExecutor(precision="bf16_split3", device="cpu", fft=True)
+    inplan = GPUExecutor(precision="bf16_split3", device="cpu", fft="plan")
     plain = GPUExecutor(precision="bf16_split3", device="cpu")
     for K, Ll in ((4, 8), (4, 16), (2, 32), (4, 64), (4, 12), (4, 24), (2, 48)):
         job = Job(0, np.zeros((1000, Ll, Ll), np.float32), K, 1.0, None, None, iterations=1)
         form, own = ex._form(job)
-        assert own == (Ll in (8, 16, 32, 64))
-        if own:
-            assert form == B.SRMRA_FP32_FFT
-            expect = (4 * 1000 * Ll * Ll + B.srmra_prepared_bytes(1000, Ll, K, form)
-                      + B.srmra_em_step_workspace_bytes(1000, Ll, K, form))
-            assert ex.footprint(job) >= expect
-        else:
-            assert form == B.srmra_plan_form(B.SRMRA_BF16_SPLIT3, Ll)
-            assert ex.footprint(job) == plain.footprint(job)
+        assert own and form == B.SRMRA_FP32_FFT
+        expect = (4 * 1000 * Ll * Ll + B.srmra_prepared_bytes(1000, Ll, K, form)
+                  + B.srmra_em_step_workspace_bytes(1000, Ll, K, form))
+        assert ex.footprint(job) >= expect
+        assert inplan._form(job) == (B.SRMRA_FP32_FFT, False)
+        assert inplan.footprint(job) == ex.footprint(job)
         assert plain._form(job) == (B.srmra_plan_form(B.SRMRA_BF16_SPLIT3, Ll), False)
+    # an L_low the FFT route does not cover goes to the plan in the executor's precision
+    job = Job(0, np.zeros((10, 20, 20), np.float32), 2, 1.0, None, None, iterations=1)
+    assert ex._form(job) == plain._form(job)
