@@ -296,12 +296,15 @@ __device__ __forceinline__ void pass2_pairs_body(const StepArgs& p, const float2
 // ---- L_low 64: one team per block, four lanes per row (lane 4r + q holds a
 // quarter of row r, see fft_quad_dit / fft_quad_dif), so a lane keeps 16
 // complex values of an image; the LDS transposes are ordered by the block
-// barrier, and every thread of the block belongs to the one team.
+// barrier, and every thread of the block belongs to the one team.  Two
+// transpose buffers alternate, so that a transpose needs one barrier (between
+// its writes and its reads): the next write to a buffer comes after the other
+// buffer's barrier, which every thread reaches only once done reading.
 namespace quad {
 constexpr int L = 64, NV = L / 4;
 constexpr int BUF = L * (L + 1);
-// team buffer, the twiddles (L / 2) and one (max, sum) slot per wave
-constexpr size_t lds() { return sizeof(float2) * ((size_t)BUF + L / 2 + 4); }
+// two transpose buffers, the twiddles (L / 2) and one (max, sum) slot per wave
+constexpr size_t lds() { return sizeof(float2) * (2 * (size_t)BUF + L / 2 + 4); }
 
 // scores of (observation o, component c) for lane (r, q): s[k] = a at
 // (t1 = 16 quad_block(q) + k, t2 = r)
@@ -320,7 +323,6 @@ __device__ __forceinline__ void score(const StepArgs& p, const float2* __restric
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < NV; ++m) v[m] = buf[(4 * m + q) * (L + 1) + r];   // column r, rows 4m + q
-    __syncthreads();
     fft_quad_dit<L, true>(v, q, tw);                       // v[k] = S[16 bq + k][r]
     const float sc = p.inv_s2 / (float)(L * L);
     const float* bet = p.betaT + (int64_t)c * (L * L) + r * L + 16 * bq;   // betaT[c][t2 = r][t1]
@@ -335,18 +337,20 @@ __device__ __forceinline__ void pass1_quad_body(const StepArgs& p, const float2*
                                                 const float2* __restrict__ xhat, int64_t chunk, int ysplit,
                                                 int nsplit, float2* sh) {
     using namespace quad;
-    float2* tw = sh + BUF;
+    float2* tw = sh + 2 * BUF;
     float2* red = tw + L / 2;
     make_twiddles<L>(tw);
     __syncthreads();
     const int lt = threadIdx.x, r = lt >> 2, q = lt & 3, bq = quad_block(q);
     const int64_t c0 = chunk * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    int flip = 0;   // the transpose buffer of the next score
     for (int64_t o = c0 + ysplit; o < c1; o += nsplit) {
         float m = -INFINITY, sm = 0.f;
         for (int c = 0; c < p.KK; ++c) {
             float s[NV];
-            score(p, yhat, xhat, o, c, sh, r, q, bq, tw, s);
+            score(p, yhat, xhat, o, c, sh + flip * BUF, r, q, bq, tw, s);
+            flip ^= 1;
             float mc = -INFINITY;
 #pragma unroll
             for (int k = 0; k < NV; ++k) mc = fmaxf(mc, s[k]);
@@ -377,7 +381,8 @@ __device__ __forceinline__ void pass2_quad_body(const StepArgs& p, const float2*
                                                 float* __restrict__ cpart, int64_t chunk, int ysplit,
                                                 float2* sh) {
     using namespace quad;
-    float2* tw = sh + BUF;
+    float2* tw = sh + 2 * BUF;
+    float2* shw = sh + BUF;   // the weights' transpose buffer (the scores' is sh)
     make_twiddles<L>(tw);
     __syncthreads();
     const int lt = threadIdx.x, r = lt >> 2, q = lt & 3, bq = quad_block(q);
@@ -402,11 +407,10 @@ __device__ __forceinline__ void pass2_quad_body(const StepArgs& p, const float2*
         // column t2 = r (its block 16 bq..), transformed along t1, then the rows
         fft_quad_dif<L, false>(v, q, tw);                  // v[k] = k1 = 4k + q, column r
 #pragma unroll
-        for (int k = 0; k < NV; ++k) sh[(4 * k + q) * (L + 1) + r] = v[k];
+        for (int k = 0; k < NV; ++k) shw[(4 * k + q) * (L + 1) + r] = v[k];
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < NV; ++m) v[m] = sh[r * (L + 1) + 4 * m + q];   // row k1 = r, n2 = 4m + q
-        __syncthreads();
+        for (int m = 0; m < NV; ++m) v[m] = shw[r * (L + 1) + 4 * m + q];   // row k1 = r, n2 = 4m + q
         fft_quad_dit<L, false>(v, q, tw);                  // v[k] = W[r][16 bq + k]
         // Y_o[r][16 bq + k], k and k + 1 in one 16-byte word of the paired layout
         const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)o * (L / 2) + 8 * bq) * L + r;
