@@ -109,3 +109,55 @@ def test_projected_em_structure():
         x = P.gaussian_blur_circular(x, float(s))
     np.testing.assert_array_equal(r_g["x"], x)
     assert len(r_g["loglik"]) == F * T
+
+
+def test_projected_em_two_outer_iterations_by_hand():
+    """Alg. 2 with F = 1 and T = 2 on the Ll = 1 model (K = Lh = 4: every
+    observation a scalar from a mixture of 16 Gaussians with means
+    x[(-s1) mod 4, (-s2) mod 4] and weights rho1[s1] rho2[s2]), computed without
+    the oracle: each EM step as a textbook known-variance mixture step
+    (responsibilities from scipy.stats.norm), each projection as the 2-D
+    circular blur written out with its taps exp(-k^2 / 2 s^2) normalised over
+    |k| <= floor(4 s + 1/2) (reading P1), at s = 1 and then s = fl32(2^-0.1)
+    (eq. decaying_function, readings P2-P3); rho carries over (P4)."""
+    from scipy.stats import norm
+    Lh, N, sigma = 4, 150, 0.5
+    rng = np.random.default_rng(31)
+    x0 = rng.standard_normal((Lh, Lh))
+    r1, r2 = rng.dirichlet(np.ones(Lh)), rng.dirichlet(np.ones(Lh))
+    y = rng.standard_normal(N) * 1.1
+    comps = [(a, b) for a in range(Lh) for b in range(Lh)]
+
+    def em_by_hand(x, p1, p2):
+        mu = np.array([x[(-a) % Lh, (-b) % Lh] for a, b in comps])
+        pi = np.array([p1[a] * p2[b] for a, b in comps])
+        dens = pi[None, :] * norm.pdf(y[:, None], loc=mu[None, :], scale=sigma)
+        resp = dens / dens.sum(1, keepdims=True)
+        nk = resp.sum(0)
+        x_new = np.empty((Lh, Lh))
+        for k, (a, b) in enumerate(comps):
+            x_new[(-a) % Lh, (-b) % Lh] = (resp[:, k] * y).sum() / nk[k]
+        pk = (nk / N).reshape(Lh, Lh)
+        return x_new, pk.sum(1), pk.sum(0)
+
+    def blur_by_hand(x, s):
+        R = min(int(np.floor(4.0 * s + 0.5)), Lh)
+        taps = {k: np.exp(-k * k / (2.0 * s * s)) for k in range(-R, R + 1)}
+        z = sum(taps.values())
+        out = np.zeros_like(x)
+        for m1 in range(Lh):
+            for m2 in range(Lh):
+                acc = 0.0
+                for k1 in range(-R, R + 1):
+                    for k2 in range(-R, R + 1):
+                        acc += taps[k1] * taps[k2] / (z * z) * x[(m1 - k1) % Lh, (m2 - k2) % Lh]
+                out[m1, m2] = acc
+        return out
+
+    x, p1, p2 = x0, r1, r2
+    for s in (1.0, float(np.float32(np.float32(1.0) * np.float32(2.0 ** -0.1)))):
+        x, p1, p2 = em_by_hand(x, p1, p2)
+        x = blur_by_hand(x, s)
+    r = P.projected_em(y.reshape(N, 1, 1), x0, np.log(np.stack([r1, r2])), sigma, Lh, 1, 2)
+    np.testing.assert_allclose(r["x"], x, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(np.exp(r["log_rho"]), np.stack([p1, p2]), rtol=1e-9)
