@@ -79,8 +79,9 @@ typedef enum {
     SRMRA_FP32_MFMA = 1,      /* FP32 matrix cores (v_mfma_f32_32x32x2 / 16x16x4)   */
     SRMRA_BF16_SPLIT3 = 2,    /* BF16 matrix cores, operands split v = hi + lo,
                                  products hi*hi + hi*lo + lo*hi, FP32 accumulate;
-                                 L_low in {16, 24, 32, 48, 64} (others return
-                                 SRMRA_EUNSUPPORTED in the single-problem calls)    */
+                                 every supported L_low (at 8 and 12 the score
+                                 maps of 8 observations and 4 or 8 components
+                                 are packed into 32x32 tiles)                       */
     SRMRA_BF16_SPLIT4 = 3,    /* as SRMRA_BF16_SPLIT3 plus the lo*lo product        */
     SRMRA_FP32_FFT = 4        /* FFT route: both contractions as products of 2-D
                                  DFTs of the L_low grid (FP32 transforms, FP64 sums
@@ -240,8 +241,8 @@ typedef struct srmra_problem {
 typedef struct srmra_plan srmra_plan;
 
 /* The precision an instance of this L_low runs in within a plan of the given
- * precision: SRMRA_BF16_SPLIT3 / SRMRA_BF16_SPLIT4 plans run L_low outside
- * {16, 24, 32, 48, 64} in SRMRA_FP32_MFMA.  Returns -1 for unsupported arguments. */
+ * precision (without a tuning entry: the plan's own; SRMRA_FP32_FFT is not a
+ * plan precision).  Returns -1 for unsupported arguments. */
 int srmra_plan_form(int precision, int L_low);
 
 /* Build a plan (host only, no device work).  `probs` is copied.  On success
@@ -260,6 +261,9 @@ int srmra_plan_create(const srmra_problem* probs, int count, int precision,
 
 /* Block layouts a tuning entry may ask for (`tile`; 0 keeps the default of
  * the form and shape):
+ * - BF16 split, L_low 8 and 12: SRMRA_TILE_TWO_PASS (scores recomputed by a
+ *   second pass; the default is the single pass while the K^2 components fit
+ *   in four blocks of 4 (L_low 8) or 8 (L_low 12));
  * - BF16 split, L_low 16: 1, 2 or 4 -- the component slots WC of a workgroup
  *   (32 / WC observations x 4 WC components; the default takes WC from K^2);
  * - BF16 split, L_low 24 and 32: SRMRA_TILE_FUSED_8OBS (single pass, 8
@@ -303,8 +307,8 @@ typedef struct srmra_tuning {
  * 0, which is srmra_plan_create).  SRMRA_EINVAL for a negative item_obs, a
  * tile the entry's form, L_low and K do not offer, or a form the plan's
  * precision does not allow;
- * SRMRA_EUNSUPPORTED for a BF16 entry at an L_low without a BF16 kernel, or
- * an FFT entry at an L_low the FFT route does not cover.  The prepared buffer
+ * SRMRA_EUNSUPPORTED for an FFT entry at an L_low the FFT route does not
+ * cover.  The prepared buffer
  * of every problem must suit the form it runs in (a BF16 split preparation
  * also serves SRMRA_FP32_MFMA; the FFT route needs an SRMRA_FP32_FFT
  * preparation, which holds the observations' DFTs); SRMRA_EWORKSPACE if it is

@@ -54,6 +54,9 @@ def candidate_tiles(form: int, L_low: int, K: int) -> List[int]:
     """Block layouts the form offers at this (L_low, K) ([0]: the default only)."""
     KK = K * K
     if form in (B.SRMRA_BF16_SPLIT3, B.SRMRA_BF16_SPLIT4):
+        if L_low in (8, 12):
+            ncw = 4 if L_low == 8 else 8   # components per block of the packed tiles
+            return [0, B.SRMRA_TILE_TWO_PASS] if (KK + ncw - 1) // ncw <= 4 else [0]
         if L_low == 16:
             return [1, 2, 4]
         if L_low in (24, 32):

@@ -128,7 +128,7 @@ struct Geom {
 };
 
 // the BF16 single pass with 16 component slots per workgroup (512 threads)
-inline bool bf16_wide_block(const Geom& g) { return g.fuse_bf16 && g.cpb == 16; }
+inline bool bf16_wide_block(const Geom& g) { return g.fuse_bf16 && g.cpb == 16 && (g.LL == 24 || g.LL == 32); }
 
 int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
               int64_t chunk_override = 0, int tile = 0) {

@@ -9,6 +9,7 @@
 #include "srmra_aux_impl.h"
 #include "srmra_batch.h"
 #include "srmra_bf16n_impl.h"
+#include "srmra_bf16p_impl.h"
 #include "srmra_fftp_impl.h"
 #include "srmra_mfma_impl.h"
 #include "srmra_valu_impl.h"
@@ -61,7 +62,20 @@ __global__ __launch_bounds__(256) void k_batch_pack_xb(const InstDesc* __restric
         d.form != FORM_BF16W && d.form != FORM_BF16X4W)
         return;
     uint4* xb = const_cast<uint4*>(d.p.xb);
-    if (d.LL == 16) {
+    if (d.LL == 8 || d.LL == 12) {
+        // item component c packs component block c (its NCT column tiles), if there is one
+        const int ncw = b16p::ncw_of(d.LL);
+        if (it.y * ncw >= d.p.KK) return;
+        if (d.LL == 8) {
+            using G = b16p::Geo<8>;
+            for (int e = threadIdx.x >> 6; e < G::NCT * G::NKS; e += 4)
+                b16p::pack_xb_body<8>(d.p, d.x, it.y * G::NCT + e / G::NKS, e % G::NKS, xb);
+        } else {
+            using G = b16p::Geo<12>;
+            for (int e = threadIdx.x >> 6; e < G::NCT * G::NKS; e += 4)
+                b16p::pack_xb_body<12>(d.p, d.x, it.y * G::NCT + e / G::NKS, e % G::NKS, xb);
+        }
+    } else if (d.LL == 16) {
         for (int ks = threadIdx.x >> 6; ks < b16s::NK; ks += 4) b16s::pack_xb_body(d.p, d.x, it.y, ks, xb);
     } else if (d.LL == 48 && (d.form == FORM_BF16F || d.form == FORM_BF16X4F)) {
         for (int e = threadIdx.x >> 6; e < b16n::T * b16n::NKS; e += 4)
@@ -163,7 +177,9 @@ void k_class_pass(const InstDesc* __restrict__ D,
             b16::Prep q;
             q.yT = d.yT;
             q.yo = d.yo;
-            if constexpr (LL == 16) {
+            if constexpr (LL == 8 || LL == 12) {
+                b16p::body<LL, NP, PASS>(d.p, q, w.y, w.z, lds);
+            } else if constexpr (LL == 16) {
                 b16s::Prep qs;
                 qs.yT = d.yT;
                 qs.yo = d.yo;
@@ -186,6 +202,11 @@ void k_class_pass(const InstDesc* __restrict__ D,
                 qn.yT = d.yT;
                 qn.yo = d.yo;
                 b16n::fused_body<NP>(d.p, qn, w.y, lds);
+            } else if constexpr (LL == 8 || LL == 12) {
+                b16::Prep q;
+                q.yT = d.yT;
+                q.yo = d.yo;
+                b16p::body<LL, NP, 3>(d.p, q, w.y, 0, lds);
             } else {
                 b16::Prep q;
                 q.yT = d.yT;
@@ -257,15 +278,19 @@ SRMRA_CLASS(FORM_VALU, 64)
 SRMRA_CLASS(FORM_MFMA, 8) SRMRA_CLASS(FORM_MFMA, 12) SRMRA_CLASS(FORM_MFMA, 16)
 SRMRA_CLASS(FORM_MFMA, 24) SRMRA_CLASS(FORM_MFMA, 32) SRMRA_CLASS(FORM_MFMA, 48)
 SRMRA_CLASS(FORM_MFMA, 64)
+SRMRA_CLASS(FORM_BF16, 8) SRMRA_CLASS(FORM_BF16, 12)
 SRMRA_CLASS(FORM_BF16, 16) SRMRA_CLASS(FORM_BF16, 24) SRMRA_CLASS(FORM_BF16, 32)
 SRMRA_CLASS(FORM_BF16, 48) SRMRA_CLASS(FORM_BF16, 64)
+SRMRA_CLASS(FORM_BF16X4, 8) SRMRA_CLASS(FORM_BF16X4, 12)
 SRMRA_CLASS(FORM_BF16X4, 16) SRMRA_CLASS(FORM_BF16X4, 24) SRMRA_CLASS(FORM_BF16X4, 32)
 SRMRA_CLASS(FORM_BF16X4, 48) SRMRA_CLASS(FORM_BF16X4, 64)
 SRMRA_CLASS(FORM_FFT, 8) SRMRA_CLASS(FORM_FFT, 12) SRMRA_CLASS(FORM_FFT, 16) SRMRA_CLASS(FORM_FFT, 24)
 SRMRA_CLASS(FORM_FFT, 32) SRMRA_CLASS(FORM_FFT, 48) SRMRA_CLASS(FORM_FFT, 64)
 #undef SRMRA_CLASS
 #define SRMRA_BF16F(F, L) template __global__ void k_class_pass<2, F, L>(const InstDesc*, const int4*, int, int*);
+SRMRA_BF16F(FORM_BF16F, 8) SRMRA_BF16F(FORM_BF16F, 12)
 SRMRA_BF16F(FORM_BF16F, 24) SRMRA_BF16F(FORM_BF16F, 32) SRMRA_BF16F(FORM_BF16F, 48)
+SRMRA_BF16F(FORM_BF16X4F, 8) SRMRA_BF16F(FORM_BF16X4F, 12)
 SRMRA_BF16F(FORM_BF16X4F, 24) SRMRA_BF16F(FORM_BF16X4F, 32) SRMRA_BF16F(FORM_BF16X4F, 48)
 #undef SRMRA_BF16F
 #define SRMRA_FUSED(L) template __global__ void k_class_pass<2, FORM_FUSED, L>(const InstDesc*, const int4*, int, int*);
@@ -283,8 +308,10 @@ const void* class_pass_fn(int pass, int form, int LL) {
     SRMRA_PICK(FORM_MFMA, 8) SRMRA_PICK(FORM_MFMA, 12) SRMRA_PICK(FORM_MFMA, 16)
     SRMRA_PICK(FORM_MFMA, 24) SRMRA_PICK(FORM_MFMA, 32) SRMRA_PICK(FORM_MFMA, 48)
     SRMRA_PICK(FORM_MFMA, 64)
+    SRMRA_PICK(FORM_BF16, 8) SRMRA_PICK(FORM_BF16, 12)
     SRMRA_PICK(FORM_BF16, 16) SRMRA_PICK(FORM_BF16, 24) SRMRA_PICK(FORM_BF16, 32)
     SRMRA_PICK(FORM_BF16, 48) SRMRA_PICK(FORM_BF16, 64)
+    SRMRA_PICK(FORM_BF16X4, 8) SRMRA_PICK(FORM_BF16X4, 12)
     SRMRA_PICK(FORM_BF16X4, 16) SRMRA_PICK(FORM_BF16X4, 24) SRMRA_PICK(FORM_BF16X4, 32)
     SRMRA_PICK(FORM_BF16X4, 48) SRMRA_PICK(FORM_BF16X4, 64)
     SRMRA_PICK(FORM_FFT, 8) SRMRA_PICK(FORM_FFT, 12) SRMRA_PICK(FORM_FFT, 16) SRMRA_PICK(FORM_FFT, 24)
@@ -295,7 +322,9 @@ const void* class_pass_fn(int pass, int form, int LL) {
     SRMRA_PICK(8) SRMRA_PICK(12) SRMRA_PICK(16) SRMRA_PICK(24) SRMRA_PICK(32) SRMRA_PICK(48) SRMRA_PICK(64)
 #undef SRMRA_PICK
 #define SRMRA_PICK(F, L) if (form == F && LL == L) return pass == 2 ? (const void*)k_class_pass<2, F, L> : nullptr;
+    SRMRA_PICK(FORM_BF16F, 8) SRMRA_PICK(FORM_BF16F, 12)
     SRMRA_PICK(FORM_BF16F, 24) SRMRA_PICK(FORM_BF16F, 32) SRMRA_PICK(FORM_BF16F, 48)
+    SRMRA_PICK(FORM_BF16X4F, 8) SRMRA_PICK(FORM_BF16X4F, 12)
     SRMRA_PICK(FORM_BF16X4F, 24) SRMRA_PICK(FORM_BF16X4F, 32) SRMRA_PICK(FORM_BF16X4F, 48)
 #undef SRMRA_PICK
     if (pass == 2 && form == FORM_BF16W && LL == 24) return (const void*)k_class_fused16<3, 24>;

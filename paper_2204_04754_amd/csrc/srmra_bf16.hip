@@ -1,8 +1,10 @@
 // BF16 split-precision kernels of the EM step (bodies in srmra_bf16_impl.h for
 // L_low 24 and 32, srmra_bf16w_impl.h for L_low 48 and 64, srmra_bf16s_impl.h
-// for L_low 16, srmra_bf16n_impl.h for the single pass at L_low 48, K^2 <= 4).
+// for L_low 16, srmra_bf16n_impl.h for the single pass at L_low 48, K^2 <= 4,
+// srmra_bf16p_impl.h for L_low 8 and 12).
 #include "../../include/srmra.h"
 #include "srmra_bf16n_impl.h"
+#include "srmra_bf16p_impl.h"
 
 namespace srmra {
 namespace b16 {
@@ -127,29 +129,84 @@ __global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __rest
 
 }  // namespace b16n
 
+namespace b16p {
+
+template <int LL, int NP>
+__global__ __launch_bounds__(256) void k_score_lse(StepArgs p, b16::Prep q) {
+    extern __shared__ float lds[];
+    body<LL, NP, 1>(p, q, blockIdx.x, blockIdx.y, lds);
+}
+
+template <int LL, int NP>
+__global__ __launch_bounds__(256) void k_backproject(StepArgs p, b16::Prep q) {
+    extern __shared__ float lds[];
+    body<LL, NP, 2>(p, q, blockIdx.x, blockIdx.y, lds);
+}
+
+// single pass: grid (chunks)
+template <int LL, int NP>
+__global__ __launch_bounds__(256) void k_fused(StepArgs p, b16::Prep q) {
+    extern __shared__ float lds[];
+    body<LL, NP, 3>(p, q, blockIdx.x, 0, lds);
+}
+
+// grid (column tiles, k-steps / 4): one (column tile, k-step) per wave
+template <int LL>
+__global__ __launch_bounds__(256) void k_pack_xb(StepArgs p, const float* __restrict__ x, uint4* __restrict__ xb) {
+    const int s = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (s < Geo<LL>::NKS) pack_xb_body<LL>(p, x, blockIdx.x, s, xb);
+}
+
+// component blocks of NCW components covering K^2, and the workgroup's block
+// slots WCB of the single pass (0: two passes)
+inline int n_blocks(int LL, int KK) { return (KK + ncw_of(LL) - 1) / ncw_of(LL); }
+inline int fused_wcb(int LL, int KK) {
+    const int nb = n_blocks(LL, KK);
+    return nb <= 1 ? 1 : (nb <= 2 ? 2 : (nb <= 4 ? 4 : 0));
+}
+
+}  // namespace b16p
+
 
 // ---------------------------------------------------------------- host side
 static bool wide_ll(int LL) { return LL == 48 || LL == 64; }
 // L_low 48 with all components in one workgroup (cpb 4): the 16 x 16-tile
 // single pass (the two-pass form at L_low 48 takes one component per block)
 static bool nine_tile(int LL, int cpb) { return LL == 48 && cpb == b16n::NW; }
-bool bf16_supported(int LL) { return LL == 16 || LL == 24 || LL == 32 || wide_ll(LL); }
+static bool packed_ll(int LL) { return LL == 8 || LL == 12; }
+bool bf16_supported(int LL) { return packed_ll(LL) || LL == 16 || LL == 24 || LL == 32 || wide_ll(LL); }
 
 // pass-1 partials per observation: one per component pair (one-tile form), per
 // (component, tile) (L_low 48 and 64) or per group of 4 components (L_low 16)
 int bf16_parts(int LL, int KK) {
     if (LL == 16) return (KK + 3) / 4;
+    if (packed_ll(LL)) return 4 * ((KK + 4 * b16p::ncw_of(LL) - 1) / (4 * b16p::ncw_of(LL)));   // one per wave
     return wide_ll(LL) ? 4 * KK : (KK + 1) / 2;
 }
 
 size_t bf16_xb_bytes(int LL, int KK) {
     if (LL == 16) return (size_t)KK * b16s::NK * 128 * sizeof(uint4);
+    if (LL == 8) return (size_t)b16p::n_blocks(8, KK) * b16p::Geo<8>::NCT * b16p::Geo<8>::NKS * 128 * sizeof(uint4);
+    if (LL == 12)
+        return (size_t)b16p::n_blocks(12, KK) * b16p::Geo<12>::NCT * b16p::Geo<12>::NKS * 128 * sizeof(uint4);
     if (wide_ll(LL)) return (size_t)KK * 2 * LL * (LL / 16) * 128 * sizeof(uint4);
     if (LL != 24 && LL != 32) return 0;
     return (size_t)KK * LL * (b16::R1P / 16) * 128 * sizeof(uint4);
 }
 
 hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, hipStream_t s) {
+    if (LL == 8) {
+        using G = b16p::Geo<8>;
+        hipLaunchKernelGGL(b16p::k_pack_xb<8>, dim3(b16p::n_blocks(8, p.KK) * G::NCT, (G::NKS + 3) / 4), dim3(256), 0,
+                           s, p, x, (uint4*)xb);
+        return hipGetLastError();
+    }
+    if (LL == 12) {
+        using G = b16p::Geo<12>;
+        hipLaunchKernelGGL(b16p::k_pack_xb<12>, dim3(b16p::n_blocks(12, p.KK) * G::NCT, (G::NKS + 3) / 4), dim3(256),
+                           0, s, p, x, (uint4*)xb);
+        return hipGetLastError();
+    }
     if (LL == 16) {
         hipLaunchKernelGGL(b16s::k_pack_xb, dim3(p.KK, 2), dim3(256), 0, s, p, x, (uint4*)xb);
         return hipGetLastError();
@@ -176,7 +233,7 @@ hipError_t launch_pack_xb(int LL, const StepArgs& p, const float* x, void* xb, h
 
 // bytes of the yT planes (the first prepared layout)
 size_t bf16_yt_bytes(int LL, int64_t N) {
-    return (size_t)N * 2 * LL * ((wide_ll(LL) || LL == 16) ? LL : b16::R1P) * 2;
+    return (size_t)N * 2 * LL * ((wide_ll(LL) || LL == 16 || packed_ll(LL)) ? LL : b16::R1P) * 2;
 }
 
 size_t bf16_prepared_extra(int LL, int64_t N) {
@@ -213,7 +270,9 @@ hipError_t launch_prep_bf16(int LL, const float* y, int64_t N, const double* cen
     if (LL == 16) return launch_prep_wide<16>(y, N, centre, ynorm, q, s);   // same layouts, one r1 slice
     if (LL == 48) return launch_prep_wide<48>(y, N, centre, ynorm, q, s);
     if (LL == 64) return launch_prep_wide<64>(y, N, centre, ynorm, q, s);
-    if (LL == 24) hipLaunchKernelGGL(b16::k_prep_bf16<24>, grid, dim3(256), 0, s, y, N, centre, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
+    if (LL == 8) hipLaunchKernelGGL((b16::k_prep_bf16<8, true>), grid, dim3(256), 0, s, y, N, centre, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
+    else if (LL == 12) hipLaunchKernelGGL((b16::k_prep_bf16<12, true>), grid, dim3(256), 0, s, y, N, centre, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
+    else if (LL == 24) hipLaunchKernelGGL(b16::k_prep_bf16<24>, grid, dim3(256), 0, s, y, N, centre, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
     else if (LL == 32) hipLaunchKernelGGL(b16::k_prep_bf16<32>, grid, dim3(256), 0, s, y, N, centre, (__bf16*)q.yT, (__bf16*)q.yo, ynorm);
     else return hipErrorInvalidValue;
     return hipGetLastError();
@@ -296,9 +355,24 @@ static hipError_t launch_bf16n(const StepArgs& p, const b16::Prep& q0, hipStream
     return hipGetLastError();
 }
 
+template <int LL, int NP>
+static hipError_t launch_bf16p(int pass, const StepArgs& p, const b16::Prep& q, hipStream_t s) {
+    const size_t lds = b16p::lds_bytes<LL>();
+    const void* f = pass == 1 ? (const void*)b16p::k_score_lse<LL, NP>
+                  : (pass == 2 ? (const void*)b16p::k_backproject<LL, NP> : (const void*)b16p::k_fused<LL, NP>);
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return hipErrorInvalidValue;
+    if (pass == 1) hipLaunchKernelGGL((b16p::k_score_lse<LL, NP>), dim3(p.n_chunks, p.n_cg), dim3(256), lds, s, p, q);
+    else if (pass == 2) hipLaunchKernelGGL((b16p::k_backproject<LL, NP>), dim3(p.n_chunks, p.n_cg), dim3(256), lds, s, p, q);
+    else hipLaunchKernelGGL((b16p::k_fused<LL, NP>), dim3(p.n_chunks), dim3(256), lds, s, p, q);
+    return hipGetLastError();
+}
+
 hipError_t launch_bf16(int LL, int np, int pass, const StepArgs& p, const void* prep_extra,
                        hipStream_t s) {
     const b16::Prep q = prep_ptrs(prep_extra, LL, p.N);
+    if (LL == 8) return np == 4 ? launch_bf16p<8, 4>(pass, p, q, s) : launch_bf16p<8, 3>(pass, p, q, s);
+    if (LL == 12) return np == 4 ? launch_bf16p<12, 4>(pass, p, q, s) : launch_bf16p<12, 3>(pass, p, q, s);
     if (pass == 3 && nine_tile(LL, p.cpb)) return np == 4 ? launch_bf16n<4>(p, q, s) : launch_bf16n<3>(p, q, s);
     if (LL == 16) return np == 4 ? launch_bf16s<4>(pass, p, q, s) : launch_bf16s<3>(pass, p, q, s);
     if (LL == 48) return np == 4 ? launch_bf16w_ll<48, 4>(pass, p, q, s) : launch_bf16w_ll<48, 3>(pass, p, q, s);
@@ -333,6 +407,21 @@ static void bf16w_geom_ll(size_t& lds1, size_t& lds2, const void*& f1, const voi
 // (max, sum) exchange spilled registers and measured no faster than the two
 // passes, slower inside the batched form; L_low 16 keeps two passes.)
 bool bf16_fused_geom(int LL, int KK, int np, int tile, int& cpb, int& nt, size_t& lds, const void*& f) {
+    if (packed_ll(LL)) {
+        // L_low 8 / 12: all components in one workgroup while they fit in 4 blocks
+        const int wcb = b16p::fused_wcb(LL, KK);
+        if (tile != 0 || wcb == 0) return false;
+        cpb = wcb * b16p::ncw_of(LL);
+        nt = 8 * (4 / wcb);
+        if (LL == 8) {
+            lds = b16p::lds_bytes<8>();
+            f = np == 4 ? (const void*)b16p::k_fused<8, 4> : (const void*)b16p::k_fused<8, 3>;
+        } else {
+            lds = b16p::lds_bytes<12>();
+            f = np == 4 ? (const void*)b16p::k_fused<12, 4> : (const void*)b16p::k_fused<12, 3>;
+        }
+        return true;
+    }
     // the layout: the default for the shape, or the one the tile asks for
     const bool small = (LL == 24 || LL == 32) && KK <= 4;
     const bool wide = (LL == 24 || LL == 32) && KK <= b16::F16_NCW * b16::F16_NW;
@@ -388,12 +477,28 @@ bool bf16_geom(int LL, int KK, int np, int tile, int& cpb, int& nt, size_t& lds1
     // allows, or two passes); 0 = the default
     if (tile != 0) {
         bool valid = false;
+        if (packed_ll(LL)) valid = tile == SRMRA_TILE_TWO_PASS;
         if (LL == 16) valid = tile == 1 || tile == 2 || tile == 4;
         if (LL == 24 || LL == 32)
             valid = tile == SRMRA_TILE_TWO_PASS || (tile == SRMRA_TILE_FUSED_8OBS && KK <= 4) ||
                     (tile == SRMRA_TILE_FUSED_4OBS && KK <= b16::F16_NCW * b16::F16_NW);
         if (LL == 48) valid = (tile == SRMRA_TILE_TWO_PASS || tile == SRMRA_TILE_16X16) && KK <= b16n::NW;
         if (!valid) return false;
+    }
+    if (packed_ll(LL)) {
+        // two passes: 4 blocks of NCW components per workgroup, 8 observations
+        cpb = 4 * b16p::ncw_of(LL);
+        nt = 8;
+        if (LL == 8) {
+            lds1 = lds2 = b16p::lds_bytes<8>();
+            f1 = np == 4 ? (const void*)b16p::k_score_lse<8, 4> : (const void*)b16p::k_score_lse<8, 3>;
+            f2 = np == 4 ? (const void*)b16p::k_backproject<8, 4> : (const void*)b16p::k_backproject<8, 3>;
+        } else {
+            lds1 = lds2 = b16p::lds_bytes<12>();
+            f1 = np == 4 ? (const void*)b16p::k_score_lse<12, 4> : (const void*)b16p::k_score_lse<12, 3>;
+            f2 = np == 4 ? (const void*)b16p::k_backproject<12, 4> : (const void*)b16p::k_backproject<12, 3>;
+        }
+        return true;
     }
     if (LL == 16) {
         const int wc = tile ? tile : b16s::wc_of(KK);

@@ -842,8 +842,9 @@ __device__ __forceinline__ void bf16_fused16_body(const StepArgs& p, const Prep&
 // the FP64 squared norms ||y_i - mu||^2.  One block per group of 8
 // observations: the group is staged in LDS with coalesced 16-byte reads, then
 // every 16-byte output run (8 BF16 values of one plane) is assembled in
-// registers and stored whole.
-template <int LL>
+// registers and stored whole.  PACKED (the packed-tile form at L_low 8 / 12):
+// yT is the transpose flattened without padding, yT[o][plane][col * Ll + r1].
+template <int LL, bool PACKED = false>
 __global__ __launch_bounds__(256) void k_prep_bf16(const float* __restrict__ y, int64_t N,
                                                    const double* __restrict__ centre,
                                                    __bf16* __restrict__ yT, __bf16* __restrict__ yo,
@@ -881,9 +882,29 @@ __global__ __launch_bounds__(256) void k_prep_bf16(const float* __restrict__ y, 
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
         if (lane == 0 && oi < N) ynorm[oi] = acc;
     }
+    if constexpr (PACKED) {
+        // yT[o][plane][f], f = col * Ll + r1: runs of 8 consecutive f
+        constexpr int RUNS = LL * LL / 8;
+        for (int e = threadIdx.x; e < 8 * RUNS; e += 256) {
+            const int o = e / RUNS, r = e % RUNS;
+            const int64_t oi = grp * 8 + o;
+            if (oi >= N) continue;
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int f = 8 * r + k;
+                v[k] = s[(o * LL + f % LL) * SP + f / LL];
+            }
+            bf16x8 h, l;
+            split8(v, h, l);
+            uint4* t = reinterpret_cast<uint4*>(yT + oi * (int64_t)(2 * LL * LL));
+            t[r] = __builtin_bit_cast(uint4, h);
+            t[RUNS + r] = __builtin_bit_cast(uint4, l);
+        }
+    }
     // yT[o][plane][r2][r1]: runs of 8 consecutive r1 (zeros past Ll)
     constexpr int JR = R1P / 8;
-    for (int e = threadIdx.x; e < 8 * LL * JR; e += 256) {
+    for (int e = threadIdx.x; e < (PACKED ? 0 : 8 * LL * JR); e += 256) {
         const int o = e / (LL * JR), r = e % (LL * JR);
         const int r2 = r / JR, jb = r % JR;
         const int64_t oi = grp * 8 + o;

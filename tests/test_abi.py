@@ -157,7 +157,7 @@ def test_tuning_table_validated_on_host(L):
     F32, BF, PL = B.SRMRA_FP32_MFMA, B.SRMRA_BF16_SPLIT3, B.SRMRA_FP32_PLAIN
     assert create(F32, [(F32, 32, 2, BF, 0)]) == B.SRMRA_EINVAL
     assert create(F32, [(F32, 32, 2, PL, 0)]) == B.SRMRA_EINVAL
-    assert create(BF, [(BF, 12, 2, BF, 0)]) == B.SRMRA_EUNSUPPORTED   # no BF16 kernel at L_low 12
+    assert create(BF, [(BF, 12, 2, BF, 0)]) == B.SRMRA_OK   # BF16 at L_low 12: packed tiles
     assert create(BF, [(BF, 32, 2, F32, -1)]) == B.SRMRA_EINVAL
     assert create(BF, [(BF, 32, 2, F32, 100)]) == B.SRMRA_OK
     assert create(BF, [(F32, 32, 2, F32, 100)]) == B.SRMRA_OK       # other precision: ignored
@@ -202,9 +202,11 @@ def test_split4_precision_accepted():
             B.srmra_em_step_workspace_bytes(N, ll, K, "bf16_split3") > 0
         assert B.srmra_prepared_bytes(N, ll, K, "bf16_split4") == \
             B.srmra_prepared_bytes(N, ll, K, "bf16_split3") > 0
-    for ll in (8, 12):   # no BF16 kernel at these L_low
-        assert B.srmra_em_step_workspace_bytes(1000, ll, 2, "bf16_split4") == 0
-        assert B.srmra_plan_form(B.SRMRA_BF16_SPLIT4, ll) == B.SRMRA_FP32_MFMA
+    for ll in (8, 12):   # the packed-tile kernels
+        for K in (1, 2, 4, 5, 6):
+            assert B.srmra_em_step_workspace_bytes(1000, ll, K, "bf16_split4") == \
+                B.srmra_em_step_workspace_bytes(1000, ll, K, "bf16_split3") > 0
+        assert B.srmra_plan_form(B.SRMRA_BF16_SPLIT4, ll) == B.SRMRA_BF16_SPLIT4
     assert B.srmra_plan_form(B.SRMRA_BF16_SPLIT4, 32) == B.SRMRA_BF16_SPLIT4
     assert B.srmra_plan_form(B.SRMRA_BF16_SPLIT4, 16) == B.SRMRA_BF16_SPLIT4
     assert B.srmra_plan_form(4, 32) == -1

@@ -14,7 +14,8 @@ from tests.gpu_helpers import check_step, oracle_step  # noqa: E402
 
 MIX = [(32, 2, 301, 0.6), (48, 3, 157, 1.1), (64, 4, 77, 1.6), (48, 2, 95, 0.9),
        (96, 4, 23, 1.9), (32, 4, 211, 0.4), (64, 2, 64, 1.3), (96, 2, 9, 2.0),
-       (128, 2, 5, 12.0)]   # L_low 64: the class whose pass-2 body fills the whole LDS
+       (128, 2, 5, 12.0),   # L_low 64: the class whose pass-2 body fills the whole LDS
+       (48, 4, 53, 1.0)]    # L_low 12: packed BF16 tiles
 
 
 def _instances(mix, config=70):
@@ -41,8 +42,7 @@ def test_mixed_batch_matches_oracle(prec):
         inst = d["inst"]
         g = be.results(j)
         ref = oracle_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K)
-        # BF16 plans run L_low 8 and 12 in FP32 MFMA
-        form = prec if not (prec.startswith("bf16") and inst.Ll in (8, 12)) else "fp32_mfma"
+        form = prec
         # The BF16 split's logits carry about 1.5 * 2^-17 ||y o x|| / sigma^2 of
         # error (per-product residual of hi + lo); x' averages it over the
         # posterior mass, so with a handful of observations (N = 9 and 5 here)
@@ -107,7 +107,7 @@ def test_autotuned_batch_matches_oracle():
     for t in be.tuning:
         assert t["form"] in (B.SRMRA_BF16_SPLIT3, B.SRMRA_FP32_MFMA) and t["item_obs"] > 0
         if t["form"] == B.SRMRA_BF16_SPLIT3:
-            assert t["L_low"] in (16, 24, 32, 48, 64)
+            assert t["L_low"] in (8, 12, 16, 24, 32, 48, 64)
         form[(t["L_low"], t["K"])] = t["form"]
     assert len(be.tune_report) >= len(classes)
     be.step()
@@ -271,8 +271,10 @@ LAYOUTS = {
     "fused_8obs": [(64, 2, 203, 0.9), (48, 2, 131, 1.1)],
     # single pass, 4 observations x 16 components (8 waves): also at K^2 = 4 and 1
     "fused_4obs": [(64, 2, 203, 0.9), (96, 3, 61, 1.2), (48, 2, 131, 1.1), (32, 1, 45, 1.3)],
-    # two passes: L_low 32 (K 2, 3), 24 (K 4) and 48 (2 x 2 tiles of 32x32)
-    "two_pass": [(64, 2, 203, 0.9), (96, 3, 61, 1.2), (96, 4, 37, 1.4), (96, 2, 77, 1.0)],
+    # two passes: L_low 32 (K 2, 3), 24 (K 4), 48 (2 x 2 tiles of 32x32), and
+    # the packed tiles at L_low 8 (K 4, 2) and 12 (K 4)
+    "two_pass": [(64, 2, 203, 0.9), (96, 3, 61, 1.2), (96, 4, 37, 1.4), (96, 2, 77, 1.0),
+                 (32, 4, 91, 1.1), (16, 2, 45, 0.8), (48, 4, 67, 1.3)],
     # 3 x 3 tiles of 16x16 at L_low 48 (K 2 and 1)
     "16x16": [(96, 2, 77, 1.0), (48, 1, 33, 1.5)],
 }
@@ -315,7 +317,8 @@ def test_fp32_two_pass_layout_and_invalid_layouts():
         ref = oracle_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K)
         check_step(inst.y, inst.x0, inst.log_rho0, inst.sigma, inst.K, be.results(j), ref, "fp32_mfma")
     bad = [(32, B.SRMRA_TILE_16X16, 2), (48, B.SRMRA_TILE_FUSED_4OBS, 2), (32, B.SRMRA_TILE_FUSED_8OBS, 3),
-           (48, B.SRMRA_TILE_16X16, 3), (16, B.SRMRA_TILE_TWO_PASS, 2)]
+           (48, B.SRMRA_TILE_16X16, 3), (16, B.SRMRA_TILE_TWO_PASS, 2), (8, B.SRMRA_TILE_FUSED_8OBS, 2),
+           (12, B.SRMRA_TILE_16X16, 2)]
     for ll, tile, K in bad:
         one = _instances([(ll * K, K, 40, 1.0)], config=82)
         with pytest.raises(B.SrmraError):
