@@ -21,7 +21,11 @@ Prints ONE JSON line.  Also reports:
    rate 78.6 TFLOP/s): algorithmic work (4 Ll^2 flop per observation x shift
    pair) and issued work (with the score recompute and the split's products);
  * cpu_baseline: the FP64 oracle on the first 2000 observations, timed on
-   this host, and every GPU form's relative error against it on that subset.
+   this host, and every GPU form's relative error against it on that subset;
+ * batched and serving: the 64-instance mix in the batched form (main
+   precision, every class on the FFT route, FP32 MFMA, plain FP32) and a short
+   Poisson serving run (60 jobs at 50 jobs/s), compact (--no-mix skips them;
+   --mode batched / serve run the full sweeps).
 """
 from __future__ import annotations
 
@@ -119,6 +123,8 @@ def parse():
                     help="serve mode: comma-separated forms (default: --precision, fp32_mfma, "
                          "fp32_plain); '<form>+fft' runs jobs at an L_low the FFT route supports "
                          "through it and the rest in <form>")
+    ap.add_argument("--no-mix", action="store_true",
+                    help="single mode: skip the compact batched-mix and serving summaries")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after the timed region, run one device-to-device copy of this many MiB "
                          "(reference kernel of known traffic for hardware-counter calibration)")
@@ -401,6 +407,90 @@ def bench_batched(args):
            "forms": forms, "tuning": tuning, "classes": classes,
            "speedup_vs_plain_fp32": forms[best]["pairs_per_s"] / forms["fp32_plain"]["pairs_per_s"]}
     print(json.dumps(out), flush=True)
+
+
+def _time_batched(ins, precision, tuning, iters):
+    """ms per step of one plan over the instances (`iters` EM steps captured as
+    one HIP graph, one warm-up replay, one timed replay) and its pairs per step."""
+    import torch
+    from paper_2204_04754_amd.batch import BatchedEM
+    be = BatchedEM(ins, precision=precision, tuning=tuning)
+    pairs = be.pairs_per_step
+    g = be.capture(iters)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    del g, be
+    torch.cuda.empty_cache()
+    return ms, pairs
+
+
+def mix_summary(precision: str) -> dict:
+    """The batched form on the 64-instance mix, compact (the default run's
+    record of it): the main precision with the library's default table and
+    with every class on the FFT route (a fixed table, no tuning), FP32 MFMA
+    and plain FP32 with fewer iterations per graph."""
+    from paper_2204_04754_amd import binding as B
+    from paper_2204_04754_amd import synth
+    t = time.perf_counter()
+    mix = synth.mixed_batch(64)
+    ins = []
+    for d in mix:
+        inst = synth.make_instance(**d)
+        ins.append(dict(y=inst.y, K=inst.K, sigma=inst.sigma, x0=inst.x0, log_rho0=inst.log_rho0))
+    fft_table = [dict(precision=B._prec(precision), L_low=ll, K=k, form=B.SRMRA_FP32_FFT, item_obs=0)
+                 for (ll, k) in sorted({(d["Lh"] // d["K"], d["K"]) for d in mix})]
+    tables = {}
+    for key, prec, tab, iters in ((precision, precision, None, 20),
+                                  (precision + "+fft_all", precision, fft_table, 20),
+                                  ("fp32_mfma", "fp32_mfma", None, 2), ("fp32_plain", "fp32_plain", None, 2)):
+        ms, pairs = _time_batched(ins, prec, tab, iters)
+        tables[key] = dict(ms_per_step=ms, pairs_per_s=pairs / (ms * 1e-3), iterations_in_graph=iters)
+    plain = tables["fp32_plain"]["pairs_per_s"]
+    for v in tables.values():
+        v["speedup_vs_plain_fp32"] = v["pairs_per_s"] / plain
+    out = {"workload": "batched_mix_64", "instances": 64, "pairs_per_step": pairs, "tables": tables,
+           "seconds": time.perf_counter() - t}
+    print(f"[bench] batched mix: " + ", ".join(f"{k} {v['ms_per_step']:.1f} ms/step" for k, v in tables.items()),
+          file=sys.stderr, flush=True)
+    return out
+
+
+def serve_summary(precision: str, rate: float = 50.0, jobs: int = 60, iterations: int = 20) -> dict:
+    """A short serving run (Poisson arrivals at `rate` jobs/s of `jobs`
+    20-iteration jobs from the serving pool), the main precision with the FFT
+    route inside the plan and alone: solves/s and p50 / p99 latency."""
+    import torch
+    from paper_2204_04754_amd import synth
+    from paper_2204_04754_amd.serve import GPUExecutor, Job, serve
+    t = time.perf_counter()
+    pool_shapes = synth.mixed_batch(11, config=4) + [dict(Lh=256, K=4, N=20000, sigma=1.0,
+                                                            config=4, instance=999)]
+    pool = [synth.make_instance(**d) for d in pool_shapes]
+    r = np.random.default_rng(int(rate * 1000) + 7)
+    arr = np.cumsum(r.exponential(1.0 / rate, size=jobs))
+    pick = [11 if r.random() < 0.1 else int(r.integers(0, 11)) for _ in range(jobs)]
+    res = {}
+    for key, fft in ((precision + "+fftplan", "plan"), (precision, False)):
+        js = [Job(k, pool[pick[k]].y, pool[pick[k]].K, pool[pick[k]].sigma, pool[pick[k]].x0,
+                  pool[pick[k]].log_rho0, iterations=iterations, arrival=float(arr[k])) for k in range(jobs)]
+        ex = GPUExecutor(precision=precision, fft=fft)
+        summ = serve(js, ex, hbm_budget=200 << 30, max_slots=64).summary()
+        res[key] = {k: summ[k] for k in ("jobs", "done", "failed", "solves_per_s", "p50_latency_s",
+                                         "p99_latency_s")}
+        del ex
+        torch.cuda.empty_cache()
+    out = {"workload": "serve_poisson_mix", "rate_jobs_per_s": rate, "jobs": jobs,
+           "iterations_per_job": iterations, "results": res, "seconds": time.perf_counter() - t}
+    print(f"[bench] serving at {rate:g} jobs/s: " + ", ".join(
+        f"{k} {v['solves_per_s']:.1f} solves/s p50 {v['p50_latency_s']:.2f} s p99 {v['p99_latency_s']:.2f} s"
+        for k, v in res.items()), file=sys.stderr, flush=True)
+    return out
 
 
 def bench_projected(args):
@@ -712,6 +802,11 @@ def main():
               f"{sr['ms_per_step']:.2f} ms/step ({time.perf_counter() - t:.1f} s)",
               file=sys.stderr, flush=True)
         del inst2
+    if not args.no_mix:
+        # the batched (64-instance mix) and serving forms, compact, so that the
+        # default run records them too (full sweeps: --mode batched / serve)
+        out["batched"] = mix_summary(args.precision)
+        out["serving"] = serve_summary(args.precision)
     if not args.no_cpu:
         n = args.cpu_sample or oracle_sample_size(inst, args.cpu_seconds)
         n = min(n, inst.N)
