@@ -63,7 +63,7 @@ TRAFFIC = {
     ("lh64_k2_n100000", "fp32_mfma", "k_fused_mfma<32>"):
         dict(bytes=428054630, src=_MFMA_SRC, sha="5fe9b8ec41a003f1"),
     ("lh128_k4_n200000_s0.5", "bf16_split3", "k_fused16_bf16<32, 3>"):
-        dict(bytes=15786206672, src=_BF16_SRC, sha="eef3a574e1956c7e"),
+        dict(bytes=15727274189, src=_BF16_SRC, sha="74937274c8f678c3"),
     ("lh256_k4_n20000", "bf16_split3", "b16w::k_backproject<64, 3>"):
         dict(bytes=7369647616, src=_BF16W_SRC, sha="f7205148b449a689"),
 }
