@@ -61,19 +61,24 @@ __global__ __launch_bounds__(256) void k_prep_y(const float* __restrict__ y, int
     bool on;
     team_of<L>(team, r, on);
     const int64_t i = (int64_t)blockIdx.x * G<L>::TEAMS + team;
-    if (!on || i >= N) return;   // no block barrier follows
+    const bool act = on && i < N;   // every lane reaches the teams' barriers
     float2* buf = sh + team * G<L>::BUF;
     const float mu = centre_of(centre);
     float2 v[L];
+    if (act) {
 #pragma unroll
-    for (int k = 0; k < L; ++k) v[k] = make_float2(y[(i * L + k) * L + r] - mu, 0.f);   // column r
-    fft1m<L, false>(v, tw);
+        for (int k = 0; k < L; ++k) v[k] = make_float2(y[(i * L + k) * L + r] - mu, 0.f);   // column r
+        fft1m<L, false>(v, tw);
 #pragma unroll
-    for (int k = 0; k < L; ++k) buf[k * (L + 1) + r] = v[k];
-    team_sync();
+        for (int k = 0; k < L; ++k) buf[k * (L + 1) + r] = v[k];
+    }
+    row::sync<L>();
+    if (act) {
 #pragma unroll
-    for (int k = 0; k < L; ++k) v[k] = buf[r * (L + 1) + k];   // row k1 = r
-    team_sync();
+        for (int k = 0; k < L; ++k) v[k] = buf[r * (L + 1) + k];   // row k1 = r
+    }
+    row::sync<L>();
+    if (!act) return;
     fft1m<L, false>(v, tw);                                     // v[k] = Y_i[r][k]
     float4* d = reinterpret_cast<float4*>(yhat) + i * (L / 2) * L + r;
 #pragma unroll
@@ -106,18 +111,23 @@ __global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int6
     bool on;
     team_of<L>(team, r, on);
     const int64_t i = (int64_t)blockIdx.x * G<L>::TEAMS + team;
-    if (!on || i >= count) return;
+    const bool act = on && i < count;   // every lane reaches the teams' barriers
     float2* buf = sh + team * G<L>::BUF;
     float2 v[L];
+    if (act) {
 #pragma unroll
-    for (int k = 0; k < L; ++k) v[k] = make_float2(in[(i * L + r) * L + k], 0.f);   // row r
-    fft1m<L, false>(v, tw);
+        for (int k = 0; k < L; ++k) v[k] = make_float2(in[(i * L + r) * L + k], 0.f);   // row r
+        fft1m<L, false>(v, tw);
 #pragma unroll
-    for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = v[k];
-    team_sync();
+        for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = v[k];
+    }
+    row::sync<L>();
+    if (act) {
 #pragma unroll
-    for (int k = 0; k < L; ++k) v[k] = buf[k * (L + 1) + r];   // column r
-    team_sync();
+        for (int k = 0; k < L; ++k) v[k] = buf[k * (L + 1) + r];   // column r
+    }
+    row::sync<L>();
+    if (!act) return;
     fft1m<L, false>(v, tw);                                     // v[k] = X[k][r]
 #pragma unroll
     for (int k = 0; k < L; ++k) out[(i * L + k) * L + r] = v[k];
@@ -308,7 +318,7 @@ hipError_t launch_dft2(int L, const float* in, int64_t count, float2* out, hipSt
             hipLaunchKernelGGL(fft::k_dft2<64>, grid, dim3(256), lds, s, in, count, out);
             break;
         case 12: case 24: case 48: {
-            const int tm = 4 * (64 / L);
+            const int tm = fft::teams_of(L);
             const dim3 g((unsigned)((count + tm - 1) / tm));
             const void* f = L == 12 ? (const void*)fft::row::k_dft2<12>
                                     : (L == 24 ? (const void*)fft::row::k_dft2<24> : (const void*)fft::row::k_dft2<48>);

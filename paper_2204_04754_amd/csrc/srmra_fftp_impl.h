@@ -22,22 +22,29 @@
 namespace srmra {
 namespace fft {
 
+// L = 3 * 2^m: teams of L lanes over the whole 256-thread block (WIDE: they
+// may span two waves, and their transposes wait on the block barrier), or
+// 64 / L teams inside each wave (wave barriers; a quarter of the lanes idle at
+// L 24 and 48)
+__host__ __device__ constexpr bool row_wide(int L) { return L % 3 == 0; }
 // teams of the two passes per 256-thread block: 2 L lanes each (L <= 32), one
-// team of four lanes per row (L 64), 64 / L teams of L lanes per wave (L = 3 * 2^m)
+// team of four lanes per row (L 64), 256 / L teams of L lanes (L = 3 * 2^m)
 __host__ __device__ inline int teams_of(int L) {
-    if (L % 3 == 0) return 4 * (64 / L);
+    if (L % 3 == 0) return row_wide(L) ? 256 / L : 4 * (64 / L);
     return L == 64 ? 1 : 256 / (2 * L);
 }
-// teams per component in pass 2 for KK components: a power of 2 (TPC) with
-// CG = teams / TPC components per block over ceil(KK / CG) component groups,
-// chosen for the largest share KK TPC / (groups x teams) of busy teams, then
-// the fewest groups, then the fewest teams per component: at KK = 9 and 4
-// teams, one component per block on all 4 teams (every team busy) instead of
-// 4 components per block (the last group's block three quarters idle)
+// teams per component in pass 2 for KK components: TPC with CG = teams / TPC
+// components per block over ceil(KK / CG) component groups, chosen for the
+// largest share KK TPC / (groups x teams) of busy teams, then the fewest
+// groups, then the fewest teams per component: at KK = 9 and 4 teams, one
+// component per block on all 4 teams (every team busy) instead of 4
+// components per block (the last group's block three quarters idle).  TPC
+// is a power of 2 for the power-of-two L and any count for L = 3 * 2^m (10
+// teams at L 24: 5 per component)
 __host__ __device__ inline int tpc_of(int L, int KK) {
     const int teams = teams_of(L);
     int best = 1, best_busy = 0, best_all = 1, best_groups = 1 << 30;
-    for (int tpc = 1; tpc <= teams; tpc *= 2) {
+    for (int tpc = 1; tpc <= teams; tpc = (L % 3 == 0) ? tpc + 1 : 2 * tpc) {
         const int cg = teams / tpc;
         const int groups = (KK + cg - 1) / cg;
         const int busy = KK * tpc, all = groups * teams;
@@ -436,51 +443,75 @@ __device__ __forceinline__ void pass2_quad_body(const StepArgs& p, const float2*
 // partials and the meaning of every sum are those of the power-of-two passes.
 namespace row {
 template <int L> struct G {
-    static constexpr int TPW = 64 / L;          // teams per wave
-    static constexpr int TEAMS = 4 * TPW;       // teams per 256-thread block
+    static constexpr bool WIDE = row_wide(L);
+    static constexpr int TEAMS = WIDE ? 256 / L : 4 * (64 / L);   // teams per 256-thread block
     static constexpr int BUF = L * (L + 1);     // float2 per team transpose buffer
 };
+// a team's exchange through its transpose buffer
+template <int L> __device__ __forceinline__ void sync() {
+    if constexpr (G<L>::WIDE) __syncthreads();
+    else team_sync();
+}
 // [transpose buffers TEAMS x BUF float2][twiddles L float2][masses TEAMS x L x L float]
 template <int L> constexpr size_t lds() {
     return sizeof(float2) * ((size_t)G<L>::TEAMS * G<L>::BUF + L) + sizeof(float) * (size_t)G<L>::TEAMS * L * L;
 }
 
-// lane -> (team, row r); on: the lane belongs to a team
+// lane -> (team, row r); on: the lane belongs to a team (lanes that do not
+// touch no team buffer but reach every barrier)
 template <int L> __device__ __forceinline__ void team_of(int& team, int& r, bool& on) {
-    const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    on = ln < G<L>::TPW * L;
-    team = wave * G<L>::TPW + (on ? ln / L : 0);
-    r = ln % L;
+    if constexpr (G<L>::WIDE) {
+        const int t = threadIdx.x;
+        on = t < G<L>::TEAMS * L;
+        team = on ? t / L : 0;
+        r = t % L;
+    } else {
+        constexpr int TPW = 64 / L;
+        const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        on = ln < TPW * L;
+        team = wave * TPW + (on ? ln / L : 0);
+        r = ln % L;
+    }
 }
 
 // scores of (observation o, component c) for lane r: s[k] = a at (t1 = k, t2 = r).
 // Row r of Y_o conj(X_c) is inverse-transformed along k2, the team exchanges
 // rows for columns, and column r is inverse-transformed along k1.
+// Lanes with !on only reach the barriers (s = -inf).
 template <int L>
 __device__ __forceinline__ void score(const StepArgs& p, const float2* __restrict__ yhat,
                                       const float2* __restrict__ xhat, int64_t o, int c, float2* buf, int r,
-                                      const float2* tw, float (&s)[L]) {
+                                      const float2* tw, float (&s)[L], bool on = true) {
     float2 v[L];
-    const float4* yr = reinterpret_cast<const float4*>(yhat) + (int64_t)o * (L / 2) * L + r;
-    const float4* xr = reinterpret_cast<const float4*>(xhat) + (int64_t)c * (L / 2) * L + r;
+    if (on) {
+        const float4* yr = reinterpret_cast<const float4*>(yhat) + (int64_t)o * (L / 2) * L + r;
+        const float4* xr = reinterpret_cast<const float4*>(xhat) + (int64_t)c * (L / 2) * L + r;
 #pragma unroll
-    for (int m = 0; m < L / 2; ++m) {
-        const float4 a = yr[m * L], b = xr[m * L];
-        v[2 * m] = cmulc(make_float2(a.x, a.y), make_float2(b.x, b.y));
-        v[2 * m + 1] = cmulc(make_float2(a.z, a.w), make_float2(b.z, b.w));
+        for (int m = 0; m < L / 2; ++m) {
+            const float4 a = yr[m * L], b = xr[m * L];
+            v[2 * m] = cmulc(make_float2(a.x, a.y), make_float2(b.x, b.y));
+            v[2 * m + 1] = cmulc(make_float2(a.z, a.w), make_float2(b.z, b.w));
+        }
+        fft1m<L, true>(v, tw);                                  // v[n2]: row k1 = r
+#pragma unroll
+        for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = v[k];
     }
-    fft1m<L, true>(v, tw);                                      // v[n2]: row k1 = r
+    sync<L>();
+    if (on) {
 #pragma unroll
-    for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = v[k];
-    team_sync();
+        for (int m = 0; m < L; ++m) v[m] = buf[m * (L + 1) + r];   // column n2 = r
+    }
+    sync<L>();
+    if (on) {
+        fft1m<L, true>(v, tw);                                  // v[k] = S[k][r]
+        const float sc = p.inv_s2 / (float)(L * L);
+        const float* bet = p.betaT + (int64_t)c * (L * L) + r * L;   // betaT[c][t2 = r][t1]
 #pragma unroll
-    for (int m = 0; m < L; ++m) v[m] = buf[m * (L + 1) + r];   // column n2 = r
-    team_sync();
-    fft1m<L, true>(v, tw);                                      // v[k] = S[k][r]
-    const float sc = p.inv_s2 / (float)(L * L);
-    const float* bet = p.betaT + (int64_t)c * (L * L) + r * L;   // betaT[c][t2 = r][t1]
+        for (int k = 0; k < L; ++k) s[k] = v[k].x * sc + bet[k];
+    } else {
 #pragma unroll
-    for (int k = 0; k < L; ++k) s[k] = v[k].x * sc + bet[k];
+        for (int k = 0; k < L; ++k) s[k] = -INFINITY;
+    }
 }
 
 // pass 1: (max, sum exp) of every observation over all components; a team per
@@ -495,16 +526,18 @@ __device__ __forceinline__ void pass1_body(const StepArgs& p, const float2* __re
     int team, r;
     bool on;
     team_of<L>(team, r, on);
-    if (!on) return;   // no block barrier follows
     float2* buf = sh + team * G<L>::BUF;
     const int64_t c0 = chunk * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    for (int64_t o = c0 + team + (int64_t)G<L>::TEAMS * ysplit; o < c1;
-         o += (int64_t)G<L>::TEAMS * nsplit) {
+    // the same trip count in every lane of the block (the teams' barriers)
+    for (int64_t base = c0 + (int64_t)G<L>::TEAMS * ysplit; base < c1; base += (int64_t)G<L>::TEAMS * nsplit) {
+        const int64_t o = base + team;
+        const bool act = on && o < c1;
+        const int64_t oc = act ? o : c0;   // an observation to read for lanes past the chunk
         float m = -INFINITY, sm = 0.f;
         for (int c = 0; c < p.KK; ++c) {
             float s[L];
-            score<L>(p, yhat, xhat, o, c, buf, r, tw, s);
+            score<L>(p, yhat, xhat, oc, c, buf, r, tw, s, on);
             float mc = -INFINITY;
 #pragma unroll
             for (int k = 0; k < L; ++k) mc = fmaxf(mc, s[k]);
@@ -516,13 +549,13 @@ __device__ __forceinline__ void pass1_body(const StepArgs& p, const float2* __re
             lse_merge(m, sm, mc, sc);
         }
         // the team's L lanes merged in lane order by its first lane
-        buf[r] = make_float2(m, sm);
-        team_sync();
-        if (r == 0) {
+        if (on) buf[r] = make_float2(m, sm);
+        sync<L>();
+        if (act && r == 0) {
             for (int k = 1; k < L; ++k) lse_merge(m, sm, buf[k].x, buf[k].y);
             p.part[o] = make_float2(m, sm);
         }
-        team_sync();
+        sync<L>();
     }
 }
 
@@ -554,25 +587,35 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const float2* __re
     float2 ab[L];   // sum of Y conj(W) at (k1 = r, k2 = k)
 #pragma unroll
     for (int k = 0; k < L; ++k) ab[k] = make_float2(0.f, 0.f);
-    if (active) {
-        for (int64_t o = c0 + u; o < c1; o += TPC) {
-            float s[L];
-            score<L>(p, yhat, xhat, o, c, buf, r, tw, s);
-            const float2 lse = p.lse[o];
-            float2 v[L];
+    // the same trip count in every lane of the block (the teams' barriers);
+    // inactive teams and observations past the chunk add nothing
+    const int cc = active ? c : 0;
+    for (int64_t base = c0; base < c1; base += TPC) {
+        const int64_t o = base + u;
+        const bool act = active && o < c1;
+        const int64_t oc = act ? o : c0;
+        float s[L];
+        score<L>(p, yhat, xhat, oc, cc, buf, r, tw, s, on);
+        const float2 lse = act ? p.lse[oc] : make_float2(0.f, 0.f);
+        float2 v[L];
 #pragma unroll
-            for (int k = 0; k < L; ++k) {
-                const float w = s[k] > -INFINITY ? __expf((s[k] - lse.x) - lse.y) : 0.f;
-                mt[k * L + r] += w;                             // (t1 = k, t2 = r): the lane's own
-                v[k] = make_float2(w, 0.f);
-            }
+        for (int k = 0; k < L; ++k) {
+            const float w = (act && s[k] > -INFINITY) ? __expf((s[k] - lse.x) - lse.y) : 0.f;
+            if (act) mt[k * L + r] += w;                        // (t1 = k, t2 = r): the lane's own
+            v[k] = make_float2(w, 0.f);
+        }
+        if (on) {
             fft1m<L, false>(v, tw);                             // column t2 = r along t1: v[k1]
 #pragma unroll
             for (int k = 0; k < L; ++k) buf[k * (L + 1) + r] = v[k];
-            team_sync();
+        }
+        sync<L>();
+        if (on) {
 #pragma unroll
             for (int m = 0; m < L; ++m) v[m] = buf[r * (L + 1) + m];   // row k1 = r
-            team_sync();
+        }
+        sync<L>();
+        if (act) {
             fft1m<L, false>(v, tw);                             // v[k] = W[r][k]
             const float4* yr = reinterpret_cast<const float4*>(yhat) + o * (L / 2) * L + r;
 #pragma unroll
