@@ -298,15 +298,14 @@ __device__ __forceinline__ void body(const StepArgs& p, const b16::Prep& q, int 
         // across it
         asm volatile("" ::: "memory");
         const int64_t obs0 = t0 + ws * G::NO;   // the wave's 8 observations
-        // a = score + beta, -inf for masked slots, formed where it is used
         bool ook[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) ook[u] = obs0 + 4 * g + u < p.N;
-        // the score tiles of one column tile at a time (with more than one, they
-        // are computed twice: once for the log-sum-exp, once for the weights)
+        // the score tiles of one column tile at a time (with more than one,
+        // they are computed twice: once for the log-sum-exp, once for the
+        // weights): tile(ct) leaves the log-joint terms a = score + beta of
+        // column tile ct in acc, -inf in masked slots
         floatx16 acc[NR][1];
-        // the score tiles of column tile ct, plus the prior, -inf in masked slots
-        // (a = score + beta: the log-joint terms), in place
         auto tile = [&](int ct) {
             if (wact) score<LL, NP, 1>(p, ys, ws * G::NO, gcb * NCT + ct, xh, xl, acc);
 #pragma unroll
