@@ -55,7 +55,7 @@ hipError_t launch_project(const float* x_in, float* x_out, int Lh, float* sigma_
 bool fft_supported(int LL);
 int fft_tpc(int LL, int KK);
 int fft_teams(int LL);
-size_t fft_lds(int LL);
+size_t fft_lds(int LL, int pass);
 const void* fft_pass2_fn(int LL);
 hipError_t launch_fft(int LL, int what, const StepArgs& p, const float* x, const float* y,
                       void* yhat, void* xhat, void* bpart, void* cpart, void* bh,
@@ -181,7 +181,8 @@ int make_geom(int64_t N, int LL, int K, int prec, bool with_norms, Geom& g,
             const int teams = fft_teams(LL);
             g.cpb = teams / fft_tpc(LL, g.KK);   // components per pass-2 block
             g.ntile = teams;
-            g.lds1 = g.lds2 = fft_lds(LL);
+            g.lds1 = fft_lds(LL, 1);
+            g.lds2 = fft_lds(LL, 2);
             f2 = fft_pass2_fn(LL);
         }
     }

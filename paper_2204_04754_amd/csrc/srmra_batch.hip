@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256, ((PASS == 1 && (FORM == FORM_BF16 || FORM == F
                                    (PASS == 2 && FORM == FORM_MFMA && LL >= 16 && LL <= 32) ||
                                    (PASS == 2 && FORM == FORM_FUSED && LL >= 16 && LL <= 24) ||
                                    ((FORM == FORM_BF16F || FORM == FORM_BF16X4F) && LL == 48) ||
-                                   (FORM == FORM_FFT && (LL == 12 || LL == 24))) ? 2 : 1)
+                                   (FORM == FORM_FFT && (LL == 12 || LL == 24 || (LL == 48 && PASS == 1)))) ? 2 : 1)
 void k_class_pass(const InstDesc* __restrict__ D,
                                                     const int4* __restrict__ items, int n_items,
                                                     int* __restrict__ counter) {

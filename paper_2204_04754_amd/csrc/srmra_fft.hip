@@ -1,4 +1,6 @@
 // Kernels of the FFT route (bodies in srmra_fftp_impl.h) and their launches.
+#include <atomic>
+
 #include "srmra_fftp_impl.h"
 
 namespace srmra {
@@ -85,10 +87,11 @@ __global__ __launch_bounds__(256) void k_prep_y(const float* __restrict__ y, int
     for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
 }
 
-// two waves per SIMD where the body fits 256 registers (L 12, 24; L 48 is held
-// to one block per CU by its LDS anyway)
+// two waves per SIMD where the body fits 256 registers: pass 1 at every L,
+// pass 2 at L 12 and 24 (at L 48 a lane's image row, its back-projection sums,
+// its posterior masses and the scores take more)
 template <int L>
-__global__ __launch_bounds__(256, L <= 24 ? 2 : 1) void k_pass1(StepArgs p, const float2* __restrict__ yhat,
+__global__ __launch_bounds__(256, 2) void k_pass1(StepArgs p, const float2* __restrict__ yhat,
                                                const float2* __restrict__ xhat) {
     extern __shared__ float2 sh[];
     pass1_body<L>(p, yhat, xhat, blockIdx.x, blockIdx.y, gridDim.y, sh);
@@ -165,15 +168,15 @@ bool fft_supported(int LL) { return LL == 8 || LL == 16 || LL == 32 || LL == 64 
 int fft_teams(int LL) { return fft::teams_of(LL); }
 int fft_tpc(int LL, int KK) { return fft::tpc_of(LL, KK); }
 
-size_t fft_lds(int LL) {   // the two passes
+size_t fft_lds(int LL, int pass) {   // dynamic LDS of pass 1 or 2
     switch (LL) {
         case 8: return fft::lds_pairs<8>();
         case 16: return fft::lds_pairs<16>();
         case 32: return fft::lds_pairs<32>();
         case 64: return fft::quad::lds();
-        case 12: return fft::row::lds<12>();
-        case 24: return fft::row::lds<24>();
-        case 48: return fft::row::lds<48>();
+        case 12: return pass == 1 ? fft::row::lds_pass1<12>() : fft::row::lds<12>();
+        case 24: return pass == 1 ? fft::row::lds_pass1<24>() : fft::row::lds<24>();
+        case 48: return pass == 1 ? fft::row::lds_pass1<48>() : fft::row::lds<48>();
     }
     return 0;
 }
@@ -196,13 +199,13 @@ template <int L>
 static hipError_t fft_launch_row(int what, const StepArgs& p, const float* x, const float* y,
                                  void* yhat, void* xhat, void* bpart, void* cpart, hipStream_t s) {
     using G = fft::row::G<L>;
-    const size_t lds = fft::row::lds<L>();
-    auto attr = [&](const void* f) {
-        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const size_t lds = fft::row::lds<L>(), lp1 = fft::row::lds_pass1<L>(), lp2 = lds;
+    auto attr = [&](const void* f, size_t bytes) {
+        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     };
     switch (what) {
         case 0:
-            if (attr((const void*)fft::row::k_prep_y<L>) != hipSuccess) return hipErrorInvalidValue;
+            if (attr((const void*)fft::row::k_prep_y<L>, lds) != hipSuccess) return hipErrorInvalidValue;
             hipLaunchKernelGGL(fft::row::k_prep_y<L>, dim3((unsigned)((p.N + G::TEAMS - 1) / G::TEAMS)), dim3(256),
                                lds, s, y, p.N, p.centre, (float2*)yhat);
             break;
@@ -214,13 +217,30 @@ static hipError_t fft_launch_row(int what, const StepArgs& p, const float* x, co
                                p.centre, (float2*)xhat);
             break;
         case 2:
-            if (attr((const void*)fft::row::k_pass1<L>) != hipSuccess) return hipErrorInvalidValue;
-            hipLaunchKernelGGL(fft::row::k_pass1<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lds, s, p,
+        {
+            if (attr((const void*)fft::row::k_pass1<L>, lp1) != hipSuccess) return hipErrorInvalidValue;
+            // the chunks are sized for pass 2's blocks per CU; pass 1 (one partial
+            // per observation) splits each chunk's observations further where
+            // more of its blocks fit a CU
+            static std::atomic<int> split{0};
+            int sp = split.load(std::memory_order_relaxed);
+            if (sp == 0) {
+                int b1 = 0, b2 = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, (const void*)fft::row::k_pass1<L>, 256, lp1) !=
+                        hipSuccess ||
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, (const void*)fft::row::k_pass2<L>, 256, lp2) !=
+                        hipSuccess)
+                    return hipErrorInvalidValue;
+                sp = (b1 > b2 && b2 > 0) ? (b1 + b2 - 1) / b2 : 1;
+                split.store(sp, std::memory_order_relaxed);
+            }
+            hipLaunchKernelGGL(fft::row::k_pass1<L>, dim3(p.n_chunks, p.n_cg * sp), dim3(256), lp1, s, p,
                                (const float2*)yhat, (const float2*)xhat);
             break;
+        }
         case 3:
-            if (attr((const void*)fft::row::k_pass2<L>) != hipSuccess) return hipErrorInvalidValue;
-            hipLaunchKernelGGL(fft::row::k_pass2<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lds, s, p,
+            if (attr((const void*)fft::row::k_pass2<L>, lp2) != hipSuccess) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(fft::row::k_pass2<L>, dim3(p.n_chunks, p.n_cg), dim3(256), lp2, s, p,
                                (const float2*)yhat, (const float2*)xhat, fft_tpc(L, p.KK), (float2*)bpart,
                                (float*)cpart);
             break;

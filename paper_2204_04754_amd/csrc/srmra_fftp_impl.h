@@ -438,23 +438,70 @@ __device__ __forceinline__ void pass2_quad_body(const StepArgs& p, const float2*
 }
 
 // ---- L_low = 3 * 2^m (12, 24, 48): teams of L lanes, one row (then column) of
-// an image per lane, 64 / L teams in each wave (a team never crosses a wave;
-// the lanes past the last team of a wave idle).  The layouts of Y and X, the
-// partials and the meaning of every sum are those of the power-of-two passes.
+// an image per lane (256 / L teams over the block, see row_wide).  The layouts
+// of Y and X, the partials and the meaning of every sum are those of the
+// power-of-two passes.
 namespace row {
 template <int L> struct G {
     static constexpr bool WIDE = row_wide(L);
     static constexpr int TEAMS = WIDE ? 256 / L : 4 * (64 / L);   // teams per 256-thread block
     static constexpr int BUF = L * (L + 1);     // float2 per team transpose buffer
+    // Pass 1 at L >= 24 transposes by halves (the real parts, then the
+    // imaginary parts, through L (L + 1) floats per team: two barriers more per
+    // transpose, half the LDS, so that more blocks share a CU: at L 48 two
+    // instead of one, at L 24 four instead of three).
+    static constexpr bool H1 = L >= 24;
+    static constexpr int PB1 = H1 ? (L * (L + 1) + 1) / 2 : BUF;   // float2 per team buffer, pass 1
 };
 // a team's exchange through its transpose buffer
 template <int L> __device__ __forceinline__ void sync() {
     if constexpr (G<L>::WIDE) __syncthreads();
     else team_sync();
 }
-// [transpose buffers TEAMS x BUF float2][twiddles L float2][masses TEAMS x L x L float]
-template <int L> constexpr size_t lds() {
-    return sizeof(float2) * ((size_t)G<L>::TEAMS * G<L>::BUF + L) + sizeof(float) * (size_t)G<L>::TEAMS * L * L;
+// preparation, DFT and pass 2: [transpose buffers TEAMS x BUF float2][twiddles L float2]
+template <int L> constexpr size_t lds() { return sizeof(float2) * ((size_t)G<L>::TEAMS * G<L>::BUF + L); }
+// pass 1: [transpose buffers TEAMS x PB1 float2][twiddles L float2]
+template <int L> constexpr size_t lds_pass1() { return sizeof(float2) * ((size_t)G<L>::TEAMS * G<L>::PB1 + L); }
+
+// the team's L x L complex image, one row or column v per lane, written at
+// wi(k) and read back at ri(m) of the team's buffer (every lane of the block
+// reaches the barriers; lanes with !on touch nothing)
+template <int L, bool H, typename WI, typename RI>
+__device__ __forceinline__ void exchange(float2 (&v)[L], float2* buf, WI wi, RI ri, bool on) {
+    if constexpr (H) {
+        float* b = reinterpret_cast<float*>(buf);
+        if (on) {
+#pragma unroll
+            for (int k = 0; k < L; ++k) b[wi(k)] = v[k].x;
+        }
+        sync<L>();
+        if (on) {
+#pragma unroll
+            for (int m = 0; m < L; ++m) v[m].x = b[ri(m)];
+        }
+        sync<L>();
+        if (on) {
+#pragma unroll
+            for (int k = 0; k < L; ++k) b[wi(k)] = v[k].y;
+        }
+        sync<L>();
+        if (on) {
+#pragma unroll
+            for (int m = 0; m < L; ++m) v[m].y = b[ri(m)];
+        }
+        sync<L>();
+    } else {
+        if (on) {
+#pragma unroll
+            for (int k = 0; k < L; ++k) buf[wi(k)] = v[k];
+        }
+        sync<L>();
+        if (on) {
+#pragma unroll
+            for (int m = 0; m < L; ++m) v[m] = buf[ri(m)];
+        }
+        sync<L>();
+    }
 }
 
 // lane -> (team, row r); on: the lane belongs to a team (lanes that do not
@@ -477,8 +524,8 @@ template <int L> __device__ __forceinline__ void team_of(int& team, int& r, bool
 // scores of (observation o, component c) for lane r: s[k] = a at (t1 = k, t2 = r).
 // Row r of Y_o conj(X_c) is inverse-transformed along k2, the team exchanges
 // rows for columns, and column r is inverse-transformed along k1.
-// Lanes with !on only reach the barriers (s = -inf).
-template <int L>
+// Lanes with !on only reach the barriers (s = -inf).  H: transpose by halves.
+template <int L, bool H>
 __device__ __forceinline__ void score(const StepArgs& p, const float2* __restrict__ yhat,
                                       const float2* __restrict__ xhat, int64_t o, int c, float2* buf, int r,
                                       const float2* tw, float (&s)[L], bool on = true) {
@@ -493,15 +540,9 @@ __device__ __forceinline__ void score(const StepArgs& p, const float2* __restric
             v[2 * m + 1] = cmulc(make_float2(a.z, a.w), make_float2(b.z, b.w));
         }
         fft1m<L, true>(v, tw);                                  // v[n2]: row k1 = r
-#pragma unroll
-        for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = v[k];
     }
-    sync<L>();
-    if (on) {
-#pragma unroll
-        for (int m = 0; m < L; ++m) v[m] = buf[m * (L + 1) + r];   // column n2 = r
-    }
-    sync<L>();
+    // row r out, column n2 = r in
+    exchange<L, H>(v, buf, [&](int k) { return r * (L + 1) + k; }, [&](int m) { return m * (L + 1) + r; }, on);
     if (on) {
         fft1m<L, true>(v, tw);                                  // v[k] = S[k][r]
         const float sc = p.inv_s2 / (float)(L * L);
@@ -520,13 +561,13 @@ template <int L>
 __device__ __forceinline__ void pass1_body(const StepArgs& p, const float2* __restrict__ yhat,
                                            const float2* __restrict__ xhat, int64_t chunk, int ysplit,
                                            int nsplit, float2* sh) {
-    float2* tw = sh + G<L>::TEAMS * G<L>::BUF;
+    float2* tw = sh + G<L>::TEAMS * G<L>::PB1;
     make_twiddles_n<L, L>(tw);
     __syncthreads();
     int team, r;
     bool on;
     team_of<L>(team, r, on);
-    float2* buf = sh + team * G<L>::BUF;
+    float2* buf = sh + team * G<L>::PB1;
     const int64_t c0 = chunk * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
     // the same trip count in every lane of the block (the teams' barriers)
@@ -537,7 +578,7 @@ __device__ __forceinline__ void pass1_body(const StepArgs& p, const float2* __re
         float m = -INFINITY, sm = 0.f;
         for (int c = 0; c < p.KK; ++c) {
             float s[L];
-            score<L>(p, yhat, xhat, oc, c, buf, r, tw, s, on);
+            score<L, G<L>::H1>(p, yhat, xhat, oc, c, buf, r, tw, s, on);
             float mc = -INFINITY;
 #pragma unroll
             for (int k = 0; k < L; ++k) mc = fmaxf(mc, s[k]);
@@ -567,26 +608,24 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const float2* __re
                                            const float2* __restrict__ xhat, int TPC, float2* __restrict__ bpart,
                                            float* __restrict__ cpart, int64_t chunk, int ysplit, float2* sh) {
     float2* tw = sh + G<L>::TEAMS * G<L>::BUF;
-    float* mass = reinterpret_cast<float*>(tw + L);              // [team][t1][t2]
     make_twiddles_n<L, L>(tw);
     int team, r;
     bool on;
     team_of<L>(team, r, on);
     float2* buf = sh + team * G<L>::BUF;
-    float* mt = mass + team * L * L;
     const int CG = G<L>::TEAMS / TPC;
     const int c = ysplit * CG + team / TPC, u = team % TPC;
     const bool active = on && team < CG * TPC && c < p.KK;
-    if (on) {
-#pragma unroll
-        for (int k = 0; k < L; ++k) mt[k * L + r] = 0.f;
-    }
     __syncthreads();
     const int64_t c0 = chunk * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
     float2 ab[L];   // sum of Y conj(W) at (k1 = r, k2 = k)
+    float acw[L];   // posterior mass at (t1 = k, t2 = r)
 #pragma unroll
-    for (int k = 0; k < L; ++k) ab[k] = make_float2(0.f, 0.f);
+    for (int k = 0; k < L; ++k) {
+        ab[k] = make_float2(0.f, 0.f);
+        acw[k] = 0.f;
+    }
     // the same trip count in every lane of the block (the teams' barriers);
     // inactive teams and observations past the chunk add nothing
     const int cc = active ? c : 0;
@@ -595,26 +634,18 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const float2* __re
         const bool act = active && o < c1;
         const int64_t oc = act ? o : c0;
         float s[L];
-        score<L>(p, yhat, xhat, oc, cc, buf, r, tw, s, on);
+        score<L, false>(p, yhat, xhat, oc, cc, buf, r, tw, s, on);
         const float2 lse = act ? p.lse[oc] : make_float2(0.f, 0.f);
         float2 v[L];
 #pragma unroll
         for (int k = 0; k < L; ++k) {
             const float w = (act && s[k] > -INFINITY) ? __expf((s[k] - lse.x) - lse.y) : 0.f;
-            if (act) mt[k * L + r] += w;                        // (t1 = k, t2 = r): the lane's own
+            acw[k] += w;
             v[k] = make_float2(w, 0.f);
         }
-        if (on) {
-            fft1m<L, false>(v, tw);                             // column t2 = r along t1: v[k1]
-#pragma unroll
-            for (int k = 0; k < L; ++k) buf[k * (L + 1) + r] = v[k];
-        }
-        sync<L>();
-        if (on) {
-#pragma unroll
-            for (int m = 0; m < L; ++m) v[m] = buf[r * (L + 1) + m];   // row k1 = r
-        }
-        sync<L>();
+        if (on) fft1m<L, false>(v, tw);                         // column t2 = r along t1: v[k1]
+        // column t2 = r out, row k1 = r in
+        exchange<L, false>(v, buf, [&](int k) { return k * (L + 1) + r; }, [&](int m) { return r * (L + 1) + m; }, on);
         if (act) {
             fft1m<L, false>(v, tw);                             // v[k] = W[r][k]
             const float4* yr = reinterpret_cast<const float4*>(yhat) + o * (L / 2) * L + r;
@@ -629,25 +660,44 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const float2* __re
         }
     }
     // the TPC teams of each component summed in a fixed order: each team's
-    // back-projection transform goes into its transpose buffer ([k1][k2], pitch
-    // L + 1), then the component's first team adds them up
+    // back-projection transform goes into its buffer ([k1][k2] at pitch L + 1),
+    // then its masses ([t1][t2]), and the component's first team adds the
+    // others' to its own, team by team
+    const bool lead = active && u == 0;
     __syncthreads();
     if (on) {
 #pragma unroll
         for (int k = 0; k < L; ++k) buf[r * (L + 1) + k] = ab[k];
     }
     __syncthreads();
-    if (active && u == 0) {
-        for (int k = 0; k < L; ++k) {
-            float2 t = make_float2(0.f, 0.f);
-            float cm = 0.f;
-            for (int j = 0; j < TPC; ++j) {
-                const float2 e = sh[(team + j) * G<L>::BUF + r * (L + 1) + k];
-                t.x += e.x; t.y += e.y;
-                cm += mass[(team + j) * L * L + k * L + r];
+    if (lead) {
+        for (int j = 1; j < TPC; ++j) {
+            const float2* o = sh + (team + j) * G<L>::BUF;
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const float2 e = o[r * (L + 1) + k];
+                ab[k].x += e.x;
+                ab[k].y += e.y;
             }
-            bpart[((chunk * p.KK + c) * L + r) * L + k] = t;       // [k1 = r][k2 = k]
-            cpart[((chunk * p.KK + c) * L + k) * L + r] = cm;      // [t1 = k][t2 = r]
+        }
+    }
+    __syncthreads();
+    if (on) {
+        float* bf = reinterpret_cast<float*>(buf);
+#pragma unroll
+        for (int k = 0; k < L; ++k) bf[k * L + r] = acw[k];
+    }
+    __syncthreads();
+    if (lead) {
+        for (int j = 1; j < TPC; ++j) {
+            const float* o = reinterpret_cast<const float*>(sh + (team + j) * G<L>::BUF);
+#pragma unroll
+            for (int k = 0; k < L; ++k) acw[k] += o[k * L + r];
+        }
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            bpart[((chunk * p.KK + c) * L + r) * L + k] = ab[k];      // [k1 = r][k2 = k]
+            cpart[((chunk * p.KK + c) * L + k) * L + r] = acw[k];     // [t1 = k][t2 = r]
         }
     }
 }
