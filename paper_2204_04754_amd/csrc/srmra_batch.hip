@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256, ((PASS == 1 && (FORM == FORM_BF16 || FORM == F
                                    (PASS == 2 && FORM == FORM_MFMA && LL >= 16 && LL <= 32) ||
                                    (PASS == 2 && FORM == FORM_FUSED && LL >= 16 && LL <= 24) ||
                                    ((FORM == FORM_BF16F || FORM == FORM_BF16X4F) && LL == 48) ||
-                                   (FORM == FORM_FFT && (LL == 12 || LL == 24 || (LL == 48 && PASS == 1)))) ? 2 : 1)
+                                   (FORM == FORM_FFT && (LL == 12 || LL == 24 || LL == 48))) ? 2 : 1)
 void k_class_pass(const InstDesc* __restrict__ D,
                                                     const int4* __restrict__ items, int n_items,
                                                     int* __restrict__ counter) {
@@ -221,6 +221,9 @@ void k_class_pass(const InstDesc* __restrict__ D,
                 else fft::pass2_quad_body(d.p, d.yhat, d.xhat, bpart, d.p.cpart, w.y, w.z, sh);
             } else if constexpr (LL % 3 == 0) {
                 if constexpr (PASS == 1) fft::row::pass1_body<LL>(d.p, d.yhat, d.xhat, w.y, w.z, d.p.n_cg, sh);
+                else if constexpr (LL == 48)
+                    fft::wpair::pass2_body<LL>(d.p, d.yhat, d.xhat, fft::tpc_of(LL, d.p.KK), bpart, d.p.cpart,
+                                               w.y, w.z, sh);
                 else fft::row::pass2_body<LL>(d.p, d.yhat, d.xhat, fft::tpc_of(LL, d.p.KK), bpart, d.p.cpart,
                                               w.y, w.z, sh);
             } else {

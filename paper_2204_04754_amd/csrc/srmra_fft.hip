@@ -87,9 +87,8 @@ __global__ __launch_bounds__(256) void k_prep_y(const float* __restrict__ y, int
     for (int k = 0; k < L; k += 2) d[(k / 2) * L] = make_float4(v[k].x, v[k].y, v[k + 1].x, v[k + 1].y);
 }
 
-// two waves per SIMD where the body fits 256 registers: pass 1 at every L,
-// pass 2 at L 12 and 24 (at L 48 a lane's image row, its back-projection sums,
-// its posterior masses and the scores take more)
+// two waves per SIMD (at most 256 registers per lane; pass 2 at L 48 runs
+// lane-pair teams, half a row per lane, to fit)
 template <int L>
 __global__ __launch_bounds__(256, 2) void k_pass1(StepArgs p, const float2* __restrict__ yhat,
                                                const float2* __restrict__ xhat) {
@@ -97,11 +96,12 @@ __global__ __launch_bounds__(256, 2) void k_pass1(StepArgs p, const float2* __re
     pass1_body<L>(p, yhat, xhat, blockIdx.x, blockIdx.y, gridDim.y, sh);
 }
 template <int L>
-__global__ __launch_bounds__(256, L <= 24 ? 2 : 1) void k_pass2(StepArgs p, const float2* __restrict__ yhat,
+__global__ __launch_bounds__(256, 2) void k_pass2(StepArgs p, const float2* __restrict__ yhat,
                                                const float2* __restrict__ xhat, int TPC,
                                                float2* __restrict__ bpart, float* __restrict__ cpart) {
     extern __shared__ float2 sh[];
-    pass2_body<L>(p, yhat, xhat, TPC, bpart, cpart, blockIdx.x, blockIdx.y, sh);
+    if constexpr (L == 48) wpair::pass2_body<L>(p, yhat, xhat, TPC, bpart, cpart, blockIdx.x, blockIdx.y, sh);
+    else pass2_body<L>(p, yhat, xhat, TPC, bpart, cpart, blockIdx.x, blockIdx.y, sh);
 }
 template <int L>
 __global__ __launch_bounds__(256) void k_dft2(const float* __restrict__ in, int64_t count,
@@ -176,7 +176,7 @@ size_t fft_lds(int LL, int pass) {   // dynamic LDS of pass 1 or 2
         case 64: return fft::quad::lds();
         case 12: return pass == 1 ? fft::row::lds_pass1<12>() : fft::row::lds<12>();
         case 24: return pass == 1 ? fft::row::lds_pass1<24>() : fft::row::lds<24>();
-        case 48: return pass == 1 ? fft::row::lds_pass1<48>() : fft::row::lds<48>();
+        case 48: return pass == 1 ? fft::row::lds_pass1<48>() : fft::wpair::lds<48>();
     }
     return 0;
 }
@@ -199,7 +199,8 @@ template <int L>
 static hipError_t fft_launch_row(int what, const StepArgs& p, const float* x, const float* y,
                                  void* yhat, void* xhat, void* bpart, void* cpart, hipStream_t s) {
     using G = fft::row::G<L>;
-    const size_t lds = fft::row::lds<L>(), lp1 = fft::row::lds_pass1<L>(), lp2 = lds;
+    const size_t lds = fft::row::lds<L>(), lp1 = fft::row::lds_pass1<L>();
+    const size_t lp2 = L == 48 ? fft::wpair::lds<L>() : lds;
     auto attr = [&](const void* f, size_t bytes) {
         return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     };
@@ -338,7 +339,7 @@ hipError_t launch_dft2(int L, const float* in, int64_t count, float2* out, hipSt
             hipLaunchKernelGGL(fft::k_dft2<64>, grid, dim3(256), lds, s, in, count, out);
             break;
         case 12: case 24: case 48: {
-            const int tm = fft::teams_of(L);
+            const int tm = L == 12 ? fft::row::G<12>::TEAMS : (L == 24 ? fft::row::G<24>::TEAMS : fft::row::G<48>::TEAMS);
             const dim3 g((unsigned)((count + tm - 1) / tm));
             const void* f = L == 12 ? (const void*)fft::row::k_dft2<12>
                                     : (L == 24 ? (const void*)fft::row::k_dft2<24> : (const void*)fft::row::k_dft2<48>);

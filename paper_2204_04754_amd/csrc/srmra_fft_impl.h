@@ -106,14 +106,15 @@ template <int L, int NTW> __device__ __forceinline__ void make_twiddles_n(float2
 }
 
 // In-register transform of v[0..L), L = 3 M with M a power of two (natural
-// order in and out), the twiddle table tw[j] = exp(-2 pi i j / L), j < L.
+// order in and out), the twiddle table tw[j] = exp(-2 pi i j / (S L)), j < S L
+// (every S-th entry is used: S = 2 for the half transforms of a lane pair).
 // With n = M n1 + n2 and k = k1 + 3 k2 (Cooley-Tukey with factors 3 and M):
 //   X[k1 + 3 k2] = sum_{n2} W_M^{n2 k2} W_L^{n2 k1} sum_{n1} x[M n1 + n2] W_3^{n1 k1}:
 // M three-point transforms, the twiddles W_L^{n2 k1}, then three length-M
 // transforms (whose twiddles W_M^j = W_L^{3 j} are every third table entry).
 // The three-point transform of (a, b, c): X0 = a + (b + c),
 // X1,2 = a - (b + c) / 2 -/+ i (sqrt(3) / 2) (b - c) (signs swapped for the inverse).
-template <int L, bool INV>
+template <int L, bool INV, int S = 1>
 __device__ __forceinline__ void fft1m(float2 (&v)[L], const float2* __restrict__ tw) {
     constexpr int M = L / 3;
     constexpr float S3 = 0.866025403784438646763723f;   // sqrt(3) / 2
@@ -127,13 +128,13 @@ __device__ __forceinline__ void fft1m(float2 (&v)[L], const float2* __restrict__
         // forward: -i S3 t2; inverse: +i S3 t2
         const float2 sr = INV ? make_float2(-S3 * t2.y, S3 * t2.x) : make_float2(S3 * t2.y, -S3 * t2.x);
         u[0][n2] = make_float2(a.x + t1.x, a.y + t1.y);
-        float2 w1 = tw[n2], w2 = tw[2 * n2];
+        float2 w1 = tw[S * n2], w2 = tw[S * 2 * n2];
         if (INV) { w1.y = -w1.y; w2.y = -w2.y; }
         u[1][n2] = n2 == 0 ? make_float2(m.x + sr.x, m.y + sr.y) : cmul(make_float2(m.x + sr.x, m.y + sr.y), w1);
         u[2][n2] = n2 == 0 ? make_float2(m.x - sr.x, m.y - sr.y) : cmul(make_float2(m.x - sr.x, m.y - sr.y), w2);
     }
 #pragma unroll
-    for (int k1 = 0; k1 < 3; ++k1) fft1t<M, INV, 3>(u[k1], tw);
+    for (int k1 = 0; k1 < 3; ++k1) fft1t<M, INV, 3 * S>(u[k1], tw);
 #pragma unroll
     for (int k1 = 0; k1 < 3; ++k1)
 #pragma unroll
@@ -147,40 +148,69 @@ __device__ __forceinline__ void fft1any(float2 (&v)[L], const float2* __restrict
     else fft1<L, INV>(v, tw);
 }
 
+// the half-length transform of a lane pair's samples: radix 2, or 3 x radix 2
+// (L / 2 = 24 at L 48), with every second entry of the length-L table
+template <int N, bool INV>
+__device__ __forceinline__ void fft_half(float2 (&v)[N], const float2* __restrict__ tw) {
+    if constexpr (N % 3 == 0) fft1m<N, INV, 2>(v, tw);
+    else fft1t<N, INV, 2>(v, tw);
+}
+
 __device__ __forceinline__ float2 shfl_pair(float2 a) {
     return make_float2(__shfl_xor(a.x, 1), __shfl_xor(a.y, 1));
 }
 
+// The pair table of a length-L transform: L / 2 ones, then W_L^k = exp(-2 pi i
+// k / L), k < L / 2; lane h of a pair reads it from entry (L / 2) h, so that
+// the butterflies below take no per-lane selects (lane 0 multiplies by one).
+template <int L> __device__ __forceinline__ void make_pair_twiddles(float2* twp) {
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        if (j < L / 2) {
+            twp[j] = make_float2(1.f, 0.f);
+        } else {
+            double s, c;
+            sincospi(-2.0 * (double)(j - L / 2) / (double)L, &s, &c);
+            twp[j] = make_float2((float)c, (float)s);
+        }
+    }
+}
+
 // A length-L transform held by the two lanes of a pair (h = lane & 1, L / 2
-// values each), tw the length-L table.
+// values each), tw the length-L table (its first half for a power-of-two L),
+// twh the lane's half of the pair table.
 // Decimation in time: v holds the samples x[2m + h]; on return v[k] = X[(L/2) h + k]
-// (X[k] = E[k] + W^k O[k], X[k + L/2] = E[k] - W^k O[k] from the two half transforms).
+// (X[k] = E[k] + W^k O[k], X[k + L/2] = E[k] - W^k O[k] from the two half
+// transforms: lane 1 forms W^k O[k], and each lane adds its partner's value to,
+// or subtracts its own from, the other's).
 template <int L, bool INV>
-__device__ __forceinline__ void fft_pair_dit(float2 (&v)[L / 2], int h, const float2* __restrict__ tw) {
-    fft1t<L / 2, INV, 2>(v, tw);
+__device__ __forceinline__ void fft_pair_dit(float2 (&v)[L / 2], int h, const float2* __restrict__ tw,
+                                             const float2* __restrict__ twh) {
+    fft_half<L / 2, INV>(v, tw);
+    const float sg = h ? -1.f : 1.f;
 #pragma unroll
     for (int k = 0; k < L / 2; ++k) {
-        const float2 q = shfl_pair(v[k]);
-        const float2 e = h ? q : v[k], o = h ? v[k] : q;
-        float2 w = tw[k];
+        float2 w = twh[k];
         if (INV) w.y = -w.y;
-        const float2 t = cmul(o, w);
-        v[k] = h ? make_float2(e.x - t.x, e.y - t.y) : make_float2(e.x + t.x, e.y + t.y);
+        const float2 t = cmul(v[k], w);                  // lane 0: E[k]; lane 1: W^k O[k]
+        const float2 q = shfl_pair(t);
+        v[k] = make_float2(q.x + sg * t.x, q.y + sg * t.y);
     }
 }
 // Decimation in frequency: v holds the half x[(L/2) h + m]; on return v[k] = X[2k + h]
 // (X[2k] from a + b, X[2k + 1] from (a - b) W^m, a and b the two halves).
 template <int L, bool INV>
-__device__ __forceinline__ void fft_pair_dif(float2 (&v)[L / 2], int h, const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft_pair_dif(float2 (&v)[L / 2], int h, const float2* __restrict__ tw,
+                                             const float2* __restrict__ twh) {
+    const float sg = h ? -1.f : 1.f;
 #pragma unroll
     for (int k = 0; k < L / 2; ++k) {
         const float2 q = shfl_pair(v[k]);
-        const float2 a = h ? q : v[k], b = h ? v[k] : q;
-        float2 w = tw[k];
+        float2 w = twh[k];
         if (INV) w.y = -w.y;
-        v[k] = h ? cmul(make_float2(a.x - b.x, a.y - b.y), w) : make_float2(a.x + b.x, a.y + b.y);
+        // lane 0: b + a; lane 1: (a - b) W^k
+        v[k] = cmul(make_float2(q.x + sg * v[k].x, q.y + sg * v[k].y), w);
     }
-    fft1t<L / 2, INV, 2>(v, tw);
+    fft_half<L / 2, INV>(v, tw);
 }
 
 // ---- four lanes per row (L = 64): lane q of a row holds a quarter of it.

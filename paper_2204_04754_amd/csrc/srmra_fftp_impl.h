@@ -27,9 +27,11 @@ namespace fft {
 // 64 / L teams inside each wave (wave barriers; a quarter of the lanes idle at
 // L 24 and 48)
 __host__ __device__ constexpr bool row_wide(int L) { return L % 3 == 0; }
-// teams of the two passes per 256-thread block: 2 L lanes each (L <= 32), one
-// team of four lanes per row (L 64), 256 / L teams of L lanes (L = 3 * 2^m)
+// teams of pass 2 per 256-thread block (pass 1's are its own): 2 L lanes each
+// (L <= 32, and L 48: lane pairs), one team of four lanes per row (L 64), 256 / L
+// teams of L lanes (L 12, 24)
 __host__ __device__ inline int teams_of(int L) {
+    if (L == 48) return 256 / (2 * L);
     if (L % 3 == 0) return row_wide(L) ? 256 / L : 4 * (64 / L);
     return L == 64 ? 1 : 256 / (2 * L);
 }
@@ -142,8 +144,9 @@ template <int L> struct GeoP {
     static constexpr int TEAMS = 256 / (2 * L);
     static constexpr int BUF = L * (L + 1);   // float2 per team buffer
 };
+// [team buffers TEAMS x BUF float2][twiddles L / 2][pair table L]
 template <int L> constexpr size_t lds_pairs() {
-    return sizeof(float2) * ((size_t)GeoP<L>::TEAMS * GeoP<L>::BUF + L / 2);
+    return sizeof(float2) * ((size_t)GeoP<L>::TEAMS * GeoP<L>::BUF + L / 2 + L);
 }
 
 // Scores of (observation o, component c) for pair (r, h): s[k] = a at
@@ -153,20 +156,21 @@ template <int L> constexpr size_t lds_pairs() {
 template <int L>
 __device__ __forceinline__ void score_pair(const StepArgs& p, const float2* __restrict__ yhat,
                                            const float2* __restrict__ xhat, int64_t o, int c,
-                                           float2* buf, int r, int h, const float2* tw, float (&s)[L / 2]) {
+                                           float2* buf, int r, int h, const float2* tw, const float2* twh,
+                                           float (&s)[L / 2]) {
     float2 v[L / 2];
     const float2* yr = yhat + ((int64_t)o * (L / 2) * L + r) * 2 + h;   // Y_o[r][2m + h] at yr[2 L m]
     const float2* xr = xhat + ((int64_t)c * (L / 2) * L + r) * 2 + h;
 #pragma unroll
     for (int m = 0; m < L / 2; ++m) v[m] = cmulc(yr[2 * L * m], xr[2 * L * m]);
-    fft_pair_dit<L, true>(v, h, tw);                       // v[k] = row r, n2 = (L/2) h + k
+    fft_pair_dit<L, true>(v, h, tw, twh);                  // v[k] = row r, n2 = (L/2) h + k
 #pragma unroll
     for (int k = 0; k < L / 2; ++k) buf[r * (L + 1) + (L / 2) * h + k] = v[k];
     team_sync();
 #pragma unroll
     for (int m = 0; m < L / 2; ++m) v[m] = buf[(2 * m + h) * (L + 1) + r];   // column r, rows 2m + h
     team_sync();
-    fft_pair_dit<L, true>(v, h, tw);                       // v[k] = S[(L/2) h + k][r]
+    fft_pair_dit<L, true>(v, h, tw, twh);                  // v[k] = S[(L/2) h + k][r]
     const float sc = p.inv_s2 / (float)(L * L);
     const float* bet = p.betaT + (int64_t)c * (L * L) + r * L + (L / 2) * h;   // betaT[c][t2 = r][t1]
 #pragma unroll
@@ -189,10 +193,13 @@ __device__ __forceinline__ void pass1_pairs_body(const StepArgs& p, const float2
                                                  const float2* __restrict__ xhat, int64_t chunk, int ysplit,
                                                  int nsplit, float2* sh) {
     float2* tw = sh + GeoP<L>::TEAMS * GeoP<L>::BUF;
+    float2* twp = tw + L / 2;
     make_twiddles<L>(tw);
+    make_pair_twiddles<L>(twp);
     __syncthreads();
     const int team = threadIdx.x / (2 * L), lt = threadIdx.x % (2 * L);
     const int r = lt >> 1, h = lt & 1;
+    const float2* twh = twp + (L / 2) * h;
     float2* buf = sh + team * GeoP<L>::BUF;
     const int64_t c0 = chunk * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
@@ -201,7 +208,7 @@ __device__ __forceinline__ void pass1_pairs_body(const StepArgs& p, const float2
         float m = -INFINITY, sm = 0.f;
         for (int c = 0; c < p.KK; ++c) {
             float s[L / 2];
-            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, s);
+            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, twh, s);
             float mc = -INFINITY;
 #pragma unroll
             for (int k = 0; k < L / 2; ++k) mc = fmaxf(mc, s[k]);
@@ -231,10 +238,13 @@ __device__ __forceinline__ void pass2_pairs_body(const StepArgs& p, const float2
                                                  float2* __restrict__ bpart, float* __restrict__ cpart,
                                                  int64_t chunk, int ysplit, float2* sh) {
     float2* tw = sh + GeoP<L>::TEAMS * GeoP<L>::BUF;
+    float2* twp = tw + L / 2;
     make_twiddles<L>(tw);
+    make_pair_twiddles<L>(twp);
     __syncthreads();
     const int team = threadIdx.x / (2 * L), lt = threadIdx.x % (2 * L);
     const int r = lt >> 1, h = lt & 1;
+    const float2* twh = twp + (L / 2) * h;
     float2* buf = sh + team * GeoP<L>::BUF;
     const int CG = GeoP<L>::TEAMS / TPC;
     const int c = ysplit * CG + team / TPC, u = team % TPC;
@@ -248,7 +258,7 @@ __device__ __forceinline__ void pass2_pairs_body(const StepArgs& p, const float2
     if (active) {
         for (int64_t o = c0 + u; o < c1; o += TPC) {
             float s[L / 2];
-            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, s);
+            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, twh, s);
             const float2 lse = p.lse[o];
             float2 v[L / 2];
 #pragma unroll
@@ -258,14 +268,14 @@ __device__ __forceinline__ void pass2_pairs_body(const StepArgs& p, const float2
                 v[k] = make_float2(w, 0.f);
             }
             // column t2 = r (its half (L/2) h..), transformed along t1, then the rows
-            fft_pair_dif<L, false>(v, h, tw);                    // v[k] = k1 = 2k + h, column r
+            fft_pair_dif<L, false>(v, h, tw, twh);               // v[k] = k1 = 2k + h, column r
 #pragma unroll
             for (int k = 0; k < L / 2; ++k) buf[(2 * k + h) * (L + 1) + r] = v[k];
             team_sync();
 #pragma unroll
             for (int m = 0; m < L / 2; ++m) v[m] = buf[r * (L + 1) + 2 * m + h];   // row k1 = r, n2 = 2m + h
             team_sync();
-            fft_pair_dit<L, false>(v, h, tw);                    // v[k] = W[r][(L/2) h + k]
+            fft_pair_dit<L, false>(v, h, tw, twh);               // v[k] = W[r][(L/2) h + k]
             // Y_o[r][(L/2) h + k], k and k + 1 in one 16-byte word of the paired layout
             const float4* yr = reinterpret_cast<const float4*>(yhat) + ((int64_t)o * (L / 2) + (L / 4) * h) * L + r;
 #pragma unroll
@@ -703,6 +713,143 @@ __device__ __forceinline__ void pass2_body(const StepArgs& p, const float2* __re
 }
 
 }  // namespace row
+
+// ---- pass 2 at L_low 48 with lane-pair teams: lane pair (r, h) holds half of
+// row (then column) r, as in the power-of-two pair teams, so a lane keeps 24
+// complex values, 24 complex sums of Y conj(W) and 24 posterior masses instead
+// of the row teams' 48 of each, and more waves fit a SIMD.  A team of 2 L = 96
+// lanes spans waves (its transposes wait on the block barrier, every lane runs
+// the same loop trips); two teams per 256-thread block, the last wave idles.
+// Partials and sums as in the pair teams' pass 2.
+namespace wpair {
+template <int L> struct G {
+    static constexpr int TEAMS = 256 / (2 * L);
+    static constexpr int BUF = L * (L + 1);   // float2 per team transpose buffer
+};
+// [transpose buffers TEAMS x BUF float2][twiddles L float2][pair table L float2]
+// [X_c of each team's component, TEAMS x L x L float2, the paired layout]
+template <int L> constexpr size_t lds() {
+    return sizeof(float2) * ((size_t)G<L>::TEAMS * G<L>::BUF + 2 * L + (size_t)G<L>::TEAMS * L * L);
+}
+
+template <int L>
+__device__ __forceinline__ void pass2_body(const StepArgs& p, const float2* __restrict__ yhat,
+                                           const float2* __restrict__ xhat, int TPC, float2* __restrict__ bpart,
+                                           float* __restrict__ cpart, int64_t chunk, int ysplit, float2* sh) {
+    float2* tw = sh + G<L>::TEAMS * G<L>::BUF;
+    float2* twp = tw + L;
+    make_twiddles_n<L, L>(tw);
+    make_pair_twiddles<L>(twp);
+    const int t = threadIdx.x;
+    const bool on = t < G<L>::TEAMS * 2 * L;   // lanes of a team (pairs never straddle it)
+    const int team = on ? t / (2 * L) : 0, lt = t % (2 * L);
+    const int r = lt >> 1, h = lt & 1;
+    const float2* twh = twp + (L / 2) * h;
+    float2* buf = sh + team * G<L>::BUF;
+    float2* xs = twp + L + team * (L * L);   // the team's X_c
+    const int CG = G<L>::TEAMS / TPC;
+    const int c = ysplit * CG + team / TPC, u = team % TPC;
+    const bool active = on && team < CG * TPC && c < p.KK;
+    const int cc = active ? c : 0;
+    if (on) {
+        const float4* src = reinterpret_cast<const float4*>(xhat + (int64_t)cc * L * L);
+        float4* dst = reinterpret_cast<float4*>(xs);
+        for (int e = lt; e < L * L / 2; e += 2 * L) dst[e] = src[e];
+    }
+    __syncthreads();
+    const int64_t c0 = chunk * p.chunk_obs;
+    const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
+    float2 ab[L / 2];   // sum of Y conj(W) at (k1 = r, k2 = (L/2) h + k)
+    float acw[L / 2];   // posterior mass at (t1 = (L/2) h + k, t2 = r)
+#pragma unroll
+    for (int k = 0; k < L / 2; ++k) {
+        ab[k] = make_float2(0.f, 0.f);
+        acw[k] = 0.f;
+    }
+    // the same trip count in every lane of the block (the teams' barriers);
+    // inactive teams and observations past the chunk add nothing
+    for (int64_t base = c0; base < c1; base += TPC) {
+        const int64_t o = base + u;
+        const bool act = active && o < c1;
+        const int64_t oc = act ? o : c0;
+        float2 v[L / 2];
+        if (on) {
+            // row r of Y_o conj(X_c) as its samples 2m + h, inverse-transformed
+            const float2* yr = yhat + (oc * (L / 2) * L + r) * 2 + h;   // Y_o[r][2m + h] at yr[2 L m]
+            const float2* xr = xs + r * 2 + h;
+#pragma unroll
+            for (int m = 0; m < L / 2; ++m) v[m] = cmulc(yr[2 * L * m], xr[2 * L * m]);
+            fft_pair_dit<L, true>(v, h, tw, twh);                     // v[k] = row r, n2 = (L/2) h + k
+#pragma unroll
+            for (int k = 0; k < L / 2; ++k) buf[r * (L + 1) + (L / 2) * h + k] = v[k];
+        }
+        __syncthreads();
+        if (on) {
+#pragma unroll
+            for (int m = 0; m < L / 2; ++m) v[m] = buf[(2 * m + h) * (L + 1) + r];   // column r, rows 2m + h
+        }
+        __syncthreads();
+        if (on) {
+            fft_pair_dit<L, true>(v, h, tw, twh);                     // v[k] = S[(L/2) h + k][r]
+            const float sc = p.inv_s2 / (float)(L * L);
+            const float* bet = p.betaT + (int64_t)cc * (L * L) + r * L + (L / 2) * h;   // betaT[c][t2 = r][t1]
+            const float2 lse = act ? p.lse[oc] : make_float2(0.f, 0.f);
+#pragma unroll
+            for (int k = 0; k < L / 2; ++k) {
+                const float a = v[k].x * sc + bet[k];
+                const float w = (act && a > -INFINITY) ? __expf((a - lse.x) - lse.y) : 0.f;
+                acw[k] += w;
+                v[k] = make_float2(w, 0.f);
+            }
+            // column t2 = r (its half (L/2) h..), transformed along t1, then the rows
+            fft_pair_dif<L, false>(v, h, tw, twh);                    // v[k] = k1 = 2k + h, column r
+#pragma unroll
+            for (int k = 0; k < L / 2; ++k) buf[(2 * k + h) * (L + 1) + r] = v[k];
+        }
+        __syncthreads();
+        if (on) {
+#pragma unroll
+            for (int m = 0; m < L / 2; ++m) v[m] = buf[r * (L + 1) + 2 * m + h];   // row k1 = r, n2 = 2m + h
+        }
+        __syncthreads();
+        if (act) {
+            fft_pair_dit<L, false>(v, h, tw, twh);                    // v[k] = W[r][(L/2) h + k]
+            // Y_o[r][(L/2) h + k], k and k + 1 in one 16-byte word of the paired layout
+            const float4* yr = reinterpret_cast<const float4*>(yhat) + (o * (L / 2) + (L / 4) * h) * L + r;
+#pragma unroll
+            for (int k = 0; k < L / 2; k += 2) {
+                const float4 a = yr[(k / 2) * L];
+                const float2 t0 = cmulc(make_float2(a.x, a.y), v[k]);
+                const float2 t1 = cmulc(make_float2(a.z, a.w), v[k + 1]);
+                ab[k].x += t0.x; ab[k].y += t0.y;
+                ab[k + 1].x += t1.x; ab[k + 1].y += t1.y;
+            }
+        }
+    }
+    // sum the TPC teams of each component in a fixed order, one plane at a time
+    // (each lane keeps its own L/2 slots of the team buffer)
+    for (int plane = 0; plane < 2; ++plane) {
+        __syncthreads();
+        if (on) {
+#pragma unroll
+            for (int k = 0; k < L / 2; ++k)
+                buf[lt * (L / 2) + k] = plane == 0 ? ab[k] : make_float2(acw[k], 0.f);
+        }
+        __syncthreads();
+        if (active && u == 0) {
+            for (int k = 0; k < L / 2; ++k) {
+                float2 e = buf[lt * (L / 2) + k];
+                for (int j = 1; j < TPC; ++j) {
+                    const float2 f = sh[(team + j) * G<L>::BUF + lt * (L / 2) + k];
+                    e.x += f.x; e.y += f.y;
+                }
+                if (plane == 0) bpart[((chunk * p.KK + c) * L + r) * L + (L / 2) * h + k] = e;   // [k1][k2]
+                else cpart[((chunk * p.KK + c) * L + (L / 2) * h + k) * L + r] = e.x;            // [t1][t2]
+            }
+        }
+    }
+}
+}  // namespace wpair
 
 // ---- FP64 sums of the partials over chunks: the back-projection's transform
 // [KK][L][L] complex, the posterior mass [KK][t1][t2] real (final)
