@@ -56,6 +56,7 @@ bool fft_supported(int LL);
 int fft_tpc(int LL, int KK);
 int fft_teams(int LL);
 size_t fft_lds(int LL, int pass);
+size_t fft_lds_class(int LL, int pass);
 const void* fft_pass2_fn(int LL);
 hipError_t launch_fft(int LL, int what, const StepArgs& p, const float* x, const float* y,
                       void* yhat, void* xhat, void* bpart, void* cpart, void* bh,
@@ -796,7 +797,7 @@ int srmra_plan_create_tuned(const srmra_problem* probs, int count, int precision
         }
         ClassLaunch& C = P->classes[cls];
         C.lds1 = std::max(C.lds1, g.lds1);
-        C.lds2 = std::max(C.lds2, g.lds2);
+        C.lds2 = std::max(C.lds2, f == FORM_FFT ? fft_lds_class(pr.L_low, 2) : g.lds2);
         // one-component items are listed component-major, so that the blocks
         // running at one time share few components' B fragments in L2
         const bool comp_major = g.cpb == 1 && is_bf16_form(f);

@@ -228,8 +228,8 @@ void k_class_pass(const InstDesc* __restrict__ D,
                                               w.y, w.z, sh);
             } else {
                 if constexpr (PASS == 1) fft::pass1_pairs_body<LL>(d.p, d.yhat, d.xhat, w.y, w.z, d.p.n_cg, sh);
-                else fft::pass2_pairs_body<LL>(d.p, d.yhat, d.xhat, fft::tpc_of(LL, d.p.KK), bpart, d.p.cpart,
-                                               w.y, w.z, sh);
+                else fft::pass2_pairs_body<LL, LL == 32>(d.p, d.yhat, d.xhat, fft::tpc_of(LL, d.p.KK), bpart,
+                                                          d.p.cpart, w.y, w.z, sh);
             }
         } else if constexpr (FORM == FORM_FUSED) {
             mfma_fused_body<LL>(d.p, w.y, lds);

@@ -181,6 +181,9 @@ size_t fft_lds(int LL, int pass) {   // dynamic LDS of pass 1 or 2
     return 0;
 }
 
+// the same in the batched class launches (pass 2 at L 32 stages X_c in LDS)
+size_t fft_lds_class(int LL, int pass) { return pass == 2 && LL == 32 ? fft::lds_pairs_xs<32>() : fft_lds(LL, pass); }
+
 const void* fft_pass2_fn(int LL) {
     switch (LL) {
         case 8: return (const void*)fft::k_fft_pass2<8>;

@@ -148,6 +148,11 @@ template <int L> struct GeoP {
 template <int L> constexpr size_t lds_pairs() {
     return sizeof(float2) * ((size_t)GeoP<L>::TEAMS * GeoP<L>::BUF + L / 2 + L);
 }
+// pass 2 with X_c staged: [X_c of each team's component, TEAMS x L x L float2,
+// the paired layout] after the above
+template <int L> constexpr size_t lds_pairs_xs() {
+    return lds_pairs<L>() + sizeof(float2) * (size_t)GeoP<L>::TEAMS * L * L;
+}
 
 // Scores of (observation o, component c) for pair (r, h): s[k] = a at
 // (t1 = (L/2) h + k, t2 = r).  Row r of Y_o conj(X_c) enters as its samples
@@ -155,12 +160,12 @@ template <int L> constexpr size_t lds_pairs() {
 // layouts.
 template <int L>
 __device__ __forceinline__ void score_pair(const StepArgs& p, const float2* __restrict__ yhat,
-                                           const float2* __restrict__ xhat, int64_t o, int c,
+                                           const float2* xc, int64_t o, int c,
                                            float2* buf, int r, int h, const float2* tw, const float2* twh,
                                            float (&s)[L / 2]) {
     float2 v[L / 2];
     const float2* yr = yhat + ((int64_t)o * (L / 2) * L + r) * 2 + h;   // Y_o[r][2m + h] at yr[2 L m]
-    const float2* xr = xhat + ((int64_t)c * (L / 2) * L + r) * 2 + h;
+    const float2* xr = xc + r * 2 + h;                                   // X_c (xc: its L x L values)
 #pragma unroll
     for (int m = 0; m < L / 2; ++m) v[m] = cmulc(yr[2 * L * m], xr[2 * L * m]);
     fft_pair_dit<L, true>(v, h, tw, twh);                  // v[k] = row r, n2 = (L/2) h + k
@@ -208,7 +213,7 @@ __device__ __forceinline__ void pass1_pairs_body(const StepArgs& p, const float2
         float m = -INFINITY, sm = 0.f;
         for (int c = 0; c < p.KK; ++c) {
             float s[L / 2];
-            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, twh, s);
+            score_pair<L>(p, yhat, xhat + (int64_t)c * L * L, o, c, buf, r, h, tw, twh, s);
             float mc = -INFINITY;
 #pragma unroll
             for (int k = 0; k < L / 2; ++k) mc = fmaxf(mc, s[k]);
@@ -231,8 +236,11 @@ __device__ __forceinline__ void pass1_pairs_body(const StepArgs& p, const float2
 // ---- pass 2: per component group, the sums over the chunk.  Component group
 // g holds CG components, TPC = TEAMS / CG teams each (observations split over
 // them); partials [chunk][c][k1][k2] of sum_i Y_i conj(W_i) (bpart, float2)
-// and [chunk][c][t1][t2] of sum_i w_i (cpart, float).
-template <int L>
+// and [chunk][c][t1][t2] of sum_i w_i (cpart, float).  XS: each team reads
+// its component's X_c from a copy in LDS (lds_pairs_xs) instead of global
+// memory (faster in the batched launches at L 32, whose items are short; the
+// single-problem launch, LDS-bound on its transposes there, reads it from L2).
+template <int L, bool XS = false>
 __device__ __forceinline__ void pass2_pairs_body(const StepArgs& p, const float2* __restrict__ yhat,
                                                  const float2* __restrict__ xhat, int TPC,
                                                  float2* __restrict__ bpart, float* __restrict__ cpart,
@@ -246,9 +254,17 @@ __device__ __forceinline__ void pass2_pairs_body(const StepArgs& p, const float2
     const int r = lt >> 1, h = lt & 1;
     const float2* twh = twp + (L / 2) * h;
     float2* buf = sh + team * GeoP<L>::BUF;
+    float2* xs = twp + L + team * (L * L);   // the team's X_c (XS)
     const int CG = GeoP<L>::TEAMS / TPC;
     const int c = ysplit * CG + team / TPC, u = team % TPC;
     const bool active = c < p.KK;
+    if (XS && active) {
+        const float4* src = reinterpret_cast<const float4*>(xhat + (int64_t)c * L * L);
+        float4* dst = reinterpret_cast<float4*>(xs);
+        for (int e = lt; e < L * L / 2; e += 2 * L) dst[e] = src[e];
+    }
+    __syncthreads();
+    const float2* xcs = XS ? xs : xhat + (int64_t)(active ? c : 0) * L * L;
     const int64_t c0 = chunk * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
     float2 ab[L / 2];   // sum of Y conj(W) at (k1 = r, k2 = (L/2) h + k)
@@ -258,7 +274,7 @@ __device__ __forceinline__ void pass2_pairs_body(const StepArgs& p, const float2
     if (active) {
         for (int64_t o = c0 + u; o < c1; o += TPC) {
             float s[L / 2];
-            score_pair<L>(p, yhat, xhat, o, c, buf, r, h, tw, twh, s);
+            score_pair<L>(p, yhat, xcs, o, c, buf, r, h, tw, twh, s);
             const float2 lse = p.lse[o];
             float2 v[L / 2];
 #pragma unroll
