@@ -197,6 +197,23 @@ const void* fft_pass2_fn(int LL) {
     return nullptr;
 }
 
+// Pass-1 blocks per chunk and component group: the chunks are sized for pass
+// 2's blocks per CU, and pass 1 (one partial per observation) splits each
+// chunk's observations over that many more blocks where more of its own fit a
+// CU (cache: per kernel pair, filled on first use; 0 if the query fails).
+static int pass1_split(const void* f1, size_t lds1, const void* f2, size_t lds2, std::atomic<int>& cache) {
+    int sp = cache.load(std::memory_order_relaxed);
+    if (sp == 0) {
+        int b1 = 0, b2 = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, f1, 256, lds1) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, f2, 256, lds2) != hipSuccess)
+            return 0;
+        sp = (b1 > b2 && b2 > 0) ? (b1 + b2 - 1) / b2 : 1;
+        cache.store(sp, std::memory_order_relaxed);
+    }
+    return sp;
+}
+
 // the passes at L_low = 3 * 2^m (what: 0 prepare Y, 1 X, 2 pass 1, 3 pass 2, 4 reduce)
 template <int L>
 static hipError_t fft_launch_row(int what, const StepArgs& p, const float* x, const float* y,
@@ -223,21 +240,10 @@ static hipError_t fft_launch_row(int what, const StepArgs& p, const float* x, co
         case 2:
         {
             if (attr((const void*)fft::row::k_pass1<L>, lp1) != hipSuccess) return hipErrorInvalidValue;
-            // the chunks are sized for pass 2's blocks per CU; pass 1 (one partial
-            // per observation) splits each chunk's observations further where
-            // more of its blocks fit a CU
             static std::atomic<int> split{0};
-            int sp = split.load(std::memory_order_relaxed);
-            if (sp == 0) {
-                int b1 = 0, b2 = 0;
-                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, (const void*)fft::row::k_pass1<L>, 256, lp1) !=
-                        hipSuccess ||
-                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, (const void*)fft::row::k_pass2<L>, 256, lp2) !=
-                        hipSuccess)
-                    return hipErrorInvalidValue;
-                sp = (b1 > b2 && b2 > 0) ? (b1 + b2 - 1) / b2 : 1;
-                split.store(sp, std::memory_order_relaxed);
-            }
+            const int sp = pass1_split((const void*)fft::row::k_pass1<L>, lp1, (const void*)fft::row::k_pass2<L>,
+                                       lp2, split);
+            if (sp == 0) return hipErrorInvalidValue;
             hipLaunchKernelGGL(fft::row::k_pass1<L>, dim3(p.n_chunks, p.n_cg * sp), dim3(256), lp1, s, p,
                                (const float2*)yhat, (const float2*)xhat);
             break;
@@ -291,8 +297,12 @@ static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, con
                 break;
             case 2: {
                 auto f = L == 64 ? fft::k_fft_pass1_q : fft::k_fft_pass1<L == 64 ? 32 : L>;
+                auto f2 = L == 64 ? fft::k_fft_pass2_q : fft::k_fft_pass2<L == 64 ? 32 : L>;
                 (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
-                hipLaunchKernelGGL(f, dim3(p.n_chunks, p.n_cg), dim3(256), lp, s, p, (const float2*)yhat,
+                static std::atomic<int> split{0};
+                const int sp = pass1_split((const void*)f, lp, (const void*)f2, lp, split);
+                if (sp == 0) return hipErrorInvalidValue;
+                hipLaunchKernelGGL(f, dim3(p.n_chunks, p.n_cg * sp), dim3(256), lp, s, p, (const float2*)yhat,
                                    (const float2*)xhat);
                 break;
             }
