@@ -39,7 +39,8 @@ __global__ __launch_bounds__(256) void k_fft_pass2(StepArgs p, const float2* __r
     extern __shared__ float2 sh[];
     pass2_pairs_body<L>(p, yhat, xhat, TPC, bpart, cpart, blockIdx.x, blockIdx.y, sh);
 }
-__global__ __launch_bounds__(256) void k_fft_pass1_q(StepArgs p, const float2* __restrict__ yhat,
+// four blocks per CU (at most 128 registers per lane; its LDS, 33 KB, allows them)
+__global__ __launch_bounds__(256, 4) void k_fft_pass1_q(StepArgs p, const float2* __restrict__ yhat,
                                                      const float2* __restrict__ xhat) {
     extern __shared__ float2 sh[];
     pass1_quad_body(p, yhat, xhat, blockIdx.x, blockIdx.y, gridDim.y, sh);
@@ -173,7 +174,7 @@ size_t fft_lds(int LL, int pass) {   // dynamic LDS of pass 1 or 2
         case 8: return fft::lds_pairs<8>();
         case 16: return fft::lds_pairs<16>();
         case 32: return fft::lds_pairs<32>();
-        case 64: return fft::quad::lds();
+        case 64: return pass == 1 ? fft::quad::lds1() : fft::quad::lds();
         case 12: return pass == 1 ? fft::row::lds_pass1<12>() : fft::row::lds<12>();
         case 24: return pass == 1 ? fft::row::lds_pass1<24>() : fft::row::lds<24>();
         case 48: return pass == 1 ? fft::row::lds_pass1<48>() : fft::wpair::lds<48>();
@@ -282,6 +283,7 @@ static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, con
     } else {
         const size_t lds = fft::lds_bytes<L>();      // preparation and X: one lane per row
         const size_t lp = L == 64 ? fft::quad::lds() : fft::lds_pairs<L>();   // the passes
+        const size_t lp1 = L == 64 ? fft::quad::lds1() : lp;                    // pass 1
         const int teams = 256 / L;
         switch (what) {
             case 0:   // prepare Y
@@ -298,11 +300,11 @@ static hipError_t fft_launch_ll(int what, const StepArgs& p, const float* x, con
             case 2: {
                 auto f = L == 64 ? fft::k_fft_pass1_q : fft::k_fft_pass1<L == 64 ? 32 : L>;
                 auto f2 = L == 64 ? fft::k_fft_pass2_q : fft::k_fft_pass2<L == 64 ? 32 : L>;
-                (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp);
+                (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lp1);
                 static std::atomic<int> split{0};
-                const int sp = pass1_split((const void*)f, lp, (const void*)f2, lp, split);
+                const int sp = pass1_split((const void*)f, lp1, (const void*)f2, lp, split);
                 if (sp == 0) return hipErrorInvalidValue;
-                hipLaunchKernelGGL(f, dim3(p.n_chunks, p.n_cg * sp), dim3(256), lp, s, p, (const float2*)yhat,
+                hipLaunchKernelGGL(f, dim3(p.n_chunks, p.n_cg * sp), dim3(256), lp1, s, p, (const float2*)yhat,
                                    (const float2*)xhat);
                 break;
             }

@@ -336,8 +336,12 @@ __device__ __forceinline__ void pass2_pairs_body(const StepArgs& p, const float2
 namespace quad {
 constexpr int L = 64, NV = L / 4;
 constexpr int BUF = L * (L + 1);
-// two transpose buffers, the twiddles (L / 2) and one (max, sum) slot per wave
+// pass 2: two transpose buffers, the twiddles (L / 2) and one (max, sum) slot per wave
 constexpr size_t lds() { return sizeof(float2) * (2 * (size_t)BUF + L / 2 + 4); }
+// pass 1: a score's transpose moves the real parts through one buffer of L (L + 1)
+// floats and the imaginary parts through another (two barriers per transpose,
+// half the LDS, twice the blocks per CU); then the twiddles and the slots
+constexpr size_t lds1() { return sizeof(float) * 2 * (size_t)BUF + sizeof(float2) * (L / 2 + 4); }
 
 // scores of (observation o, component c) for lane (r, q): s[k] = a at
 // (t1 = 16 quad_block(q) + k, t2 = r)
@@ -362,6 +366,35 @@ __device__ __forceinline__ void score(const StepArgs& p, const float2* __restric
 #pragma unroll
     for (int k = 0; k < NV; ++k) s[k] = v[k].x * sc + bet[k];
 }
+
+// the same scores with the transpose by halves through the float buffers bre, bim
+__device__ __forceinline__ void score_h(const StepArgs& p, const float2* __restrict__ yhat,
+                                        const float2* __restrict__ xhat, int64_t o, int c, float* bre,
+                                        float* bim, int r, int q, int bq, const float2* tw, float (&s)[NV]) {
+    float2 v[NV];
+    const float2* yr = yhat + (((int64_t)o * (L / 2) + (q >> 1)) * L + r) * 2 + (q & 1);
+    const float2* xr = xhat + (((int64_t)c * (L / 2) + (q >> 1)) * L + r) * 2 + (q & 1);
+#pragma unroll
+    for (int m = 0; m < NV; ++m) v[m] = cmulc(yr[4 * L * m], xr[4 * L * m]);
+    fft_quad_dit<L, true>(v, q, tw);                       // v[k] = row r, n2 = 16 bq + k
+    // a thread writes a buffer only after the barrier that follows every
+    // thread's reads of it in the previous score
+#pragma unroll
+    for (int k = 0; k < NV; ++k) bre[r * (L + 1) + 16 * bq + k] = v[k].x;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NV; ++m) v[m].x = bre[(4 * m + q) * (L + 1) + r];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) bim[r * (L + 1) + 16 * bq + k] = v[k].y;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NV; ++m) v[m].y = bim[(4 * m + q) * (L + 1) + r];   // column r, rows 4m + q
+    fft_quad_dit<L, true>(v, q, tw);                       // v[k] = S[16 bq + k][r]
+    const float sc = p.inv_s2 / (float)(L * L);
+    const float* bet = p.betaT + (int64_t)c * (L * L) + r * L + 16 * bq;   // betaT[c][t2 = r][t1]
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s[k] = v[k].x * sc + bet[k];
+}
 }  // namespace quad
 
 // pass 1 at L_low 64: block (chunk, y) takes the chunk's observations y,
@@ -370,20 +403,20 @@ __device__ __forceinline__ void pass1_quad_body(const StepArgs& p, const float2*
                                                 const float2* __restrict__ xhat, int64_t chunk, int ysplit,
                                                 int nsplit, float2* sh) {
     using namespace quad;
-    float2* tw = sh + 2 * BUF;
+    float* bre = reinterpret_cast<float*>(sh);
+    float* bim = bre + BUF;
+    float2* tw = reinterpret_cast<float2*>(bim + BUF);
     float2* red = tw + L / 2;
     make_twiddles<L>(tw);
     __syncthreads();
     const int lt = threadIdx.x, r = lt >> 2, q = lt & 3, bq = quad_block(q);
     const int64_t c0 = chunk * p.chunk_obs;
     const int64_t c1 = min<int64_t>(p.N, c0 + p.chunk_obs);
-    int flip = 0;   // the transpose buffer of the next score
     for (int64_t o = c0 + ysplit; o < c1; o += nsplit) {
         float m = -INFINITY, sm = 0.f;
         for (int c = 0; c < p.KK; ++c) {
             float s[NV];
-            score(p, yhat, xhat, o, c, sh + flip * BUF, r, q, bq, tw, s);
-            flip ^= 1;
+            score_h(p, yhat, xhat, o, c, bre, bim, r, q, bq, tw, s);
             float mc = -INFINITY;
 #pragma unroll
             for (int k = 0; k < NV; ++k) mc = fmaxf(mc, s[k]);
